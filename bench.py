@@ -1,0 +1,196 @@
+"""Guidance-gradient throughput on one MI355X.
+
+Workload: batch of 16 denoised estimates v0hat (seeded layered/faulted 70 x 70
+models, dx = 10 m, 1500-4500 m/s), 5 surface shots x 70 receivers, 1000 time
+samples at dt = 1 ms, 15 Hz Ricker, 40-cell sponge, reflecting top.  One step
+is the whole guidance path for the batch: forward modelling with the history
+kept, W2 misfit and adjoint source, adjoint gradient, preconditioned update.
+Observations are synthesised once from a seeded "true" model before timing;
+inputs are resident in HBM when the timed region starts.
+
+Prints one JSON line (see the keys below).  --gpus > 1 is refused: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+NZ = NX = 70
+NS, NT, NB, B = 5, 1000, 40, 16
+HBM_PEAK_GBS = 8000.0
+
+
+def make_inputs():
+    import fwi_inputs as fi
+
+    acq = fi.surface_acquisition(NZ, NX, ns=NS, nt=NT, nb=NB)
+    v0hat = np.stack([fi.faulted_model(NZ, NX, s) for s in range(B)])
+    v_true = fi.faulted_model(NZ, NX, 1000)
+    w = fi.ricker(NT, acq.dt, acq.f_peak)
+    return acq, v0hat, v_true, w
+
+
+def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
+    """The FP64 oracle, as it stands, on the first n_samples of the batch."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    dobs = oracle.forward(acq, v_true, w)
+    obs = oracle.w2_prepare(dobs, acq.dt)
+    t0 = time.perf_counter()
+    J, g, _, _ = oracle.objective_and_gradient(acq, v0hat[:n_samples], w, obs)
+    import fwi_inputs as fi
+
+    x0 = fi.to_normalised(v0hat[:n_samples])
+    oracle.guidance(x0, g, g, x0, unit_scale=1500.0)
+    dt = time.perf_counter() - t0
+    return {
+        "value": n_samples / dt,
+        "unit": "grads/s",
+        "cores": min(threads, n_samples * NS),
+        "kind": "oracle",
+        "sample": f"{n_samples} of the {B} samples ({n_samples * NS} shot units), same grid/steps; forward + W2 + "
+                  f"reverse-mode gradient + guidance update in FP64, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_16393_amd import FwiPlan, FwiW2Loss, guidance_step  # noqa: F401
+    import fwi_inputs as fi
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    acq, v0hat, v_true, w = make_inputs()
+    plan = FwiPlan(acq, max_batch=B, device=dev)
+    wt = torch.tensor(w, dtype=torch.float32, device=dev)
+    dobs = plan.forward(torch.tensor(v_true[None], dtype=torch.float32, device=dev), wt, keep_for_adjoint=False)
+    plan.set_obs(dobs[0].contiguous())
+    v = torch.tensor(v0hat, dtype=torch.float32, device=dev)
+    x0 = torch.tensor(fi.to_normalised(v0hat), dtype=torch.float32, device=dev)
+    d = torch.empty((B, NS, acq.nr, NT), dtype=torch.float32, device=dev)
+    J = torch.empty(B, dtype=torch.float64, device=dev)
+    adj = torch.empty_like(d)
+    g = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
+    vn = torch.empty_like(g)
+    rho = torch.empty(B, dtype=torch.float32, device=dev)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    stage_ms = np.zeros(4)
+
+    def step(record=False):
+        if record:
+            ev[0].record()
+        plan.forward(v, wt, keep_for_adjoint=True, out=d)
+        if record:
+            ev[1].record()
+        plan.w2_misfit(d, want_adjoint=True, J_out=J, adj_out=adj)
+        if record:
+            ev[2].record()
+        plan.adjoint_gradient(v, adj, out=g)
+        if record:
+            ev[3].record()
+        guidance_step(x0, g, g, x0, unit_scale=1500.0, out=vn, rho_out=rho)
+        if record:
+            ev[4].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    for _ in range(args.steps):
+        step()
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    # per-stage durations (HIP events on the stream the kernels run on), averaged over a few more steps
+    reps = max(3, min(args.steps, 10))
+    for _ in range(reps):
+        step(record=True)
+        torch.cuda.synchronize()
+        stage_ms += np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(4)])
+    stage_ms /= reps
+    if plan.status() != 0:
+        print("device-side check failed", file=sys.stderr)
+        sys.exit(1)
+
+    ms_per_step = total_ms / args.steps
+    value = B * args.steps / (total_ms / 1e3)
+    nzp, nxp = acq.padded_shape
+    npts = nzp * nxp
+    updates = B * NS * (NT - 1) * npts  # per sweep
+    # algorithmic bytes per sweep: read u^n, u^{n-1}, K and write u^{n+1} (16 B) per point-update,
+    # plus 4 B per model-region point for the forward history (written forward, read by the adjoint)
+    alg_bytes = 16.0 * updates + 4.0 * B * NS * (NT - 1) * NZ * NX
+    fwd_ms, adj_ms = stage_ms[0], stage_ms[2]
+    dom_ms = max(fwd_ms, adj_ms)
+    dom = "adjoint sweep (k_wave_lds, ADJ)" if adj_ms >= fwd_ms else "forward sweep (k_wave_lds)"
+    achieved = alg_bytes / (dom_ms / 1e3) / 1e9
+    out = {
+        "metric": "guidance grads/s (70x70, 5 shots, 1k steps) plain vs surrogate @cos>=0.95",
+        "value": round(value, 2),
+        "unit": "grads/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain-solver guidance gradient: 16 faulted 70x70 models (dx=10 m, 1500-4500 m/s), 5 surface "
+                        "shots x 70 receivers, 1000 samples at dt=1 ms, 15 Hz Ricker, 40-cell sponge, W2 misfit, "
+                        "adjoint gradient, preconditioned update",
+            "batch": B,
+            "padded_grid": [nzp, nxp],
+            "path": "lds-resident" if plan.info["path"] == 0 else "tiled",
+        },
+        "stage_ms": {"forward": round(stage_ms[0], 4), "w2_misfit": round(stage_ms[1], 4),
+                     "adjoint_gradient": round(stage_ms[2], 4), "guidance": round(stage_ms[3], 4)},
+        "gpts_per_s": round(2 * updates / (ms_per_step / 1e3) / 1e9, 2),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "surrogate": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(acq, v0hat, v_true, w)
+    print(json.dumps(out))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

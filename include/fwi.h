@@ -1,0 +1,201 @@
+/*
+ * fwi.h -- C ABI of the MI355X (gfx950) likelihood-guidance library for
+ * physics-guided diffusion full-waveform inversion
+ * ("Robust Physics-Guided Diffusion for Full-Waveform Inversion", arXiv 2603.16393).
+ *
+ * One call of the guidance path per reverse-diffusion step (Algorithm 2, the
+ * gradient, preconditioner and update lines) is
+ *
+ *     fwi_forward            d_syn = F(v)                    (Sec. 2.1, Sec. 6.1)
+ *     fwi_w2_misfit          J(v), dJ/dd_syn                 (Sec. 5.1, Sec. 6.2)
+ *     fwi_adjoint_gradient   g = dJ/dv                       (adjoint of F applied to dJ/dd_syn)
+ *     fwi_guidance_step      v_{i-1} = v'_{i-1} - rho_i D_i h (Sec. 5.2, Eqs. tv, rho, kappa, precond_step)
+ *
+ * after a one-time fwi_set_obs (weights, shift constants, observed quantiles
+ * and S_obs of Sec. 5.1 (I)-(III)).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers unless marked HOST; they are owned by
+ *     the caller, must stay valid until the work queued on `stream` has run,
+ *     and are row-major with the last index contiguous.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream); all
+ *     calls only enqueue work on it and return without synchronising, except
+ *     fwi_plan_create / fwi_plan_destroy / fwi_status.
+ *   - Velocities are in m/s, lengths in m, times in s; model row 0 is the
+ *     surface (the reflecting top boundary), x is the fast axis.
+ *   - Return value: FWI_OK (0) or a negative fwi_status_code.  Argument errors
+ *     are detected on the host before anything is enqueued.  Conditions that
+ *     can only be seen on the device (a velocity outside (0, v_max], NaN/Inf)
+ *     raise a sticky flag that fwi_status reports.  Nothing throws.
+ *   - A plan is not thread-safe: use one plan per host thread and stream.
+ */
+#ifndef FWI_H
+#define FWI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FWI_OK = 0,
+    FWI_EINVAL = -1,   /* invalid argument (shape, index, NULL pointer, parameter range) */
+    FWI_ECFL = -2,     /* v_max dt sqrt(2048/315 (1/dx^2 + 1/dz^2)) >= 2: explicit scheme unstable */
+    FWI_ENOMEM = -3,   /* device allocation failed or the memory budget is too small */
+    FWI_EHIP = -4,     /* a HIP runtime call failed */
+    FWI_ESTATE = -5,   /* call out of order (no observations set, no stored forward state, ...) */
+    FWI_EDEVICE = -6   /* device-side check failed (velocity not finite, <= 0 or > v_max) */
+} fwi_status_code;
+
+/* Grid, time axis and acquisition (Sec. 2.1: grid V of nodal velocities,
+ * receiver restriction R, data array N_s x N_r x N_T; Sec. 6.3.1 geometry).
+ * Index arrays are HOST pointers, copied by fwi_plan_create.  Source and
+ * receiver nodes must lie in the model grid; receiver nodes must be distinct. */
+typedef struct {
+    int nz, nx;            /* model grid rows (depth) and columns */
+    double dz, dx;         /* grid spacings (m) */
+    double dt;             /* time step (s); trace sample n is the field at t_n = n dt */
+    int nt;                /* samples per trace (>= 2); nt - 1 time steps are taken */
+    int nb;                /* damping-sponge width in cells on the left, right and bottom
+                              (and the top when free_surface == 0) */
+    int free_surface;      /* 1: reflecting top, d_n u = 0 by even mirroring (Eq. solving) */
+    double v_max;          /* declared upper bound of v: sets the sponge strength and is
+                              checked against the CFL limit at plan creation */
+    int ns;                /* shots */
+    const int* src_iz;     /* HOST [ns] source rows */
+    const int* src_ix;     /* HOST [ns] source columns */
+    int nr;                /* receivers, one spread shared by all shots */
+    const int* rec_iz;     /* HOST [nr] receiver rows */
+    const int* rec_ix;     /* HOST [nr] receiver columns */
+} fwi_geometry;
+
+/* Misfit settings (Sec. 5.1 and Sec. 6.2).  Paper values: k = 100,
+ * eps_prime = 1e-9, n_xi = 1000, c_factor = 1.1, squared = 0, reduction = 0. */
+typedef struct {
+    double k;          /* amplitude weight omega = 1/(1 + k |d_obs| / max|d_obs|) (Eq. omega_def); 0 = raw traces */
+    double eps_prime;  /* added to the trapezoid mass before normalising (Sec. 6.2) */
+    int n_xi;          /* uniform xi grid j/(n_xi-1) for the quantile integral (>= 2) */
+    double c_factor;   /* c' = c_factor |min_t omega d_obs| per trace (Sec. 5.1 (II)) */
+    int squared;       /* 0: sum W2 / sum ||Q_obs||  (Eq. final_objective)
+                          1: sum W2^2 / sum ||Q_obs||^2 (raw-trace W2 baseline, Sec. 6) */
+    int reduction;     /* 0: divide by the observation scale S_obs; 1: average over pairs */
+} fwi_w2_params;
+
+/* Guidance-update settings (Sec. 5.2).  Paper fixed values: c = 0.1,
+ * tau = 0, eps = 1e-4 (Sec. 6.3); gamma and rho0 per dataset (Table 'parameter'). */
+typedef struct {
+    double rho0;        /* base guidance strength */
+    double c;           /* TV decay scale of rho (Eq. rho), > 0 */
+    double tau;         /* TV tolerance of rho (Eq. rho) */
+    double gamma;       /* exponent of the diagonal scaling (Eq. kappa), >= 0 */
+    double eps;         /* regulariser of the diagonal scaling (Eq. kappa), > 0 */
+    double kappa_max;   /* optional cap on kappa (the optional clipping of Algorithm 2); <= 0: off */
+    double unit_scale;  /* chain factor from the gradients' units to the diffusion state's
+                           (e.g. 1500 when v = 1500 + 1500 (x + 1) m/s and g is per m/s) */
+} fwi_guidance_params;
+
+typedef struct fwi_plan fwi_plan;
+
+/* Read-only description of a plan's layout. */
+typedef struct {
+    int nzp, nxp;              /* padded grid */
+    int path;                  /* 0: whole field resident in LDS, one workgroup per (sample, shot);
+                                  1: tiled sweep from HBM, one launch per time step */
+    int store_mode;            /* 0: full history of D = L u + s kept for the adjoint;
+                                  1: checkpoints every `ckpt_every` steps plus recomputation */
+    int ckpt_every;
+    int max_batch;
+    size_t device_bytes;       /* device memory held by the plan */
+} fwi_plan_info;
+
+/* Creates a plan for up to `max_batch` velocity samples on the current device.
+ * Validates the geometry (FWI_EINVAL), the CFL condition for v_max (FWI_ECFL),
+ * and allocates every workspace up front: padded coefficients, the forward
+ * history (full or checkpointed, whichever fits `mem_budget_bytes`; 0 = no
+ * limit beyond device memory) and the observation cache.  FWI_ENOMEM if even
+ * the checkpointed layout does not fit.  *plan receives the handle. */
+int fwi_plan_create(const fwi_geometry* geom, int max_batch, size_t mem_budget_bytes, fwi_plan** plan);
+
+/* Execution options for fwi_plan_create_ex. */
+typedef struct {
+    int force_path;     /* -1: automatic; 0: LDS-resident (FWI_EINVAL if the field does not fit);
+                           1: tiled sweep */
+    int ckpt_every;     /* 0: automatic (full history when it fits the budget, else checkpoints);
+                           > 0: checkpoint every ckpt_every steps and recompute (tiled path only) */
+} fwi_plan_options;
+
+/* fwi_plan_create with explicit execution options (NULL = automatic). */
+int fwi_plan_create_ex(const fwi_geometry* geom, int max_batch, size_t mem_budget_bytes,
+                       const fwi_plan_options* options, fwi_plan** plan);
+
+/* Frees the plan's device memory after synchronising the device. */
+int fwi_plan_destroy(fwi_plan* plan);
+
+int fwi_plan_get_info(const fwi_plan* plan, fwi_plan_info* info);
+
+/* Observation side of the misfit (Sec. 5.1 (I)-(III), Sec. 6.2): from
+ * d_obs [ns][nr][nt] computes the weights omega, the per-trace shift c', the
+ * observed quantiles on the xi grid and the scale S_obs, all kept by the plan
+ * (d_obs itself is not retained).  Must precede fwi_w2_misfit. */
+int fwi_set_obs(fwi_plan* plan, const float* d_obs, const fwi_w2_params* params, void* stream);
+
+/* Forward modelling (Eq. solving with the discretisation of Sec. 6.1):
+ * 8th-order central differences in space, leapfrog in time, damping sponge,
+ * even mirror at the top, point source wavelet[n] / (dx dz) at the shot node,
+ * d_syn[b][s][r][n] = u^n at receiver r (so d_syn[..][0] = 0).
+ *   v        [B][nz][nx]  velocity (m/s)
+ *   wavelet  [nt]         source time function f(t_n)
+ *   d_syn    [B][ns][nr][nt] output
+ *   keep_for_adjoint: 1 keeps the forward history (or its checkpoints) for a
+ *   following fwi_adjoint_gradient with the same v and B.  B <= max_batch. */
+int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, float* d_syn,
+                int keep_for_adjoint, void* stream);
+
+/* Wasserstein-2 misfit per sample and its adjoint source (Eqs. pdf_map,
+ * Wp_1d, final_objective; numerics of Sec. 6.2): weighted, shifted traces
+ * -> densities -> trapezoid CDFs -> quantiles on the xi grid -> W2 per pair,
+ * summed and normalised.  Scans and quantiles run in FP64.
+ *   d_syn    [B][ns][nr][nt]
+ *   J        [B] output (double)
+ *   adj_src  [B][ns][nr][nt] output dJ/dd_syn, or NULL to skip the adjoint. */
+int fwi_w2_misfit(fwi_plan* plan, int B, const float* d_syn, double* J, float* adj_src, void* stream);
+
+/* Adjoint-state gradient (the transpose of the linearised forward map
+ * applied to the adjoint source): the adjoint field is stepped backward in
+ * time with the receivers as sources and correlated at zero lag with the
+ * stored forward term D = L u + s, then padded cells are folded onto their
+ * edge cells and shots are summed.
+ *   v        [B][nz][nx]  must equal the v of the preceding keep_for_adjoint forward
+ *   adj_src  [B][ns][nr][nt]  dJ/dd_syn
+ *   scale    [B] per-sample factor applied to the gradient (e.g. dL/dJ), or NULL for 1
+ *   grad     [B][nz][nx] output dJ/dv per m/s, summed over shots.
+ * FWI_ESTATE if no forward state of this batch size is stored. */
+int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj_src, const float* scale,
+                         float* grad, void* stream);
+
+/* Preconditioned guidance update (Eqs. tv, rho, kappa, precond_step), per sample b:
+ *   TV   = (1/(nz nx)) sum of |forward differences| of v0hat in x and z (those that exist)
+ *   rho  = rho0 exp(-max(TV - tau, 0) / c)
+ *   kappa_j = ((max_j |s g_j| + eps) / (|s g_j| + eps))^gamma   (capped at kappa_max if > 0)
+ *   v_next = v_prop - rho kappa (s h),   s = unit_scale
+ * All fields [B][nz][nx]: v_prop = v'_{i-1}, h = grad wrt the diffusion state
+ * v_i (the caller's chain rule through the clean estimate), g = grad wrt the
+ * clean estimate, v0hat = the clean estimate in diffusion-state units.
+ * rho_out [B] (may be NULL).  Needs no plan. */
+int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h, const float* g,
+                      const float* v0hat, const fwi_guidance_params* params, float* v_next, float* rho_out,
+                      void* stream);
+
+/* Synchronises the plan's device and returns FWI_OK, or the first recorded
+ * device-side error (FWI_EDEVICE for an invalid velocity) and clears it. */
+int fwi_status(fwi_plan* plan);
+
+/* Static description of a status code. */
+const char* fwi_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWI_H */

@@ -1,0 +1,104 @@
+"""ctypes binding of libfwi.so (the C ABI declared in include/fwi.h).
+
+Argument marshalling only: every computation runs in the HIP kernels behind
+the ABI.  Importing this module fails loudly when the library has not been
+built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwi.so")
+
+c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+c_int_p = ctypes.POINTER(ctypes.c_int)
+
+FWI_OK, FWI_EINVAL, FWI_ECFL, FWI_ENOMEM, FWI_EHIP, FWI_ESTATE, FWI_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+
+# Every symbol include/fwi.h declares.
+EXPORTED = (
+    "fwi_plan_create",
+    "fwi_plan_create_ex",
+    "fwi_plan_destroy",
+    "fwi_plan_get_info",
+    "fwi_set_obs",
+    "fwi_forward",
+    "fwi_w2_misfit",
+    "fwi_adjoint_gradient",
+    "fwi_guidance_step",
+    "fwi_status",
+    "fwi_error_string",
+)
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("nz", c_int), ("nx", c_int), ("dz", c_double), ("dx", c_double), ("dt", c_double), ("nt", c_int),
+        ("nb", c_int), ("free_surface", c_int), ("v_max", c_double), ("ns", c_int), ("src_iz", c_int_p),
+        ("src_ix", c_int_p), ("nr", c_int), ("rec_iz", c_int_p), ("rec_ix", c_int_p),
+    ]
+
+
+class W2Params(ctypes.Structure):
+    _fields_ = [("k", c_double), ("eps_prime", c_double), ("n_xi", c_int), ("c_factor", c_double),
+                ("squared", c_int), ("reduction", c_int)]
+
+
+class GuidanceParams(ctypes.Structure):
+    _fields_ = [("rho0", c_double), ("c", c_double), ("tau", c_double), ("gamma", c_double), ("eps", c_double),
+                ("kappa_max", c_double), ("unit_scale", c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nzp", c_int), ("nxp", c_int), ("path", c_int), ("store_mode", c_int), ("ckpt_every", c_int),
+                ("max_batch", c_int), ("device_bytes", c_size_t)]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("force_path", c_int), ("ckpt_every", c_int)]
+
+
+class FwiError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = load().fwi_error_string(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what} failed: {msg} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Loads libfwi.so; raises if it is missing (build with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfwi.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    L.fwi_plan_create.argtypes = [ctypes.POINTER(Geometry), c_int, c_size_t, ctypes.POINTER(P)]
+    L.fwi_plan_create_ex.argtypes = [ctypes.POINTER(Geometry), c_int, c_size_t, ctypes.POINTER(PlanOptions),
+                                     ctypes.POINTER(P)]
+    L.fwi_plan_destroy.argtypes = [P]
+    L.fwi_plan_get_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    L.fwi_set_obs.argtypes = [P, P, ctypes.POINTER(W2Params), P]
+    L.fwi_forward.argtypes = [P, c_int, P, P, P, c_int, P]
+    L.fwi_w2_misfit.argtypes = [P, c_int, P, P, P, P]
+    L.fwi_adjoint_gradient.argtypes = [P, c_int, P, P, P, P, P]
+    L.fwi_guidance_step.argtypes = [c_int, c_int, c_int, P, P, P, P, ctypes.POINTER(GuidanceParams), P, P, P]
+    L.fwi_status.argtypes = [P]
+    L.fwi_error_string.argtypes = [c_int]
+    L.fwi_error_string.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "fwi_error_string":
+            getattr(L, name).restype = c_int
+    _lib = L
+    return _lib
+
+
+def check(code: int, what: str):
+    if code != FWI_OK:
+        raise FwiError(code, what)

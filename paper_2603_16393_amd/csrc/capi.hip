@@ -1,0 +1,408 @@
+// C ABI of libfwi: plan management, argument validation and dispatch to the
+// HIP kernels.  Every step of the guidance path runs in the kernels of
+// wave.hip, w2.hip and guidance.hip; this file only checks arguments, owns
+// device workspaces and enqueues launches on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <set>
+#include <utility>
+
+#include "fwi_internal.h"
+
+struct fwi_plan : public fwi::Plan {};
+
+namespace fwi {
+
+size_t w2_lds_requirement(int nt, int nxi);
+
+static int dev_alloc(Plan& p, void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) return FWI_OK;
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return FWI_ENOMEM;
+    }
+    p.allocs.push_back(*ptr);
+    p.device_bytes += bytes;
+    return FWI_OK;
+}
+
+template <class T>
+static int alloc_n(Plan& p, T** ptr, size_t n) {
+    return dev_alloc(p, (void**)ptr, n * sizeof(T));
+}
+
+static void free_all(Plan& p) {
+    for (void* a : p.allocs) (void)hipFree(a);
+    p.allocs.clear();
+    p.device_bytes = 0;
+}
+
+static int validate_geometry(const fwi_geometry* g, int max_batch) {
+    if (!g || max_batch < 1) return FWI_EINVAL;
+    if (g->nz < 1 || g->nx < 1 || g->nt < 2 || g->nb < 0 || g->ns < 1 || g->nr < 1) return FWI_EINVAL;
+    if (!(g->dz > 0) || !(g->dx > 0) || !(g->dt > 0) || !(g->v_max > 0)) return FWI_EINVAL;
+    if (!std::isfinite(g->dz) || !std::isfinite(g->dx) || !std::isfinite(g->dt) || !std::isfinite(g->v_max))
+        return FWI_EINVAL;
+    if (!g->src_iz || !g->src_ix || !g->rec_iz || !g->rec_ix) return FWI_EINVAL;
+    for (int s = 0; s < g->ns; ++s)
+        if (g->src_iz[s] < 0 || g->src_iz[s] >= g->nz || g->src_ix[s] < 0 || g->src_ix[s] >= g->nx) return FWI_EINVAL;
+    std::set<std::pair<int, int>> seen;
+    for (int r = 0; r < g->nr; ++r) {
+        if (g->rec_iz[r] < 0 || g->rec_iz[r] >= g->nz || g->rec_ix[r] < 0 || g->rec_ix[r] >= g->nx) return FWI_EINVAL;
+        if (!seen.insert({g->rec_iz[r], g->rec_ix[r]}).second) return FWI_EINVAL;  // distinct receiver nodes
+    }
+    const double r = g->v_max * g->dt * std::sqrt(2048.0 / 315.0 * (1.0 / (g->dx * g->dx) + 1.0 / (g->dz * g->dz)));
+    if (!(r < 2.0)) return FWI_ECFL;
+    const long nzp = (long)g->nz + g->nb + (g->free_surface ? 0 : g->nb);
+    const long nxp = (long)g->nx + 2L * g->nb;
+    if (nzp * nxp > (1L << 30)) return FWI_EINVAL;
+    return FWI_OK;
+}
+
+static int create(const fwi_geometry* geom, int max_batch, size_t budget, const fwi_plan_options* opt,
+                  fwi_plan** out) {
+    if (!out) return FWI_EINVAL;
+    *out = nullptr;
+    int st = validate_geometry(geom, max_batch);
+    if (st) return st;
+    fwi_plan_options o{-1, 0};
+    if (opt) o = *opt;
+    if (o.force_path < -1 || o.force_path > 1 || o.ckpt_every < 0) return FWI_EINVAL;
+
+    fwi_plan* pp = new (std::nothrow) fwi_plan();
+    if (!pp) return FWI_ENOMEM;
+    Plan& p = *pp;
+    p.g = *geom;
+    p.src_iz.assign(geom->src_iz, geom->src_iz + geom->ns);
+    p.src_ix.assign(geom->src_ix, geom->src_ix + geom->ns);
+    p.rec_iz.assign(geom->rec_iz, geom->rec_iz + geom->nr);
+    p.rec_ix.assign(geom->rec_ix, geom->rec_ix + geom->nr);
+    p.g.src_iz = p.src_iz.data();
+    p.g.src_ix = p.src_ix.data();
+    p.g.rec_iz = p.rec_iz.data();
+    p.g.rec_ix = p.rec_ix.data();
+    p.g.free_surface = geom->free_surface ? 1 : 0;
+    p.ztop = p.g.free_surface ? 0 : p.g.nb;
+    p.nzp = p.g.nz + p.g.nb + (p.g.free_surface ? 0 : p.g.nb);
+    p.nxp = p.g.nx + 2 * p.g.nb;
+    p.npts = p.nzp * p.nxp;
+    p.max_batch = max_batch;
+    p.budget = budget;
+    p.device_bytes = 0;
+    (void)hipGetDevice(&p.device);
+
+    const int ns = p.g.ns, nr = p.g.nr, nt = p.g.nt;
+    const size_t nf = (size_t)max_batch * ns;
+    const size_t npts = (size_t)p.npts;
+    const size_t nsteps = (size_t)nt - 1;
+
+    // the LDS-resident sweep needs every receiver on one row (the surface
+    // spread of Sec. 2.1, or one buried row)
+    bool one_row = true;
+    for (int r = 1; r < nr; ++r) one_row = one_row && (p.rec_iz[r] == p.rec_iz[0]);
+    bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, &p.lds_X, &p.lds_P, &p.lds_ncg, &p.lds_nstrip);
+    if (o.force_path == 0 && (!lds_ok || o.ckpt_every > 0)) {
+        delete pp;
+        return FWI_EINVAL;
+    }
+    p.path = (o.force_path == 1 || !lds_ok || o.ckpt_every > 0) ? 1 : 0;
+
+    // fixed-size buffers
+    size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
+                   nf * nr * 8 + (size_t)ns * nr * 1000 * 8;
+    if (p.path == 1) fixed += 6 * nf * npts * sizeof(float);
+    const size_t full_store = nf * nsteps * npts * sizeof(float);
+    size_t avail = budget;
+    if (avail == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        avail = free_b > ((size_t)2 << 30) ? free_b - ((size_t)2 << 30) : free_b / 2;
+    }
+    if (o.ckpt_every > 0) {
+        p.store_mode = 1;
+        p.ckpt_every = std::min<int>(o.ckpt_every, (int)nsteps);
+    } else if (fixed + full_store <= avail) {
+        p.store_mode = 0;
+        p.ckpt_every = 0;
+    } else {
+        if (p.path == 0) p.path = 1;  // checkpointing runs on the tiled sweep
+        p.store_mode = 1;
+        int K = (int)std::ceil(std::sqrt(2.0 * (double)nsteps));
+        p.ckpt_every = std::max(1, std::min<int>(K, (int)nsteps));
+    }
+    if (p.store_mode == 1) {
+        p.nseg = (int)((nsteps + p.ckpt_every - 1) / p.ckpt_every);
+        const size_t need = fixed + 6 * nf * npts * sizeof(float) +
+                            nf * ((size_t)p.ckpt_every + 2 * (size_t)p.nseg) * npts * sizeof(float);
+        if (need > avail) {
+            delete pp;
+            return FWI_ENOMEM;
+        }
+    }
+
+    // host-side tables
+    std::vector<float> ex(p.nxp, 0.f), ez(p.nzp, 0.f), wrow(p.nzp, 1.f);
+    if (p.g.nb > 0) {
+        const double base = 3.0 * p.g.v_max * std::log(1e3) / (2.0 * p.g.nb);
+        for (int ix = 0; ix < p.nxp; ++ix) {
+            int d = 0;
+            if (ix < p.g.nb) d = p.g.nb - ix;
+            if (ix >= p.g.nb + p.g.nx) d = ix - (p.g.nb + p.g.nx - 1);
+            const double r = (double)d / p.g.nb;
+            ex[ix] = (float)(base * r * r / p.g.dx * p.g.dt / 2.0);
+        }
+        for (int iz = 0; iz < p.nzp; ++iz) {
+            int d = 0;
+            if (iz >= p.ztop + p.g.nz) d = iz - (p.ztop + p.g.nz - 1);
+            if (!p.g.free_surface && iz < p.ztop) d = p.ztop - iz;
+            const double r = (double)d / p.g.nb;
+            ez[iz] = (float)(base * r * r / p.g.dz * p.g.dt / 2.0);
+        }
+    }
+    if (p.g.free_surface) wrow[0] = 0.5f;
+    std::vector<int> src_pt(ns), rec_pt(nr), rec_map;
+    std::vector<float> rec_invw(nr);
+    for (int s = 0; s < ns; ++s) src_pt[s] = (p.src_iz[s] + p.ztop) * p.nxp + p.src_ix[s] + p.g.nb;
+    p.rec_z0 = 1 << 30;
+    p.rec_z1 = -1;
+    for (int r = 0; r < nr; ++r) {
+        const int z = p.rec_iz[r] + p.ztop;
+        rec_pt[r] = z * p.nxp + p.rec_ix[r] + p.g.nb;
+        rec_invw[r] = 1.0f / wrow[z];
+        p.rec_z0 = std::min(p.rec_z0, z);
+        p.rec_z1 = std::max(p.rec_z1, z);
+    }
+    std::vector<int> rec_of_col;
+    if (p.path == 1) {
+        rec_map.assign(npts, -1);
+        for (int r = 0; r < nr; ++r) rec_map[rec_pt[r]] = r;
+    } else {
+        p.rec_row = p.rec_iz[0] + p.ztop;
+        rec_of_col.assign(p.nxp, -1);
+        for (int r = 0; r < nr; ++r) rec_of_col[p.rec_ix[r] + p.g.nb] = r;
+    }
+
+    // device allocations
+    st = FWI_OK;
+    st = st ? st : alloc_n(p, &p.K, (size_t)max_batch * npts);
+    st = st ? st : alloc_n(p, &p.ex, (size_t)p.nxp);
+    st = st ? st : alloc_n(p, &p.ez, (size_t)p.nzp);
+    st = st ? st : alloc_n(p, &p.wgt_row, (size_t)p.nzp);
+    st = st ? st : alloc_n(p, &p.src_pt, (size_t)ns);
+    st = st ? st : alloc_n(p, &p.rec_pt, (size_t)nr);
+    st = st ? st : alloc_n(p, &p.rec_invw, (size_t)nr);
+    st = st ? st : alloc_n(p, &p.gpad, nf * npts);
+    st = st ? st : alloc_n(p, &p.flags, 1);
+    st = st ? st : alloc_n(p, &p.wav, (size_t)nt);
+    st = st ? st : alloc_n(p, &p.omega, (size_t)ns * nr * nt);
+    st = st ? st : alloc_n(p, &p.cprime, (size_t)ns * nr);
+    st = st ? st : alloc_n(p, &p.qnorm, (size_t)ns * nr);
+    st = st ? st : alloc_n(p, &p.sobs, 2);
+    st = st ? st : alloc_n(p, &p.w2pair, nf * nr);
+    if (p.path == 1) {
+        st = st ? st : alloc_n(p, &p.rec_map, npts);
+        st = st ? st : alloc_n(p, &p.state, 3 * nf * npts);
+        st = st ? st : alloc_n(p, &p.astate, 3 * nf * npts);
+    } else {
+        st = st ? st : alloc_n(p, &p.rec_of_col, (size_t)p.nxp);
+    }
+    if (p.store_mode == 0) {
+        st = st ? st : alloc_n(p, &p.Dstore, nf * nsteps * npts);
+    } else {
+        st = st ? st : alloc_n(p, &p.Dstore, nf * (size_t)p.ckpt_every * npts);
+        st = st ? st : alloc_n(p, &p.ckpt, nf * (size_t)p.nseg * 2 * npts);
+    }
+    if (!st) {
+        st = hip_ok(hipMemcpy(p.ex, ex.data(), ex.size() * sizeof(float), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(p.ez, ez.data(), ez.size() * sizeof(float), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(p.wgt_row, wrow.data(), wrow.size() * sizeof(float), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(p.src_pt, src_pt.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(p.rec_pt, rec_pt.data(), nr * sizeof(int), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(p.rec_invw, rec_invw.data(), nr * sizeof(float), hipMemcpyHostToDevice));
+        if (p.path == 1)
+            st = st ? st : hip_ok(hipMemcpy(p.rec_map, rec_map.data(), npts * sizeof(int), hipMemcpyHostToDevice));
+        else
+            st = st ? st
+                    : hip_ok(hipMemcpy(p.rec_of_col, rec_of_col.data(), p.nxp * sizeof(int), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemset(p.flags, 0, sizeof(int)));
+        st = st ? st : hip_ok(hipDeviceSynchronize());
+    }
+    if (st) {
+        (void)hipGetLastError();
+        free_all(p);
+        delete pp;
+        return st;
+    }
+    *out = pp;
+    return FWI_OK;
+}
+
+}  // namespace fwi
+
+using namespace fwi;
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+int fwi_plan_create(const fwi_geometry* geom, int max_batch, size_t mem_budget_bytes, fwi_plan** plan) {
+    return create(geom, max_batch, mem_budget_bytes, nullptr, plan);
+}
+
+int fwi_plan_create_ex(const fwi_geometry* geom, int max_batch, size_t mem_budget_bytes,
+                       const fwi_plan_options* options, fwi_plan** plan) {
+    return create(geom, max_batch, mem_budget_bytes, options, plan);
+}
+
+int fwi_plan_destroy(fwi_plan* plan) {
+    if (!plan) return FWI_EINVAL;
+    (void)hipSetDevice(plan->device);
+    int st = hip_ok(hipDeviceSynchronize());
+    free_all(*plan);
+    delete plan;
+    return st;
+}
+
+int fwi_plan_get_info(const fwi_plan* plan, fwi_plan_info* info) {
+    if (!plan || !info) return FWI_EINVAL;
+    info->nzp = plan->nzp;
+    info->nxp = plan->nxp;
+    info->path = plan->path;
+    info->store_mode = plan->store_mode;
+    info->ckpt_every = plan->ckpt_every;
+    info->max_batch = plan->max_batch;
+    info->device_bytes = plan->device_bytes;
+    return FWI_OK;
+}
+
+int fwi_set_obs(fwi_plan* plan, const float* d_obs, const fwi_w2_params* params, void* stream) {
+    if (!plan || !d_obs || !params) return FWI_EINVAL;
+    const fwi_w2_params& w = *params;
+    if (!(w.k >= 0) || !(w.eps_prime >= 0) || w.n_xi < 2 || !(w.c_factor >= 0) || (w.squared != 0 && w.squared != 1) ||
+        (w.reduction != 0 && w.reduction != 1))
+        return FWI_EINVAL;
+    if (w2_lds_requirement(plan->g.nt, w.n_xi) > (size_t)kLdsBytes) return FWI_EINVAL;
+    (void)hipSetDevice(plan->device);
+    Plan& p = *plan;
+    if (p.qobs_cap < w.n_xi) {
+        if (p.qobs) {
+            (void)hipStreamSynchronize(as_stream(stream));
+            auto it = std::find(p.allocs.begin(), p.allocs.end(), (void*)p.qobs);
+            if (it != p.allocs.end()) p.allocs.erase(it);
+            (void)hipFree(p.qobs);
+            p.device_bytes -= (size_t)p.qobs_cap * p.g.ns * p.g.nr * sizeof(double);
+            p.qobs = nullptr;
+        }
+        int st = alloc_n(p, &p.qobs, (size_t)w.n_xi * p.g.ns * p.g.nr);
+        if (st) return st;
+        p.qobs_cap = w.n_xi;
+    }
+    p.w2p = w;
+    int st = launch_w2_obs(p, d_obs, as_stream(stream));
+    if (st) return st;
+    p.have_obs = 1;
+    return FWI_OK;
+}
+
+int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, float* d_syn, int keep_for_adjoint,
+                void* stream) {
+    if (!plan || B < 0 || B > plan->max_batch) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (!v || !wavelet || !d_syn) return FWI_EINVAL;
+    (void)hipSetDevice(plan->device);
+    Plan& p = *plan;
+    hipStream_t st = as_stream(stream);
+    int rc = launch_prep_velocity(p, B, v, st);
+    if (rc) return rc;
+    p.stored_B = 0;
+    if (keep_for_adjoint) {
+        rc = launch_copy(p.wav, wavelet, (size_t)p.g.nt, st);
+        if (rc) return rc;
+    }
+    if (p.path == 0)
+        rc = launch_lds_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
+    else
+        rc = tiled_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
+    if (rc) return rc;
+    p.stored_B = keep_for_adjoint ? B : 0;
+    return FWI_OK;
+}
+
+int fwi_w2_misfit(fwi_plan* plan, int B, const float* d_syn, double* J, float* adj_src, void* stream) {
+    if (!plan || B < 0 || B > plan->max_batch) return FWI_EINVAL;
+    if (!plan->have_obs) return FWI_ESTATE;
+    if (B == 0) return FWI_OK;
+    if (!d_syn || !J) return FWI_EINVAL;
+    (void)hipSetDevice(plan->device);
+    return launch_w2_misfit(*plan, B, d_syn, J, adj_src, as_stream(stream));
+}
+
+int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj_src, const float* scale, float* grad,
+                         void* stream) {
+    if (!plan || B < 0 || B > plan->max_batch) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (!v || !adj_src || !grad) return FWI_EINVAL;
+    if (plan->stored_B != B) return FWI_ESTATE;
+    (void)hipSetDevice(plan->device);
+    Plan& p = *plan;
+    hipStream_t st = as_stream(stream);
+    int rc = launch_prep_velocity(p, B, v, st);
+    if (rc) return rc;
+    if (p.path == 0)
+        rc = launch_lds_adjoint(p, B, adj_src, nullptr, st);
+    else
+        rc = tiled_adjoint(p, B, adj_src, p.wav, nullptr, st);
+    if (rc) return rc;
+    return launch_fold_gradient(p, B, scale, grad, st);
+}
+
+int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h, const float* g, const float* v0hat,
+                      const fwi_guidance_params* params, float* v_next, float* rho_out, void* stream) {
+    if (B < 0 || nz < 1 || nx < 1 || !params) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (!v_prop || !h || !g || !v0hat || !v_next) return FWI_EINVAL;
+    const fwi_guidance_params& gp = *params;
+    if (!(gp.c > 0) || !(gp.eps > 0) || !(gp.gamma >= 0) || !std::isfinite(gp.rho0) || !std::isfinite(gp.tau) ||
+        !std::isfinite(gp.unit_scale))
+        return FWI_EINVAL;
+    return launch_guidance(B, nz, nx, v_prop, h, g, v0hat, gp, v_next, rho_out, as_stream(stream));
+}
+
+int fwi_status(fwi_plan* plan) {
+    if (!plan) return FWI_EINVAL;
+    (void)hipSetDevice(plan->device);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return FWI_EHIP;
+    }
+    int flags = 0;
+    if (hipMemcpy(&flags, plan->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return FWI_EHIP;
+    if (flags) {
+        (void)hipMemset(plan->flags, 0, sizeof(int));
+        (void)hipDeviceSynchronize();
+        return FWI_EDEVICE;
+    }
+    return FWI_OK;
+}
+
+const char* fwi_error_string(int code) {
+    switch (code) {
+        case FWI_OK: return "ok";
+        case FWI_EINVAL: return "invalid argument";
+        case FWI_ECFL: return "CFL condition violated for the declared v_max";
+        case FWI_ENOMEM: return "out of device memory or memory budget";
+        case FWI_EHIP: return "HIP runtime error";
+        case FWI_ESTATE: return "call out of order (observations or forward state missing)";
+        case FWI_EDEVICE: return "device-side check failed (velocity not finite, <= 0 or > v_max)";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

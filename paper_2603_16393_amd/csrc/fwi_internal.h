@@ -1,0 +1,161 @@
+// Internal declarations shared by the HIP translation units of libfwi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "fwi.h"
+
+namespace fwi {
+
+// Weights of the 8th-order central second derivative, offsets 0..4.
+#define FWI_W0 (-205.0f / 72.0f)
+#define FWI_W1 (8.0f / 5.0f)
+#define FWI_W2 (-1.0f / 5.0f)
+#define FWI_W3 (8.0f / 315.0f)
+#define FWI_W4 (-1.0f / 560.0f)
+
+// 8th-order second difference of a 9-point window in difference form:
+// sum_k W_k [(u(+k) - u) + (u(-k) - u)].  Neighbouring values of a resolved
+// field are close, so each difference is (nearly) exact and the sum carries
+// no cancellation of the size of u.
+#define FWI_LAPD(c, m4, m3, m2, m1, p1, p2, p3, p4)                                     \
+    (FWI_W1 * (((m1) - (c)) + ((p1) - (c))) + FWI_W2 * (((m2) - (c)) + ((p2) - (c))) + \
+     FWI_W3 * (((m3) - (c)) + ((p3) - (c))) + FWI_W4 * (((m4) - (c)) + ((p4) - (c))))
+
+// Largest LDS allocation of one workgroup on gfx950.
+constexpr int kLdsBytes = 160 * 1024;
+constexpr int kLdsThreads = 512;
+constexpr int kLdsMaxP = 48;   // rows per thread of the LDS-resident sweep (multiple of 4)
+
+// Device flag bits.
+constexpr int kFlagBadVelocity = 1;
+
+struct Plan;
+
+// Time stepping keeps (u^n, w^n = u^n - u^{n-1}) and advances
+//   D^n     = sum_k W_k [(u(+k) - u) + (u(-k) - u)] / h^2 per axis + s^n
+//   w^{n+1} = A ((1 - e) w^n + K D^n),   u^{n+1} = u^n + w^{n+1}
+// which is the leapfrog recursion rearranged so that FP32 rounding neither
+// cancels in the Laplacian nor feeds back through the second difference.
+
+// Arguments of the LDS-resident time loop (one workgroup per (sample, shot) field).
+struct LdsArgs {
+    int nzp, nxp, npts;      // padded grid
+    int S;                   // LDS row stride (ncg * X + 8)
+    int X, P;                // columns and rows of one thread's register tile
+    int ncg, nstrip;         // column groups and row strips (threads = ncg * nstrip)
+    int fs;                  // reflecting top
+    int nt, ns, nr;
+    int rec_row;             // padded row holding every receiver
+    float rec_invw;          // 1/w on that row (2 on a reflecting top row)
+    float idz2, idx2, src_scale;   // 1/dz^2, 1/dx^2, 1/(dx dz)
+    const float* K;          // [B][npts] (v dt)^2
+    const float* wavelet;    // [nt]
+    const int* src_pt;       // [ns] padded linear index
+    const int* rec_of_col;   // [nxp] receiver index on rec_row, or -1
+    float* traces;           // forward: d_syn out [B][ns][nr][nt]
+    const float* adj;        // adjoint: [B][ns][nr][nt]
+    float* Dstore;           // [B*ns][nt-1][npts]
+    float* gpad;             // adjoint out: [B*ns][npts] sum_n psi^{n+1} D^n
+    int store;               // forward: write D
+};
+
+// Arguments of one tiled step (fields in HBM).
+struct TileArgs {
+    int nzp, nxp, npts;
+    int fs;
+    int nt, ns, nr;
+    int nfields;
+    float idz2, idx2, src_scale;
+    const float* K;
+    const float* wavelet;
+    const int* src_pt;
+    const int* rec_map;      // [npts] receiver index or -1
+    const float* rec_invw;
+    int rec_z0, rec_z1;      // receiver row range (inclusive) for a block-uniform skip
+    const float* ucur;       // [nfields][npts] u^n
+    float* unxt;             // [nfields][npts] u^{n+1} (output)
+    float* wst;              // [nfields][npts] w^n in, w^{n+1} out
+    float* traces;
+    const float* adj;
+    float* Dout;             // forward: D^n destination [nfields][dstride] slice for this step, or null
+    const float* Din;        // adjoint: D^{n} source for the accumulation, or null
+    size_t dstride;          // elements between fields in Dout/Din
+    float* acc;              // adjoint: [nfields][npts] running sum of psi D
+};
+
+struct Plan {
+    fwi_geometry g;                      // host copy (index pointers point into vectors below)
+    std::vector<int> src_iz, src_ix, rec_iz, rec_ix;
+    int nzp, nxp, npts, ztop;
+    int max_batch;
+    size_t budget;
+    int device;
+    int path;                            // 0 LDS-resident, 1 tiled
+    int store_mode;                      // 0 full, 1 checkpointed
+    int ckpt_every;
+    int nseg;
+    int lds_X = 0, lds_P = 0, lds_ncg = 0, lds_nstrip = 0;
+    size_t device_bytes;
+    std::vector<void*> allocs;
+
+    // device buffers
+    float* K = nullptr;          // [max_batch][npts]
+    float* ex = nullptr;         // [nxp] sponge term eta_x dt/2 per padded column
+    float* ez = nullptr;         // [nzp] sponge term eta_z dt/2 per padded row
+    float* wgt_row = nullptr;    // [nzp]
+    int* src_pt = nullptr;       // [ns]
+    int* rec_pt = nullptr;       // [nr]
+    int* rec_map = nullptr;      // [npts] (tiled path)
+    int* rec_of_col = nullptr;   // [nxp] (LDS path)
+    int rec_row = -1;            // padded row of the receivers when they share one row
+    float* rec_invw = nullptr;   // [nr]
+    float* Dstore = nullptr;     // full: [max_batch*ns][nt-1][npts]; ckpt: [max_batch*ns][ckpt_every][npts]
+    float* ckpt = nullptr;       // ckpt: [max_batch*ns][nseg][2][npts] (u^n, w^n)
+    float* state = nullptr;      // tiled: [3][max_batch*ns][npts] u (ping-pong) and w
+    float* astate = nullptr;     // tiled adjoint: [3][max_batch*ns][npts]
+    float* acc = nullptr;        // tiled adjoint: [max_batch*ns][npts]
+    float* gpad = nullptr;       // [max_batch*ns][npts]
+    int* flags = nullptr;        // [1]
+    float* wav = nullptr;        // [nt] copy of the kept forward's wavelet (segment recomputation)
+    int rec_z0 = 0, rec_z1 = -1;
+
+    // observation cache
+    int have_obs = 0;
+    fwi_w2_params w2p;
+    double* omega = nullptr;     // [ns*nr*nt]
+    double* cprime = nullptr;    // [ns*nr]
+    double* qobs = nullptr;      // [ns*nr*n_xi]
+    double* qnorm = nullptr;     // [ns*nr] per-trace (int Q_obs^2) (squared) or its root
+    double* sobs = nullptr;      // [1]
+    double* w2pair = nullptr;    // [max_batch*ns*nr]
+    int qobs_cap = 0;            // n_xi capacity of qobs
+
+    int stored_B = 0;            // batch of the forward state kept for the adjoint (0 = none)
+};
+
+// Register-tile layout of the LDS-resident sweep for an nzp x nxp padded
+// field (false if the field does not fit in LDS).
+bool lds_choose_layout(int nzp, int nxp, int* X, int* P, int* ncg, int* nstrip);
+size_t lds_bytes(int X, int P, int ncg, int nstrip);
+
+// Launchers (return FWI_OK or FWI_EHIP).
+int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st);
+int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
+int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wavelet, hipStream_t st);
+int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st);
+int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float* traces_scratch, hipStream_t st);
+int launch_fold_gradient(const Plan& p, int B, const float* scale, float* grad, hipStream_t st);
+int launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
+int launch_w2_obs(Plan& p, const float* d_obs, hipStream_t st);
+int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st);
+int launch_guidance(int B, int nz, int nx, const float* v_prop, const float* h, const float* g, const float* v0hat,
+                    const fwi_guidance_params& gp, float* v_next, float* rho_out, hipStream_t st);
+
+inline int hip_ok(hipError_t e) { return e == hipSuccess ? FWI_OK : FWI_EHIP; }
+
+}  // namespace fwi

@@ -1,0 +1,325 @@
+// Acoustic wave propagation on gfx950: forward modelling and the adjoint
+// sweep with the zero-lag imaging condition.
+//
+// Scheme (the constant-density acoustic equation of Sec. 2.1 with the solver
+// settings of Sec. 6.1; a damping sponge stands in for the PML):
+//   D^n     = L u^n + s^n                    (8th-order Laplacian; s^n = f_n/(dx dz) at the source node)
+//   (1 + e) u^{n+1} = 2 u^n - (1 - e) u^{n-1} + K D^n,   K = (v dt)^2,  e = eta dt / 2,
+// advanced as w^{n+1} = ((1 - e) w^n + K D^n)/(1 + e), u^{n+1} = u^n + w^{n+1}
+// with the Laplacian summed as differences from the centre value (FP32
+// rounding then neither cancels in L nor feeds back through 2u^n - u^{n-1}).
+// Traces: d^n = u^n at the receivers.  With W = diag(1/2 on a reflecting top
+// row, 1 elsewhere), W L is symmetric, so the adjoint field psi obeys the same
+// recursion backward in time with sources a^n / w at the receivers, and
+//   dJ/dv_pad = (2 w / v) sum_n psi^{n+1} D^n,
+// folded onto the model by transposing the edge replication.
+//
+// Two execution paths:
+//  * LDS-resident (wave_lds.hip): one workgroup per (sample, shot) keeps the
+//    whole padded field in LDS for all nt-1 steps.
+//  * tiled: fields too large for LDS are swept one time step per launch in
+//    64 x 16 tiles staged through LDS with a 4-cell halo.
+#include <algorithm>
+#include <cmath>
+
+#include "fwi_internal.h"
+
+namespace fwi {
+
+// ---------------------------------------------------------------------------
+// Velocity -> padded coefficient K = (v dt)^2, with the device-side check.
+__global__ void k_prep_velocity(int B, int nz, int nx, int nzp, int nxp, int ztop, int nb, float dt, float vmax,
+                                const float* __restrict__ v, float* __restrict__ K, int* __restrict__ flags) {
+    const int npts = nzp * nxp;
+    const long total = (long)B * npts;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int b = (int)(i / npts);
+        const int p = (int)(i - (long)b * npts);
+        const int iz = p / nxp, ix = p - (p / nxp) * nxp;
+        const int mz = min(max(iz - ztop, 0), nz - 1);
+        const int mx = min(max(ix - nb, 0), nx - 1);
+        const float vv = v[(size_t)b * nz * nx + mz * nx + mx];
+        if (!(vv > 0.f) || !(vv <= vmax)) atomicOr(flags, kFlagBadVelocity);  // also catches NaN
+        const float c = vv * dt;
+        K[i] = c * c;
+    }
+}
+
+int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st) {
+    const long total = (long)B * p.npts;
+    const int threads = 256;
+    const int blocks = (int)std::min<long>((total + threads - 1) / threads, 65535);
+    hipLaunchKernelGGL(k_prep_velocity, dim3(blocks), dim3(threads), 0, st, B, p.g.nz, p.g.nx, p.nzp, p.nxp, p.ztop,
+                       p.g.nb, (float)p.g.dt, (float)p.g.v_max, v, p.K, p.flags);
+    return hip_ok(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Tiled sweep: one launch per time step.  Block = 64 columns x 4 strips of 4
+// rows (a 64 x 16 tile); the tile of u^n plus a 4-cell halo is staged in LDS.
+constexpr int TX = 64, TZ = 16, TSTRIP = 4, TROWS = TZ / TSTRIP;
+
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const float* __restrict__ ex_g,
+                                                   const float* __restrict__ ez_g) {
+    constexpr int SS = TX + 8;
+    __shared__ float tile[(TZ + 8) * SS];
+    const int field = blockIdx.z;
+    const int b = field / a.ns;
+    const int s = field - b * a.ns;
+    const int x0 = blockIdx.x * TX, zt = blockIdx.y * TZ;
+    const int tx = threadIdx.x % TX, ts = threadIdx.x / TX;
+    const int nxp = a.nxp, nzp = a.nzp;
+    const float* uc = a.ucur + (size_t)field * a.npts;
+    float* un_g = a.unxt + (size_t)field * a.npts;
+    float* wg = a.wst + (size_t)field * a.npts;
+
+    for (int i = threadIdx.x; i < (TZ + 8) * SS; i += 256) {
+        const int r = i / SS, c = i - (i / SS) * SS;
+        int gz = zt + r - 4;
+        const int gx = x0 + c - 4;
+        if (a.fs && gz < 0) gz = -gz;
+        float val = 0.f;
+        if (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) val = uc[gz * nxp + gx];
+        tile[i] = val;
+    }
+    __syncthreads();
+    const int gx = x0 + tx;
+    if (gx >= nxp) return;
+    const float exv = ex_g[gx];
+    const int sp = a.src_pt[s];
+    const bool check_rec = (zt + TZ > a.rec_z0) && (zt <= a.rec_z1);
+#pragma unroll
+    for (int j = 0; j < TROWS; ++j) {
+        const int lz = ts * TROWS + j;
+        const int gz = zt + lz;
+        if (gz >= nzp) break;
+        const int p = gz * nxp + gx;
+        const int li = (lz + 4) * SS + tx + 4;
+        const float c = tile[li];
+        const float lzs = FWI_LAPD(c, tile[li - 4 * SS], tile[li - 3 * SS], tile[li - 2 * SS], tile[li - SS],
+                                   tile[li + SS], tile[li + 2 * SS], tile[li + 3 * SS], tile[li + 4 * SS]);
+        const float lxs = FWI_LAPD(c, tile[li - 4], tile[li - 3], tile[li - 2], tile[li - 1], tile[li + 1],
+                                   tile[li + 2], tile[li + 3], tile[li + 4]);
+        float D = lzs * a.idz2 + lxs * a.idx2;
+        int r = -1;
+        if (check_rec) r = a.rec_map[p];
+        if (!ADJ && p == sp) D += a.wavelet[m] * a.src_scale;
+        if (ADJ && r >= 0) D += a.rec_invw[r] * a.adj[((size_t)field * a.nr + r) * a.nt + (a.nt - 1 - m)];
+        const float e = exv + ez_g[gz];
+        const float Kp = a.K[(size_t)b * a.npts + p];
+        const float wn = ((1.f - e) * wg[p] + Kp * D) / (1.f + e);
+        const float un = c + wn;
+        wg[p] = wn;
+        un_g[p] = un;
+        if (ADJ) {
+            if (a.Din) a.acc[(size_t)field * a.npts + p] += un * a.Din[(size_t)field * a.dstride + p];
+        } else {
+            if (a.Dout) a.Dout[(size_t)field * a.dstride + p] = D;
+            if (r >= 0 && a.traces) a.traces[((size_t)field * a.nr + r) * a.nt + m + 1] = un;
+        }
+    }
+}
+
+__global__ void k_fill(float* __restrict__ x, size_t n, float val) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = val;
+}
+
+__global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Receiver sample 0 of every trace is u^0 = 0.
+__global__ void k_zero_first_sample(float* __restrict__ traces, int ntr, int nt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ntr) traces[(size_t)i * nt] = 0.f;
+}
+
+static void fill(float* x, size_t n, float v, hipStream_t st) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    if (n) hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, x, n, v);
+}
+
+static void copy(float* dst, const float* src, size_t n, hipStream_t st) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    if (n) hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, dst, src, n);
+}
+
+int launch_copy(float* dst, const float* src, size_t n, hipStream_t st) {
+    copy(dst, src, n, st);
+    return hip_ok(hipGetLastError());
+}
+
+static TileArgs make_tile_args(const Plan& p, int B) {
+    TileArgs a{};
+    a.nzp = p.nzp;
+    a.nxp = p.nxp;
+    a.npts = p.npts;
+    a.fs = p.g.free_surface ? 1 : 0;
+    a.nt = p.g.nt;
+    a.ns = p.g.ns;
+    a.nr = p.g.nr;
+    a.nfields = B * p.g.ns;
+    a.idz2 = (float)(1.0 / (p.g.dz * p.g.dz));
+    a.idx2 = (float)(1.0 / (p.g.dx * p.g.dx));
+    a.src_scale = (float)(1.0 / (p.g.dx * p.g.dz));
+    a.K = p.K;
+    a.src_pt = p.src_pt;
+    a.rec_map = p.rec_map;
+    a.rec_invw = p.rec_invw;
+    a.rec_z0 = p.rec_z0;
+    a.rec_z1 = p.rec_z1;
+    return a;
+}
+
+static dim3 tile_grid(const Plan& p, int nfields) {
+    return dim3((p.nxp + TX - 1) / TX, (p.nzp + TZ - 1) / TZ, nfields);
+}
+
+// Copies (u, w) of every field between the state buffers and checkpoint slot c.
+static void ckpt_copy(Plan& p, int nf, int c, const float* u, const float* w, float* u_out, float* w_out,
+                      bool save, hipStream_t st) {
+    for (int f = 0; f < nf; ++f) {
+        float* slot = p.ckpt + ((size_t)f * p.nseg + c) * 2 * p.npts;
+        const size_t off = (size_t)f * p.npts;
+        if (save) {
+            copy(slot, u + off, p.npts, st);
+            copy(slot + p.npts, w + off, p.npts, st);
+        } else {
+            copy(u_out + off, slot, p.npts, st);
+            copy(w_out + off, slot + p.npts, p.npts, st);
+        }
+    }
+}
+
+// Forward sweep of the tiled path; keeps D (full) or checkpoints of (u^n, w^n).
+int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st) {
+    const int nf = B * p.g.ns;
+    const size_t fs = (size_t)nf * p.npts;
+    float* u0 = p.state;
+    float* u1 = p.state + fs;
+    float* w = p.state + 2 * fs;
+    fill(p.state, 3 * fs, 0.f, st);
+    if (traces) hipLaunchKernelGGL(k_zero_first_sample, dim3((nf * p.g.nr + 255) / 256), dim3(256), 0, st, traces,
+                                   nf * p.g.nr, p.g.nt);
+    TileArgs a = make_tile_args(p, B);
+    a.traces = traces;
+    a.wavelet = wavelet;
+    a.wst = w;
+    const dim3 grid = tile_grid(p, nf);
+    const int nsteps = p.g.nt - 1;
+    a.dstride = (size_t)nsteps * p.npts;
+    for (int n = 0; n < nsteps; ++n) {
+        if (keep && p.store_mode == 1 && n % p.ckpt_every == 0)
+            ckpt_copy(p, nf, n / p.ckpt_every, u0, w, nullptr, nullptr, true, st);
+        a.ucur = u0;
+        a.unxt = u1;
+        a.Dout = (keep && p.store_mode == 0) ? p.Dstore + (size_t)n * p.npts : nullptr;
+        hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, a, n, p.ex, p.ez);
+        std::swap(u0, u1);
+    }
+    return hip_ok(hipGetLastError());
+}
+
+// Adjoint sweep of the tiled path; gpad receives sum_n psi^{n+1} D^n per padded cell.
+int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float* /*traces_scratch*/,
+                  hipStream_t st) {
+    const int nf = B * p.g.ns;
+    const size_t fs = (size_t)nf * p.npts;
+    const int nsteps = p.g.nt - 1;
+    float* a0 = p.astate;
+    float* a1 = p.astate + fs;
+    float* aw = p.astate + 2 * fs;
+    fill(p.astate, 3 * fs, 0.f, st);
+    fill(p.gpad, fs, 0.f, st);
+    TileArgs aa = make_tile_args(p, B);
+    aa.adj = adj;
+    aa.acc = p.gpad;
+    aa.wavelet = wavelet;
+    aa.wst = aw;
+    const dim3 grid = tile_grid(p, nf);
+    if (p.store_mode == 0) {
+        aa.dstride = (size_t)nsteps * p.npts;
+        for (int m = 0; m < nsteps; ++m) {
+            aa.ucur = a0;
+            aa.unxt = a1;
+            aa.Din = p.Dstore + (size_t)(nsteps - 1 - m) * p.npts;
+            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ex, p.ez);
+            std::swap(a0, a1);
+        }
+        return hip_ok(hipGetLastError());
+    }
+    // checkpointed: recompute each segment's D, then step the adjoint through it
+    TileArgs fa = make_tile_args(p, B);
+    fa.wavelet = wavelet;
+    fa.traces = nullptr;
+    const int K = p.ckpt_every;
+    fa.dstride = (size_t)K * p.npts;
+    aa.dstride = (size_t)K * p.npts;
+    for (int c = p.nseg - 1; c >= 0; --c) {
+        const int n0 = c * K;
+        const int n1 = std::min(n0 + K, nsteps);
+        float* f0 = p.state;
+        float* f1 = p.state + fs;
+        float* fw = p.state + 2 * fs;
+        ckpt_copy(p, nf, c, nullptr, nullptr, f0, fw, false, st);
+        fa.wst = fw;
+        for (int n = n0; n < n1; ++n) {
+            fa.ucur = f0;
+            fa.unxt = f1;
+            fa.Dout = p.Dstore + (size_t)(n - n0) * p.npts;
+            hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, fa, n, p.ex, p.ez);
+            std::swap(f0, f1);
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const int m = nsteps - 1 - n;
+            aa.ucur = a0;
+            aa.unxt = a1;
+            aa.Din = p.Dstore + (size_t)(n - n0) * p.npts;
+            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ex, p.ez);
+            std::swap(a0, a1);
+        }
+    }
+    return hip_ok(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// grad[b][iz][ix] = scale[b] * sum_s sum_{padded p -> (iz, ix)} gpad[b, s][p] * 2 w_p dt / sqrt(K_p)
+// (2 w / v with v = sqrt(K)/dt), summed in a fixed order.
+__global__ void k_fold_gradient(int B, int ns, int nz, int nx, int nzp, int nxp, int ztop, int nb, float dt,
+                                const float* __restrict__ K, const float* __restrict__ wgt_row,
+                                const float* __restrict__ gpad, const float* __restrict__ scale,
+                                float* __restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * nz * nx) return;
+    const int b = i / (nz * nx);
+    const int q = i - b * nz * nx;
+    const int iz = q / nx, ix = q - (q / nx) * nx;
+    const int zlo = (iz == 0) ? 0 : iz + ztop;
+    const int zhi = (iz == nz - 1) ? nzp - 1 : iz + ztop;
+    const int xlo = (ix == 0) ? 0 : ix + nb;
+    const int xhi = (ix == nx - 1) ? nxp - 1 : ix + nb;
+    const int npts = nzp * nxp;
+    const float* Kb = K + (size_t)b * npts;
+    float sum = 0.f;
+    for (int s = 0; s < ns; ++s) {
+        const float* gp = gpad + ((size_t)b * ns + s) * npts;
+        for (int z = zlo; z <= zhi; ++z)
+            for (int x = xlo; x <= xhi; ++x) {
+                const int p = z * nxp + x;
+                sum += gp[p] * (2.f * wgt_row[z] * dt / sqrtf(Kb[p]));
+            }
+    }
+    grad[i] = sum * (scale ? scale[b] : 1.f);
+}
+
+int launch_fold_gradient(const Plan& p, int B, const float* scale, float* grad, hipStream_t st) {
+    const int n = B * p.g.nz * p.g.nx;
+    hipLaunchKernelGGL(k_fold_gradient, dim3((n + 255) / 256), dim3(256), 0, st, B, p.g.ns, p.g.nz, p.g.nx, p.nzp,
+                       p.nxp, p.ztop, p.g.nb, (float)p.g.dt, p.K, p.wgt_row, p.gpad, scale, grad);
+    return hip_ok(hipGetLastError());
+}
+
+}  // namespace fwi

@@ -1,0 +1,83 @@
+"""The C ABI library loads and exports every symbol include/fwi.h declares
+(no GPU needed); host-side argument validation returns before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fwi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(fwi_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("fwi_forward", "fwi_w2_misfit", "fwi_adjoint_gradient", "fwi_guidance_step", "fwi_set_obs",
+              "fwi_plan_create", "fwi_plan_destroy", "fwi_status"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.fwi_error_string(-2).decode().startswith("CFL")
+
+
+def _geom(nz=10, nx=10, dt=1e-3, vmax=4500.0, src=(0, 5), recs=((0, 1), (0, 2))):
+    from paper_2603_16393_amd import _lib
+
+    keep = [np.array([src[0]], np.int32), np.array([src[1]], np.int32),
+            np.array([r[0] for r in recs], np.int32), np.array([r[1] for r in recs], np.int32)]
+    p = [k.ctypes.data_as(_lib.c_int_p) for k in keep]
+    g = _lib.Geometry(nz, nx, 10.0, 10.0, dt, 100, 4, 1, vmax, 1, p[0], p[1], len(recs), p[2], p[3])
+    return g, keep
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dt=2e-3), -2),                 # CFL: 4500 * 2e-3 / 10 = 0.9 > 0.5546
+    (dict(src=(10, 5)), -1),             # source outside the model
+    (dict(recs=((0, 1), (0, 1))), -1),   # duplicate receiver node
+    (dict(recs=((0, 1), (3, 10))), -1),  # receiver outside
+    (dict(vmax=-1.0), -1),
+])
+def test_plan_create_validation(kw, code):
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    g, keep = _geom(**kw)
+    h = ctypes.c_void_p()
+    assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == code
+    assert not h.value
+
+
+def test_guidance_validation():
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    bad = _lib.GuidanceParams(1.0, 0.0, 0.0, 0.5, 1e-4, 0.0, 1.0)  # c = 0
+    x = ctypes.c_void_p(16)
+    assert L.fwi_guidance_step(1, 4, 4, x, x, x, x, ctypes.byref(bad), x, None, None) == -1
+    ok = _lib.GuidanceParams(1.0, 0.1, 0.0, 0.5, 1e-4, 0.0, 1.0)
+    assert L.fwi_guidance_step(0, 4, 4, None, None, None, None, ctypes.byref(ok), None, None, None) == 0
+
+
+def test_product_has_no_oracle_or_cpu_path():
+    """The product package never imports the oracle, and the HIP library is required."""
+    pkg = os.path.join(ROOT, "paper_2603_16393_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "fwi_oracle" not in src, f
