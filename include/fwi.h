@@ -107,6 +107,7 @@ typedef struct {
     int ckpt_every;
     int max_batch;
     size_t device_bytes;       /* device memory held by the plan */
+    int lds_tile_x, lds_tile_z;  /* register tile of the LDS-resident path (0 on the tiled path) */
 } fwi_plan_info;
 
 /* Creates a plan for up to `max_batch` velocity samples on the current device.
@@ -123,6 +124,8 @@ typedef struct {
                            1: tiled sweep */
     int ckpt_every;     /* 0: automatic (full history when it fits the budget, else checkpoints);
                            > 0: checkpoint every ckpt_every steps and recompute (tiled path only) */
+    int lds_tile_x;     /* LDS-resident path: columns x rows of one thread's register tile;   */
+    int lds_tile_z;     /* 0, 0 = the built-in cost model's choice; FWI_EINVAL if not available */
 } fwi_plan_options;
 
 /* fwi_plan_create with explicit execution options (NULL = automatic). */

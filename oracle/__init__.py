@@ -62,7 +62,7 @@ def lib():
         L.orc_stencil_weights.argtypes = [_dp]
         L.orc_stencil_weights.restype = None
         L.orc_apply_laplacian.argtypes = [i, i, d, d, i, _dp, _dp, i]
-        L.orc_sponge.argtypes = [i, i, d, d, i, i, d, _dp]
+        L.orc_sponge.argtypes = [i, i, d, d, d, i, i, d, _dp]
         L.orc_wavefield.argtypes = [i, i, d, d, d, i, i, i, d, i, i, _dp, _dp, i, i, _dp]
         L.orc_cfl_number.argtypes = [d, d, d, d]
         L.orc_cfl_number.restype = d
@@ -237,11 +237,12 @@ def apply_laplacian(u: np.ndarray, dz: float, dx: float, free_surface: bool, tra
 
 
 def sponge(acq) -> np.ndarray:
+    """Velocity-damping factor a of every padded node (1 in the model)."""
     nzp, nxp = acq.padded_shape
-    eta = np.zeros((nzp, nxp))
-    _chk(lib().orc_sponge(acq.nz, acq.nx, acq.dz, acq.dx, acq.nb, int(acq.free_surface), acq.v_max, _p(eta)),
+    a = np.zeros((nzp, nxp))
+    _chk(lib().orc_sponge(acq.nz, acq.nx, acq.dz, acq.dx, acq.dt, acq.nb, int(acq.free_surface), acq.v_max, _p(a)),
          "orc_sponge")
-    return eta
+    return a
 
 
 def wavefield(acq, v, wavelet, shot: int = 0, nsteps: int | None = None, check_cfl: bool = True) -> np.ndarray:

@@ -21,7 +21,8 @@
  * Discrete choices the paper leaves open (each is listed in the design notes):
  *   - 8th-order central weights for the second derivative; mirror (even)
  *     ghosts above row 0 implement the reflecting top boundary d_n u = 0;
- *   - a quadratic-profile damping sponge replaces the paper's PML;
+ *   - a damping sponge (separable velocity-damping factor with the quadratic
+ *     textbook profile) replaces the paper's PML;
  *   - the point source f(t) delta(x - xi) is injected as f(t_n)/(dx dz) at the
  *     source node; sample n of a trace is u^n at the receiver node, t_n = n dt;
  *   - quantile = first crossing of the linearly interpolated trapezoid CDF,
@@ -81,23 +82,29 @@ static void pad_velocity(const Grid* g, const double* v, double* vp) {
         }
 }
 
-/* Sponge damping eta (1/s): quadratic in the depth into the layer, per axis
- * eta_axis = 3 vmax ln(1/R) / (2 nb h_axis) * (delta/nb)^2, summed over axes. */
-static void sponge_eta(const Grid* g, double vmax, double* eta) {
+/* Damping sponge (replaces the paper's PML): per axis the classic quadratic
+ * profile eta = 3 vmax ln(1/R) / (2 nb h) (delta/nb)^2 (delta = cells into the
+ * layer), turned into a velocity-damping factor a = (1 - eta dt/2)/(1 + eta dt/2)
+ * per axis; the factor of a node is the product of its two axis factors
+ * (1 in the model region). */
+static double axis_damping(int delta, int nb, double h, double vmax, double dt) {
+    if (nb <= 0 || delta <= 0) return 1.0;
+    double r = (double)delta / nb;
+    double eta = 3.0 * vmax * log(1.0 / SPONGE_R) / (2.0 * nb * h) * r * r;
+    double e = eta * dt / 2.0;
+    return (1.0 - e) / (1.0 + e);
+}
+
+static void sponge_factor(const Grid* g, double vmax, double* a) {
     for (int iz = 0; iz < g->nzp; ++iz)
         for (int ix = 0; ix < g->nxp; ++ix) {
-            double e = 0.0;
-            if (g->nb > 0) {
-                int dzc = 0, dxc = 0;
-                if (iz >= g->ztop + g->nz) dzc = iz - (g->ztop + g->nz - 1);
-                if (!g->fs && iz < g->ztop) dzc = g->ztop - iz;
-                if (ix < g->nb) dxc = g->nb - ix;
-                if (ix >= g->nb + g->nx) dxc = ix - (g->nb + g->nx - 1);
-                double base = 3.0 * vmax * log(1.0 / SPONGE_R) / (2.0 * g->nb);
-                double rz = (double)dzc / g->nb, rx = (double)dxc / g->nb;
-                e = base * (rz * rz / g->dz + rx * rx / g->dx);
-            }
-            eta[iz * g->nxp + ix] = e;
+            int dzc = 0, dxc = 0;
+            if (iz >= g->ztop + g->nz) dzc = iz - (g->ztop + g->nz - 1);
+            if (!g->fs && iz < g->ztop) dzc = g->ztop - iz;
+            if (ix < g->nb) dxc = g->nb - ix;
+            if (ix >= g->nb + g->nx) dxc = ix - (g->nb + g->nx - 1);
+            a[iz * g->nxp + ix] = axis_damping(dzc, g->nb, g->dz, vmax, g->dt) *
+                                  axis_damping(dxc, g->nb, g->dx, vmax, g->dt);
         }
 }
 
@@ -150,25 +157,18 @@ double orc_cfl_number(double vmax, double dt, double dz, double dx) {
     return vmax * dt * sqrt(2048.0 / 315.0 * (1.0 / (dx * dx) + 1.0 / (dz * dz))) / 2.0;
 }
 
-/* Per-unit coefficient fields: C = dt^2 v^2, A = 1/(1 + eta dt/2), Bc = 1 - eta dt/2. */
+/* Per-unit coefficient fields: C = dt^2 v^2 and the sponge factor a. */
 typedef struct {
-    double *vp, *C, *A, *Bc;
+    double *vp, *C, *a;
 } Coefs;
 
 static int coefs_make(const Grid* g, const double* v, double vmax_decl, Coefs* cf) {
     int np = g->nzp * g->nxp;
     cf->vp = (double*)malloc(sizeof(double) * np);
     cf->C = (double*)malloc(sizeof(double) * np);
-    cf->A = (double*)malloc(sizeof(double) * np);
-    cf->Bc = (double*)malloc(sizeof(double) * np);
-    if (!cf->vp || !cf->C || !cf->A || !cf->Bc) return ORC_ENOMEM;
-    double* eta = cf->A; /* reuse as scratch */
-    sponge_eta(g, vmax_decl, eta);
-    for (int p = 0; p < np; ++p) {
-        double e = eta[p] * g->dt / 2.0;
-        cf->Bc[p] = 1.0 - e;
-        cf->A[p] = 1.0 / (1.0 + e);
-    }
+    cf->a = (double*)malloc(sizeof(double) * np);
+    if (!cf->vp || !cf->C || !cf->a) return ORC_ENOMEM;
+    sponge_factor(g, vmax_decl, cf->a);
     pad_velocity(g, v, cf->vp);
     for (int p = 0; p < np; ++p) cf->C[p] = g->dt * g->dt * cf->vp[p] * cf->vp[p];
     return ORC_OK;
@@ -177,12 +177,13 @@ static int coefs_make(const Grid* g, const double* v, double vmax_decl, Coefs* c
 static void coefs_free(Coefs* cf) {
     free(cf->vp);
     free(cf->C);
-    free(cf->A);
-    free(cf->Bc);
+    free(cf->a);
 }
 
 /* One time step: D = L u^n + s^n (s^n = f_n/(dx dz) at the source node),
- * u^{n+1} = A (2 u^n - Bc u^{n-1} + C D).  D is returned when requested. */
+ * u^{n+1} = (1 + a) u^n - a u^{n-1} + C D, i.e. leapfrog (a = 1) in the model
+ * and a damped velocity u^{n+1} - u^n = a (u^n - u^{n-1}) + C D in the sponge.
+ * D is returned when requested. */
 static void fwd_step(const Grid* g, const Coefs* cf, const double* ucur, const double* uprev,
                      double* unext, int src_p, double src_amp, double* Dout) {
     for (int iz = 0; iz < g->nzp; ++iz)
@@ -191,7 +192,7 @@ static void fwd_step(const Grid* g, const Coefs* cf, const double* ucur, const d
             double D = lap_at(g, ucur, iz, ix);
             if (p == src_p) D += src_amp / (g->dx * g->dz);
             if (Dout) Dout[p] = D;
-            unext[p] = cf->A[p] * (2.0 * ucur[p] - cf->Bc[p] * uprev[p] + cf->C[p] * D);
+            unext[p] = (1.0 + cf->a[p]) * ucur[p] - cf->a[p] * uprev[p] + cf->C[p] * D;
         }
 }
 
@@ -232,11 +233,11 @@ static int forward_unit(const Grid* g, const Coefs* cf, const double* wavelet, i
 
 /* Reverse-mode derivative of one unit.  Given a^n = dJ/d(trace sample n),
  * returns gC[p] = dJ/dC[p] and, optionally, gw[n] = dJ/df_n.
- * The forward recursion is u^{n+1} = A(2u^n - Bc u^{n-1} + C(L u^n + s^n)),
+ * The forward recursion is u^{n+1} = (1+a) u^n - a u^{n-1} + C (L u^n + s^n),
  * n = 0..N-2, with u^0 = u^{-1} = 0 and trace samples d^n = u^n(rec).
  * Adjoint variables ub^n = dJ/du^n satisfy
- *   ub^n = R^T a^n + 2 A ub^{n+1} + L^T(C A ub^{n+1}) - Bc A ub^{n+2},
- * and dJ/dC += A ub^{n+1} (L u^n + s^n) for every step n. */
+ *   ub^n = R^T a^n + (1+a) ub^{n+1} + L^T(C ub^{n+1}) - a ub^{n+2},
+ * and dJ/dC += ub^{n+1} (L u^n + s^n) for every step n. */
 static int reverse_unit(const Grid* g, const Coefs* cf, const double* wavelet, int src_p, int nr,
                         const int* rec_p, const double* adj, double* gC, double* gw) {
     int np = g->nzp * g->nxp;
@@ -292,14 +293,14 @@ static int reverse_unit(const Grid* g, const Coefs* cf, const double* wavelet, i
                     D[p] = d;
                 }
             for (int p = 0; p < np; ++p) {
-                q[p] = cf->A[p] * ub1[p];
+                q[p] = ub1[p];
                 Cq[p] = cf->C[p] * q[p];
                 gC[p] += q[p] * D[p];
             }
             if (gw) gw[n] += q[src_p] * cf->C[src_p] / (g->dx * g->dz);
             lap_transpose(g, Cq, LTq);
             for (int p = 0; p < np; ++p)
-                ub0[p] = 2.0 * q[p] + LTq[p] - cf->Bc[p] * cf->A[p] * ub2[p];
+                ub0[p] = (1.0 + cf->a[p]) * q[p] + LTq[p] - cf->a[p] * ub2[p];
             for (int r = 0; r < nr; ++r) ub0[rec_p[r]] += adj[(size_t)r * N + n];
             double* t = ub2;
             ub2 = ub1;
@@ -717,12 +718,12 @@ int orc_apply_laplacian(int nzp, int nxp, double dz, double dx, int fs, const do
     return ORC_OK;
 }
 
-/* Sponge damping field of the padded grid, for checks of the profile. */
-int orc_sponge(int nz, int nx, double dz, double dx, int nb, int fs, double vmax, double* eta) {
+/* Sponge damping factor a of the padded grid, for checks of the profile. */
+int orc_sponge(int nz, int nx, double dz, double dx, double dt, int nb, int fs, double vmax, double* a) {
     Grid g;
-    int st = grid_init(&g, nz, nx, dz, dx, 1.0, 2, nb, fs);
+    int st = grid_init(&g, nz, nx, dz, dx, dt, 2, nb, fs);
     if (st) return st;
-    sponge_eta(&g, vmax, eta);
+    sponge_factor(&g, vmax, a);
     return ORC_OK;
 }
 

@@ -69,7 +69,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     *out = nullptr;
     int st = validate_geometry(geom, max_batch);
     if (st) return st;
-    fwi_plan_options o{-1, 0};
+    fwi_plan_options o{-1, 0, 0, 0};
     if (opt) o = *opt;
     if (o.force_path < -1 || o.force_path > 1 || o.ckpt_every < 0) return FWI_EINVAL;
 
@@ -104,7 +104,12 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // spread of Sec. 2.1, or one buried row)
     bool one_row = true;
     for (int r = 1; r < nr; ++r) one_row = one_row && (p.rec_iz[r] == p.rec_iz[0]);
-    bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, &p.lds_X, &p.lds_P, &p.lds_ncg, &p.lds_nstrip);
+    bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, o.lds_tile_x, o.lds_tile_z, &p.lds_X, &p.lds_P,
+                                               &p.lds_ncg, &p.lds_nstrip);
+    if ((o.lds_tile_x > 0 || o.lds_tile_z > 0) && !lds_ok) {
+        delete pp;
+        return FWI_EINVAL;
+    }
     if (o.force_path == 0 && (!lds_ok || o.ckpt_every > 0)) {
         delete pp;
         return FWI_EINVAL;
@@ -148,22 +153,27 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     }
 
     // host-side tables
-    std::vector<float> ex(p.nxp, 0.f), ez(p.nzp, 0.f), wrow(p.nzp, 1.f);
+    // sponge: per axis the quadratic profile eta = 3 v_max ln(1/R)/(2 nb h) (delta/nb)^2,
+    // R = 1e-3, as the velocity-damping factor (1 - eta dt/2)/(1 + eta dt/2)
+    std::vector<float> axf(p.nxp, 1.f), azf(p.nzp, 1.f), wrow(p.nzp, 1.f);
     if (p.g.nb > 0) {
         const double base = 3.0 * p.g.v_max * std::log(1e3) / (2.0 * p.g.nb);
+        auto factor = [&](int d, double h) {
+            const double r = (double)d / p.g.nb;
+            const double e = base * r * r / h * p.g.dt / 2.0;
+            return (float)((1.0 - e) / (1.0 + e));
+        };
         for (int ix = 0; ix < p.nxp; ++ix) {
             int d = 0;
             if (ix < p.g.nb) d = p.g.nb - ix;
             if (ix >= p.g.nb + p.g.nx) d = ix - (p.g.nb + p.g.nx - 1);
-            const double r = (double)d / p.g.nb;
-            ex[ix] = (float)(base * r * r / p.g.dx * p.g.dt / 2.0);
+            axf[ix] = d > 0 ? factor(d, p.g.dx) : 1.f;
         }
         for (int iz = 0; iz < p.nzp; ++iz) {
             int d = 0;
             if (iz >= p.ztop + p.g.nz) d = iz - (p.ztop + p.g.nz - 1);
             if (!p.g.free_surface && iz < p.ztop) d = p.ztop - iz;
-            const double r = (double)d / p.g.nb;
-            ez[iz] = (float)(base * r * r / p.g.dz * p.g.dt / 2.0);
+            azf[iz] = d > 0 ? factor(d, p.g.dz) : 1.f;
         }
     }
     if (p.g.free_surface) wrow[0] = 0.5f;
@@ -192,13 +202,14 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // device allocations
     st = FWI_OK;
     st = st ? st : alloc_n(p, &p.K, (size_t)max_batch * npts);
-    st = st ? st : alloc_n(p, &p.ex, (size_t)p.nxp);
-    st = st ? st : alloc_n(p, &p.ez, (size_t)p.nzp);
+    st = st ? st : alloc_n(p, &p.ax, (size_t)p.nxp);
+    st = st ? st : alloc_n(p, &p.az, (size_t)p.nzp);
     st = st ? st : alloc_n(p, &p.wgt_row, (size_t)p.nzp);
     st = st ? st : alloc_n(p, &p.src_pt, (size_t)ns);
     st = st ? st : alloc_n(p, &p.rec_pt, (size_t)nr);
     st = st ? st : alloc_n(p, &p.rec_invw, (size_t)nr);
     st = st ? st : alloc_n(p, &p.gpad, nf * npts);
+    st = st ? st : alloc_n(p, &p.fold_tmp, (size_t)max_batch * p.nzp * p.g.nx);
     st = st ? st : alloc_n(p, &p.flags, 1);
     st = st ? st : alloc_n(p, &p.wav, (size_t)nt);
     st = st ? st : alloc_n(p, &p.omega, (size_t)ns * nr * nt);
@@ -220,8 +231,8 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.ckpt, nf * (size_t)p.nseg * 2 * npts);
     }
     if (!st) {
-        st = hip_ok(hipMemcpy(p.ex, ex.data(), ex.size() * sizeof(float), hipMemcpyHostToDevice));
-        st = st ? st : hip_ok(hipMemcpy(p.ez, ez.data(), ez.size() * sizeof(float), hipMemcpyHostToDevice));
+        st = hip_ok(hipMemcpy(p.ax, axf.data(), axf.size() * sizeof(float), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(p.az, azf.data(), azf.size() * sizeof(float), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.wgt_row, wrow.data(), wrow.size() * sizeof(float), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.src_pt, src_pt.data(), ns * sizeof(int), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.rec_pt, rec_pt.data(), nr * sizeof(int), hipMemcpyHostToDevice));
@@ -279,6 +290,8 @@ int fwi_plan_get_info(const fwi_plan* plan, fwi_plan_info* info) {
     info->ckpt_every = plan->ckpt_every;
     info->max_batch = plan->max_batch;
     info->device_bytes = plan->device_bytes;
+    info->lds_tile_x = plan->path == 0 ? plan->lds_X : 0;
+    info->lds_tile_z = plan->path == 0 ? plan->lds_P : 0;
     return FWI_OK;
 }
 
@@ -356,7 +369,7 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
     int rc = launch_prep_velocity(p, B, v, st);
     if (rc) return rc;
     if (p.path == 0)
-        rc = launch_lds_adjoint(p, B, adj_src, nullptr, st);
+        rc = launch_lds_adjoint(p, B, adj_src, p.wav, st);
     else
         rc = tiled_adjoint(p, B, adj_src, p.wav, nullptr, st);
     if (rc) return rc;

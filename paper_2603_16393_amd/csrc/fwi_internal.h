@@ -38,9 +38,10 @@ struct Plan;
 
 // Time stepping keeps (u^n, w^n = u^n - u^{n-1}) and advances
 //   D^n     = sum_k W_k [(u(+k) - u) + (u(-k) - u)] / h^2 per axis + s^n
-//   w^{n+1} = A ((1 - e) w^n + K D^n),   u^{n+1} = u^n + w^{n+1}
-// which is the leapfrog recursion rearranged so that FP32 rounding neither
-// cancels in the Laplacian nor feeds back through the second difference.
+//   w^{n+1} = a w^n + K D^n,   u^{n+1} = u^n + w^{n+1},   a = a_x a_z (1 in the model)
+// which is the leapfrog recursion u^{n+1} = (1 + a) u^n - a u^{n-1} + K D^n
+// rearranged so that FP32 rounding neither cancels in the Laplacian nor
+// feeds back through the second difference.
 
 // Arguments of the LDS-resident time loop (one workgroup per (sample, shot) field).
 struct LdsArgs {
@@ -105,8 +106,8 @@ struct Plan {
 
     // device buffers
     float* K = nullptr;          // [max_batch][npts]
-    float* ex = nullptr;         // [nxp] sponge term eta_x dt/2 per padded column
-    float* ez = nullptr;         // [nzp] sponge term eta_z dt/2 per padded row
+    float* ax = nullptr;         // [nxp] sponge damping factor per padded column
+    float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]
     int* src_pt = nullptr;       // [ns]
     int* rec_pt = nullptr;       // [nr]
@@ -120,6 +121,7 @@ struct Plan {
     float* astate = nullptr;     // tiled adjoint: [3][max_batch*ns][npts]
     float* acc = nullptr;        // tiled adjoint: [max_batch*ns][npts]
     float* gpad = nullptr;       // [max_batch*ns][npts]
+    float* fold_tmp = nullptr;   // [max_batch][nzp][nx] column-folded gradient
     int* flags = nullptr;        // [1]
     float* wav = nullptr;        // [nt] copy of the kept forward's wavelet (segment recomputation)
     int rec_z0 = 0, rec_z1 = -1;
@@ -140,7 +142,8 @@ struct Plan {
 
 // Register-tile layout of the LDS-resident sweep for an nzp x nxp padded
 // field (false if the field does not fit in LDS).
-bool lds_choose_layout(int nzp, int nxp, int* X, int* P, int* ncg, int* nstrip);
+// req_X, req_P > 0 restrict the choice to that tile.
+bool lds_choose_layout(int nzp, int nxp, int req_X, int req_P, int* X, int* P, int* ncg, int* nstrip);
 size_t lds_bytes(int X, int P, int ncg, int nstrip);
 
 // Launchers (return FWI_OK or FWI_EHIP).

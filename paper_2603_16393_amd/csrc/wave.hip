@@ -4,10 +4,10 @@
 // Scheme (the constant-density acoustic equation of Sec. 2.1 with the solver
 // settings of Sec. 6.1; a damping sponge stands in for the PML):
 //   D^n     = L u^n + s^n                    (8th-order Laplacian; s^n = f_n/(dx dz) at the source node)
-//   (1 + e) u^{n+1} = 2 u^n - (1 - e) u^{n-1} + K D^n,   K = (v dt)^2,  e = eta dt / 2,
-// advanced as w^{n+1} = ((1 - e) w^n + K D^n)/(1 + e), u^{n+1} = u^n + w^{n+1}
-// with the Laplacian summed as differences from the centre value (FP32
-// rounding then neither cancels in L nor feeds back through 2u^n - u^{n-1}).
+//   u^{n+1} = (1 + a) u^n - a u^{n-1} + K D^n,   K = (v dt)^2,  a = a_x(x) a_z(z) (1 in the model),
+// advanced as w^{n+1} = a w^n + K D^n, u^{n+1} = u^n + w^{n+1} with the
+// Laplacian summed as differences from the centre value (FP32 rounding then
+// neither cancels in L nor feeds back through the second difference).
 // Traces: d^n = u^n at the receivers.  With W = diag(1/2 on a reflecting top
 // row, 1 elsewhere), W L is symmetric, so the adjoint field psi obeys the same
 // recursion backward in time with sources a^n / w at the receivers, and
@@ -60,8 +60,8 @@ int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st) {
 constexpr int TX = 64, TZ = 16, TSTRIP = 4, TROWS = TZ / TSTRIP;
 
 template <bool ADJ>
-__global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const float* __restrict__ ex_g,
-                                                   const float* __restrict__ ez_g) {
+__global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const float* __restrict__ ax_g,
+                                                   const float* __restrict__ az_g) {
     constexpr int SS = TX + 8;
     __shared__ float tile[(TZ + 8) * SS];
     const int field = blockIdx.z;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const floa
     __syncthreads();
     const int gx = x0 + tx;
     if (gx >= nxp) return;
-    const float exv = ex_g[gx];
+    const float axv = ax_g[gx];
     const int sp = a.src_pt[s];
     const bool check_rec = (zt + TZ > a.rec_z0) && (zt <= a.rec_z1);
 #pragma unroll
@@ -106,9 +106,8 @@ __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const floa
         if (check_rec) r = a.rec_map[p];
         if (!ADJ && p == sp) D += a.wavelet[m] * a.src_scale;
         if (ADJ && r >= 0) D += a.rec_invw[r] * a.adj[((size_t)field * a.nr + r) * a.nt + (a.nt - 1 - m)];
-        const float e = exv + ez_g[gz];
         const float Kp = a.K[(size_t)b * a.npts + p];
-        const float wn = ((1.f - e) * wg[p] + Kp * D) / (1.f + e);
+        const float wn = fmaf(Kp, D, (axv * az_g[gz]) * wg[p]);
         const float un = c + wn;
         wg[p] = wn;
         un_g[p] = un;
@@ -217,7 +216,7 @@ int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep,
         a.ucur = u0;
         a.unxt = u1;
         a.Dout = (keep && p.store_mode == 0) ? p.Dstore + (size_t)n * p.npts : nullptr;
-        hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, a, n, p.ex, p.ez);
+        hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, a, n, p.ax, p.az);
         std::swap(u0, u1);
     }
     return hip_ok(hipGetLastError());
@@ -246,7 +245,7 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
             aa.ucur = a0;
             aa.unxt = a1;
             aa.Din = p.Dstore + (size_t)(nsteps - 1 - m) * p.npts;
-            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ex, p.ez);
+            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ax, p.az);
             std::swap(a0, a1);
         }
         return hip_ok(hipGetLastError());
@@ -270,7 +269,7 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
             fa.ucur = f0;
             fa.unxt = f1;
             fa.Dout = p.Dstore + (size_t)(n - n0) * p.npts;
-            hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, fa, n, p.ex, p.ez);
+            hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, fa, n, p.ax, p.az);
             std::swap(f0, f1);
         }
         for (int n = n1 - 1; n >= n0; --n) {
@@ -278,7 +277,7 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
             aa.ucur = a0;
             aa.unxt = a1;
             aa.Din = p.Dstore + (size_t)(n - n0) * p.npts;
-            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ex, p.ez);
+            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ax, p.az);
             std::swap(a0, a1);
         }
     }
@@ -287,11 +286,33 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
 
 // ---------------------------------------------------------------------------
 // grad[b][iz][ix] = scale[b] * sum_s sum_{padded p -> (iz, ix)} gpad[b, s][p] * 2 w_p dt / sqrt(K_p)
-// (2 w / v with v = sqrt(K)/dt), summed in a fixed order.
-__global__ void k_fold_gradient(int B, int ns, int nz, int nx, int nzp, int nxp, int ztop, int nb, float dt,
-                                const float* __restrict__ K, const float* __restrict__ wgt_row,
-                                const float* __restrict__ gpad, const float* __restrict__ scale,
-                                float* __restrict__ grad) {
+// (2 w / v with v = sqrt(K)/dt): the transpose of the edge replication, done
+// as two separable passes (padded columns onto model columns, then padded
+// rows onto model rows), each summed in a fixed order.
+__global__ void k_fold_columns(int B, int ns, int nx, int nzp, int nxp, int nb, float dt, const float* __restrict__ K,
+                               const float* __restrict__ wgt_row, const float* __restrict__ gpad,
+                               float* __restrict__ tmp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * nzp * nx) return;
+    const int b = i / (nzp * nx);
+    const int q = i - b * nzp * nx;
+    const int z = q / nx, ix = q - (q / nx) * nx;
+    const int xlo = (ix == 0) ? 0 : ix + nb;
+    const int xhi = (ix == nx - 1) ? nxp - 1 : ix + nb;
+    const int npts = nzp * nxp;
+    const float* Kr = K + (size_t)b * npts + z * nxp;
+    const float wz = 2.f * wgt_row[z] * dt;
+    float sum = 0.f;
+    for (int x = xlo; x <= xhi; ++x) {
+        float gs = 0.f;
+        for (int s = 0; s < ns; ++s) gs += gpad[((size_t)b * ns + s) * npts + z * nxp + x];
+        sum += gs * (wz / sqrtf(Kr[x]));
+    }
+    tmp[i] = sum;
+}
+
+__global__ void k_fold_rows(int B, int nz, int nx, int nzp, int ztop, const float* __restrict__ tmp,
+                            const float* __restrict__ scale, float* __restrict__ grad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * nz * nx) return;
     const int b = i / (nz * nx);
@@ -299,26 +320,18 @@ __global__ void k_fold_gradient(int B, int ns, int nz, int nx, int nzp, int nxp,
     const int iz = q / nx, ix = q - (q / nx) * nx;
     const int zlo = (iz == 0) ? 0 : iz + ztop;
     const int zhi = (iz == nz - 1) ? nzp - 1 : iz + ztop;
-    const int xlo = (ix == 0) ? 0 : ix + nb;
-    const int xhi = (ix == nx - 1) ? nxp - 1 : ix + nb;
-    const int npts = nzp * nxp;
-    const float* Kb = K + (size_t)b * npts;
     float sum = 0.f;
-    for (int s = 0; s < ns; ++s) {
-        const float* gp = gpad + ((size_t)b * ns + s) * npts;
-        for (int z = zlo; z <= zhi; ++z)
-            for (int x = xlo; x <= xhi; ++x) {
-                const int p = z * nxp + x;
-                sum += gp[p] * (2.f * wgt_row[z] * dt / sqrtf(Kb[p]));
-            }
-    }
+    for (int z = zlo; z <= zhi; ++z) sum += tmp[((size_t)b * nzp + z) * nx + ix];
     grad[i] = sum * (scale ? scale[b] : 1.f);
 }
 
 int launch_fold_gradient(const Plan& p, int B, const float* scale, float* grad, hipStream_t st) {
-    const int n = B * p.g.nz * p.g.nx;
-    hipLaunchKernelGGL(k_fold_gradient, dim3((n + 255) / 256), dim3(256), 0, st, B, p.g.ns, p.g.nz, p.g.nx, p.nzp,
-                       p.nxp, p.ztop, p.g.nb, (float)p.g.dt, p.K, p.wgt_row, p.gpad, scale, grad);
+    const int n1 = B * p.nzp * p.g.nx;
+    hipLaunchKernelGGL(k_fold_columns, dim3((n1 + 255) / 256), dim3(256), 0, st, B, p.g.ns, p.g.nx, p.nzp, p.nxp,
+                       p.g.nb, (float)p.g.dt, p.K, p.wgt_row, p.gpad, p.fold_tmp);
+    const int n2 = B * p.g.nz * p.g.nx;
+    hipLaunchKernelGGL(k_fold_rows, dim3((n2 + 255) / 256), dim3(256), 0, st, B, p.g.nz, p.g.nx, p.nzp, p.ztop,
+                       p.fold_tmp, scale, grad);
     return hip_ok(hipGetLastError());
 }
 

@@ -3,33 +3,37 @@
 //
 // One 512-thread workgroup per (sample, shot) field keeps u^n and u^{n+1} of
 // the whole padded field in LDS for all nt-1 steps, so HBM sees only the
-// history of D = L u + s (written by the forward sweep, read by the adjoint)
-// and the traces.  Thread (cg, strip) owns an X-column by P-row register tile
+// history of D = L u (written by the forward sweep, read by the adjoint) and
+// the traces.  Thread (cg, strip) owns an X-column by P-row register tile
 // (columns cg*X.., rows strip*P..): it keeps w, K and, in the adjoint, the
 // imaging sum of its points in registers, loads its (P+8)-row column window
 // once per step and only the 4 + 4 outer x-neighbours of each row, so a step
 // costs (P+8)/P + 8/X LDS reads and one LDS write per point.
 //
+// The per-point loop is branch-free: the few points with a source, a receiver
+// or an adjoint injection are corrected afterwards by their owning thread.
+// The source term is left out of the stored D; the adjoint adds its
+// correlation psi s at the source node itself.
+//
 // LDS layout: two planes of R = nstrip*P + 8 rows x S = ncg*X + 8 columns with
 // a 4-cell zero apron (padded cell (z, x) lives at LDS (z + 4, x + 4)), then
-// the per-row sponge term ez[nstrip*P].  Rows and columns beyond the padded
-// grid that round the tiles up are never written and stay zero.  All
-// receivers sit on one padded row, so the owner of a receiver node records
-// it (forward) or injects its adjoint source (adjoint) itself.
+// the per-row sponge factor az[nstrip*P].  Cells beyond the padded grid that
+// round the tiles up have K = 0 and start at zero, so they remain zero even
+// though they are written every step.
 #include <algorithm>
 
 #include "fwi_internal.h"
 
 namespace fwi {
 
-template <int X, int P, bool ADJ>
-__global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float* __restrict__ ex_g,
-                                                          const float* __restrict__ ez_g) {
+template <int X, int P, bool ADJ, bool EXACT, bool STORE>
+__global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float* __restrict__ ax_g,
+                                                          const float* __restrict__ az_g) {
     extern __shared__ float lds[];
     const int S = a.S;
     const int R = a.nstrip * P + 8;
     const int plane = R * S;
-    float* ez_s = lds + 2 * plane;
+    float* az_s = lds + 2 * plane;
     const int field = blockIdx.x;
     const int b = field / a.ns;
     const int s = field - b * a.ns;
@@ -39,26 +43,31 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
     const int nsteps = a.nt - 1;
 
     for (int i = tid; i < 2 * plane; i += blockDim.x) lds[i] = 0.f;
-    for (int i = tid; i < a.nstrip * P; i += blockDim.x) ez_s[i] = (i < nzp) ? ez_g[i] : 0.f;
+    for (int i = tid; i < a.nstrip * P; i += blockDim.x) az_s[i] = (i < nzp) ? az_g[i] : 1.f;
 
     const int cg = tid % a.ncg;
     const int strip = tid / a.ncg;
     const bool active = strip < a.nstrip;
     const int x0 = cg * X;
     const int z0 = strip * P;
+    const bool mirror_top = a.fs && z0 == 0;
+
+    // weights of the Laplacian with the grid spacings folded in
+    const float wz1 = FWI_W1 * a.idz2, wz2 = FWI_W2 * a.idz2, wz3 = FWI_W3 * a.idz2, wz4 = FWI_W4 * a.idz2;
+    const float wx1 = FWI_W1 * a.idx2, wx2 = FWI_W2 * a.idx2, wx3 = FWI_W3 * a.idx2, wx4 = FWI_W4 * a.idx2;
 
     float Kr[P][X];
     float wr[P][X];
     float acc[P][X];
-    float exv[X];
+    float axv[X];
     int rr[X];
-    int src_jc = -1;  // j * X + c of this field's source, if this thread owns it
-    int rec_j = -1;   // tile row of the receiver row, if it crosses this tile
+    int src_j = -1, src_c = -1;  // tile position of this field's source, if this thread owns it
+    int rec_j = -1;              // tile row of the receiver row, if it crosses this tile
     const float* Kb = a.K + (size_t)b * npts;
 #pragma unroll
     for (int c = 0; c < X; ++c) {
         const int x = x0 + c;
-        exv[c] = (active && x < nxp) ? ex_g[x] : 0.f;
+        axv[c] = (active && x < nxp) ? ax_g[x] : 1.f;
         rr[c] = -1;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -69,10 +78,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
         }
     }
     if (active) {
-        if (!ADJ) {
-            const int sp = a.src_pt[s];
-            const int sz = sp / nxp, sx = sp - (sp / nxp) * nxp;
-            if (sx >= x0 && sx < x0 + X && sz >= z0 && sz < z0 + P) src_jc = (sz - z0) * X + (sx - x0);
+        const int sp = a.src_pt[s];
+        const int sz = sp / nxp, sx = sp - (sp / nxp) * nxp;
+        if (sx >= x0 && sx < x0 + X && sz >= z0 && sz < z0 + P) {
+            src_j = sz - z0;
+            src_c = sx - x0;
         }
         if (a.rec_row >= z0 && a.rec_row < z0 + P) {
             rec_j = a.rec_row - z0;
@@ -81,72 +91,127 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
         }
     }
     const size_t trfield = (size_t)field * a.nr * a.nt;
-    if (!ADJ) {
+    if (!ADJ && rec_j >= 0) {
 #pragma unroll
         for (int c = 0; c < X; ++c)
             if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt] = 0.f;
     }
-    const float* Dfield = a.Dstore + (size_t)field * nsteps * npts;
+    float* Dfield = a.Dstore + (size_t)field * nsteps * npts;
+    float* Drow0 = Dfield + z0 * nxp + x0;  // this thread's tile corner in one D slice
     __syncthreads();
 
     float* cur = lds;          // u^n
     float* nxt = lds + plane;  // receives u^{n+1}
     for (int m = 0; m < nsteps; ++m) {
         if (active) {
+            // D^{N-2-m} of the tile is requested first so its latency overlaps the LDS work
+            float dr[P][X];
+            if (ADJ) {
+                const float* Dr = Drow0 + (size_t)(nsteps - 1 - m) * npts;
+#pragma unroll
+                for (int j = 0; j < P; ++j)
+#pragma unroll
+                    for (int c = 0; c < X; ++c)
+                        dr[j][c] = (EXACT || (z0 + j < nzp && x0 + c < nxp)) ? Dr[j * nxp + c] : 0.f;
+            }
             float win[P + 8][X];
+            const float* cb = cur + (z0 + 4) * S + x0 + 4;  // LDS cell of the tile corner
 #pragma unroll
             for (int q = 0; q < P + 8; ++q) {
-                int row = z0 - 4 + q;
-                if (a.fs) row = row < 0 ? -row : row;  // even mirror above a reflecting top
-                const float* rp = cur + (row + 4) * S + x0 + 4;
+                const float* rp = cb + (q - 4) * S;
+                if (q < 4 && mirror_top) rp = cb + (4 - q) * S;  // even mirror above a reflecting top
 #pragma unroll
                 for (int c = 0; c < X; ++c) win[q][c] = rp[c];
             }
-            float inj[X];
-#pragma unroll
-            for (int c = 0; c < X; ++c) {
-                inj[c] = 0.f;
-                if (ADJ && rr[c] >= 0) inj[c] = a.adj[trfield + (size_t)rr[c] * a.nt + (nsteps - m)] * a.rec_invw;
-            }
-            const float srcv = (!ADJ && src_jc >= 0) ? a.wavelet[m] * a.src_scale : 0.f;
-            float* Dw = (!ADJ && a.store) ? const_cast<float*>(Dfield) + (size_t)m * npts : nullptr;
-            const float* Dr = ADJ ? Dfield + (size_t)(nsteps - 1 - m) * npts : nullptr;
+            float* Dw = (!ADJ && STORE) ? Drow0 + (size_t)m * npts : nullptr;
+            float* nb_ = nxt + (z0 + 4) * S + x0 + 4;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-                const int z = z0 + j;
-                const float* rp = cur + (z + 4) * S + x0 + 4;
-                float xr[X + 8];  // row z, columns x0-4 .. x0+X+3
+                const float* rp = cb + j * S;
+                float xl[4], xh[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    xr[c] = rp[c - 4];
-                    xr[X + 4 + c] = rp[X + c];
+                    xl[c] = rp[c - 4];
+                    xh[c] = rp[X + c];
                 }
-#pragma unroll
-                for (int c = 0; c < X; ++c) xr[c + 4] = win[j + 4][c];
-                const float e_z = ez_s[z];
+                const float azr = az_s[z0 + j];
 #pragma unroll
                 for (int c = 0; c < X; ++c) {
+                    // row neighbours x-4 .. x+4 of column c
+                    float xr[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        const int cc = c + k - 4;
+                        xr[k] = cc < 0 ? xl[cc + 4] : (cc >= X ? xh[cc - X] : win[j + 4][cc]);
+                    }
                     const float u0 = win[j + 4][c];
-                    const float lz = FWI_LAPD(u0, win[j][c], win[j + 1][c], win[j + 2][c], win[j + 3][c],
-                                              win[j + 5][c], win[j + 6][c], win[j + 7][c], win[j + 8][c]);
-                    const float lx = FWI_LAPD(u0, xr[c], xr[c + 1], xr[c + 2], xr[c + 3], xr[c + 5], xr[c + 6],
-                                              xr[c + 7], xr[c + 8]);
-                    float D = lz * a.idz2 + lx * a.idx2;
-                    if (!ADJ && j * X + c == src_jc) D += srcv;
-                    if (ADJ && j == rec_j) D += inj[c];
-                    const float e = exv[c] + e_z;
-                    const float wn = ((1.f - e) * wr[j][c] + Kr[j][c] * D) / (1.f + e);
+                    float D = wz1 * ((win[j + 3][c] - u0) + (win[j + 5][c] - u0));
+                    D = fmaf(wz2, (win[j + 2][c] - u0) + (win[j + 6][c] - u0), D);
+                    D = fmaf(wz3, (win[j + 1][c] - u0) + (win[j + 7][c] - u0), D);
+                    D = fmaf(wz4, (win[j][c] - u0) + (win[j + 8][c] - u0), D);
+                    D = fmaf(wx1, (xr[3] - u0) + (xr[5] - u0), D);
+                    D = fmaf(wx2, (xr[2] - u0) + (xr[6] - u0), D);
+                    D = fmaf(wx3, (xr[1] - u0) + (xr[7] - u0), D);
+                    D = fmaf(wx4, (xr[0] - u0) + (xr[8] - u0), D);
+                    const float wn = fmaf(Kr[j][c], D, (axv[c] * azr) * wr[j][c]);
                     const float un = u0 + wn;
                     wr[j][c] = wn;
-                    const int x = x0 + c;
-                    if (z < nzp && x < nxp) {
-                        nxt[(z + 4) * S + x + 4] = un;
-                        const int p = z * nxp + x;
-                        if (Dw) Dw[p] = D;
-                        if (ADJ) acc[j][c] += un * Dr[p];  // psi^{N-1-m} D^{N-2-m}
-                        if (!ADJ && j == rec_j && rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt + m + 1] = un;
+                    nb_[j * S + c] = un;
+                    if (STORE && !ADJ) {
+                        if (EXACT || (z0 + j < nzp && x0 + c < nxp)) Dw[j * nxp + c] = D;
                     }
                 }
+            }
+            // point corrections of the owning threads
+            if (ADJ && rec_j >= 0) {
+                // adjoint sources a^{N-1-m}/w enter like the forward source: w += K inj
+#pragma unroll
+                for (int j = 0; j < P; ++j)
+                    if (j == rec_j) {
+#pragma unroll
+                        for (int c = 0; c < X; ++c)
+                            if (rr[c] >= 0) {
+                                const float dv = Kr[j][c] * a.adj[trfield + (size_t)rr[c] * a.nt + (nsteps - m)] *
+                                                 a.rec_invw;
+                                wr[j][c] += dv;
+                                nb_[j * S + c] += dv;
+                            }
+                    }
+            }
+            if (ADJ) {
+                // imaging: psi^{N-1-m} (read back from this thread's own LDS writes) times
+                // D^{N-2-m}, whose loads were issued at the top of the step
+#pragma unroll
+                for (int j = 0; j < P; ++j)
+#pragma unroll
+                    for (int c = 0; c < X; ++c) acc[j][c] = fmaf(nb_[j * S + c], dr[j][c], acc[j][c]);
+            }
+            if (src_j >= 0) {
+                if (!ADJ) {
+                    const float sv = a.wavelet[m] * a.src_scale;
+#pragma unroll
+                    for (int j = 0; j < P; ++j)
+#pragma unroll
+                        for (int c = 0; c < X; ++c)
+                            if (j == src_j && c == src_c) {
+                                const float dv = Kr[j][c] * sv;
+                                wr[j][c] += dv;
+                                nb_[j * S + c] += dv;
+                            }
+                } else {
+                    // the source's share of D^{N-2-m}: acc += psi^{N-1-m} s^{N-2-m}
+                    const float sv = a.wavelet[nsteps - 1 - m] * a.src_scale;
+#pragma unroll
+                    for (int j = 0; j < P; ++j)
+#pragma unroll
+                        for (int c = 0; c < X; ++c)
+                            if (j == src_j && c == src_c) acc[j][c] = fmaf(nb_[j * S + c], sv, acc[j][c]);
+                }
+            }
+            if (!ADJ && rec_j >= 0) {
+#pragma unroll
+                for (int c = 0; c < X; ++c)
+                    if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt + m + 1] = nb_[rec_j * S + c];
             }
         }
         __syncthreads();
@@ -165,13 +230,12 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
     }
 }
 
-// Instantiated tiles (X columns, P rows): those whose forward and adjoint
-// kernels fit the 256 VGPRs a 512-thread workgroup allows without (or, for
-// (3, 12), with a small) spill.
+// Instantiated tiles (X columns, P rows).  (3, 11) tiles the 110 x 150 padded
+// field of a 70 x 70 model with a 40-cell sponge exactly.
 #define FWI_LDS_TILES(M) \
-    M(1, 8) M(1, 12) M(1, 16) M(1, 20) M(1, 24) \
-    M(2, 8) M(2, 12)                            \
-    M(3, 8) M(3, 12)                            \
+    M(1, 8) M(1, 12) M(1, 16) M(1, 20) \
+    M(2, 8) M(2, 12)                   \
+    M(3, 8) M(3, 11) M(3, 12)          \
     M(4, 8)
 
 size_t lds_bytes(int X, int P, int ncg, int nstrip) {
@@ -183,11 +247,11 @@ size_t lds_bytes(int X, int P, int ncg, int nstrip) {
 // Chooses the instantiated tile with the fewest LDS operations per step
 // (reads (P+8)/P + 8/X and one write per point, counting the rounding-up
 // waste) among those that fit 512 threads and the LDS.
-bool lds_choose_layout(int nzp, int nxp, int* Xo, int* Po, int* ncgo, int* nstripo) {
+bool lds_choose_layout(int nzp, int nxp, int req_X, int req_P, int* Xo, int* Po, int* ncgo, int* nstripo) {
     double best = 1e300;
     bool found = false;
 #define FWI_TRY(XX, PP)                                                                                   \
-    {                                                                                                     \
+    if ((req_X <= 0 || req_X == XX) && (req_P <= 0 || req_P == PP)) {                                     \
         const int ncg = (nxp + XX - 1) / XX;                                                              \
         const int nstrip = (nzp + PP - 1) / PP;                                                           \
         if (ncg * nstrip <= kLdsThreads && lds_bytes(XX, PP, ncg, nstrip) <= (size_t)kLdsBytes) {         \
@@ -208,14 +272,15 @@ bool lds_choose_layout(int nzp, int nxp, int* Xo, int* Po, int* ncgo, int* nstri
     return found;
 }
 
-template <bool ADJ>
-static int lds_dispatch(const LdsArgs& a, int nfields, hipStream_t st, const float* ex, const float* ez) {
+template <bool ADJ, bool STORE>
+static int lds_dispatch(const LdsArgs& a, int nfields, hipStream_t st, const float* ax, const float* az) {
     const size_t bytes = lds_bytes(a.X, a.P, a.ncg, a.nstrip);
+    const bool exact = a.ncg * a.X == a.nxp && a.nstrip * a.P == a.nzp;
 #define FWI_CASE(XX, PP)                                                                                  \
     if (a.X == XX && a.P == PP) {                                                                         \
-        auto kern = k_wave_lds<XX, PP, ADJ>;                                                              \
+        auto kern = exact ? k_wave_lds<XX, PP, ADJ, true, STORE> : k_wave_lds<XX, PP, ADJ, false, STORE>; \
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);   \
-        hipLaunchKernelGGL(kern, dim3(nfields), dim3(kLdsThreads), bytes, st, a, ex, ez);                 \
+        hipLaunchKernelGGL(kern, dim3(nfields), dim3(kLdsThreads), bytes, st, a, ax, az);                 \
         return hip_ok(hipGetLastError());                                                                 \
     }
     FWI_LDS_TILES(FWI_CASE)
@@ -255,14 +320,15 @@ int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet
     a.traces = traces;
     a.wavelet = wavelet;
     a.store = store;
-    return lds_dispatch<false>(a, B * p.g.ns, st, p.ex, p.ez);
+    if (store) return lds_dispatch<false, true>(a, B * p.g.ns, st, p.ax, p.az);
+    return lds_dispatch<false, false>(a, B * p.g.ns, st, p.ax, p.az);
 }
 
 int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wavelet, hipStream_t st) {
     LdsArgs a = make_lds_args(p);
     a.adj = adj;
     a.wavelet = wavelet;
-    return lds_dispatch<true>(a, B * p.g.ns, st, p.ex, p.ez);
+    return lds_dispatch<true, false>(a, B * p.g.ns, st, p.ax, p.az);
 }
 
 }  // namespace fwi
