@@ -64,17 +64,73 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
     }
 
 
+def bench_checkpointed(args):
+    """Adjoint with checkpointing: 400 x 800 model (dx = 10 m) with a 50-cell sponge, 20 surface shots x 800
+    receivers, 4000 samples at dt = 0.8 ms, 10 Hz Ricker, smooth-plus-layered model with a high-velocity lens
+    (1500-5000 m/s); forward (u, w) checkpointed every 100 steps under a fixed memory budget."""
+    import torch
+
+    import fwi_inputs as fi
+    from paper_2603_16393_amd import FwiPlan
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nz, nx, ns, nt = 400, 800, 20, 4000
+    acq = fi.surface_acquisition(nz, nx, ns=ns, shot_cols=np.arange(ns) * 40, nt=nt, nb=50, dt=8e-4, f_peak=10.0,
+                                 v_max=5000.0)
+    v = fi.large_lens_model(nz, nx, seed=0)
+    vt = fi.large_lens_model(nz, nx, seed=1)
+    w = fi.ricker(nt, acq.dt, acq.f_peak)
+    budget = 16 << 30
+    plan = FwiPlan(acq, max_batch=1, device=dev, mem_budget_bytes=budget, ckpt_every=100)
+    wt = torch.tensor(w, dtype=torch.float32, device=dev)
+    dobs = plan.forward(torch.tensor(vt[None], dtype=torch.float32, device=dev), wt, keep_for_adjoint=False)
+    plan.set_obs(dobs[0].contiguous())
+    vg = torch.tensor(v[None], dtype=torch.float32, device=dev)
+
+    def step():
+        d = plan.forward(vg, wt, keep_for_adjoint=True)
+        J, adj = plan.w2_misfit(d)
+        return plan.adjoint_gradient(vg, adj)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    nzp, nxp = acq.padded_shape
+    updates = 3 * ns * (nt - 1) * nzp * nxp  # forward, recomputation, adjoint
+    print(json.dumps({
+        "metric": "checkpointed guidance gradient (400x800, 20 shots, 4k steps)",
+        "value": round(1e3 / ms, 4), "unit": "grads/s", "ms_per_gradient": round(ms, 2), "steps": args.steps,
+        "gpts_per_s": round(updates / (ms / 1e3) / 1e9, 2),
+        "plan": {k: plan.info[k] for k in ("path", "store_mode", "ckpt_every", "device_bytes")},
+        "memory_budget_bytes": budget, "dtype": "f32", "data": "synthetic",
+    }))
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["guidance", "checkpointed"], default="guidance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "checkpointed":
+        bench_checkpointed(args)
+        return
 
     import torch
 

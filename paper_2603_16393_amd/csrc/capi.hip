@@ -36,6 +36,11 @@ static int alloc_n(Plan& p, T** ptr, size_t n) {
 }
 
 static void free_all(Plan& p) {
+    release_graphs(p);
+    if (p.cap) {
+        (void)hipStreamDestroy(p.cap);
+        p.cap = nullptr;
+    }
     for (void* a : p.allocs) (void)hipFree(a);
     p.allocs.clear();
     p.device_bytes = 0;
@@ -119,7 +124,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // fixed-size buffers
     size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
                    nf * nr * 8 + (size_t)ns * nr * 1000 * 8;
-    if (p.path == 1) fixed += 6 * nf * npts * sizeof(float);
+    if (p.path == 1) fixed += (6 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
     const size_t full_store = nf * nsteps * npts * sizeof(float);
     size_t avail = budget;
     if (avail == 0) {
@@ -221,6 +226,9 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.rec_map, npts);
         st = st ? st : alloc_n(p, &p.state, 3 * nf * npts);
         st = st ? st : alloc_n(p, &p.astate, 3 * nf * npts);
+        st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
+        st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
+        if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
     } else {
         st = st ? st : alloc_n(p, &p.rec_of_col, (size_t)p.nxp);
     }

@@ -138,7 +138,18 @@ struct Plan {
     int qobs_cap = 0;            // n_xi capacity of qobs
 
     int stored_B = 0;            // batch of the forward state kept for the adjoint (0 = none)
+
+    // tiled path: sweeps captured as graphs on a private stream, replayed on the caller's
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_fwd[2] = {nullptr, nullptr};  // keep = 0 / 1
+    int g_fwd_B[2] = {0, 0};
+    hipGraphExec_t g_adj = nullptr;
+    int g_adj_B = 0;
+    float* trace_buf = nullptr;  // [max_batch*ns][nr][nt] traces written by the forward graph
+    float* adj_buf = nullptr;    // [max_batch*ns][nr][nt] adjoint source read by the adjoint graph
 };
+
+void release_graphs(Plan& p);
 
 // Register-tile layout of the LDS-resident sweep for an nzp x nxp padded
 // field (false if the field does not fit in LDS).

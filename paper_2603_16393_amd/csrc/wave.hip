@@ -17,8 +17,14 @@
 // Two execution paths:
 //  * LDS-resident (wave_lds.hip): one workgroup per (sample, shot) keeps the
 //    whole padded field in LDS for all nt-1 steps.
-//  * tiled: fields too large for LDS are swept one time step per launch in
-//    64 x 16 tiles staged through LDS with a 4-cell halo.
+//  * tiled (this file): fields too large for LDS are swept one time step per
+//    launch in 64 x 16 tiles staged through LDS with a 4-cell halo.  Each
+//    sweep's launches are captured once into a hipGraph on a plan-owned
+//    stream and replayed on the caller's stream; the graph touches only
+//    plan-owned buffers (traces and adjoint sources are staged through them).
+//    When the full history of D does not fit the memory budget, the forward
+//    sweep saves (u, w) every ckpt_every steps and the adjoint sweep recomputes
+//    each segment's D before stepping backward through it.
 #include <algorithm>
 #include <cmath>
 
@@ -130,20 +136,38 @@ __global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, s
         dst[i] = src[i];
 }
 
+// Checkpoint slot c of every field <-> (u, w): ckpt layout [field][seg][2][npts].
+template <bool SAVE>
+__global__ void k_ckpt(float* __restrict__ ckpt, float* __restrict__ u, float* __restrict__ w, int nf, int nseg,
+                       int c, int npts) {
+    const size_t n = (size_t)nf * npts;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t f = i / npts, q = i - f * npts;
+        float* slot = ckpt + ((f * nseg + c) * 2) * npts;
+        if (SAVE) {
+            slot[q] = u[i];
+            slot[npts + q] = w[i];
+        } else {
+            u[i] = slot[q];
+            w[i] = slot[npts + q];
+        }
+    }
+}
+
 // Receiver sample 0 of every trace is u^0 = 0.
 __global__ void k_zero_first_sample(float* __restrict__ traces, int ntr, int nt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntr) traces[(size_t)i * nt] = 0.f;
 }
 
+static int grid_for(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
+
 static void fill(float* x, size_t n, float v, hipStream_t st) {
-    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-    if (n) hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, x, n, v);
+    if (n) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, x, n, v);
 }
 
 static void copy(float* dst, const float* src, size_t n, hipStream_t st) {
-    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-    if (n) hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, dst, src, n);
+    if (n) hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
 }
 
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t st) {
@@ -177,54 +201,37 @@ static dim3 tile_grid(const Plan& p, int nfields) {
     return dim3((p.nxp + TX - 1) / TX, (p.nzp + TZ - 1) / TZ, nfields);
 }
 
-// Copies (u, w) of every field between the state buffers and checkpoint slot c.
-static void ckpt_copy(Plan& p, int nf, int c, const float* u, const float* w, float* u_out, float* w_out,
-                      bool save, hipStream_t st) {
-    for (int f = 0; f < nf; ++f) {
-        float* slot = p.ckpt + ((size_t)f * p.nseg + c) * 2 * p.npts;
-        const size_t off = (size_t)f * p.npts;
-        if (save) {
-            copy(slot, u + off, p.npts, st);
-            copy(slot + p.npts, w + off, p.npts, st);
-        } else {
-            copy(u_out + off, slot, p.npts, st);
-            copy(w_out + off, slot + p.npts, p.npts, st);
-        }
-    }
-}
-
-// Forward sweep of the tiled path; keeps D (full) or checkpoints of (u^n, w^n).
-int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st) {
+// Enqueues the whole forward sweep of B samples on st (reads p.wav, writes p.trace_buf).
+static void enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
     const int nf = B * p.g.ns;
     const size_t fs = (size_t)nf * p.npts;
     float* u0 = p.state;
     float* u1 = p.state + fs;
     float* w = p.state + 2 * fs;
     fill(p.state, 3 * fs, 0.f, st);
-    if (traces) hipLaunchKernelGGL(k_zero_first_sample, dim3((nf * p.g.nr + 255) / 256), dim3(256), 0, st, traces,
-                                   nf * p.g.nr, p.g.nt);
+    hipLaunchKernelGGL(k_zero_first_sample, dim3((nf * p.g.nr + 255) / 256), dim3(256), 0, st, p.trace_buf,
+                       nf * p.g.nr, p.g.nt);
     TileArgs a = make_tile_args(p, B);
-    a.traces = traces;
-    a.wavelet = wavelet;
+    a.traces = p.trace_buf;
+    a.wavelet = p.wav;
     a.wst = w;
     const dim3 grid = tile_grid(p, nf);
     const int nsteps = p.g.nt - 1;
     a.dstride = (size_t)nsteps * p.npts;
     for (int n = 0; n < nsteps; ++n) {
         if (keep && p.store_mode == 1 && n % p.ckpt_every == 0)
-            ckpt_copy(p, nf, n / p.ckpt_every, u0, w, nullptr, nullptr, true, st);
+            hipLaunchKernelGGL(k_ckpt<true>, dim3(grid_for(fs)), dim3(256), 0, st, p.ckpt, u0, w, nf, p.nseg,
+                               n / p.ckpt_every, p.npts);
         a.ucur = u0;
         a.unxt = u1;
         a.Dout = (keep && p.store_mode == 0) ? p.Dstore + (size_t)n * p.npts : nullptr;
         hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, a, n, p.ax, p.az);
         std::swap(u0, u1);
     }
-    return hip_ok(hipGetLastError());
 }
 
-// Adjoint sweep of the tiled path; gpad receives sum_n psi^{n+1} D^n per padded cell.
-int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float* /*traces_scratch*/,
-                  hipStream_t st) {
+// Enqueues the whole adjoint sweep (reads p.adj_buf, p.wav; writes p.gpad).
+static void enqueue_adjoint(Plan& p, int B, hipStream_t st) {
     const int nf = B * p.g.ns;
     const size_t fs = (size_t)nf * p.npts;
     const int nsteps = p.g.nt - 1;
@@ -234,9 +241,9 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
     fill(p.astate, 3 * fs, 0.f, st);
     fill(p.gpad, fs, 0.f, st);
     TileArgs aa = make_tile_args(p, B);
-    aa.adj = adj;
+    aa.adj = p.adj_buf;
     aa.acc = p.gpad;
-    aa.wavelet = wavelet;
+    aa.wavelet = p.wav;
     aa.wst = aw;
     const dim3 grid = tile_grid(p, nf);
     if (p.store_mode == 0) {
@@ -248,29 +255,32 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
             hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ax, p.az);
             std::swap(a0, a1);
         }
-        return hip_ok(hipGetLastError());
+        return;
     }
     // checkpointed: recompute each segment's D, then step the adjoint through it
     TileArgs fa = make_tile_args(p, B);
-    fa.wavelet = wavelet;
+    fa.wavelet = p.wav;
     fa.traces = nullptr;
     const int K = p.ckpt_every;
     fa.dstride = (size_t)K * p.npts;
     aa.dstride = (size_t)K * p.npts;
+    float* f0 = p.state;
+    float* f1 = p.state + fs;
+    float* fw = p.state + 2 * fs;
+    fa.wst = fw;
     for (int c = p.nseg - 1; c >= 0; --c) {
         const int n0 = c * K;
         const int n1 = std::min(n0 + K, nsteps);
-        float* f0 = p.state;
-        float* f1 = p.state + fs;
-        float* fw = p.state + 2 * fs;
-        ckpt_copy(p, nf, c, nullptr, nullptr, f0, fw, false, st);
-        fa.wst = fw;
+        hipLaunchKernelGGL(k_ckpt<false>, dim3(grid_for(fs)), dim3(256), 0, st, p.ckpt, p.state, fw, nf, p.nseg, c,
+                           p.npts);
+        float* g0 = f0;
+        float* g1 = f1;
         for (int n = n0; n < n1; ++n) {
-            fa.ucur = f0;
-            fa.unxt = f1;
+            fa.ucur = g0;
+            fa.unxt = g1;
             fa.Dout = p.Dstore + (size_t)(n - n0) * p.npts;
             hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, fa, n, p.ax, p.az);
-            std::swap(f0, f1);
+            std::swap(g0, g1);
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int m = nsteps - 1 - n;
@@ -281,7 +291,58 @@ int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float*
             std::swap(a0, a1);
         }
     }
+}
+
+// Captures enqueue(p.cap) into an executable graph.
+template <class F>
+static int capture(Plan& p, hipGraphExec_t* exec, F&& enqueue) {
+    if (*exec) {
+        (void)hipGraphExecDestroy(*exec);
+        *exec = nullptr;
+    }
+    if (hipStreamBeginCapture(p.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return FWI_EHIP;
+    enqueue(p.cap);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(p.cap, &g) != hipSuccess || !g) return FWI_EHIP;
+    const hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return hip_ok(e);
+}
+
+int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st) {
+    copy(p.wav, wavelet, (size_t)p.g.nt, st);
+    const int k = keep ? 1 : 0;
+    if (!p.g_fwd[k] || p.g_fwd_B[k] != B) {
+        const int rc = capture(p, &p.g_fwd[k], [&](hipStream_t cs) { enqueue_forward(p, B, keep, cs); });
+        if (rc) return rc;
+        p.g_fwd_B[k] = B;
+    }
+    if (hipGraphLaunch(p.g_fwd[k], st) != hipSuccess) return FWI_EHIP;
+    copy(traces, p.trace_buf, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
     return hip_ok(hipGetLastError());
+}
+
+int tiled_adjoint(Plan& p, int B, const float* adj, const float* /*wavelet*/, float* /*unused*/, hipStream_t st) {
+    copy(p.adj_buf, adj, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
+    if (!p.g_adj || p.g_adj_B != B) {
+        const int rc = capture(p, &p.g_adj, [&](hipStream_t cs) { enqueue_adjoint(p, B, cs); });
+        if (rc) return rc;
+        p.g_adj_B = B;
+    }
+    if (hipGraphLaunch(p.g_adj, st) != hipSuccess) return FWI_EHIP;
+    return hip_ok(hipGetLastError());
+}
+
+void release_graphs(Plan& p) {
+    for (int k = 0; k < 2; ++k)
+        if (p.g_fwd[k]) {
+            (void)hipGraphExecDestroy(p.g_fwd[k]);
+            p.g_fwd[k] = nullptr;
+        }
+    if (p.g_adj) {
+        (void)hipGraphExecDestroy(p.g_adj);
+        p.g_adj = nullptr;
+    }
 }
 
 // ---------------------------------------------------------------------------
