@@ -64,6 +64,97 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
     }
 
 
+SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surrogate_70x70.npy")
+GUIDED_STEPS = 200
+
+
+def guided_run(plan, wt, v_true, sur, predictor, steps=GUIDED_STEPS, record=False):
+    """16 samples x `steps` reverse steps, t from 1 down to 0.005; the clean
+    estimates come from the stand-in denoiser v0hat = clip(v_true + t zeta_b).
+    Each step: guidance gradient (solver, or judged prediction above t = 0.5)
+    and the preconditioned update.  Returns (seconds, stats, served) where
+    served lists (step, gradient copy) for predicted steps when record=True."""
+    import torch
+
+    import fwi_inputs as fi
+    from paper_2603_16393_amd import guidance_step
+    from paper_2603_16393_amd.guided import GuidanceGradients
+
+    dev = plan.device
+    zeta = torch.tensor(np.stack([fi.stand_in_zeta(NZ, NX, b) for b in range(B)]), dtype=torch.float32, device=dev)
+    vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
+    ts = np.linspace(1.0, 0.005, steps)
+    src = GuidanceGradients(plan, wt, B, surrogate=sur, predictor=predictor)
+    v = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
+    x0 = torch.empty_like(v)
+    vn = torch.empty_like(v)
+    rho = torch.empty(B, dtype=torch.float32, device=dev)
+    served = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, t in enumerate(ts):
+        torch.clamp(vt + float(t) * zeta, fi.V_LO, fi.V_HI, out=v)   # stand-in denoiser output
+        n_pred = src.stats.served_predicted
+        J, g = src(float(t), v)
+        torch.sub(v, fi.V_LO, out=x0).div_(0.5 * (fi.V_HI - fi.V_LO)).sub_(1.0)
+        guidance_step(x0, g, g, x0, unit_scale=1500.0, out=vn, rho_out=rho)
+        if record and src.stats.served_predicted > n_pred:
+            served.append((i, g.clone()))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, src.stats, served
+
+
+def surrogate_guidance(plan, wt, v_true):
+    """Plain solver guidance vs judged surrogate-assisted guidance (and the same
+    schedule without the network) over 16 x 200 steps; the served predicted
+    gradients are checked against the solver afterwards (untimed)."""
+    import torch
+
+    import fwi_inputs as fi
+    from paper_2603_16393_amd.surrogate import Surrogate, judge
+
+    if not os.path.exists(SURROGATE_WEIGHTS):
+        return {"error": f"no trained weights at {os.path.relpath(SURROGATE_WEIGHTS, ROOT)}"}
+    sur = Surrogate(B, device=plan.device)
+    sur.set_params(np.load(SURROGATE_WEIGHTS))
+    guided_run(plan, wt, v_true, None, "surrogate", steps=8)           # warm-up
+    guided_run(plan, wt, v_true, sur, "surrogate", steps=8)
+    t_plain, _, _ = guided_run(plan, wt, v_true, None, "surrogate")
+    res = {"plain_steps_per_s": round(B * GUIDED_STEPS / t_plain, 2)}
+    dev = plan.device
+    zeta = torch.tensor(np.stack([fi.stand_in_zeta(NZ, NX, b) for b in range(B)]), dtype=torch.float32, device=dev)
+    vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
+    ts = np.linspace(1.0, 0.005, GUIDED_STEPS)
+    g_ex = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
+    for name, pred, net in (("surrogate", "surrogate", sur), ("anchor_only", "anchor", None)):
+        t_run, st, _ = guided_run(plan, wt, v_true, net, pred)
+        _, _, served = guided_run(plan, wt, v_true, net, pred, record=True)   # same schedule, kept for checking
+        cos_all = []
+        for i, g in served:
+            v = torch.clamp(vt + float(ts[i]) * zeta, fi.V_LO, fi.V_HI)
+            d = plan.forward(v, wt, keep_for_adjoint=True)
+            _, adj = plan.w2_misfit(d, want_adjoint=True)
+            plan.adjoint_gradient(v, adj, out=g_ex)
+            cos_all += judge(g, g_ex)[0].tolist()
+        c = np.array(cos_all) if cos_all else np.ones(1)
+        res[name] = {
+            "steps_per_s": round(B * GUIDED_STEPS / t_run, 2),
+            "speedup_vs_plain": round(t_plain / t_run, 3),
+            "solver_batches": st.exact_batches,
+            "surrogate_batches": st.surrogate_batches,
+            "predicted_steps": st.served_predicted,
+            "judged": st.judged,
+            "judge_passed": st.passed,
+            "served_cos": {"min": round(float(c.min()), 4), "p5": round(float(np.percentile(c, 5)), 4),
+                           "median": round(float(np.median(c)), 4), "frac_ge_0.95": round(float(np.mean(c >= 0.95)), 4)},
+        }
+    res["protocol"] = (f"{B} samples x {GUIDED_STEPS} steps, t = 1 -> 0.005; stand-in denoiser clip(v_true + t zeta_b); "
+                       "t > 0.5: anchor + surrogate change, solver judge (cos >= 0.95, misfit error <= 5%) with an "
+                       "adaptive interval (4, x2 on pass up to 32, /2 on fail); t <= 0.5: solver")
+    sur.close()
+    return res
+
+
 def bench_checkpointed(args):
     """Adjoint with checkpointing: 400 x 800 model (dx = 10 m) with a 50-cell sponge, 20 surface shots x 800
     receivers, 4000 samples at dt = 0.8 ms, 10 Hz Ricker, smooth-plus-layered model with a high-velocity lens
@@ -122,6 +213,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--workload", choices=["guidance", "checkpointed"], default="guidance")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -242,6 +334,8 @@ def main():
         "surrogate": None,
         "cpu_baseline": None,
     }
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_guidance(plan, wt, v_true)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(acq, v0hat, v_true, w)
     print(json.dumps(out))

@@ -221,8 +221,11 @@ def smooth_noise(nz: int, nx: int, seed: int, sigma_cells: float = 3.0, std: flo
     r = int(math.ceil(3 * sigma_cells))
     k = np.exp(-0.5 * (np.arange(-r, r + 1) / sigma_cells) ** 2)
     k /= k.sum()
-    w = np.apply_along_axis(lambda a: np.convolve(a, k, mode="same"), 0, w)
-    w = np.apply_along_axis(lambda a: np.convolve(a, k, mode="same"), 1, w)
+    from scipy.ndimage import convolve1d
+
+    # zero-padded 'same' convolution along each axis (the kernel is symmetric)
+    w = convolve1d(w, k, axis=0, mode="constant", cval=0.0)
+    w = convolve1d(w, k, axis=1, mode="constant", cval=0.0)
     return w * (std / w.std())
 
 
@@ -234,3 +237,31 @@ def to_normalised(v: np.ndarray) -> np.ndarray:
 def from_normalised(x: np.ndarray) -> np.ndarray:
     """Diffusion state in [-1, 1] -> physical velocity (m/s)."""
     return V_LO + (x + 1.0) * 0.5 * (V_HI - V_LO)
+
+
+def stand_in_estimate(v_true: np.ndarray, t: float, zeta: np.ndarray) -> np.ndarray:
+    """Stand-in for a denoiser's clean estimate at noise level t (no score network
+    is part of this build): clip(v_true + t zeta, V_LO, V_HI)."""
+    return np.clip(v_true + t * zeta, V_LO, V_HI)
+
+
+def stand_in_zeta(nz: int, nx: int, sample: int) -> np.ndarray:
+    """Per-sample smooth perturbation of the stand-in estimates: white noise
+    smoothed by a 3-cell Gaussian, std 600 m/s (seed 7000 + sample)."""
+    return smooth_noise(nz, nx, 7000 + sample, sigma_cells=3.0, std=600.0)
+
+
+def surrogate_training_pair(seed: int, nz: int = 70, nx: int = 70):
+    """One training input for the trace surrogate and a perturbation of it.
+
+    v: a dipping-layer faulted model (seed 10^6 + seed) plus t zeta with
+    t ~ U(0, 1) and zeta smooth noise (3-cell Gaussian, std 600 m/s), the
+    distribution of the stand-in estimates; delta: smooth noise (Gaussian of
+    U(2, 8) cells, std U(30, 100) m/s), clipped so v + delta stays in range.
+    Returns (v, v + delta) as float64 [nz, nx]."""
+    rng = np.random.default_rng(2_000_000 + seed)
+    base = faulted_model(nz, nx, 1_000_000 + seed)
+    t = rng.uniform(0.0, 1.0)
+    v = np.clip(base + t * smooth_noise(nz, nx, 3_000_000 + seed, 3.0, 600.0), V_LO, V_HI)
+    d = smooth_noise(nz, nx, 4_000_000 + seed, rng.uniform(2.0, 8.0), rng.uniform(30.0, 100.0))
+    return v, np.clip(v + d, V_LO, V_HI)

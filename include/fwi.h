@@ -190,6 +190,107 @@ int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h
                       const float* v0hat, const fwi_guidance_params* params, float* v_next, float* rho_out,
                       void* stream);
 
+/* ------------------------------------------------------------------------
+ * Building blocks of the learned surrogate (BF16 storage, FP32 accumulation).
+ * ------------------------------------------------------------------------ */
+
+/* Batched GEMM on the matrix cores: for b < batch,
+ *   C[b] = alpha op(A[b]) op(B[b]) + beta C[b] (+ bias[n]),
+ * or with reduce_batch = 1 a single C = alpha sum_b op(A[b]) op(B[b]) + beta C.
+ * A, B: BF16 bit patterns (uint16); op(A)[m][k] = transA ? A[k lda + m] : A[m lda + k],
+ * op(B)[k][n] = transB ? B[n ldb + k] : B[k ldb + n]; batch b starts at A + b strideA
+ * (elements), likewise B and C.  Exactly one of C32 (FP32) and C16 (BF16) is
+ * non-NULL.  bias: FP32 [N] or NULL.  splitk > 1 (batch == 1 or reduce_batch
+ * only) splits the reduction into splitk partial sums kept in work
+ * (FP32, splitk * M * N elements, caller-owned) and added in a fixed order.
+ * Accumulation is FP32; results are deterministic.  FWI_EINVAL on bad shapes. */
+int fwi_nn_gemm(int M, int N, int K, int batch, const void* A, long lda, long strideA, int transA, const void* B,
+                long ldb, long strideB, int transB, float* C32, void* C16, long ldc, long strideC, float alpha,
+                float beta, const float* bias, int reduce_batch, int splitk, float* work, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the forward map (Sec. 7, future work: a cheaper stand-in for
+ * the wave solver inside guidance), fixed shapes: v [B][70][70] m/s ->
+ * traces [B][5][70][1000] in the layout of fwi_forward's d_syn.
+ *
+ * Network: lift of (v, z, x) features to 64 channels on a 72 x 72 grid;
+ * 4 encoder blocks {depthwise 3x3, 64->128 GELU 128->64, residual};
+ * a learned depth->time map (72 -> 256 rows); 4 decoder blocks {mixing along
+ * x, depthwise 3x3, 64->128 GELU 128->64, residuals}; a 64->8 head; a learned
+ * time up-sampling 256 -> 1000; traces = out_scale * (channels 0..4, columns
+ * 0..69).  GEMM operands and stored activations are BF16, accumulation FP32.
+ *
+ * Parameters are one FP32 vector of fwi_sur_param_count() entries in the
+ * order lift_w[3][64], lift_b[64], encoder blocks 0..3 {dw_k[64][3][3],
+ * dw_b[64], w1[64][128], b1[128], w2[128][64], b2[64]}, d2t[256][72],
+ * decoder blocks 0..3 {xm[72][72], dw_k, dw_b, w1, b1, w2, b2}, proj_w[64][8],
+ * proj_b[8], up[1000][256], out_scale[1].  out_scale is not trained (its
+ * gradient entry stays 0).
+ *
+ * The object owns its parameters, Adam state and activation buffers (about
+ * 135 MB per sample of max_batch); it lives on the device current at creation
+ * and is not thread-safe (one stream at a time).  Device arrays are the
+ * caller's.  Calls marked asynchronous return after enqueueing on `stream`.
+ * ------------------------------------------------------------------------ */
+typedef struct fwi_surrogate fwi_surrogate;
+
+typedef struct {
+    float lr, beta1, beta2, eps; /* Adam */
+    float loss_k;                /* trace weight 1/(1 + loss_k |target| / max_sample |target|) */
+    float pair_weight;           /* > 0: B is even and samples B/2..B-1 perturb samples 0..B/2-1 (see
+                                    fwi_sur_train_step) */
+} fwi_sur_train_params;
+
+/* dims[5] <- {nz, nx, ns, nr, nt} = {70, 70, 5, 70, 1000}. */
+int fwi_sur_shape(int* dims);
+long fwi_sur_param_count(void);
+/* max_batch in [1, 128]; parameters start at zero (set them before use). */
+int fwi_sur_create(int max_batch, fwi_surrogate** out);
+int fwi_sur_destroy(fwi_surrogate* s);
+/* Synchronous host <-> device copies of the FP32 parameter vector; set also
+ * refreshes the BF16 copies and resets the Adam state. */
+int fwi_sur_set_params(fwi_surrogate* s, const float* host_params);
+int fwi_sur_get_params(fwi_surrogate* s, float* host_params);
+/* Weight gradients of the last fwi_sur_backward(want_weight_grads = 1) or
+ * training step (synchronous). */
+int fwi_sur_get_grads(fwi_surrogate* s, float* host_grads);
+/* traces = S(v) for B <= max_batch samples (asynchronous).  Keeps the
+ * activations for fwi_sur_backward. */
+int fwi_sur_forward(fwi_surrogate* s, int B, const float* v, float* traces, void* stream);
+/* Vector-Jacobian product of the last fwi_sur_forward (same B, else
+ * FWI_ESTATE): dv = (dS/dv)^T dtraces (dv may be NULL), and with
+ * want_weight_grads the parameter gradient (asynchronous). */
+int fwi_sur_backward(fwi_surrogate* s, int B, const float* dtraces, float* dv, int want_weight_grads, void* stream);
+/* One Adam step on the weighted mean-square trace loss
+ *   L = (1/(B 5 70 1000)) sum (w (S(v) - target))^2,
+ *   w = 1/(1 + loss_k |target| / max over the sample of |target|),
+ * plus, with pair_weight > 0 (B even, h = B/2, sample h + b a perturbation of
+ * sample b), the finite-difference term that trains directional derivatives
+ *   pair_weight (1/(h 5 70 1000)) sum_b (w_b ((S(v_{h+b}) - S(v_b)) - (target_{h+b} - target_b)))^2
+ * with w_b the weight of sample b;
+ * loss_out (device float, may be NULL) receives L before the step
+ * (asynchronous). */
+int fwi_sur_train_step(fwi_surrogate* s, int B, const float* v, const float* target,
+                       const fwi_sur_train_params* params, float* loss_out, void* stream);
+
+/* Judge of a stand-in gradient against the solver's (Sec. 7, future work), per
+ * sample b < B over n entries: cos_out[b] = <g_a, g_b> / (|g_a| |g_b|) (0 if
+ * either is zero) and, if jerr_out is non-NULL, jerr_out[b] =
+ * |J_a[b] - J_b[b]| / |J_b[b]| (0 if J_b[b] = 0).  Device arrays; FP64 sums in
+ * a fixed order (asynchronous). */
+int fwi_judge(int B, int n, const float* g_a, const float* g_b, const double* J_a, const double* J_b,
+              float* cos_out, float* jerr_out, void* stream);
+
+/* Multi-fidelity prediction (Sec. 7, future work: multi-fidelity surrogate
+ * strategies): the exact solver's value at an anchor model plus the
+ * surrogate's change since that anchor,
+ *   g_out = g_anchor + (s_now - s_anchor)            [B][n] FP32,
+ *   J_out = J_anchor + (Js_now - Js_anchor)          [B] FP64 (all four NULL or non-NULL).
+ * g_out may alias g_anchor or s_now (element-wise).  Asynchronous. */
+int fwi_mf_predict(int B, int n, const float* g_anchor, const float* s_now, const float* s_anchor, float* g_out,
+                   const double* J_anchor, const double* Js_now, const double* Js_anchor, double* J_out,
+                   void* stream);
+
 /* Synchronises the plan's device and returns FWI_OK, or the first recorded
  * device-side error (FWI_EDEVICE for an invalid velocity) and clears it. */
 int fwi_status(fwi_plan* plan);

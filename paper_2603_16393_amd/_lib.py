@@ -30,6 +30,19 @@ EXPORTED = (
     "fwi_guidance_step",
     "fwi_status",
     "fwi_error_string",
+    "fwi_nn_gemm",
+    "fwi_sur_shape",
+    "fwi_sur_param_count",
+    "fwi_sur_create",
+    "fwi_sur_destroy",
+    "fwi_sur_set_params",
+    "fwi_sur_get_params",
+    "fwi_sur_get_grads",
+    "fwi_sur_forward",
+    "fwi_sur_backward",
+    "fwi_sur_train_step",
+    "fwi_judge",
+    "fwi_mf_predict",
 )
 
 
@@ -58,6 +71,11 @@ class PlanInfo(ctypes.Structure):
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("force_path", c_int), ("ckpt_every", c_int), ("lds_tile_x", c_int), ("lds_tile_z", c_int)]
+
+
+class SurTrainParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("loss_k", ctypes.c_float), ("pair_weight", ctypes.c_float)]
 
 
 class FwiError(RuntimeError):
@@ -92,9 +110,25 @@ def load():
     L.fwi_status.argtypes = [P]
     L.fwi_error_string.argtypes = [c_int]
     L.fwi_error_string.restype = ctypes.c_char_p
+    cl, cf = ctypes.c_long, ctypes.c_float
+    L.fwi_nn_gemm.argtypes = [c_int, c_int, c_int, c_int, P, cl, cl, c_int, P, cl, cl, c_int, P, P, cl, cl, cf, cf, P,
+                              c_int, c_int, P, P]
+    L.fwi_sur_shape.argtypes = [P]
+    L.fwi_sur_param_count.argtypes = []
+    L.fwi_sur_create.argtypes = [c_int, ctypes.POINTER(P)]
+    L.fwi_sur_destroy.argtypes = [P]
+    L.fwi_sur_set_params.argtypes = [P, P]
+    L.fwi_sur_get_params.argtypes = [P, P]
+    L.fwi_sur_get_grads.argtypes = [P, P]
+    L.fwi_sur_forward.argtypes = [P, c_int, P, P, P]
+    L.fwi_sur_backward.argtypes = [P, c_int, P, P, c_int, P]
+    L.fwi_sur_train_step.argtypes = [P, c_int, P, P, ctypes.POINTER(SurTrainParams), P, P]
+    L.fwi_judge.argtypes = [c_int, c_int, P, P, P, P, P, P, P]
+    L.fwi_mf_predict.argtypes = [c_int, c_int, P, P, P, P, P, P, P, P, P]
     for name in EXPORTED:
         if name != "fwi_error_string":
             getattr(L, name).restype = c_int
+    L.fwi_sur_param_count.restype = cl
     _lib = L
     return _lib
 

@@ -1,0 +1,66 @@
+// Internal declarations of the learned surrogate's building blocks (BF16
+// storage, FP32 accumulation) and its model object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "fwi.h"
+
+namespace fwi {
+
+typedef uint16_t bf16_t;  // bfloat16 bit pattern
+
+__host__ __device__ inline float bf2f(bf16_t h) {
+    union {
+        uint32_t u;
+        float f;
+    } v;
+    v.u = (uint32_t)h << 16;
+    return v.f;
+}
+
+// round to nearest even; NaN stays NaN
+__host__ __device__ inline bf16_t f2bf(float f) {
+    union {
+        uint32_t u;
+        float f;
+    } v;
+    v.f = f;
+    if ((v.u & 0x7f800000u) == 0x7f800000u && (v.u & 0x007fffffu)) return (bf16_t)((v.u >> 16) | 0x40);
+    const uint32_t r = v.u + 0x7fffu + ((v.u >> 16) & 1u);
+    return (bf16_t)(r >> 16);
+}
+
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b] (+ bias[n]) for b < batch,
+// or, with reduce_batch, C = alpha * sum_b op(A[b]) op(B[b]) + beta * C.
+// A, B are BF16; op(A)[m][k] = transA ? A[k * lda + m] : A[m * lda + k],
+// op(B)[k][n] = transB ? B[n * ldb + k] : B[k * ldb + n].  C is FP32 (C32) or
+// BF16 (C16, exactly one of the two non-null).  Accumulation is FP32 on MFMA.
+struct GemmArgs {
+    int M = 0, N = 0, K = 0, batch = 1;
+    const bf16_t* A = nullptr;
+    long lda = 0, strideA = 0;
+    int transA = 0;
+    const bf16_t* B = nullptr;
+    long ldb = 0, strideB = 0;
+    int transB = 0;
+    float* C32 = nullptr;
+    bf16_t* C16 = nullptr;
+    long ldc = 0, strideC = 0;
+    float alpha = 1.f, beta = 0.f;
+    const float* bias = nullptr;  // [N], added after alpha*acc + beta*C
+    int reduce_batch = 0;
+    // split-K over the (batch, k) reduction (batch == 1 or reduce_batch only):
+    // partial sums go to work[splitk][M][N] and are added in split order
+    int splitk = 1;
+    float* work = nullptr;
+};
+
+int gemm_bf16(const GemmArgs& g, hipStream_t st);
+
+}  // namespace fwi

@@ -1,0 +1,427 @@
+// The learned trace surrogate: model object, forward (inference), backward
+// (input gradient and weight gradients), and one Adam training step, all on
+// the BF16 matrix-core GEMM of gemm.hip and the kernels of nn.hip.
+//
+// Storage: FP32 master parameters in one vector (layout of SurLayout), a BF16
+// copy of every GEMM weight (W1, W2, Xm, T, W_p, U), BF16 NHWC activations
+// kept for the backward pass, FP32 gradient streams with a BF16 copy wherever
+// a gradient is a GEMM operand.  The order of the layers is that of the
+// network description in nn_ops.h.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "nn_internal.h"
+#include "nn_ops.h"
+
+namespace fwi {
+namespace {
+
+constexpr int kMaxSurBatch = 128;
+constexpr long kWorkFloats = 4L << 20;   // split-K partials (16 MiB)
+constexpr long kPartFloats = 512L * 10 * kC + 1024;
+
+struct BfMap {  // offsets of the BF16 copies
+    long enc_w1[kNBLK], enc_w2[kNBLK], dec_w1[kNBLK], dec_w2[kNBLK], dec_xm[kNBLK], d2t, proj_w, up, total;
+};
+
+}  // namespace
+}  // namespace fwi
+
+struct fwi_surrogate {
+    int device = 0, max_batch = 0, step = 0;
+    fwi::SurLayout L;
+    fwi::BfMap M;
+    std::vector<void*> allocs;
+    float *P = nullptr, *G = nullptr, *Am = nullptr, *Av = nullptr;
+    int* bf_index = nullptr;
+    fwi::bf16_t* W = nullptr;
+    // activations (BF16)
+    fwi::bf16_t *hin[fwi::kNBLK + 1], *ae[fwi::kNBLK], *pe[fwi::kNBLK], *qe[fwi::kNBLK];
+    fwi::bf16_t *gin[fwi::kNBLK + 1], *g1[fwi::kNBLK], *ad[fwi::kNBLK], *pd[fwi::kNBLK], *qd[fwi::kNBLK];
+    fwi::bf16_t *tmp = nullptr, *o = nullptr;
+    float *out32 = nullptr, *vcache = nullptr;
+    int cachedB = 0;
+    // gradient streams
+    fwi::bf16_t *dout16 = nullptr, *do16 = nullptr, *dg16 = nullptr, *dp16 = nullptr;
+    float *do32 = nullptr, *dg32 = nullptr, *dq32 = nullptr, *dp32 = nullptr, *da32 = nullptr;
+    float *part = nullptr, *work = nullptr;
+    // training
+    float *pred = nullptr, *dtr = nullptr, *mx = nullptr, *lpart = nullptr, *lval = nullptr;
+};
+
+namespace fwi {
+namespace {
+
+BfMap bf_map() {
+    BfMap m{};
+    long o = 0;
+    for (int i = 0; i < kNBLK; ++i) {
+        m.enc_w1[i] = o, o += kC * kCH;
+        m.enc_w2[i] = o, o += kCH * kC;
+    }
+    m.d2t = o, o += kT * kZ;
+    for (int i = 0; i < kNBLK; ++i) {
+        m.dec_xm[i] = o, o += kX * kX;
+        m.dec_w1[i] = o, o += kC * kCH;
+        m.dec_w2[i] = o, o += kCH * kC;
+    }
+    m.proj_w = o, o += kC * kS;
+    m.up = o, o += kNT * kT;
+    m.total = o;
+    return m;
+}
+
+template <class T>
+bool dalloc(fwi_surrogate* s, T** p, long n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)std::max<long>(n, 1) * sizeof(T)) != hipSuccess) return false;
+    s->allocs.push_back(q);
+    *p = (T*)q;
+    return true;
+}
+
+void free_all(fwi_surrogate* s) {
+    for (void* p : s->allocs) hipFree(p);
+    s->allocs.clear();
+}
+
+// split count for a reduction of `steps` K-steps onto `tiles` output tiles
+int pick_splitk(int M, int N, long steps) {
+    const long tiles = (long)((M + 63) / 64) * ((N + 63) / 64);
+    long sk = (512 + tiles - 1) / tiles;
+    sk = std::min<long>(sk, std::max<long>(1, steps / 8));
+    sk = std::min<long>(sk, kWorkFloats / ((long)M * N));
+    return (int)std::max<long>(1, std::min<long>(sk, 256));
+}
+
+struct Ctx {
+    fwi_surrogate* s;
+    hipStream_t st;
+    int rc = FWI_OK;
+
+    // C = op(A) op(B) (+ bias) per batch
+    void mm(int M, int N, int K, int batch, const bf16_t* A, long lda, long sA, int tA, const bf16_t* B, long ldb,
+            long sB, int tB, float* C32, bf16_t* C16, long ldc, long sC, const float* bias, float beta = 0.f) {
+        if (rc != FWI_OK) return;
+        GemmArgs g;
+        g.M = M, g.N = N, g.K = K, g.batch = batch;
+        g.A = A, g.lda = lda, g.strideA = sA, g.transA = tA;
+        g.B = B, g.ldb = ldb, g.strideB = sB, g.transB = tB;
+        g.C32 = C32, g.C16 = C16, g.ldc = ldc, g.strideC = sC, g.beta = beta, g.bias = bias;
+        rc = gemm_bf16(g, st);
+    }
+    // weight gradient C = sum over batch (and rows) of op(A) op(B), split-K
+    void wgrad(int M, int N, int K, int batch, const bf16_t* A, long lda, long sA, int tA, const bf16_t* B, long ldb,
+               long sB, int tB, float* C32, long ldc) {
+        if (rc != FWI_OK) return;
+        GemmArgs g;
+        g.M = M, g.N = N, g.K = K, g.batch = batch;
+        g.A = A, g.lda = lda, g.strideA = sA, g.transA = tA;
+        g.B = B, g.ldb = ldb, g.strideB = sB, g.transB = tB;
+        g.C32 = C32, g.ldc = ldc;
+        g.reduce_batch = batch > 1;
+        g.splitk = pick_splitk(M, N, (long)batch * ((K + 31) / 32));
+        g.work = s->work;
+        rc = gemm_bf16(g, st);
+    }
+};
+
+// ---------------------------------------------------------------------------
+int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStream_t st) {
+    Ctx c{s, st};
+    const SurLayout& L = s->L;
+    const BfMap& M = s->M;
+    const float* P = s->P;
+    const bf16_t* W = s->W;
+    const int re = B * kZ * kX, rd = B * kT * kX;
+    nn::copy_f32((long)B * kNZ * kNX, v, s->vcache, st);
+    nn::lift_fwd(B, v, P + L.lift_w, P + L.lift_b, s->hin[0], st);
+    for (int i = 0; i < kNBLK; ++i) {
+        nn::dw_fwd(B, kZ, kX, s->hin[i], P + L.enc_dw_k[i], P + L.enc_dw_b[i], s->ae[i], st);
+        c.mm(re, kCH, kC, 1, s->ae[i], kC, 0, 0, W + M.enc_w1[i], kCH, 0, 0, nullptr, s->pe[i], kCH, 0,
+             P + L.enc_b1[i]);
+        nn::gelu_fwd((long)re * kCH, s->pe[i], s->qe[i], st);
+        c.mm(re, kC, kCH, 1, s->qe[i], kCH, 0, 0, W + M.enc_w2[i], kC, 0, 0, nullptr, s->tmp, kC, 0, P + L.enc_b2[i]);
+        nn::add_bf16((long)re * kC, s->hin[i], s->tmp, s->hin[i + 1], st);
+    }
+    // depth -> time: per sample [T][X C] = T[T][Z] h[Z][X C]
+    const long xc = (long)kX * kC;
+    c.mm(kT, (int)xc, kZ, B, W + M.d2t, kZ, 0, 0, s->hin[kNBLK], xc, kZ * xc, 0, nullptr, s->gin[0], xc, kT * xc,
+         nullptr);
+    for (int i = 0; i < kNBLK; ++i) {
+        // mixing along x: per (sample, t) [X][C] = Xm[X][X] g[X][C]
+        c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 0, s->gin[i], kC, xc, 0, nullptr, s->tmp, kC, xc, nullptr);
+        nn::add_bf16((long)rd * kC, s->gin[i], s->tmp, s->g1[i], st);
+        nn::dw_fwd(B, kT, kX, s->g1[i], P + L.dec_dw_k[i], P + L.dec_dw_b[i], s->ad[i], st);
+        c.mm(rd, kCH, kC, 1, s->ad[i], kC, 0, 0, W + M.dec_w1[i], kCH, 0, 0, nullptr, s->pd[i], kCH, 0,
+             P + L.dec_b1[i]);
+        nn::gelu_fwd((long)rd * kCH, s->pd[i], s->qd[i], st);
+        c.mm(rd, kC, kCH, 1, s->qd[i], kCH, 0, 0, W + M.dec_w2[i], kC, 0, 0, nullptr, s->tmp, kC, 0, P + L.dec_b2[i]);
+        nn::add_bf16((long)rd * kC, s->g1[i], s->tmp, s->gin[i + 1], st);
+    }
+    c.mm(rd, kS, kC, 1, s->gin[kNBLK], kC, 0, 0, W + M.proj_w, kS, 0, 0, nullptr, s->o, kS, 0, P + L.proj_b);
+    // time up-sampling: per sample [NT][X S] = U[NT][T] o[T][X S] (FP32 out)
+    const long xs = (long)kX * kS;
+    c.mm(kNT, (int)xs, kT, B, W + M.up, kT, 0, 0, s->o, xs, kT * xs, 0, s->out32, nullptr, xs, kNT * xs, nullptr);
+    if (c.rc != FWI_OK) return c.rc;
+    nn::out_fwd(B, s->out32, P + L.out_scale, traces, st);
+    s->cachedB = B;
+    return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+// Chain rule through the last forward_impl (same B).  dv may be NULL; with
+// want_w the weight gradients are written to s->G (every entry but out_scale).
+int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want_w, hipStream_t st) {
+    Ctx c{s, st};
+    const SurLayout& L = s->L;
+    const BfMap& M = s->M;
+    const float* P = s->P;
+    float* G = s->G;
+    const bf16_t* W = s->W;
+    const int re = B * kZ * kX, rd = B * kT * kX;
+    const long xc = (long)kX * kC, xs = (long)kX * kS;
+
+    nn::out_bwd(B, dtr, P + L.out_scale, s->dout16, st);
+    if (want_w)  // dU = sum_n dout_n o_n^T
+        c.wgrad(kNT, kT, (int)xs, B, s->dout16, xs, kNT * xs, 0, s->o, xs, kT * xs, 1, G + L.up, kT);
+    // do_n = U^T dout_n
+    c.mm(kT, (int)xs, kNT, B, W + M.up, kT, 0, 1, s->dout16, xs, kNT * xs, 0, s->do32, nullptr, xs, kT * xs, nullptr);
+    nn::to_bf16((long)rd * kS, s->do32, s->do16, st);
+    if (want_w) {
+        c.wgrad(kC, kS, rd, 1, s->gin[kNBLK], kC, 0, 1, s->do16, kS, 0, 0, G + L.proj_w, kS);
+        nn::colsum(rd, kS, s->do32, G + L.proj_b, s->part, st);
+    }
+    c.mm(rd, kC, kS, 1, s->do16, kS, 0, 0, W + M.proj_w, kS, 0, 1, s->dg32, nullptr, kC, 0, nullptr);
+
+    for (int i = kNBLK - 1; i >= 0; --i) {
+        nn::to_bf16((long)rd * kC, s->dg32, s->dg16, st);
+        if (want_w) {
+            c.wgrad(kCH, kC, rd, 1, s->qd[i], kCH, 0, 1, s->dg16, kC, 0, 0, G + L.dec_w2[i], kC);
+            nn::colsum(rd, kC, s->dg32, G + L.dec_b2[i], s->part, st);
+        }
+        c.mm(rd, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.dec_w2[i], kC, 0, 1, s->dq32, nullptr, kCH, 0, nullptr);
+        nn::gelu_bwd((long)rd * kCH, s->dq32, s->pd[i], s->dp32, s->dp16, st);
+        if (want_w) {
+            c.wgrad(kC, kCH, rd, 1, s->ad[i], kC, 0, 1, s->dp16, kCH, 0, 0, G + L.dec_w1[i], kCH);
+            nn::colsum(rd, kCH, s->dp32, G + L.dec_b1[i], s->part, st);
+        }
+        c.mm(rd, kC, kCH, 1, s->dp16, kCH, 0, 0, W + M.dec_w1[i], kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
+        if (c.rc != FWI_OK) return c.rc;
+        // dg1 = dg + dw^T(da)   (in place in dg32)
+        nn::dw_bwd(B, kT, kX, s->g1[i], s->da32, P + L.dec_dw_k[i], s->dg32, want_w ? G + L.dec_dw_k[i] : nullptr,
+                   G + L.dec_dw_b[i], s->part, st);
+        nn::to_bf16((long)rd * kC, s->dg32, s->dg16, st);
+        if (want_w)  // dXm = sum_{n,t} dg1_{nt} g_{nt}^T
+            c.wgrad(kX, kX, kC, B * kT, s->dg16, kC, xc, 0, s->gin[i], kC, xc, 1, G + L.dec_xm[i], kX);
+        // dg = dg1 + Xm^T dg1
+        c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 1, s->dg16, kC, xc, 0, s->dg32, nullptr, kC, xc, nullptr,
+             1.f);
+    }
+    nn::to_bf16((long)rd * kC, s->dg32, s->dg16, st);
+    if (want_w)  // dT = sum_n dy_n h_n^T
+        c.wgrad(kT, kZ, (int)xc, B, s->dg16, xc, kT * xc, 0, s->hin[kNBLK], xc, kZ * xc, 1, G + L.d2t, kZ);
+    // dh_n = T^T dy_n  (into dg32, whose FP32 contents are no longer needed)
+    float* dh = s->dg32;
+    c.mm(kZ, (int)xc, kT, B, W + M.d2t, kZ, 0, 1, s->dg16, xc, kT * xc, 0, dh, nullptr, xc, kZ * xc, nullptr);
+
+    for (int i = kNBLK - 1; i >= 0; --i) {
+        nn::to_bf16((long)re * kC, dh, s->dg16, st);
+        if (want_w) {
+            c.wgrad(kCH, kC, re, 1, s->qe[i], kCH, 0, 1, s->dg16, kC, 0, 0, G + L.enc_w2[i], kC);
+            nn::colsum(re, kC, dh, G + L.enc_b2[i], s->part, st);
+        }
+        c.mm(re, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.enc_w2[i], kC, 0, 1, s->dq32, nullptr, kCH, 0, nullptr);
+        nn::gelu_bwd((long)re * kCH, s->dq32, s->pe[i], s->dp32, s->dp16, st);
+        if (want_w) {
+            c.wgrad(kC, kCH, re, 1, s->ae[i], kC, 0, 1, s->dp16, kCH, 0, 0, G + L.enc_w1[i], kCH);
+            nn::colsum(re, kCH, s->dp32, G + L.enc_b1[i], s->part, st);
+        }
+        c.mm(re, kC, kCH, 1, s->dp16, kCH, 0, 0, W + M.enc_w1[i], kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
+        if (c.rc != FWI_OK) return c.rc;
+        nn::dw_bwd(B, kZ, kX, s->hin[i], s->da32, P + L.enc_dw_k[i], dh, want_w ? G + L.enc_dw_k[i] : nullptr,
+                   G + L.enc_dw_b[i], s->part, st);
+    }
+    nn::lift_bwd(B, s->vcache, dh, P + L.lift_w, dv, want_w ? G + L.lift_w : nullptr, G + L.lift_b, s->part, st);
+    return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+int build_bf_index(fwi_surrogate* s) {
+    const SurLayout& L = s->L;
+    const BfMap& M = s->M;
+    std::vector<int> idx((size_t)L.total, -1);
+    auto map = [&](long p, long b, long n) {
+        for (long i = 0; i < n; ++i) idx[(size_t)(p + i)] = (int)(b + i);
+    };
+    for (int i = 0; i < kNBLK; ++i) {
+        map(L.enc_w1[i], M.enc_w1[i], kC * kCH);
+        map(L.enc_w2[i], M.enc_w2[i], kCH * kC);
+        map(L.dec_w1[i], M.dec_w1[i], kC * kCH);
+        map(L.dec_w2[i], M.dec_w2[i], kCH * kC);
+        map(L.dec_xm[i], M.dec_xm[i], kX * kX);
+    }
+    map(L.d2t, M.d2t, kT * kZ);
+    map(L.proj_w, M.proj_w, kC * kS);
+    map(L.up, M.up, kNT * kT);
+    return hipMemcpy(s->bf_index, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess
+               ? FWI_OK
+               : FWI_EHIP;
+}
+
+bool create_buffers(fwi_surrogate* s) {
+    const long Bm = s->max_batch;
+    const long pe = Bm * kZ * kX, pd = Bm * kT * kX;
+    const long T = s->L.total;
+    bool ok = dalloc(s, &s->P, T) && dalloc(s, &s->G, T) && dalloc(s, &s->Am, T) && dalloc(s, &s->Av, T) &&
+              dalloc(s, &s->bf_index, T) && dalloc(s, &s->W, s->M.total);
+    for (int i = 0; i <= kNBLK && ok; ++i) ok = dalloc(s, &s->hin[i], pe * kC) && dalloc(s, &s->gin[i], pd * kC);
+    for (int i = 0; i < kNBLK && ok; ++i)
+        ok = dalloc(s, &s->ae[i], pe * kC) && dalloc(s, &s->pe[i], pe * kCH) && dalloc(s, &s->qe[i], pe * kCH) &&
+             dalloc(s, &s->g1[i], pd * kC) && dalloc(s, &s->ad[i], pd * kC) && dalloc(s, &s->pd[i], pd * kCH) &&
+             dalloc(s, &s->qd[i], pd * kCH);
+    const long ntr = Bm * kNS * kNR * kNT;
+    ok = ok && dalloc(s, &s->tmp, pd * kC) && dalloc(s, &s->o, pd * kS) && dalloc(s, &s->out32, Bm * kNT * kX * kS) &&
+         dalloc(s, &s->vcache, Bm * kNZ * kNX) && dalloc(s, &s->dout16, Bm * kNT * kX * kS) &&
+         dalloc(s, &s->do16, pd * kS) && dalloc(s, &s->do32, pd * kS) && dalloc(s, &s->dg16, pd * kC) &&
+         dalloc(s, &s->dg32, pd * kC) && dalloc(s, &s->dq32, pd * kCH) && dalloc(s, &s->dp32, pd * kCH) &&
+         dalloc(s, &s->dp16, pd * kCH) && dalloc(s, &s->da32, pd * kC) && dalloc(s, &s->part, kPartFloats) &&
+         dalloc(s, &s->work, kWorkFloats) && dalloc(s, &s->pred, ntr) && dalloc(s, &s->dtr, ntr) &&
+         dalloc(s, &s->mx, Bm) && dalloc(s, &s->lpart, 2048) && dalloc(s, &s->lval, 1);
+    return ok;
+}
+
+}  // namespace
+}  // namespace fwi
+
+using namespace fwi;
+
+extern "C" {
+
+int fwi_sur_shape(int* dims) {
+    if (!dims) return FWI_EINVAL;
+    dims[0] = kNZ, dims[1] = kNX, dims[2] = kNS, dims[3] = kNR, dims[4] = kNT;
+    return FWI_OK;
+}
+
+long fwi_sur_param_count(void) { return sur_layout().total; }
+
+int fwi_sur_create(int max_batch, fwi_surrogate** out) {
+    if (!out || max_batch < 1 || max_batch > kMaxSurBatch) return FWI_EINVAL;
+    *out = nullptr;
+    fwi_surrogate* s = new (std::nothrow) fwi_surrogate();
+    if (!s) return FWI_ENOMEM;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return FWI_EHIP;
+    }
+    s->max_batch = max_batch;
+    s->L = sur_layout();
+    s->M = bf_map();
+    if (!create_buffers(s)) {
+        free_all(s);
+        delete s;
+        return FWI_ENOMEM;
+    }
+    int rc = build_bf_index(s);
+    const size_t pb = (size_t)s->L.total * sizeof(float);
+    if (rc == FWI_OK &&
+        (hipMemset(s->P, 0, pb) != hipSuccess || hipMemset(s->G, 0, pb) != hipSuccess ||
+         hipMemset(s->Am, 0, pb) != hipSuccess || hipMemset(s->Av, 0, pb) != hipSuccess ||
+         hipMemset(s->W, 0, (size_t)s->M.total * sizeof(bf16_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+        rc = FWI_EHIP;
+    if (rc != FWI_OK) {
+        free_all(s);
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return FWI_OK;
+}
+
+int fwi_sur_destroy(fwi_surrogate* s) {
+    if (!s) return FWI_OK;
+    hipSetDevice(s->device);
+    hipDeviceSynchronize();
+    free_all(s);
+    delete s;
+    return FWI_OK;
+}
+
+int fwi_sur_set_params(fwi_surrogate* s, const float* host) {
+    if (!s || !host) return FWI_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess) return FWI_EHIP;
+    const size_t pb = (size_t)s->L.total * sizeof(float);
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(s->P, host, pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->Am, 0, pb) != hipSuccess || hipMemset(s->Av, 0, pb) != hipSuccess)
+        return FWI_EHIP;
+    s->step = 0;
+    nn::refresh_bf16(s->L.total, s->P, s->bf_index, s->W, nullptr);
+    return hipDeviceSynchronize() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+static int copy_out(fwi_surrogate* s, const float* src, float* host) {
+    if (!s || !host) return FWI_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return FWI_EHIP;
+    return hipMemcpy(host, src, (size_t)s->L.total * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess ? FWI_OK
+                                                                                                         : FWI_EHIP;
+}
+
+int fwi_sur_get_params(fwi_surrogate* s, float* host) { return copy_out(s, s ? s->P : nullptr, host); }
+int fwi_sur_get_grads(fwi_surrogate* s, float* host) { return copy_out(s, s ? s->G : nullptr, host); }
+
+int fwi_sur_forward(fwi_surrogate* s, int B, const float* v, float* traces, void* stream) {
+    if (!s || !v || !traces || B < 0 || B > s->max_batch) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (hipSetDevice(s->device) != hipSuccess) return FWI_EHIP;
+    return forward_impl(s, B, v, traces, (hipStream_t)stream);
+}
+
+int fwi_sur_backward(fwi_surrogate* s, int B, const float* dtraces, float* dv, int want_weight_grads, void* stream) {
+    if (!s || !dtraces || B < 0 || B > s->max_batch) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (B != s->cachedB) return FWI_ESTATE;
+    if (!dv && !want_weight_grads) return FWI_OK;
+    if (hipSetDevice(s->device) != hipSuccess) return FWI_EHIP;
+    return backward_impl(s, B, dtraces, dv, want_weight_grads, (hipStream_t)stream);
+}
+
+int fwi_sur_train_step(fwi_surrogate* s, int B, const float* v, const float* target,
+                       const fwi_sur_train_params* tp, float* loss_out, void* stream) {
+    if (!s || !v || !target || !tp || B < 1 || B > s->max_batch) return FWI_EINVAL;
+    if (!(tp->lr > 0.f) || !(tp->beta1 >= 0.f && tp->beta1 < 1.f) || !(tp->beta2 >= 0.f && tp->beta2 < 1.f) ||
+        !(tp->eps > 0.f) || !(tp->loss_k >= 0.f) || !(tp->pair_weight >= 0.f) ||
+        (tp->pair_weight > 0.f && B % 2 != 0))
+        return FWI_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess) return FWI_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = forward_impl(s, B, v, s->pred, st);
+    if (rc != FWI_OK) return rc;
+    nn::loss(B, s->pred, target, tp->loss_k, tp->pair_weight, s->dtr, loss_out ? loss_out : s->lval, s->mx, s->lpart, st);
+    rc = backward_impl(s, B, s->dtr, nullptr, 1, st);
+    if (rc != FWI_OK) return rc;
+    ++s->step;
+    nn::adam(s->L.total, s->P, s->G, s->Am, s->Av, tp->lr, tp->beta1, tp->beta2, tp->eps, s->step, s->bf_index, s->W,
+             st);
+    return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+int fwi_judge(int B, int n, const float* g_a, const float* g_b, const double* J_a, const double* J_b, float* cos_out,
+              float* jerr_out, void* stream) {
+    if (B < 0 || n < 1 || !g_a || !g_b || !cos_out || (jerr_out && (!J_a || !J_b))) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    nn::judge(B, n, g_a, g_b, J_a, J_b, cos_out, jerr_out, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+int fwi_mf_predict(int B, int n, const float* g_anchor, const float* s_now, const float* s_anchor, float* g_out,
+                   const double* J_anchor, const double* Js_now, const double* Js_anchor, double* J_out,
+                   void* stream) {
+    if (B < 0 || n < 1 || !g_anchor || !s_now || !s_anchor || !g_out) return FWI_EINVAL;
+    if (J_out && (!J_anchor || !Js_now || !Js_anchor)) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    nn::mf_predict((long)B * n, g_anchor, s_now, s_anchor, g_out, B, J_anchor, Js_now, Js_anchor, J_out,
+                   (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+"""Judged surrogate-assisted guidance gradients (paper_2603_16393_amd.guided)
+on the GPU: the prediction arithmetic, the judge's fallback and recovery
+(forced from the host through its thresholds), and what the trained network
+adds over reusing the last exact gradient."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surrogate_70x70.npy")
+B = 4
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import fwi_inputs as fi
+    from paper_2603_16393_amd import FwiPlan
+    from paper_2603_16393_amd.surrogate import Surrogate, init_params
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    acq = fi.surface_acquisition(70, 70, ns=5, nt=1000, nb=40)
+    w = torch.tensor(fi.ricker(acq.nt, acq.dt, acq.f_peak), dtype=torch.float32, device=dev)
+    plan = FwiPlan(acq, max_batch=B, device=dev)
+    v_true = fi.faulted_model(70, 70, 1000)
+    dobs = plan.forward(torch.tensor(v_true[None], dtype=torch.float32, device=dev), w, keep_for_adjoint=False)
+    plan.set_obs(dobs[0].contiguous())
+    sur = Surrogate(B, device=dev)
+    sur.set_params(init_params(0, out_scale=0.016))
+    zeta = torch.tensor(np.stack([fi.stand_in_zeta(70, 70, b) for b in range(B)]), dtype=torch.float32, device=dev)
+    vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
+    return dev, plan, w, sur, zeta, vt
+
+
+def _v(vt, zeta, t):
+    return torch.clamp(vt + t * zeta, 1500.0, 4500.0).contiguous()
+
+
+def test_mf_predict_arithmetic(setup):
+    from paper_2603_16393_amd.surrogate import mf_predict
+
+    dev = setup[0]
+    g = torch.Generator(device=dev).manual_seed(0)
+    a, s, sa = (torch.randn((3, 70, 70), device=dev, generator=g) for _ in range(3))
+    Ja, Js, Jsa = (torch.rand(3, device=dev, dtype=torch.float64, generator=g) for _ in range(3))
+    out = torch.empty_like(a)
+    Jo = torch.empty_like(Ja)
+    mf_predict(a, s, sa, out, Ja, Js, Jsa, Jo)
+    assert torch.equal(out, a + (s - sa))
+    assert torch.equal(Jo, Ja + (Js - Jsa))
+    mf_predict(a, s, sa, a)  # in place on the anchor
+    assert torch.equal(a, out)
+
+
+def test_plain_below_switch_and_exact_values(setup):
+    from paper_2603_16393_amd.guided import GuidanceGradients
+
+    dev, plan, w, sur, zeta, vt = setup
+    src = GuidanceGradients(plan, w, B, surrogate=sur, t_switch=0.5)
+    v = _v(vt, zeta, 0.3)
+    J, g = src(0.3, v)
+    J, g = J.clone(), g.clone()
+    d = plan.forward(v, w, keep_for_adjoint=True)
+    J2, adj = plan.w2_misfit(d)
+    g2 = plan.adjoint_gradient(v, adj)
+    assert torch.equal(J, J2) and torch.equal(g, g2)
+    assert src.stats.served_predicted == 0 and src.stats.surrogate_batches == 0
+
+
+def test_judge_adapts_interval_and_falls_back(setup):
+    """Always-pass thresholds double the interval; impossible ones drive it to 0
+    (solver every step) while every returned gradient is the solver's."""
+    from paper_2603_16393_amd.guided import GuidanceGradients
+
+    dev, plan, w, sur, zeta, vt = setup
+    ts = np.linspace(1.0, 0.6, 30)
+    ok = GuidanceGradients(plan, w, B, surrogate=sur, cos_min=-2.0, jerr_max=1e30, k0=1, k_max=8)
+    for t in ts:
+        ok(float(t), _v(vt, zeta, float(t)))
+    assert ok.stats.judged >= 2 and ok.stats.passed == ok.stats.judged
+    assert max(ok.stats.k_trace) == 8
+    assert ok.stats.served_predicted + ok.stats.served_exact == len(ts)
+    assert ok.stats.served_predicted > len(ts) // 2
+
+    bad = GuidanceGradients(plan, w, B, surrogate=sur, cos_min=1.5, jerr_max=-1.0, k0=4, k_max=8)
+    for t in ts:
+        J, g = bad(float(t), _v(vt, zeta, float(t)))
+    assert bad.stats.passed == 0 and bad.stats.k_trace[-1] == 0
+    # once the interval reached 0 every step is a judged solver step
+    first_zero = bad.stats.k_trace.index(0)
+    assert bad.stats.served_exact >= len(ts) - 8
+    v = _v(vt, zeta, float(ts[-1]))
+    d = plan.forward(v, w, keep_for_adjoint=True)
+    J2, adj = plan.w2_misfit(d)
+    assert torch.equal(J, J2)
+    assert torch.equal(g, plan.adjoint_gradient(v, adj))
+    assert first_zero <= 3
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained surrogate weights in the tree")
+def test_trained_surrogate_improves_on_anchor_reuse(setup):
+    """Same fixed schedule (judge every 8 steps over t in (1, 0.5]) with and
+    without the trained network: the network's predictions of the misfit are
+    closer to the solver's, and its gradients are no worse."""
+    from paper_2603_16393_amd.guided import GuidanceGradients
+    from paper_2603_16393_amd.surrogate import Surrogate
+
+    dev, plan, w, _, zeta, vt = setup
+    net = Surrogate(B, device=dev)
+    net.set_params(np.load(WEIGHTS))
+    ts = np.linspace(1.0, 0.505, 100)
+    res = {}
+    for name, pred, s in (("net", "surrogate", net), ("anchor", "anchor", None)):
+        src = GuidanceGradients(plan, w, B, surrogate=s, predictor=pred, k0=8, adapt=False,
+                                cos_min=-2.0, jerr_max=1e30)
+        for t in ts:
+            src(float(t), _v(vt, zeta, float(t)))
+        res[name] = (np.array(src.stats.judge_cos), np.array(src.stats.judge_jerr))
+    net.close()
+    cn, jn = res["net"]
+    ca, ja = res["anchor"]
+    print("judged cos median net / anchor", np.median(cn), np.median(ca), "misfit err median", np.median(jn),
+          np.median(ja))
+    assert np.median(jn) < 0.5 * np.median(ja)
+    assert np.median(cn) >= np.median(ca) - 0.01

@@ -1,0 +1,214 @@
+"""Surrogate network on the GPU (fwi_sur_* through the C ABI) vs the FP64
+reference of oracle/surrogate.py.
+
+Tolerances.  The GPU stores activations in BF16 exactly where the reference
+rounds (rounding=True), but its FP32 accumulation order differs from FP64, so
+a few roundings land on the other side of a BF16 tie-interval.  Perturbing v
+by 1e-7 relative in the reference (which flips roundings at the same rate)
+moves the traces by 5e-3 relative L2, the input gradient by 6e-4 and the
+weight gradients by up to 5e-3.  The GPU backward also rounds its gradient
+streams to BF16 where they feed a GEMM (2^-9 relative each, about 10 in
+series), which the reference does not.  Bars: traces 2e-2, gradients 3e-2
+relative L2, gradient cosine >= 0.999.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+@pytest.fixture(scope="module")
+def case(dev):
+    from oracle import surrogate as S
+    import fwi_inputs as fi
+    from paper_2603_16393_amd.surrogate import Surrogate
+
+    params = S.init_params(3)
+    v = np.stack([fi.faulted_model(70, 70, s) for s in (1, 2)]).astype(np.float32)
+    rng = np.random.default_rng(7)
+    dtr = rng.standard_normal((2, S.NS, S.NR, S.NT)).astype(np.float32)
+    ref_tr, cache = S.forward(params, v.astype(np.float64), rounding=True)
+    ref_dv, ref_g = S.backward(params, cache, dtr.astype(np.float64))
+    sur = Surrogate(max_batch=4, device=dev)
+    sur.set_params(params)
+    return S, params, v, dtr, ref_tr, ref_dv, ref_g, sur
+
+
+def test_forward_matches_reference(dev, case):
+    S, params, v, dtr, ref_tr, ref_dv, ref_g, sur = case
+    tr = sur.forward(torch.tensor(v, device=dev))
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    err = _rel(got, ref_tr)
+    print("forward rel L2", err)
+    assert err <= 2e-2
+    for b in range(2):  # per sample and per shot as well
+        for s in range(S.NS):
+            assert _rel(got[b, s], ref_tr[b, s]) <= 4e-2
+
+
+def test_input_gradient_matches_reference(dev, case):
+    S, params, v, dtr, ref_tr, ref_dv, ref_g, sur = case
+    sur.forward(torch.tensor(v, device=dev))
+    dv = sur.backward(torch.tensor(dtr, device=dev))
+    torch.cuda.synchronize()
+    got = dv.cpu().numpy()
+    err = _rel(got, ref_dv)
+    cos = float(np.sum(got * ref_dv) / np.linalg.norm(got) / np.linalg.norm(ref_dv))
+    print("dv rel L2", err, "cos", cos)
+    assert err <= 3e-2 and cos >= 0.999
+
+
+def test_weight_gradients_match_reference(dev, case):
+    from paper_2603_16393_amd.surrogate import unpack
+
+    S, params, v, dtr, ref_tr, ref_dv, ref_g, sur = case
+    sur.forward(torch.tensor(v, device=dev))
+    sur.backward(torch.tensor(dtr, device=dev), want_input_grad=False, want_weight_grads=True)
+    g = unpack(sur.get_grads())
+    worst = {}
+    for name, ref in ref_g.items():
+        worst[name] = _rel(g[name], ref)
+    print("worst weight-grad rel L2", max(worst.items(), key=lambda kv: kv[1]))
+    for name, e in worst.items():
+        assert e <= 3e-2, (name, e)
+    assert g["out_scale"] == 0.0
+
+
+def test_backward_is_deterministic(dev, case):
+    S, params, v, dtr, *_, sur = case
+    vt, dt = torch.tensor(v, device=dev), torch.tensor(dtr, device=dev)
+    outs = []
+    for _ in range(2):
+        tr = sur.forward(vt).clone()
+        dv = sur.backward(dt, want_weight_grads=True).clone()
+        outs.append((tr, dv, sur.get_grads()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_batch_independence_and_ragged_batch(dev, case):
+    """Sample b of a batch equals the same sample run alone (odd B = 3)."""
+    S, params, v, dtr, *_, sur = case
+    import fwi_inputs as fi
+
+    v3 = np.concatenate([v, fi.faulted_model(70, 70, 9)[None].astype(np.float32)])
+    full = sur.forward(torch.tensor(v3, device=dev)).clone()
+    one = sur.forward(torch.tensor(v3[2:3], device=dev)).clone()
+    assert torch.equal(full[2:3], one)
+
+
+def test_loss_and_adam_step(dev, case):
+    """The train step's loss and gradient equal forward + weighted-MSE
+    derivative + backward, and the update is one Adam step on them."""
+    from paper_2603_16393_amd.surrogate import Surrogate, pack
+
+    S, params, v, dtr, *_ = case
+    sur = Surrogate(max_batch=2, device=dev)
+    sur.set_params(params)
+    vt = torch.tensor(v, device=dev)
+    rng = np.random.default_rng(11)
+    pred = sur.forward(vt).cpu().numpy().astype(np.float64)
+    tgt = (pred + 0.01 * rng.standard_normal(pred.shape)).astype(np.float32)
+    k = 5.0
+    mx = np.abs(tgt).reshape(2, -1).max(axis=1)[:, None, None, None]
+    w = 1.0 / (1.0 + k * np.abs(tgt) / mx)
+    r = w * (pred - tgt)
+    L_ref = np.sum(r * r) / pred.size
+    d_ref = (2 * w * r / pred.size).astype(np.float32)
+    sur.forward(vt)
+    sur.backward(torch.tensor(d_ref, device=dev), want_input_grad=False, want_weight_grads=True)
+    g_ref = sur.get_grads().astype(np.float64)
+    p0 = pack(params).astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    loss = sur.train_step(vt, torch.tensor(tgt, device=dev), lr=lr, beta1=b1, beta2=b2, eps=eps, loss_k=k)
+    assert float(loss.item()) == pytest.approx(L_ref, rel=1e-4)
+    g = sur.get_grads().astype(np.float64)
+    assert _rel(g, g_ref) <= 1e-3
+    p1 = sur.get_params().astype(np.float64)
+    m = (1 - b1) * g
+    vv = (1 - b2) * g * g
+    step = lr * (m / (1 - b1)) / (np.sqrt(vv / (1 - b2)) + eps)
+    assert np.allclose(p1, p0 - step, rtol=1e-5, atol=1e-7)
+    sur.close()
+
+
+def test_training_reduces_loss(dev, case):
+    from paper_2603_16393_amd.surrogate import Surrogate, init_params
+
+    S, params, v, *_ = case
+    sur = Surrogate(max_batch=2, device=dev)
+    p = init_params(0, out_scale=0.05)
+    sur.set_params(p)
+    vt = torch.tensor(v, device=dev)
+    tgt = torch.tensor(np.ascontiguousarray(S.forward(params, v.astype(np.float64), rounding=True)[0], np.float32),
+                       device=dev)
+    losses = [float(sur.train_step(vt, tgt, lr=2e-3).item()) for _ in range(30)]
+    print("loss", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    sur.close()
+
+
+def test_judge_matches_numpy(dev):
+    from paper_2603_16393_amd.surrogate import judge
+
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((5, 70, 70)).astype(np.float32)
+    b = (a + 0.3 * rng.standard_normal(a.shape)).astype(np.float32)
+    b[4] = 0.0
+    Ja = rng.random(5) + 0.5
+    Jb = rng.random(5) + 0.5
+    Jb[3] = 0.0
+    cos, jerr = judge(torch.tensor(a, device=dev), torch.tensor(b, device=dev), torch.tensor(Ja, device=dev),
+                      torch.tensor(Jb, device=dev))
+    cos, jerr = cos.cpu().numpy(), jerr.cpu().numpy()
+    A, Bm = a.reshape(5, -1).astype(np.float64), b.reshape(5, -1).astype(np.float64)
+    for i in range(4):
+        ref = A[i] @ Bm[i] / np.linalg.norm(A[i]) / np.linalg.norm(Bm[i])
+        assert cos[i] == pytest.approx(ref, rel=1e-6)
+    assert cos[4] == 0.0
+    assert jerr[3] == 0.0
+    for i in (0, 1, 2, 4):
+        assert jerr[i] == pytest.approx(abs(Ja[i] - Jb[i]) / abs(Jb[i]), rel=1e-6)
+
+
+def test_argument_errors(dev, case):
+    from paper_2603_16393_amd import _lib
+    from paper_2603_16393_amd.surrogate import Surrogate
+
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.fwi_sur_create(0, ctypes.byref(h)) == _lib.FWI_EINVAL
+    assert L.fwi_sur_create(1000, ctypes.byref(h)) == _lib.FWI_EINVAL
+    S, params, v, *_ , sur = case
+    vt = torch.tensor(v, device=dev)
+    sur.forward(vt)
+    d1 = torch.zeros((1, 5, 70, 1000), device=dev)
+    with pytest.raises(_lib.FwiError) as e:
+        sur.backward(d1)  # forward was run with B = 2
+    assert e.value.code == _lib.FWI_ESTATE
+    big = torch.zeros((5, 70, 70), device=dev)
+    with pytest.raises(_lib.FwiError) as e:
+        sur.forward(big)
+    assert e.value.code == _lib.FWI_EINVAL
+    tp = _lib.SurTrainParams(-1.0, 0.9, 0.999, 1e-8, 0.0, 0.0)
+    tgt = torch.zeros((2, 5, 70, 1000), device=dev)
+    rc = L.fwi_sur_train_step(sur._h, 2, ctypes.c_void_p(vt.data_ptr()), ctypes.c_void_p(tgt.data_ptr()),
+                              ctypes.byref(tp), None, None)
+    assert rc == _lib.FWI_EINVAL
