@@ -14,6 +14,8 @@ runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -62,6 +64,28 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
         "sample": f"{n_samples} of the {B} samples ({n_samples * NS} shot units), same grid/steps; forward + W2 + "
                   f"reverse-mode gradient + guidance update in FP64, {dt:.1f} s",
     }
+
+
+# HBM bytes per sweep launch of the default workload from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+# scaled by the same counters' reading for the library's plain copy kernel (profiles/
+# k_wave_lds_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
+TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/fwi_internal.h")
+TRAFFIC_SHA1 = "0aa2e863ef1181a1e12ba6f87ef4b029931a7c02"
+TRAFFIC_BYTES = {"forward": 5304064184.0, "adjoint": 5308392439.0}
+
+
+def kernel_sources_sha1():
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind):
+    if TRAFFIC_SHA1 is None or TRAFFIC_BYTES.get(kind) is None or kernel_sources_sha1() != TRAFFIC_SHA1:
+        return None
+    return TRAFFIC_BYTES[kind]
 
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surrogate_70x70.npy")
@@ -214,6 +238,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run the library's plain copy kernel on 512 MiB three times "
+                         "(the reference dispatch for HBM traffic counters) and exit")
     ap.add_argument("--workload", choices=["guidance", "checkpointed"], default="guidance")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -232,7 +259,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     acq, v0hat, v_true, w = make_inputs()
-    plan = FwiPlan(acq, max_batch=B, device=dev)
+    plan = FwiPlan(acq, max_batch=B, device=dev, timing=True)
     wt = torch.tensor(w, dtype=torch.float32, device=dev)
     dobs = plan.forward(torch.tensor(v_true[None], dtype=torch.float32, device=dev), wt, keep_for_adjoint=False)
     plan.set_obs(dobs[0].contiguous())
@@ -267,6 +294,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.warmup:
+        plan.sweep_ms()  # restart the per-sweep event averages at the timed region
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     t_start.record()
@@ -275,6 +304,23 @@ def main():
     t_end.record()
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
+    # mean device time of the forward and adjoint sweep kernels over the timed steps (HIP events the
+    # library records on the stream it launches them on)
+    fwd_sweep_ms, adj_sweep_ms = plan.sweep_ms()
+    if args.copy_calibration:
+        from paper_2603_16393_amd import _lib
+
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            _lib.check(_lib.load().fwi_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "fwi_copy")
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+        print(f"copy calibration: 3 x {nbytes} bytes", file=sys.stderr)
+        plan.close()
+        return
     # per-stage durations (HIP events on the stream the kernels run on), averaged over a few more steps
     reps = max(3, min(args.steps, 10))
     for _ in range(reps):
@@ -294,10 +340,11 @@ def main():
     # algorithmic bytes per sweep: read u^n, u^{n-1}, K and write u^{n+1} (16 B) per point-update,
     # plus 4 B per model-region point for the forward history (written forward, read by the adjoint)
     alg_bytes = 16.0 * updates + 4.0 * B * NS * (NT - 1) * NZ * NX
-    fwd_ms, adj_ms = stage_ms[0], stage_ms[2]
-    dom_ms = max(fwd_ms, adj_ms)
-    dom = "adjoint sweep (k_wave_lds, ADJ)" if adj_ms >= fwd_ms else "forward sweep (k_wave_lds)"
+    adj_dominant = adj_sweep_ms >= fwd_sweep_ms
+    dom_ms = max(fwd_sweep_ms, adj_sweep_ms)
+    dom = "k_wave_lds<ADJ> (adjoint sweep)" if adj_dominant else "k_wave_lds (forward sweep)"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
+    traffic = measured_traffic("adjoint" if adj_dominant else "forward")
     out = {
         "metric": "guidance grads/s (70x70, 5 shots, 1k steps) plain vs surrogate @cos>=0.95",
         "value": round(value, 2),
@@ -329,8 +376,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "launch_ms": round(dom_ms, 4),
         },
+        "sweep_ms": {"forward": round(fwd_sweep_ms, 4), "adjoint": round(adj_sweep_ms, 4)},
         "surrogate": None,
         "cpu_baseline": None,
     }

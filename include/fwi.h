@@ -126,6 +126,8 @@ typedef struct {
                            > 0: checkpoint every ckpt_every steps and recompute (tiled path only) */
     int lds_tile_x;     /* LDS-resident path: columns x rows of one thread's register tile;   */
     int lds_tile_z;     /* 0, 0 = the built-in cost model's choice; FWI_EINVAL if not available */
+    int timing;         /* 1: record HIP events around each forward and adjoint sweep on the caller's
+                           stream (read with fwi_plan_sweep_ms); 0: off */
 } fwi_plan_options;
 
 /* fwi_plan_create with explicit execution options (NULL = automatic). */
@@ -290,6 +292,22 @@ int fwi_judge(int B, int n, const float* g_a, const float* g_b, const double* J_
 int fwi_mf_predict(int B, int n, const float* g_anchor, const float* s_now, const float* s_anchor, float* g_out,
                    const double* J_anchor, const double* Js_now, const double* Js_anchor, double* J_out,
                    void* stream);
+
+/* Mean device time, in ms, of the forward sweeps (the nt - 1 time steps of
+ * fwi_forward, without the velocity preparation) and of the adjoint sweeps
+ * (of fwi_adjoint_gradient, without the gradient fold) enqueued since the
+ * previous call (at most the last 256 of each), from the HIP events of a plan
+ * created with options.timing = 1; then starts counting afresh.  Waits for
+ * those events.  Either pointer may be NULL.  FWI_ESTATE if timing is off or
+ * a requested kind of sweep has not run since the previous call. */
+int fwi_plan_sweep_ms(fwi_plan* plan, float* forward_ms, float* adjoint_ms);
+
+/* Plain device-to-device copy of `bytes` bytes by one kernel (16-byte vector
+ * loads and stores when both pointers are 16-byte aligned), asynchronous on
+ * `stream`.  The buffers must not overlap.  It reads and writes exactly
+ * `bytes` bytes each, which makes it the reference kernel for calibrating
+ * hardware traffic counters. */
+int fwi_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Synchronises the plan's device and returns FWI_OK, or the first recorded
  * device-side error (FWI_EDEVICE for an invalid velocity) and clears it. */

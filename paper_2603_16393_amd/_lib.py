@@ -29,6 +29,8 @@ EXPORTED = (
     "fwi_adjoint_gradient",
     "fwi_guidance_step",
     "fwi_status",
+    "fwi_plan_sweep_ms",
+    "fwi_copy",
     "fwi_error_string",
     "fwi_nn_gemm",
     "fwi_sur_shape",
@@ -70,7 +72,8 @@ class PlanInfo(ctypes.Structure):
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("force_path", c_int), ("ckpt_every", c_int), ("lds_tile_x", c_int), ("lds_tile_z", c_int)]
+    _fields_ = [("force_path", c_int), ("ckpt_every", c_int), ("lds_tile_x", c_int), ("lds_tile_z", c_int),
+                ("timing", c_int)]
 
 
 class SurTrainParams(ctypes.Structure):
@@ -108,6 +111,8 @@ def load():
     L.fwi_adjoint_gradient.argtypes = [P, c_int, P, P, P, P, P]
     L.fwi_guidance_step.argtypes = [c_int, c_int, c_int, P, P, P, P, ctypes.POINTER(GuidanceParams), P, P, P]
     L.fwi_status.argtypes = [P]
+    L.fwi_plan_sweep_ms.argtypes = [P, P, P]
+    L.fwi_copy.argtypes = [P, P, c_size_t, P]
     L.fwi_error_string.argtypes = [c_int]
     L.fwi_error_string.restype = ctypes.c_char_p
     cl, cf = ctypes.c_long, ctypes.c_float

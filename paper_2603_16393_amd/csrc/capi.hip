@@ -37,6 +37,11 @@ static int alloc_n(Plan& p, T** ptr, size_t n) {
 
 static void free_all(Plan& p) {
     release_graphs(p);
+    for (auto* ring : {&p.ev_fwd, &p.ev_adj}) {
+        for (hipEvent_t e : *ring)
+            if (e) (void)hipEventDestroy(e);
+        ring->clear();
+    }
     if (p.cap) {
         (void)hipStreamDestroy(p.cap);
         p.cap = nullptr;
@@ -74,9 +79,9 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     *out = nullptr;
     int st = validate_geometry(geom, max_batch);
     if (st) return st;
-    fwi_plan_options o{-1, 0, 0, 0};
+    fwi_plan_options o{-1, 0, 0, 0, 0};
     if (opt) o = *opt;
-    if (o.force_path < -1 || o.force_path > 1 || o.ckpt_every < 0) return FWI_EINVAL;
+    if (o.force_path < -1 || o.force_path > 1 || o.ckpt_every < 0 || o.timing < 0 || o.timing > 1) return FWI_EINVAL;
 
     fwi_plan* pp = new (std::nothrow) fwi_plan();
     if (!pp) return FWI_ENOMEM;
@@ -120,6 +125,17 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         return FWI_EINVAL;
     }
     p.path = (o.force_path == 1 || !lds_ok || o.ckpt_every > 0) ? 1 : 0;
+    p.timing = o.timing;
+    if (p.timing)
+        for (auto* ring : {&p.ev_fwd, &p.ev_adj}) {
+            ring->assign(2 * Plan::kTimingRing, nullptr);
+            for (hipEvent_t& e : *ring)
+                if (hipEventCreate(&e) != hipSuccess) {
+                    free_all(p);
+                    delete pp;
+                    return FWI_EHIP;
+                }
+        }
 
     // fixed-size buffers
     size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
@@ -347,11 +363,17 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
         rc = launch_copy(p.wav, wavelet, (size_t)p.g.nt, st);
         if (rc) return rc;
     }
+    const int slot_f = p.n_fwd_rec % Plan::kTimingRing;
+    if (p.timing && hipEventRecord(p.ev_fwd[2 * slot_f], st) != hipSuccess) return FWI_EHIP;
     if (p.path == 0)
         rc = launch_lds_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     else
         rc = tiled_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     if (rc) return rc;
+    if (p.timing) {
+        if (hipEventRecord(p.ev_fwd[2 * slot_f + 1], st) != hipSuccess) return FWI_EHIP;
+        ++p.n_fwd_rec;
+    }
     p.stored_B = keep_for_adjoint ? B : 0;
     return FWI_OK;
 }
@@ -376,11 +398,17 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
     hipStream_t st = as_stream(stream);
     int rc = launch_prep_velocity(p, B, v, st);
     if (rc) return rc;
+    const int slot_a = p.n_adj_rec % Plan::kTimingRing;
+    if (p.timing && hipEventRecord(p.ev_adj[2 * slot_a], st) != hipSuccess) return FWI_EHIP;
     if (p.path == 0)
         rc = launch_lds_adjoint(p, B, adj_src, p.wav, st);
     else
         rc = tiled_adjoint(p, B, adj_src, p.wav, nullptr, st);
     if (rc) return rc;
+    if (p.timing) {
+        if (hipEventRecord(p.ev_adj[2 * slot_a + 1], st) != hipSuccess) return FWI_EHIP;
+        ++p.n_adj_rec;
+    }
     return launch_fold_gradient(p, B, scale, grad, st);
 }
 
@@ -394,6 +422,40 @@ int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h
         !std::isfinite(gp.unit_scale))
         return FWI_EINVAL;
     return launch_guidance(B, nz, nx, v_prop, h, g, v0hat, gp, v_next, rho_out, as_stream(stream));
+}
+
+static int ring_mean(const std::vector<hipEvent_t>& ring, int& n_rec, float* out) {
+    if (n_rec == 0) return FWI_ESTATE;
+    const int n = std::min(n_rec, Plan::kTimingRing);
+    const int first = n_rec - n;
+    double sum = 0.0;
+    for (int i = first; i < n_rec; ++i) {
+        const int s = i % Plan::kTimingRing;
+        float ms = 0.f;
+        if (hipEventSynchronize(ring[2 * s + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, ring[2 * s], ring[2 * s + 1]) != hipSuccess)
+            return FWI_EHIP;
+        sum += ms;
+    }
+    *out = (float)(sum / n);
+    n_rec = 0;
+    return FWI_OK;
+}
+
+int fwi_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (bytes && (!dst || !src)) return FWI_EINVAL;
+    return launch_copy_bytes(dst, src, bytes, as_stream(stream));
+}
+
+int fwi_plan_sweep_ms(fwi_plan* plan, float* forward_ms, float* adjoint_ms) {
+    if (!plan) return FWI_EINVAL;
+    Plan& p = *plan;
+    if (!p.timing) return FWI_ESTATE;
+    if ((forward_ms && p.n_fwd_rec == 0) || (adjoint_ms && p.n_adj_rec == 0)) return FWI_ESTATE;
+    (void)hipSetDevice(p.device);
+    int rc = forward_ms ? ring_mean(p.ev_fwd, p.n_fwd_rec, forward_ms) : FWI_OK;
+    if (rc == FWI_OK && adjoint_ms) rc = ring_mean(p.ev_adj, p.n_adj_rec, adjoint_ms);
+    return rc;
 }
 
 int fwi_status(fwi_plan* plan) {

@@ -147,6 +147,13 @@ struct Plan {
     int g_adj_B = 0;
     float* trace_buf = nullptr;  // [max_batch*ns][nr][nt] traces written by the forward graph
     float* adj_buf = nullptr;    // [max_batch*ns][nr][nt] adjoint source read by the adjoint graph
+
+    // optional HIP events around forward / adjoint sweeps: rings of start/stop
+    // pairs; n_*_rec counts the sweeps recorded since the last query
+    static constexpr int kTimingRing = 256;
+    int timing = 0;
+    std::vector<hipEvent_t> ev_fwd, ev_adj;  // [2 * kTimingRing] each
+    int n_fwd_rec = 0, n_adj_rec = 0;
 };
 
 void release_graphs(Plan& p);
@@ -159,6 +166,7 @@ size_t lds_bytes(int X, int P, int ncg, int nstrip);
 
 // Launchers (return FWI_OK or FWI_EHIP).
 int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st);
+int launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st);
 int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
 int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wavelet, hipStream_t st);
 int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st);

@@ -175,6 +175,29 @@ int launch_copy(float* dst, const float* src, size_t n, hipStream_t st) {
     return hip_ok(hipGetLastError());
 }
 
+// plain byte copy: 16-byte vectors for the aligned body, bytes for the tail
+__global__ void k_copy_bytes(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src, size_t nvec,
+                             size_t tail) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    uint4* d = reinterpret_cast<uint4*>(dst);
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    for (size_t i = t0; i < nvec; i += stride) d[i] = s[i];
+    for (size_t i = t0; i < tail; i += stride) dst[nvec * 16 + i] = src[nvec * 16 + i];
+}
+
+int launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (!bytes) return FWI_OK;
+    const bool vec = ((uintptr_t)dst % 16 == 0) && ((uintptr_t)src % 16 == 0);
+    const size_t nvec = vec ? bytes / 16 : 0;
+    const size_t tail = bytes - nvec * 16;
+    const size_t work = std::max(nvec, tail);
+    const int grid = (int)std::min<size_t>((work + 255) / 256, 2048 * 8);
+    hipLaunchKernelGGL(k_copy_bytes, dim3(grid), dim3(256), 0, st, (unsigned char*)dst, (const unsigned char*)src,
+                       nvec, tail);
+    return hip_ok(hipGetLastError());
+}
+
 static TileArgs make_tile_args(const Plan& p, int B) {
     TileArgs a{};
     a.nzp = p.nzp;

@@ -55,7 +55,7 @@ class FwiPlan:
     """
 
     def __init__(self, acq, max_batch: int, mem_budget_bytes: int = 0, force_path: int = -1, ckpt_every: int = 0,
-                 device: Optional[torch.device] = None, lds_tile: tuple = (0, 0)):
+                 device: Optional[torch.device] = None, lds_tile: tuple = (0, 0), timing: bool = False):
         L = _lib.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.nz, self.nx, self.nt = int(acq.nz), int(acq.nx), int(acq.nt)
@@ -67,7 +67,7 @@ class FwiPlan:
                                    int(acq.nb), int(bool(acq.free_surface)), float(acq.v_max), self.ns, ip[0], ip[1],
                                    self.nr, ip[2], ip[3])
         self.max_batch = int(max_batch)
-        opts = _lib.PlanOptions(int(force_path), int(ckpt_every), int(lds_tile[0]), int(lds_tile[1]))
+        opts = _lib.PlanOptions(int(force_path), int(ckpt_every), int(lds_tile[0]), int(lds_tile[1]), int(bool(timing)))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(L.fwi_plan_create_ex(ctypes.byref(self._geom), self.max_batch, int(mem_budget_bytes),
@@ -134,6 +134,12 @@ class FwiPlan:
         check(_lib.load().fwi_adjoint_gradient(self._h, B, _ptr(v), _ptr(adj), _ptr(scale), _ptr(out), _stream()),
               "fwi_adjoint_gradient")
         return out
+
+    def sweep_ms(self):
+        """(forward, adjoint) mean device ms of the sweeps since the previous call; needs timing=True."""
+        f, a = ctypes.c_float(), ctypes.c_float()
+        check(_lib.load().fwi_plan_sweep_ms(self._h, ctypes.byref(f), ctypes.byref(a)), "fwi_plan_sweep_ms")
+        return f.value, a.value
 
     def status(self) -> int:
         """Synchronises and returns the device-side status code (0 = ok)."""
