@@ -265,3 +265,23 @@ def surrogate_training_pair(seed: int, nz: int = 70, nx: int = 70):
     v = np.clip(base + t * smooth_noise(nz, nx, 3_000_000 + seed, 3.0, 600.0), V_LO, V_HI)
     d = smooth_noise(nz, nx, 4_000_000 + seed, rng.uniform(2.0, 8.0), rng.uniform(30.0, 100.0))
     return v, np.clip(v + d, V_LO, V_HI)
+
+
+def uneven_requests(n: int = 64, seed0: int = 2000, nb: int = 40, sizes=(70, 140, 256), nts=(1000, 1500, 2500),
+                    shots=(5, 10)):
+    """Requests of an uneven guidance batch: request r (seed seed0 + r) draws a
+    square grid size from `sizes`, a trace length from `nts` and U{shots}
+    surface shots placed evenly, one receiver per surface column, dt = 1 ms,
+    15 Hz Ricker, dx = 10 m, an nb-cell sponge, and a faulted (even r) or
+    layered (odd r) model in 1500-4500 m/s.  Returns [(acq, v, wavelet)]."""
+    out = []
+    for r in range(n):
+        rng = np.random.default_rng(seed0 + r)
+        size = int(sizes[int(rng.integers(0, len(sizes)))])
+        nt = int(nts[int(rng.integers(0, len(nts)))])
+        ns = int(rng.integers(shots[0], shots[1] + 1))
+        acq = surface_acquisition(size, size, ns=ns, nt=nt, nb=nb)
+        v = faulted_model(size, size, seed0 + r) if r % 2 == 0 else layered_model(
+            size, size, seed0 + r, n_layers=2 + r % 3, depth_range=(size // 7, size - size // 7))
+        out.append((acq, v, ricker(nt, acq.dt, acq.f_peak)))
+    return out

@@ -302,6 +302,51 @@ int fwi_mf_predict(int B, int n, const float* g_anchor, const float* s_now, cons
  * a requested kind of sweep has not run since the previous call. */
 int fwi_plan_sweep_ms(fwi_plan* plan, float* forward_ms, float* adjoint_ms);
 
+/* ------------------------------------------------------------------------
+ * Uneven batches: requests with their own grids, trace lengths and shots
+ * (the same scheme as fwi_forward, Sec. 2.1 and Sec. 6.1), swept by one
+ * persistent launch.  Every (request, shot) field is one work unit run to
+ * completion by one workgroup; units are queued longest first.  Fields whose
+ * padded grid fits the LDS (and whose receivers share a row) run LDS-resident;
+ * larger ones are swept from HBM tile by tile.  The tile of each size class is
+ * chosen at creation by timing the compiled candidates (autotune = 1; results
+ * are kept for the process) or by a cost model (autotune = 0).
+ *
+ * Packed layouts (offsets from fwi_batch_get_info, in elements):
+ *   v        request r: [nz_r][nx_r] at v_offset
+ *   wavelets request r: [nt_r] at wavelet_offset (one wavelet for its shots)
+ *   traces   request r: [ns_r][nr_r][nt_r] at trace_offset
+ * ------------------------------------------------------------------------ */
+typedef struct fwi_batch fwi_batch;
+
+typedef struct {
+    int autotune;   /* 1: time the candidate tiles per size class at creation; 0: cost model */
+} fwi_batch_options;
+
+typedef struct {
+    size_t v_offset, wavelet_offset, trace_offset;
+    int nzp, nxp;           /* padded grid */
+    int kind;               /* 0: LDS-resident, 1: swept from HBM */
+    int tile_x, tile_z;     /* kind 0: register tile (columns, rows); kind 1: sweep tile */
+    int tuned;              /* 1 if the tile was picked by timing */
+} fwi_batch_request_info;
+
+/* Validates every geometry (FWI_EINVAL / FWI_ECFL as fwi_plan_create), builds
+ * the tables and the unit queue, allocates per-unit state (about 12 bytes per
+ * padded point for each HBM-swept field) and runs the autotuner on the
+ * current device (synchronous). */
+int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_options* options, fwi_batch** batch);
+int fwi_batch_destroy(fwi_batch* batch);
+int fwi_batch_get_info(const fwi_batch* batch, int request, fwi_batch_request_info* info);
+/* Total elements of the packed v, wavelet and trace buffers (any may be NULL). */
+int fwi_batch_sizes(const fwi_batch* batch, size_t* v_elems, size_t* wavelet_elems, size_t* trace_elems);
+/* Forward modelling of every request (traces as fwi_forward's d_syn, sample 0
+ * = 0) in one persistent launch after one coefficient launch (asynchronous).
+ * Velocities outside (0, v_max_r] raise the flag read by fwi_batch_status. */
+int fwi_batch_forward(fwi_batch* batch, const float* v, const float* wavelets, float* traces, void* stream);
+/* Synchronises; FWI_OK or FWI_EDEVICE (and clears the flag). */
+int fwi_batch_status(fwi_batch* batch);
+
 /* Plain device-to-device copy of `bytes` bytes by one kernel (16-byte vector
  * loads and stores when both pointers are 16-byte aligned), asynchronous on
  * `stream`.  The buffers must not overlap.  It reads and writes exactly

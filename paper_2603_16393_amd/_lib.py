@@ -31,6 +31,12 @@ EXPORTED = (
     "fwi_status",
     "fwi_plan_sweep_ms",
     "fwi_copy",
+    "fwi_batch_create",
+    "fwi_batch_destroy",
+    "fwi_batch_get_info",
+    "fwi_batch_sizes",
+    "fwi_batch_forward",
+    "fwi_batch_status",
     "fwi_error_string",
     "fwi_nn_gemm",
     "fwi_sur_shape",
@@ -76,6 +82,15 @@ class PlanOptions(ctypes.Structure):
                 ("timing", c_int)]
 
 
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("autotune", c_int)]
+
+
+class BatchRequestInfo(ctypes.Structure):
+    _fields_ = [("v_offset", c_size_t), ("wavelet_offset", c_size_t), ("trace_offset", c_size_t), ("nzp", c_int),
+                ("nxp", c_int), ("kind", c_int), ("tile_x", c_int), ("tile_z", c_int), ("tuned", c_int)]
+
+
 class SurTrainParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("loss_k", ctypes.c_float), ("pair_weight", ctypes.c_float)]
@@ -113,6 +128,12 @@ def load():
     L.fwi_status.argtypes = [P]
     L.fwi_plan_sweep_ms.argtypes = [P, P, P]
     L.fwi_copy.argtypes = [P, P, c_size_t, P]
+    L.fwi_batch_create.argtypes = [c_int, P, ctypes.POINTER(BatchOptions), ctypes.POINTER(P)]
+    L.fwi_batch_destroy.argtypes = [P]
+    L.fwi_batch_get_info.argtypes = [P, c_int, ctypes.POINTER(BatchRequestInfo)]
+    L.fwi_batch_sizes.argtypes = [P, ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t)]
+    L.fwi_batch_forward.argtypes = [P, P, P, P, P]
+    L.fwi_batch_status.argtypes = [P]
     L.fwi_error_string.argtypes = [c_int]
     L.fwi_error_string.restype = ctypes.c_char_p
     cl, cf = ctypes.c_long, ctypes.c_float

@@ -1,0 +1,685 @@
+// Uneven batches: many requests with their own grid sizes, trace lengths and
+// shot counts swept by ONE persistent launch.
+//
+// Work unit = one (request, shot) field for its whole time loop.  The launch
+// holds one 512-thread workgroup per compute unit; each workgroup takes the
+// next unit from a device counter (units are queued longest first, so the
+// long fields start early and the short ones fill the tail) and runs it to the
+// end, so no workgroup ever waits on another.  Two kinds of unit:
+//  * fields whose padded grid fits the LDS run the register-tiled LDS-resident
+//    time loop (wave_lds_body.h) with this request's tile;
+//  * larger fields keep (u^n, u^{n+1}, w) in HBM (the unit's own arrays, hot in
+//    L2 / MALL) and sweep them tile by tile each step, staging each tile of u
+//    plus its 4-cell halo in LDS.
+// The tile of each size class (LDS register tile or HBM sweep tile) comes from
+// the autotuner below, which times the candidates on a short sweep of the
+// class's first unit replicated over every compute unit.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+
+#include "fwi_internal.h"
+#include "wave_lds_body.h"
+
+namespace fwi {
+
+// Variants compiled into the persistent kernel.
+//   LDS-resident register tiles (X, P, exact cover of the padded grid)
+#define FWI_BATCH_LDS(M) M(0, 3, 11, true) M(1, 3, 11, false) M(2, 3, 12, false) M(3, 2, 12, false) M(4, 4, 8, false) M(5, 1, 16, false)
+constexpr int kBatchLdsVariants = 6;
+//   HBM sweep tiles (TX columns, TZ rows)
+#define FWI_BATCH_GLB(M) M(0, 64, 16) M(1, 64, 32) M(2, 64, 64) M(3, 128, 16) M(4, 128, 32)
+constexpr int kBatchGlbVariants = 5;
+
+struct BatchUnit {
+    int kind;       // 0: LDS-resident, 1: HBM sweep
+    int variant;    // index into the list of its kind
+    int nsteps;     // time steps to take (nt - 1, or fewer when tuning)
+    long long tr_off, w_off;  // offsets of this unit's traces and wavelet in the call's packed buffers
+    LdsArgs la;     // kind 0: pointers already offset to this unit (field index 0)
+    // kind 1
+    int nzp, nxp, fs, nt, nr, src_pt, rec_z0, rec_z1;
+    float idz2, idx2, src_scale;
+    const float* K;
+    const float* wavelet;
+    const int* rec_map;
+    float* ua;
+    float* ub;
+    float* w;
+    float* traces;  // [nr][nt] of this unit
+    const float* ax;
+    const float* az;
+};
+
+template <int TX, int TZ>
+__device__ void glb_field_forward(const BatchUnit& U, float* lds) {
+    constexpr int SS = TX + 8;
+    constexpr int NRG = kLdsThreads / TX;  // row groups
+    constexpr int RZ = TZ / NRG;            // rows per thread
+    static_assert(TZ % NRG == 0, "tile rows must split over the row groups");
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, tr = tid / TX;
+    const int nzp = U.nzp, nxp = U.nxp;
+    const int npts = nzp * nxp;
+    for (int i = tid; i < npts; i += kLdsThreads) {
+        U.ua[i] = 0.f;
+        U.w[i] = 0.f;
+    }
+    for (int r = tid; r < U.nr; r += kLdsThreads) U.traces[(size_t)r * U.nt] = 0.f;
+    __syncthreads();
+    const int ntx = (nxp + TX - 1) / TX, ntz = (nzp + TZ - 1) / TZ;
+    const float* cur = U.ua;
+    float* nxt = U.ub;
+    for (int m = 0; m < U.nsteps; ++m) {
+        for (int tzi = 0; tzi < ntz; ++tzi) {
+            const int zt = tzi * TZ;
+            const bool rec_rows = (zt + TZ > U.rec_z0) && (zt <= U.rec_z1);
+            for (int txi = 0; txi < ntx; ++txi) {
+                const int x0 = txi * TX;
+                for (int i = tid; i < (TZ + 8) * SS; i += kLdsThreads) {
+                    const int r = i / SS, c = i - (i / SS) * SS;
+                    int gz = zt + r - 4;
+                    const int gx = x0 + c - 4;
+                    if (U.fs && gz < 0) gz = -gz;  // even mirror above a reflecting top
+                    lds[i] = (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) ? cur[gz * nxp + gx] : 0.f;
+                }
+                __syncthreads();
+                const int gx = x0 + tx;
+                if (gx < nxp) {
+                    const float axv = U.ax[gx];
+#pragma unroll
+                    for (int j = 0; j < RZ; ++j) {
+                        const int lz = tr * RZ + j;
+                        const int gz = zt + lz;
+                        if (gz < nzp) {
+                            const int p = gz * nxp + gx;
+                            const int li = (lz + 4) * SS + tx + 4;
+                            const float c = lds[li];
+                            const float lzs = FWI_LAPD(c, lds[li - 4 * SS], lds[li - 3 * SS], lds[li - 2 * SS],
+                                                       lds[li - SS], lds[li + SS], lds[li + 2 * SS], lds[li + 3 * SS],
+                                                       lds[li + 4 * SS]);
+                            const float lxs = FWI_LAPD(c, lds[li - 4], lds[li - 3], lds[li - 2], lds[li - 1],
+                                                       lds[li + 1], lds[li + 2], lds[li + 3], lds[li + 4]);
+                            float D = lzs * U.idz2 + lxs * U.idx2;
+                            if (p == U.src_pt) D += U.wavelet[m] * U.src_scale;
+                            const float wn = fmaf(U.K[p], D, (axv * U.az[gz]) * U.w[p]);
+                            const float un = c + wn;
+                            U.w[p] = wn;
+                            nxt[p] = un;
+                            if (rec_rows) {
+                                const int r = U.rec_map[p];
+                                if (r >= 0) U.traces[(size_t)r * U.nt + m + 1] = un;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        float* t = const_cast<float*>(cur);
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+__device__ void run_unit_forward(const BatchUnit& U, float* lds) {
+    if (U.kind == 0) {
+#define FWI_LDS_CASE(ID, XX, PP, EX) \
+    if (U.variant == ID) {           \
+        lds_field<XX, PP, false, EX, false>(U.la, 0, U.ax, U.az, lds); \
+        return;                      \
+    }
+        FWI_BATCH_LDS(FWI_LDS_CASE)
+#undef FWI_LDS_CASE
+    } else {
+#define FWI_GLB_CASE(ID, TXX, TZZ) \
+    if (U.variant == ID) {         \
+        glb_field_forward<TXX, TZZ>(U, lds); \
+        return;                    \
+    }
+        FWI_BATCH_GLB(FWI_GLB_CASE)
+#undef FWI_GLB_CASE
+    }
+}
+
+__global__ __launch_bounds__(kLdsThreads) void k_batch_forward(const BatchUnit* __restrict__ units, int nunits,
+                                                               int* __restrict__ counter) {
+    extern __shared__ float lds[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int u = __builtin_amdgcn_readfirstlane(next);  // uniform: descriptor fields load as scalars
+        __syncthreads();
+        if (u >= nunits) break;  // every workgroup leaves once the queue is drained
+        run_unit_forward(units[u], lds);
+        __syncthreads();
+    }
+}
+
+// Points the queued units at this call's packed traces and wavelets.
+__global__ void k_batch_bind(BatchUnit* __restrict__ units, int nunits, float* __restrict__ traces,
+                             const float* __restrict__ wavelets) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nunits) return;
+    BatchUnit& U = units[u];
+    if (U.kind == 0) {
+        U.la.traces = traces + U.tr_off;
+        U.la.wavelet = wavelets + U.w_off;
+    } else {
+        U.traces = traces + U.tr_off;
+        U.wavelet = wavelets + U.w_off;
+    }
+}
+
+__global__ void k_reset_counter(int* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+// K = (v dt)^2 on every request's padded grid (edge-replicated velocity) in
+// one launch; thread i finds its request by bisection over the point offsets.
+struct PrepReq {
+    long long pt_off;   // first padded point of the request in the packed K
+    long long v_off;    // first model cell in the packed velocity
+    int nz, nx, nzp, nxp, ztop, nb;
+    float dt, vmax;
+};
+
+__global__ void k_batch_prep(const PrepReq* __restrict__ req, int nreq, long long total, const float* __restrict__ v,
+                             float* __restrict__ K, int* __restrict__ flags) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nreq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (req[mid].pt_off <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const PrepReq& q = req[lo];
+        const int p = (int)(i - q.pt_off);
+        const int iz = p / q.nxp, ix = p - (p / q.nxp) * q.nxp;
+        const int mz = min(max(iz - q.ztop, 0), q.nz - 1);
+        const int mx = min(max(ix - q.nb, 0), q.nx - 1);
+        const float vv = v[q.v_off + (long long)mz * q.nx + mx];
+        if (!(vv > 0.f) || !(vv <= q.vmax)) atomicOr(flags, kFlagBadVelocity);
+        const float c = vv * q.dt;
+        K[i] = c * c;
+    }
+}
+
+}  // namespace fwi
+
+// ---------------------------------------------------------------------------
+// Host side
+using namespace fwi;
+
+struct fwi_batch {
+    int device = 0, nreq = 0, n_cu = 0;
+    std::vector<fwi_geometry> g;
+    std::vector<std::vector<int>> idx;           // host copies of the index arrays
+    std::vector<int> nzp, nxp, ztop, kind, variant, tuned;
+    std::vector<long long> v_off, w_off, tr_off, pt_off;
+    long long v_total = 0, w_total = 0, tr_total = 0, pt_total = 0;
+    std::vector<BatchUnit> units;                // queue order
+    std::vector<int> unit_req;                   // request of each queued unit
+    BatchUnit* d_units = nullptr;
+    PrepReq* d_prep = nullptr;
+    int* counter = nullptr;
+    int* flags = nullptr;
+    float* K = nullptr;
+    size_t lds_bytes = 0;
+    std::vector<void*> allocs;
+    std::vector<std::pair<int, int>> shape;      // (nzp, nxp) of each request
+};
+
+namespace {
+
+struct TuneKey {
+    int nzp, nxp, kind, exact;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(nzp, nxp, kind, exact) < std::tie(o.nzp, o.nxp, o.kind, o.exact);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;  // process-wide autotuner results
+
+struct LdsVar {
+    int X, P;
+    bool exact;
+};
+const LdsVar kLdsVar[kBatchLdsVariants] = {
+#define FWI_V(ID, XX, PP, EX) {XX, PP, EX},
+    FWI_BATCH_LDS(FWI_V)
+#undef FWI_V
+};
+struct GlbVar {
+    int TX, TZ;
+};
+const GlbVar kGlbVar[kBatchGlbVariants] = {
+#define FWI_V(ID, TXX, TZZ) {TXX, TZZ},
+    FWI_BATCH_GLB(FWI_V)
+#undef FWI_V
+};
+
+size_t glb_lds(int v) { return (size_t)(kGlbVar[v].TZ + 8) * (kGlbVar[v].TX + 8) * sizeof(float); }
+
+bool lds_var_fits(int v, int nzp, int nxp, int* ncg, int* nstrip) {
+    const LdsVar& L = kLdsVar[v];
+    *ncg = (nxp + L.X - 1) / L.X;
+    *nstrip = (nzp + L.P - 1) / L.P;
+    const bool exact = *ncg * L.X == nxp && *nstrip * L.P == nzp;
+    if (L.exact != exact) return false;
+    return *ncg * *nstrip <= kLdsThreads && lds_bytes(L.X, L.P, *ncg, *nstrip) <= (size_t)kLdsBytes;
+}
+
+template <class T>
+int balloc(fwi_batch* b, T** p, size_t n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return FWI_ENOMEM;
+    b->allocs.push_back(q);
+    *p = (T*)q;
+    return FWI_OK;
+}
+
+void bfree(fwi_batch* b) {
+    for (void* q : b->allocs) (void)hipFree(q);
+    b->allocs.clear();
+}
+
+int launch_units(BatchUnit* d_units, int nunits, int* counter, int grid, size_t lds, float* traces,
+                 const float* wavelets, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_bind, dim3((nunits + 255) / 256), dim3(256), 0, st, d_units, nunits, traces, wavelets);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    hipFuncSetAttribute((const void*)k_batch_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_batch_forward, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
+    return hip_ok(hipGetLastError());
+}
+
+// Fills the unit descriptor of (request r, shot s) for a given kind/variant.
+// Per-unit device arrays (state, traces) are passed in.
+struct ReqDev {
+    float* ax;
+    float* az;
+    int* src_pt;
+    int* rec_map;
+    int* rec_of_col;
+    HostTables ht;
+};
+
+BatchUnit make_unit(const fwi_batch* b, int r, int s, int kind, int variant, const ReqDev& rd, const float* K,
+                    long long w_off, long long tr_off, float* state, int nsteps) {
+    const fwi_geometry& g = b->g[r];
+    BatchUnit U{};
+    U.kind = kind;
+    U.variant = variant;
+    U.nsteps = nsteps;
+    U.tr_off = tr_off;
+    U.w_off = w_off;
+    U.ax = rd.ax;
+    U.az = rd.az;
+    const int nzp = b->nzp[r], nxp = b->nxp[r];
+    if (kind == 0) {
+        const LdsVar& V = kLdsVar[variant];
+        LdsArgs& a = U.la;
+        a.nzp = nzp;
+        a.nxp = nxp;
+        a.npts = nzp * nxp;
+        a.X = V.X;
+        a.P = V.P;
+        a.ncg = (nxp + V.X - 1) / V.X;
+        a.nstrip = (nzp + V.P - 1) / V.P;
+        a.S = a.ncg * a.X + 8;
+        a.fs = g.free_surface ? 1 : 0;
+        a.nt = nsteps + 1;
+        a.ns = 1;
+        a.nr = g.nr;
+        a.rec_row = rd.ht.rec_row;
+        a.rec_invw = (g.free_surface && rd.ht.rec_row == 0) ? 2.f : 1.f;
+        a.idz2 = (float)(1.0 / (g.dz * g.dz));
+        a.idx2 = (float)(1.0 / (g.dx * g.dx));
+        a.src_scale = (float)(1.0 / (g.dx * g.dz));
+        a.K = K;
+        a.src_pt = rd.src_pt + s;
+        a.rec_of_col = rd.rec_of_col;
+        a.store = 0;
+    } else {
+        U.nzp = nzp;
+        U.nxp = nxp;
+        U.fs = g.free_surface ? 1 : 0;
+        U.nt = nsteps + 1;
+        U.nr = g.nr;
+        U.src_pt = rd.ht.src_pt[s];
+        U.rec_z0 = rd.ht.rec_z0;
+        U.rec_z1 = rd.ht.rec_z1;
+        U.idz2 = (float)(1.0 / (g.dz * g.dz));
+        U.idx2 = (float)(1.0 / (g.dx * g.dx));
+        U.src_scale = (float)(1.0 / (g.dx * g.dz));
+        U.K = K;
+        U.rec_map = rd.rec_map;
+        const size_t npts = (size_t)nzp * nxp;
+        U.ua = state;
+        U.ub = state + npts;
+        U.w = state + 2 * npts;
+    }
+    return U;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_options* opt, fwi_batch** out) {
+    if (!out || nreq < 1 || !geoms) return FWI_EINVAL;
+    *out = nullptr;
+    fwi_batch_options o{1};
+    if (opt) o = *opt;
+    if (o.autotune < 0 || o.autotune > 1) return FWI_EINVAL;
+    for (int r = 0; r < nreq; ++r) {
+        const int st = validate_geometry(&geoms[r], 1);
+        if (st) return st;
+    }
+    fwi_batch* b = new (std::nothrow) fwi_batch();
+    if (!b) return FWI_ENOMEM;
+    (void)hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
+        delete b;
+        return FWI_EHIP;
+    }
+    b->n_cu = prop.multiProcessorCount;
+    b->nreq = nreq;
+    b->g.assign(geoms, geoms + nreq);
+    b->idx.resize(4 * (size_t)nreq);
+    std::vector<ReqDev> rd(nreq);
+    int st = FWI_OK;
+    for (int r = 0; r < nreq; ++r) {
+        fwi_geometry& g = b->g[r];
+        b->idx[4 * r + 0].assign(g.src_iz, g.src_iz + g.ns);
+        b->idx[4 * r + 1].assign(g.src_ix, g.src_ix + g.ns);
+        b->idx[4 * r + 2].assign(g.rec_iz, g.rec_iz + g.nr);
+        b->idx[4 * r + 3].assign(g.rec_ix, g.rec_ix + g.nr);
+        g.src_iz = b->idx[4 * r + 0].data();
+        g.src_ix = b->idx[4 * r + 1].data();
+        g.rec_iz = b->idx[4 * r + 2].data();
+        g.rec_ix = b->idx[4 * r + 3].data();
+        g.free_surface = g.free_surface ? 1 : 0;
+        const int ztop = g.free_surface ? 0 : g.nb;
+        const int nzp = g.nz + g.nb + ztop, nxp = g.nx + 2 * g.nb;
+        b->ztop.push_back(ztop);
+        b->nzp.push_back(nzp);
+        b->nxp.push_back(nxp);
+        b->v_off.push_back(b->v_total);
+        b->w_off.push_back(b->w_total);
+        b->tr_off.push_back(b->tr_total);
+        b->pt_off.push_back(b->pt_total);
+        b->v_total += (long long)g.nz * g.nx;
+        b->w_total += g.nt;
+        b->tr_total += (long long)g.ns * g.nr * g.nt;
+        b->pt_total += (long long)nzp * nxp;
+        build_host_tables(g, nzp, nxp, ztop, rd[r].ht);
+        st = st ? st : balloc(b, &rd[r].ax, (size_t)nxp);
+        st = st ? st : balloc(b, &rd[r].az, (size_t)nzp);
+        st = st ? st : balloc(b, &rd[r].src_pt, (size_t)g.ns);
+        st = st ? st : balloc(b, &rd[r].rec_map, (size_t)nzp * nxp);
+        st = st ? st : balloc(b, &rd[r].rec_of_col, (size_t)nxp);
+        if (st) break;
+        const HostTables& t = rd[r].ht;
+        st = hip_ok(hipMemcpy(rd[r].ax, t.ax.data(), nxp * sizeof(float), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(rd[r].az, t.az.data(), nzp * sizeof(float), hipMemcpyHostToDevice));
+        st = st ? st : hip_ok(hipMemcpy(rd[r].src_pt, t.src_pt.data(), g.ns * sizeof(int), hipMemcpyHostToDevice));
+        st = st ? st
+                : hip_ok(hipMemcpy(rd[r].rec_map, t.rec_map.data(), t.rec_map.size() * sizeof(int),
+                                   hipMemcpyHostToDevice));
+        st = st ? st
+                : hip_ok(hipMemcpy(rd[r].rec_of_col, t.rec_of_col.data(), nxp * sizeof(int), hipMemcpyHostToDevice));
+        if (st) break;
+    }
+    st = st ? st : balloc(b, &b->K, (size_t)b->pt_total);
+    st = st ? st : balloc(b, &b->counter, 1);
+    st = st ? st : balloc(b, &b->flags, 1);
+    if (st == FWI_OK && hipMemset(b->flags, 0, sizeof(int)) != hipSuccess) st = FWI_EHIP;
+    // kinds: LDS-resident when some variant fits and the receivers share a row
+    b->kind.assign(nreq, 1);
+    b->variant.assign(nreq, 0);
+    b->tuned.assign(nreq, 0);
+    for (int r = 0; r < nreq && st == FWI_OK; ++r) {
+        int ncg, nstrip;
+        if (rd[r].ht.one_row)
+            for (int v = 0; v < kBatchLdsVariants; ++v)
+                if (lds_var_fits(v, b->nzp[r], b->nxp[r], &ncg, &nstrip)) b->kind[r] = 0;
+    }
+
+    // autotuning per size class: every candidate on a 64-step sweep of the
+    // class's first request, one copy per compute unit
+    const int tune_steps = 64;
+    for (int r = 0; r < nreq && st == FWI_OK; ++r) {
+        const int nzp = b->nzp[r], nxp = b->nxp[r];
+        int ncg, nstrip;
+        std::vector<int> cands;
+        bool exact = false;
+        if (b->kind[r] == 0) {
+            for (int v = 0; v < kBatchLdsVariants; ++v)
+                if (lds_var_fits(v, nzp, nxp, &ncg, &nstrip)) {
+                    cands.push_back(v);
+                    exact = exact || kLdsVar[v].exact;
+                }
+        } else {
+            for (int v = 0; v < kBatchGlbVariants; ++v) cands.push_back(v);
+        }
+        const TuneKey key{nzp, nxp, b->kind[r], exact ? 1 : 0};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                b->variant[r] = it->second;
+                b->tuned[r] = 1;
+                continue;
+            }
+        }
+        if (!o.autotune || cands.size() == 1 || b->g[r].nt - 1 < tune_steps) {
+            // cost model: LDS operations per point (LDS kind), fewest tiles (HBM kind)
+            int best = cands[0];
+            double bc = 1e300;
+            for (int v : cands) {
+                double c;
+                if (b->kind[r] == 0) {
+                    const LdsVar& L = kLdsVar[v];
+                    lds_var_fits(v, nzp, nxp, &ncg, &nstrip);
+                    c = (double)ncg * L.X * nstrip * L.P * ((L.P + 8.0) / L.P + 8.0 / L.X + 1.0);
+                } else {
+                    const GlbVar& G = kGlbVar[v];
+                    c = (double)((nxp + G.TX - 1) / G.TX * G.TX) * ((nzp + G.TZ - 1) / G.TZ * G.TZ) *
+                        (1.0 + 8.0 / G.TZ + 8.0 / G.TX);
+                }
+                if (c < bc) {
+                    bc = c;
+                    best = v;
+                }
+            }
+            b->variant[r] = best;
+            continue;
+        }
+        const fwi_geometry& g = b->g[r];
+        const int copies = b->n_cu;
+        const size_t npts = (size_t)nzp * nxp;
+        float *Kt = nullptr, *wt = nullptr, *trt = nullptr, *stt = nullptr;
+        BatchUnit* du = nullptr;
+        std::vector<void*> tmp;
+        auto talloc = [&](void** p, size_t bytes) {
+            if (st) return;
+            if (hipMalloc(p, std::max<size_t>(bytes, 4)) != hipSuccess) {
+                st = FWI_ENOMEM;
+                return;
+            }
+            tmp.push_back(*p);
+        };
+        talloc((void**)&Kt, npts * sizeof(float));
+        talloc((void**)&wt, (size_t)g.nt * sizeof(float));
+        talloc((void**)&trt, (size_t)copies * g.nr * (tune_steps + 1) * sizeof(float));
+        talloc((void**)&stt, b->kind[r] == 1 ? (size_t)copies * 3 * npts * sizeof(float) : 4);
+        talloc((void**)&du, (size_t)copies * sizeof(BatchUnit));
+        if (st == FWI_OK) {
+            // a smooth 2000 m/s medium and a unit impulse train stand in for the request's data
+            std::vector<float> kh(npts, (float)std::pow(2000.0 * g.dt, 2));
+            std::vector<float> wh(g.nt, 0.f);
+            wh[1] = 1.f;
+            st = hip_ok(hipMemcpy(Kt, kh.data(), npts * sizeof(float), hipMemcpyHostToDevice));
+            st = st ? st : hip_ok(hipMemcpy(wt, wh.data(), g.nt * sizeof(float), hipMemcpyHostToDevice));
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (st == FWI_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = FWI_EHIP;
+        float best_ms = 1e30f;
+        int best = cands[0];
+        for (int v : cands) {
+            if (st) break;
+            std::vector<BatchUnit> hu(copies);
+            for (int c = 0; c < copies; ++c)
+                hu[c] = make_unit(b, r, 0, b->kind[r], v, rd[r], Kt, 0, (long long)c * g.nr * (tune_steps + 1),
+                                  stt + (b->kind[r] == 1 ? (size_t)c * 3 * npts : 0), tune_steps);
+            st = hip_ok(hipMemcpy(du, hu.data(), copies * sizeof(BatchUnit), hipMemcpyHostToDevice));
+            const size_t lb =
+                b->kind[r] == 0 ? lds_bytes(kLdsVar[v].X, kLdsVar[v].P, hu[0].la.ncg, hu[0].la.nstrip) : glb_lds(v);
+            for (int rep = 0; rep < 2 && st == FWI_OK; ++rep) {  // first run warms up
+                st = hip_ok(hipEventRecord(e0, nullptr));
+                st = st ? st : launch_units(du, copies, b->counter, copies, lb, trt, wt, nullptr);
+                st = st ? st : hip_ok(hipEventRecord(e1, nullptr));
+                st = st ? st : hip_ok(hipEventSynchronize(e1));
+            }
+            float ms = 0.f;
+            if (st == FWI_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (void* p : tmp) (void)hipFree(p);
+        if (st) break;
+        b->variant[r] = best;
+        b->tuned[r] = 1;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+    }
+
+    // units, longest first
+    if (st == FWI_OK) {
+        struct Job {
+            double cost;
+            int r, s;
+        };
+        std::vector<Job> jobs;
+        size_t state_elems = 0;
+        for (int r = 0; r < nreq; ++r)
+            for (int s = 0; s < b->g[r].ns; ++s) {
+                jobs.push_back({(double)b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1), r, s});
+                if (b->kind[r] == 1) state_elems += 3 * (size_t)b->nzp[r] * b->nxp[r];
+            }
+        std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& c) { return a.cost > c.cost; });
+        float* state = nullptr;
+        st = balloc(b, &state, state_elems);
+        size_t so = 0;
+        for (const Job& j : jobs) {
+            if (st) break;
+            const int r = j.r;
+            const long long tr_off = b->tr_off[r] + (long long)j.s * b->g[r].nr * b->g[r].nt;
+            float* sp = nullptr;
+            if (b->kind[r] == 1) {
+                sp = state + so;
+                so += 3 * (size_t)b->nzp[r] * b->nxp[r];
+            }
+            BatchUnit U = make_unit(b, r, j.s, b->kind[r], b->variant[r], rd[r], b->K + b->pt_off[r], b->w_off[r],
+                                    tr_off, sp, b->g[r].nt - 1);
+            b->units.push_back(U);
+            b->unit_req.push_back(r);
+            const size_t lb = b->kind[r] == 0 ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip) : glb_lds(U.variant);
+            b->lds_bytes = std::max(b->lds_bytes, lb);
+        }
+        st = st ? st : balloc(b, &b->d_units, b->units.size());
+        st = st ? st
+                : hip_ok(hipMemcpy(b->d_units, b->units.data(), b->units.size() * sizeof(BatchUnit),
+                                   hipMemcpyHostToDevice));
+        std::vector<PrepReq> pr(nreq);
+        for (int r = 0; r < nreq; ++r)
+            pr[r] = {b->pt_off[r], b->v_off[r], b->g[r].nz, b->g[r].nx, b->nzp[r], b->nxp[r], b->ztop[r], b->g[r].nb,
+                     (float)b->g[r].dt, (float)b->g[r].v_max};
+        st = st ? st : balloc(b, &b->d_prep, (size_t)nreq);
+        st = st ? st : hip_ok(hipMemcpy(b->d_prep, pr.data(), nreq * sizeof(PrepReq), hipMemcpyHostToDevice));
+    }
+    if (st == FWI_OK && hipDeviceSynchronize() != hipSuccess) st = FWI_EHIP;
+    if (st) {
+        bfree(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FWI_OK;
+}
+
+int fwi_batch_destroy(fwi_batch* b) {
+    if (!b) return FWI_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    bfree(b);
+    delete b;
+    return FWI_OK;
+}
+
+int fwi_batch_get_info(const fwi_batch* b, int r, fwi_batch_request_info* info) {
+    if (!b || !info || r < 0 || r >= b->nreq) return FWI_EINVAL;
+    info->v_offset = (size_t)b->v_off[r];
+    info->wavelet_offset = (size_t)b->w_off[r];
+    info->trace_offset = (size_t)b->tr_off[r];
+    info->nzp = b->nzp[r];
+    info->nxp = b->nxp[r];
+    info->kind = b->kind[r];
+    if (b->kind[r] == 0) {
+        info->tile_x = kLdsVar[b->variant[r]].X;
+        info->tile_z = kLdsVar[b->variant[r]].P;
+    } else {
+        info->tile_x = kGlbVar[b->variant[r]].TX;
+        info->tile_z = kGlbVar[b->variant[r]].TZ;
+    }
+    info->tuned = b->tuned[r];
+    return FWI_OK;
+}
+
+int fwi_batch_sizes(const fwi_batch* b, size_t* v_elems, size_t* wavelet_elems, size_t* trace_elems) {
+    if (!b) return FWI_EINVAL;
+    if (v_elems) *v_elems = (size_t)b->v_total;
+    if (wavelet_elems) *wavelet_elems = (size_t)b->w_total;
+    if (trace_elems) *trace_elems = (size_t)b->tr_total;
+    return FWI_OK;
+}
+
+int fwi_batch_forward(fwi_batch* b, const float* v, const float* wavelets, float* traces, void* stream) {
+    if (!b || !v || !wavelets || !traces) return FWI_EINVAL;
+    (void)hipSetDevice(b->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const long long total = b->pt_total;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_batch_prep, dim3(blocks), dim3(256), 0, st, b->d_prep, b->nreq, total, v, b->K, b->flags);
+    if (hipGetLastError() != hipSuccess) return FWI_EHIP;
+    const int grid = std::min<int>(b->n_cu, (int)b->units.size());
+    return launch_units(b->d_units, (int)b->units.size(), b->counter, grid, b->lds_bytes, traces, wavelets, st);
+}
+
+int fwi_batch_status(fwi_batch* b) {
+    if (!b) return FWI_EINVAL;
+    (void)hipSetDevice(b->device);
+    if (hipDeviceSynchronize() != hipSuccess) return FWI_EHIP;
+    int flags = 0;
+    if (hipMemcpy(&flags, b->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return FWI_EHIP;
+    if (flags) {
+        (void)hipMemset(b->flags, 0, sizeof(int));
+        (void)hipDeviceSynchronize();
+        return FWI_EDEVICE;
+    }
+    return FWI_OK;
+}
+
+}  // extern "C"

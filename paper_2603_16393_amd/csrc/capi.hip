@@ -51,7 +51,7 @@ static void free_all(Plan& p) {
     p.device_bytes = 0;
 }
 
-static int validate_geometry(const fwi_geometry* g, int max_batch) {
+int validate_geometry(const fwi_geometry* g, int max_batch) {
     if (!g || max_batch < 1) return FWI_EINVAL;
     if (g->nz < 1 || g->nx < 1 || g->nt < 2 || g->nb < 0 || g->ns < 1 || g->nr < 1) return FWI_EINVAL;
     if (!(g->dz > 0) || !(g->dx > 0) || !(g->dt > 0) || !(g->v_max > 0)) return FWI_EINVAL;
@@ -71,6 +71,57 @@ static int validate_geometry(const fwi_geometry* g, int max_batch) {
     const long nxp = (long)g->nx + 2L * g->nb;
     if (nzp * nxp > (1L << 30)) return FWI_EINVAL;
     return FWI_OK;
+}
+
+void build_host_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, HostTables& t) {
+    // sponge: per axis the quadratic profile eta = 3 v_max ln(1/R)/(2 nb h) (delta/nb)^2,
+    // R = 1e-3, as the velocity-damping factor (1 - eta dt/2)/(1 + eta dt/2)
+    t.ax.assign(nxp, 1.f);
+    t.az.assign(nzp, 1.f);
+    t.wrow.assign(nzp, 1.f);
+    if (g.nb > 0) {
+        const double base = 3.0 * g.v_max * std::log(1e3) / (2.0 * g.nb);
+        auto factor = [&](int d, double h) {
+            const double r = (double)d / g.nb;
+            const double e = base * r * r / h * g.dt / 2.0;
+            return (float)((1.0 - e) / (1.0 + e));
+        };
+        for (int ix = 0; ix < nxp; ++ix) {
+            int d = 0;
+            if (ix < g.nb) d = g.nb - ix;
+            if (ix >= g.nb + g.nx) d = ix - (g.nb + g.nx - 1);
+            t.ax[ix] = d > 0 ? factor(d, g.dx) : 1.f;
+        }
+        for (int iz = 0; iz < nzp; ++iz) {
+            int d = 0;
+            if (iz >= ztop + g.nz) d = iz - (ztop + g.nz - 1);
+            if (!g.free_surface && iz < ztop) d = ztop - iz;
+            t.az[iz] = d > 0 ? factor(d, g.dz) : 1.f;
+        }
+    }
+    if (g.free_surface) t.wrow[0] = 0.5f;
+    const int ns = g.ns, nr = g.nr;
+    t.src_pt.resize(ns);
+    t.rec_pt.resize(nr);
+    t.rec_invw.resize(nr);
+    for (int s = 0; s < ns; ++s) t.src_pt[s] = (g.src_iz[s] + ztop) * nxp + g.src_ix[s] + g.nb;
+    t.rec_z0 = 1 << 30;
+    t.rec_z1 = -1;
+    t.one_row = true;
+    for (int r = 0; r < nr; ++r) {
+        const int z = g.rec_iz[r] + ztop;
+        t.rec_pt[r] = z * nxp + g.rec_ix[r] + g.nb;
+        t.rec_invw[r] = 1.0f / t.wrow[z];
+        t.rec_z0 = std::min(t.rec_z0, z);
+        t.rec_z1 = std::max(t.rec_z1, z);
+        t.one_row = t.one_row && g.rec_iz[r] == g.rec_iz[0];
+    }
+    t.rec_map.assign((size_t)nzp * nxp, -1);
+    for (int r = 0; r < nr; ++r) t.rec_map[t.rec_pt[r]] = r;
+    t.rec_row = t.one_row ? g.rec_iz[0] + ztop : -1;
+    t.rec_of_col.assign(nxp, -1);
+    if (t.one_row)
+        for (int r = 0; r < nr; ++r) t.rec_of_col[g.rec_ix[r] + g.nb] = r;
 }
 
 static int create(const fwi_geometry* geom, int max_batch, size_t budget, const fwi_plan_options* opt,
@@ -174,50 +225,22 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     }
 
     // host-side tables
-    // sponge: per axis the quadratic profile eta = 3 v_max ln(1/R)/(2 nb h) (delta/nb)^2,
-    // R = 1e-3, as the velocity-damping factor (1 - eta dt/2)/(1 + eta dt/2)
-    std::vector<float> axf(p.nxp, 1.f), azf(p.nzp, 1.f), wrow(p.nzp, 1.f);
-    if (p.g.nb > 0) {
-        const double base = 3.0 * p.g.v_max * std::log(1e3) / (2.0 * p.g.nb);
-        auto factor = [&](int d, double h) {
-            const double r = (double)d / p.g.nb;
-            const double e = base * r * r / h * p.g.dt / 2.0;
-            return (float)((1.0 - e) / (1.0 + e));
-        };
-        for (int ix = 0; ix < p.nxp; ++ix) {
-            int d = 0;
-            if (ix < p.g.nb) d = p.g.nb - ix;
-            if (ix >= p.g.nb + p.g.nx) d = ix - (p.g.nb + p.g.nx - 1);
-            axf[ix] = d > 0 ? factor(d, p.g.dx) : 1.f;
-        }
-        for (int iz = 0; iz < p.nzp; ++iz) {
-            int d = 0;
-            if (iz >= p.ztop + p.g.nz) d = iz - (p.ztop + p.g.nz - 1);
-            if (!p.g.free_surface && iz < p.ztop) d = p.ztop - iz;
-            azf[iz] = d > 0 ? factor(d, p.g.dz) : 1.f;
-        }
-    }
-    if (p.g.free_surface) wrow[0] = 0.5f;
-    std::vector<int> src_pt(ns), rec_pt(nr), rec_map;
-    std::vector<float> rec_invw(nr);
-    for (int s = 0; s < ns; ++s) src_pt[s] = (p.src_iz[s] + p.ztop) * p.nxp + p.src_ix[s] + p.g.nb;
-    p.rec_z0 = 1 << 30;
-    p.rec_z1 = -1;
-    for (int r = 0; r < nr; ++r) {
-        const int z = p.rec_iz[r] + p.ztop;
-        rec_pt[r] = z * p.nxp + p.rec_ix[r] + p.g.nb;
-        rec_invw[r] = 1.0f / wrow[z];
-        p.rec_z0 = std::min(p.rec_z0, z);
-        p.rec_z1 = std::max(p.rec_z1, z);
-    }
-    std::vector<int> rec_of_col;
+    HostTables ht;
+    build_host_tables(p.g, p.nzp, p.nxp, p.ztop, ht);
+    const std::vector<float>& axf = ht.ax;
+    const std::vector<float>& azf = ht.az;
+    const std::vector<float>& wrow = ht.wrow;
+    const std::vector<int>& src_pt = ht.src_pt;
+    const std::vector<int>& rec_pt = ht.rec_pt;
+    const std::vector<float>& rec_invw = ht.rec_invw;
+    p.rec_z0 = ht.rec_z0;
+    p.rec_z1 = ht.rec_z1;
+    std::vector<int> rec_of_col, rec_map;
     if (p.path == 1) {
-        rec_map.assign(npts, -1);
-        for (int r = 0; r < nr; ++r) rec_map[rec_pt[r]] = r;
+        rec_map = ht.rec_map;
     } else {
-        p.rec_row = p.rec_iz[0] + p.ztop;
-        rec_of_col.assign(p.nxp, -1);
-        for (int r = 0; r < nr; ++r) rec_of_col[p.rec_ix[r] + p.g.nb] = r;
+        p.rec_row = ht.rec_row;
+        rec_of_col = ht.rec_of_col;
     }
 
     // device allocations

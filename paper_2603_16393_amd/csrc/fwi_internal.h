@@ -158,6 +158,21 @@ struct Plan {
 
 void release_graphs(Plan& p);
 
+// Argument checks shared by plans and batches (FWI_OK, FWI_EINVAL or FWI_ECFL).
+int validate_geometry(const fwi_geometry* g, int max_batch);
+
+// Host tables of one geometry on its padded grid (ztop = rows of sponge above
+// the model): sponge factors per axis, row weights (1/2 on a reflecting top),
+// source and receiver points, receiver lookup by point and, when every
+// receiver shares one row, by column.
+struct HostTables {
+    std::vector<float> ax, az, wrow, rec_invw;
+    std::vector<int> src_pt, rec_pt, rec_map, rec_of_col;
+    int rec_z0 = 0, rec_z1 = -1, rec_row = -1;
+    bool one_row = true;
+};
+void build_host_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, HostTables& t);
+
 // Register-tile layout of the LDS-resident sweep for an nzp x nxp padded
 // field (false if the field does not fit in LDS).
 // req_X, req_P > 0 restrict the choice to that tile.

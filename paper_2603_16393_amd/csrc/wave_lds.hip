@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "fwi_internal.h"
+#include "wave_lds_body.h"
 
 namespace fwi {
 
@@ -30,204 +31,7 @@ template <int X, int P, bool ADJ, bool EXACT, bool STORE>
 __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float* __restrict__ ax_g,
                                                           const float* __restrict__ az_g) {
     extern __shared__ float lds[];
-    const int S = a.S;
-    const int R = a.nstrip * P + 8;
-    const int plane = R * S;
-    float* az_s = lds + 2 * plane;
-    const int field = blockIdx.x;
-    const int b = field / a.ns;
-    const int s = field - b * a.ns;
-    const int tid = threadIdx.x;
-    const int npts = a.npts;
-    const int nxp = a.nxp, nzp = a.nzp;
-    const int nsteps = a.nt - 1;
-
-    for (int i = tid; i < 2 * plane; i += blockDim.x) lds[i] = 0.f;
-    for (int i = tid; i < a.nstrip * P; i += blockDim.x) az_s[i] = (i < nzp) ? az_g[i] : 1.f;
-
-    const int cg = tid % a.ncg;
-    const int strip = tid / a.ncg;
-    const bool active = strip < a.nstrip;
-    const int x0 = cg * X;
-    const int z0 = strip * P;
-    const bool mirror_top = a.fs && z0 == 0;
-
-    // weights of the Laplacian with the grid spacings folded in
-    const float wz1 = FWI_W1 * a.idz2, wz2 = FWI_W2 * a.idz2, wz3 = FWI_W3 * a.idz2, wz4 = FWI_W4 * a.idz2;
-    const float wx1 = FWI_W1 * a.idx2, wx2 = FWI_W2 * a.idx2, wx3 = FWI_W3 * a.idx2, wx4 = FWI_W4 * a.idx2;
-
-    float Kr[P][X];
-    float wr[P][X];
-    float acc[P][X];
-    float axv[X];
-    int rr[X];
-    int src_j = -1, src_c = -1;  // tile position of this field's source, if this thread owns it
-    int rec_j = -1;              // tile row of the receiver row, if it crosses this tile
-    const float* Kb = a.K + (size_t)b * npts;
-#pragma unroll
-    for (int c = 0; c < X; ++c) {
-        const int x = x0 + c;
-        axv[c] = (active && x < nxp) ? ax_g[x] : 1.f;
-        rr[c] = -1;
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int z = z0 + j;
-            Kr[j][c] = (active && z < nzp && x < nxp) ? Kb[z * nxp + x] : 0.f;
-            wr[j][c] = 0.f;
-            acc[j][c] = 0.f;
-        }
-    }
-    if (active) {
-        const int sp = a.src_pt[s];
-        const int sz = sp / nxp, sx = sp - (sp / nxp) * nxp;
-        if (sx >= x0 && sx < x0 + X && sz >= z0 && sz < z0 + P) {
-            src_j = sz - z0;
-            src_c = sx - x0;
-        }
-        if (a.rec_row >= z0 && a.rec_row < z0 + P) {
-            rec_j = a.rec_row - z0;
-#pragma unroll
-            for (int c = 0; c < X; ++c) rr[c] = (x0 + c < nxp) ? a.rec_of_col[x0 + c] : -1;
-        }
-    }
-    const size_t trfield = (size_t)field * a.nr * a.nt;
-    if (!ADJ && rec_j >= 0) {
-#pragma unroll
-        for (int c = 0; c < X; ++c)
-            if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt] = 0.f;
-    }
-    float* Dfield = a.Dstore + (size_t)field * nsteps * npts;
-    float* Drow0 = Dfield + z0 * nxp + x0;  // this thread's tile corner in one D slice
-    __syncthreads();
-
-    float* cur = lds;          // u^n
-    float* nxt = lds + plane;  // receives u^{n+1}
-    for (int m = 0; m < nsteps; ++m) {
-        if (active) {
-            // D^{N-2-m} of the tile is requested first so its latency overlaps the LDS work
-            float dr[P][X];
-            if (ADJ) {
-                const float* Dr = Drow0 + (size_t)(nsteps - 1 - m) * npts;
-#pragma unroll
-                for (int j = 0; j < P; ++j)
-#pragma unroll
-                    for (int c = 0; c < X; ++c)
-                        dr[j][c] = (EXACT || (z0 + j < nzp && x0 + c < nxp)) ? Dr[j * nxp + c] : 0.f;
-            }
-            float win[P + 8][X];
-            const float* cb = cur + (z0 + 4) * S + x0 + 4;  // LDS cell of the tile corner
-#pragma unroll
-            for (int q = 0; q < P + 8; ++q) {
-                const float* rp = cb + (q - 4) * S;
-                if (q < 4 && mirror_top) rp = cb + (4 - q) * S;  // even mirror above a reflecting top
-#pragma unroll
-                for (int c = 0; c < X; ++c) win[q][c] = rp[c];
-            }
-            float* Dw = (!ADJ && STORE) ? Drow0 + (size_t)m * npts : nullptr;
-            float* nb_ = nxt + (z0 + 4) * S + x0 + 4;
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const float* rp = cb + j * S;
-                float xl[4], xh[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    xl[c] = rp[c - 4];
-                    xh[c] = rp[X + c];
-                }
-                const float azr = az_s[z0 + j];
-#pragma unroll
-                for (int c = 0; c < X; ++c) {
-                    // row neighbours x-4 .. x+4 of column c
-                    float xr[9];
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) {
-                        const int cc = c + k - 4;
-                        xr[k] = cc < 0 ? xl[cc + 4] : (cc >= X ? xh[cc - X] : win[j + 4][cc]);
-                    }
-                    const float u0 = win[j + 4][c];
-                    float D = wz1 * ((win[j + 3][c] - u0) + (win[j + 5][c] - u0));
-                    D = fmaf(wz2, (win[j + 2][c] - u0) + (win[j + 6][c] - u0), D);
-                    D = fmaf(wz3, (win[j + 1][c] - u0) + (win[j + 7][c] - u0), D);
-                    D = fmaf(wz4, (win[j][c] - u0) + (win[j + 8][c] - u0), D);
-                    D = fmaf(wx1, (xr[3] - u0) + (xr[5] - u0), D);
-                    D = fmaf(wx2, (xr[2] - u0) + (xr[6] - u0), D);
-                    D = fmaf(wx3, (xr[1] - u0) + (xr[7] - u0), D);
-                    D = fmaf(wx4, (xr[0] - u0) + (xr[8] - u0), D);
-                    const float wn = fmaf(Kr[j][c], D, (axv[c] * azr) * wr[j][c]);
-                    const float un = u0 + wn;
-                    wr[j][c] = wn;
-                    nb_[j * S + c] = un;
-                    if (STORE && !ADJ) {
-                        if (EXACT || (z0 + j < nzp && x0 + c < nxp)) Dw[j * nxp + c] = D;
-                    }
-                }
-            }
-            // point corrections of the owning threads
-            if (ADJ && rec_j >= 0) {
-                // adjoint sources a^{N-1-m}/w enter like the forward source: w += K inj
-#pragma unroll
-                for (int j = 0; j < P; ++j)
-                    if (j == rec_j) {
-#pragma unroll
-                        for (int c = 0; c < X; ++c)
-                            if (rr[c] >= 0) {
-                                const float dv = Kr[j][c] * a.adj[trfield + (size_t)rr[c] * a.nt + (nsteps - m)] *
-                                                 a.rec_invw;
-                                wr[j][c] += dv;
-                                nb_[j * S + c] += dv;
-                            }
-                    }
-            }
-            if (ADJ) {
-                // imaging: psi^{N-1-m} (read back from this thread's own LDS writes) times
-                // D^{N-2-m}, whose loads were issued at the top of the step
-#pragma unroll
-                for (int j = 0; j < P; ++j)
-#pragma unroll
-                    for (int c = 0; c < X; ++c) acc[j][c] = fmaf(nb_[j * S + c], dr[j][c], acc[j][c]);
-            }
-            if (src_j >= 0) {
-                if (!ADJ) {
-                    const float sv = a.wavelet[m] * a.src_scale;
-#pragma unroll
-                    for (int j = 0; j < P; ++j)
-#pragma unroll
-                        for (int c = 0; c < X; ++c)
-                            if (j == src_j && c == src_c) {
-                                const float dv = Kr[j][c] * sv;
-                                wr[j][c] += dv;
-                                nb_[j * S + c] += dv;
-                            }
-                } else {
-                    // the source's share of D^{N-2-m}: acc += psi^{N-1-m} s^{N-2-m}
-                    const float sv = a.wavelet[nsteps - 1 - m] * a.src_scale;
-#pragma unroll
-                    for (int j = 0; j < P; ++j)
-#pragma unroll
-                        for (int c = 0; c < X; ++c)
-                            if (j == src_j && c == src_c) acc[j][c] = fmaf(nb_[j * S + c], sv, acc[j][c]);
-                }
-            }
-            if (!ADJ && rec_j >= 0) {
-#pragma unroll
-                for (int c = 0; c < X; ++c)
-                    if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt + m + 1] = nb_[rec_j * S + c];
-            }
-        }
-        __syncthreads();
-        float* t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    if (ADJ && active) {
-#pragma unroll
-        for (int j = 0; j < P; ++j)
-#pragma unroll
-            for (int c = 0; c < X; ++c) {
-                const int z = z0 + j, x = x0 + c;
-                if (z < nzp && x < nxp) a.gpad[(size_t)field * npts + z * nxp + x] = acc[j][c];
-            }
-    }
+    lds_field<X, P, ADJ, EXACT, STORE>(a, blockIdx.x, ax_g, az_g, lds);
 }
 
 // Instantiated tiles (X columns, P rows).  (3, 11) tiles the 110 x 150 padded

@@ -1,0 +1,136 @@
+"""Uneven batches in one persistent launch (fwi_batch_*) vs the FP64 oracle
+and vs the per-geometry plan, through the C ABI.
+
+Bars: seismograms relative L2 <= 1e-4 against the oracle (the FP32-stencil
+target); against the plan's own sweep for the same geometry the arithmetic
+per point is the same, so traces must agree bitwise (LDS-resident units vs
+the LDS path, HBM-swept units vs the tiled path).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import fwi_inputs as fi
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / np.linalg.norm(b))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def _small_requests():
+    """Five requests: LDS-resident sizes, a buried receiver row, receivers on two
+    rows (swept from HBM), a grid too large for the LDS, a sponge on top."""
+    reqs = []
+    a0 = fi.surface_acquisition(24, 30, ns=2, nt=300, nb=8)
+    reqs.append((a0, fi.faulted_model(24, 30, 1)))
+    a1 = fi.surface_acquisition(40, 40, ns=3, nt=257, nb=10, rec_row=5)
+    reqs.append((a1, fi.layered_model(40, 40, 2, depth_range=(5, 35))))
+    a2 = fi.surface_acquisition(30, 36, ns=2, nt=211, nb=6)
+    a2 = dataclasses.replace(a2, rec_iz=np.where(np.arange(a2.nr) % 2 == 0, 0, 3).astype(np.int32))
+    reqs.append((a2, fi.faulted_model(30, 36, 3)))
+    a3 = fi.surface_acquisition(100, 120, ns=2, nt=180, nb=20)
+    reqs.append((a3, fi.faulted_model(100, 120, 4)))
+    a4 = fi.surface_acquisition(20, 26, ns=1, nt=150, nb=8, free_surface=False, src_row=3, rec_row=2)
+    reqs.append((a4, fi.layered_model(20, 26, 5, depth_range=(4, 16))))
+    return [(a, v, fi.ricker(a.nt, a.dt, a.f_peak)) for a, v in reqs]
+
+
+@pytest.mark.parametrize("autotune", [True, False])
+def test_small_uneven_batch_vs_oracle_and_plans(dev, autotune):
+    import oracle
+    from paper_2603_16393_amd import FwiPlan
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = _small_requests()
+    b = FwiBatch([a for a, _, _ in reqs], autotune=autotune, device=dev)
+    kinds = [i["kind"] for i in b.info]
+    _say(f"kinds {kinds} tiles {[(i['tile_x'], i['tile_z'], i['tuned']) for i in b.info]}")
+    assert kinds[0] == 0 and kinds[1] == 0 and kinds[2] == 1 and kinds[3] == 1
+    v = b.pack_velocity([m for _, m, _ in reqs])
+    w = b.pack_wavelets([x for _, _, x in reqs])
+    tr = b.forward(v, w)
+    tr2 = b.forward(v, w)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    assert torch.equal(tr, tr2)
+    for r, (a, m, wav) in enumerate(reqs):
+        got = b.traces_of(tr, r).cpu().numpy()
+        ref = oracle.forward(a, np.asarray(m, np.float32).astype(np.float64),
+                             np.asarray(wav, np.float32).astype(np.float64))
+        err = _rel(got, ref)
+        _say(f"request {r} kind {kinds[r]}: traces rel L2 vs oracle {err:.2e}")
+        assert err <= 1e-4
+        assert np.all(got[:, :, 0] == 0.0)
+        plan = FwiPlan(a, max_batch=1, device=dev, force_path=-1 if kinds[r] == 0 else 1)
+        assert plan.info["path"] == kinds[r]
+        d = plan.forward(torch.tensor(np.asarray(m, np.float32)[None], device=dev),
+                         torch.tensor(np.asarray(wav, np.float32), device=dev), keep_for_adjoint=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(d[0].cpu().numpy(), got), f"request {r}: batch and plan sweeps differ"
+        plan.close()
+    b.close()
+
+
+def test_invalid_velocity_flag(dev):
+    from paper_2603_16393_amd import _lib
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = _small_requests()[:2]
+    b = FwiBatch([a for a, _, _ in reqs], autotune=False, device=dev)
+    models = [m.copy() for _, m, _ in reqs]
+    models[1][3, 4] = 5000.0  # above v_max
+    b.forward(b.pack_velocity(models), b.pack_wavelets([x for _, _, x in reqs]))
+    assert b.status() == _lib.FWI_EDEVICE
+    assert b.status() == 0
+    b.close()
+
+
+def test_uneven_64_requests_sampled_vs_oracle(dev):
+    """The 64-request mixed batch (70/140/256 grids, 1000/1500/2500 steps,
+    5-10 shots) in the launch configuration the benchmark times; one shot of
+    one request per size class checked against the oracle."""
+    import oracle
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = fi.uneven_requests()
+    b = FwiBatch([a for a, _, _ in reqs], autotune=True, device=dev)
+    v = b.pack_velocity([m for _, m, _ in reqs])
+    w = b.pack_wavelets([x for _, _, x in reqs])
+    tr = b.forward(v, w)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    assert bool(torch.isfinite(tr).all())
+    seen = set()
+    for r, (a, m, wav) in enumerate(reqs):
+        if a.nz in seen:
+            continue
+        seen.add(a.nz)
+        s = a.ns - 1
+        sub = a.subset_shots([s])
+        ref = oracle.forward(sub, np.asarray(m, np.float32).astype(np.float64),
+                             np.asarray(wav, np.float32).astype(np.float64))[0]
+        got = b.traces_of(tr, r)[s].cpu().numpy()
+        err = _rel(got, ref)
+        _say(f"request {r} ({a.nz}x{a.nx}, nt {a.nt}, shot {s}/{a.ns}, kind {b.info[r]['kind']}): rel L2 {err:.2e}")
+        assert err <= 1e-4
+    assert seen == {70, 140, 256}
+    b.close()
