@@ -179,6 +179,79 @@ def surrogate_guidance(plan, wt, v_true):
     return res
 
 
+def bench_uneven(args):
+    """64 requests (seeds 2000 + r): 70x70 / 140x140 / 256x256 grids with a 40-cell sponge, 1000 / 1500 / 2500
+    samples at dt = 1 ms, 5-10 surface shots, faulted or layered models in 1500-4500 m/s; forward modelling of
+    every (request, shot) field in one persistent launch with autotuned tiles.  Per-size rates come from
+    launches of the same kernel over each size class alone."""
+    import torch
+
+    import fwi_inputs as fi
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    reqs = fi.uneven_requests()
+
+    def run(sel, reps):
+        t0 = time.perf_counter()
+        b = FwiBatch([reqs[r][0] for r in sel], autotune=True, device=dev)
+        t_create = time.perf_counter() - t0
+        v = b.pack_velocity([reqs[r][1] for r in sel])
+        w = b.pack_wavelets([reqs[r][2] for r in sel])
+        tr = b.forward(v, w)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.forward(v, w, out=tr)
+        e1.record()
+        torch.cuda.synchronize()
+        if b.status() != 0:
+            print("device-side check failed", file=sys.stderr)
+            sys.exit(1)
+        ms = e0.elapsed_time(e1) / reps
+        upd = sum(reqs[r][0].ns * (reqs[r][0].nt - 1) * (reqs[r][0].nz + reqs[r][0].nb) *
+                  (reqs[r][0].nx + 2 * reqs[r][0].nb) for r in sel)
+        tiles = sorted({(b.info[i]["nzp"], b.info[i]["nxp"], b.info[i]["kind"], b.info[i]["tile_x"],
+                         b.info[i]["tile_z"]) for i in range(len(sel))})
+        b.close()
+        return ms, upd, t_create, tiles
+
+    reps = max(1, args.steps)
+    ms, upd, t_create, tiles = run(list(range(len(reqs))), reps)
+    gpts = upd / (ms / 1e3) / 1e9
+    per_size = {}
+    for size in (70, 140, 256):
+        sel = [r for r in range(len(reqs)) if reqs[r][0].nz == size]
+        m2, u2, _, _ = run(sel, reps)
+        g2 = u2 / (m2 / 1e3) / 1e9
+        per_size[f"{size}x{size}"] = {"requests": len(sel), "units": sum(reqs[r][0].ns for r in sel),
+                                      "ms": round(m2, 3), "gpts_per_s": round(g2, 1),
+                                      "hbm_frac_alg": round(16.0 * g2 / HBM_PEAK_GBS, 4)}
+    out = {
+        "metric": "uneven batch forward GPts/s (64 requests, 70/140/256 grids, 1000-2500 steps)",
+        "value": round(gpts, 1),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 1,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "uneven batch: 64 requests (seeds 2000+r), 461 (request, shot) fields, "
+                               f"{upd / 1e9:.2f} G point-updates per launch, one persistent launch"},
+        "per_size": per_size,
+        "hbm_frac_alg": round(16.0 * gpts / HBM_PEAK_GBS, 4),
+        "tiles": [{"padded": [t[0], t[1]], "kind": "lds" if t[2] == 0 else "hbm", "tile": [t[3], t[4]]} for t in tiles],
+        "create_s": round(t_create, 3),
+    }
+    print(json.dumps(out))
+
+
 def bench_checkpointed(args):
     """Adjoint with checkpointing: 400 x 800 model (dx = 10 m) with a 50-cell sponge, 20 surface shots x 800
     receivers, 4000 samples at dt = 0.8 ms, 10 Hz Ricker, smooth-plus-layered model with a high-velocity lens
@@ -241,7 +314,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the library's plain copy kernel on 512 MiB three times "
                          "(the reference dispatch for HBM traffic counters) and exit")
-    ap.add_argument("--workload", choices=["guidance", "checkpointed"], default="guidance")
+    ap.add_argument("--workload", choices=["guidance", "checkpointed", "uneven"], default="guidance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
@@ -249,6 +322,9 @@ def main():
         sys.exit(2)
     if args.workload == "checkpointed":
         bench_checkpointed(args)
+        return
+    if args.workload == "uneven":
+        bench_uneven(args)
         return
 
     import torch
