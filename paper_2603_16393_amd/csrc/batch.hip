@@ -9,9 +9,9 @@
 //  * fields whose padded grid fits the LDS run the register-tiled LDS-resident
 //    time loop (wave_lds_body.h) with this request's tile;
 //  * larger fields keep (u^n, u^{n+1}, w) in HBM (the unit's own arrays, hot in
-//    L2 / MALL) and sweep them tile by tile each step, staging each tile of u
-//    plus its 4-cell halo in LDS.
-// The tile of each size class (LDS register tile or HBM sweep tile) comes from
+//    L2 / MALL) and stream them column panel by column panel each step
+//    (glb_field_forward).
+// The tile of each size class (LDS register tile or HBM prefetch depth) comes from
 // the autotuner below, which times the candidates on a short sweep of the
 // class's first unit replicated over every compute unit.
 #include <algorithm>
@@ -30,8 +30,8 @@ namespace fwi {
 //   LDS-resident register tiles (X, P, exact cover of the padded grid)
 #define FWI_BATCH_LDS(M) M(0, 3, 11, true) M(1, 3, 11, false) M(2, 3, 12, false) M(3, 2, 12, false) M(4, 4, 8, false) M(5, 1, 16, false)
 constexpr int kBatchLdsVariants = 6;
-//   HBM sweep tiles (TX columns, TZ rows)
-#define FWI_BATCH_GLB(M) M(0, 64, 16) M(1, 64, 32) M(2, 64, 64) M(3, 128, 16) M(4, 128, 32)
+//   HBM sweeps (RB rows loaded ahead per block, SMUL x the minimal row segments per column group)
+#define FWI_BATCH_GLB(M) M(0, 2, 1) M(1, 4, 1) M(2, 8, 1) M(3, 4, 2) M(4, 8, 2)
 constexpr int kBatchGlbVariants = 5;
 
 struct BatchUnit {
@@ -54,91 +54,168 @@ struct BatchUnit {
     const float* az;
 };
 
-template <int TX, int TZ>
-__device__ void glb_field_forward(const BatchUnit& U, float* lds) {
-    constexpr int SS = TX + 8;
-    constexpr int NRG = kLdsThreads / TX;  // row groups
-    constexpr int RZ = TZ / NRG;            // rows per thread
-    static_assert(TZ % NRG == 0, "tile rows must split over the row groups");
-    const int tid = threadIdx.x;
-    const int tx = tid % TX, tr = tid / TX;
-    const int nzp = U.nzp, nxp = U.nxp;
+// HBM-swept field: wave w of the workgroup owns 64-column panels (column
+// group, row segment) and walks down each panel's rows.  Each lane keeps the
+// 9-row window of u^n of its column in registers (rolled as it walks), takes
+// its 8 x-neighbours from the wave's own row buffer in LDS (the panel's 64
+// columns plus 4 halo columns on each side), and issues the loads of the next
+// RB rows (u, K, w, halo) before computing the current ones, so the latency
+// of HBM / MALL overlaps the arithmetic.  One workgroup barrier per time step
+// separates u^n (read) from u^{n+1} (written).
+template <int RB, int SMUL>
+__device__ void glb_field_forward(const BatchUnit& Ug, float* lds) {
+    constexpr int NW = kLdsThreads / 64;
+    // descriptor fields in registers: stores to the field arrays may not be
+    // assumed to leave a descriptor in global memory unchanged
+    const int nzp = Ug.nzp, nxp = Ug.nxp, nsteps = Ug.nsteps, nt = Ug.nt, nr = Ug.nr, fs = Ug.fs;
+    const int src_pt = Ug.src_pt, rec_z0 = Ug.rec_z0, rec_z1 = Ug.rec_z1;
+    const float idz2 = Ug.idz2, idx2 = Ug.idx2, src_scale = Ug.src_scale;
+    const float* __restrict__ K = Ug.K;
+    const float* __restrict__ wavelet = Ug.wavelet;
+    const int* __restrict__ rec_map = Ug.rec_map;
+    const float* __restrict__ ax = Ug.ax;
+    const float* __restrict__ az = Ug.az;
+    float* ua = Ug.ua;
+    float* ub = Ug.ub;
+    float* __restrict__ wst = Ug.w;
+    float* __restrict__ traces = Ug.traces;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wave index is uniform across the wave: made explicit so that panel
+    // rows, bounds and clamps derived from it are scalar (SALU) arithmetic
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int npts = nzp * nxp;
     for (int i = tid; i < npts; i += kLdsThreads) {
-        U.ua[i] = 0.f;
-        U.w[i] = 0.f;
+        ua[i] = 0.f;
+        wst[i] = 0.f;
     }
-    for (int r = tid; r < U.nr; r += kLdsThreads) U.traces[(size_t)r * U.nt] = 0.f;
+    for (int r = tid; r < nr; r += kLdsThreads) traces[(size_t)r * nt] = 0.f;
     __syncthreads();
-    const int ntx = (nxp + TX - 1) / TX, ntz = (nzp + TZ - 1) / TZ;
-    const float* cur = U.ua;
-    float* nxt = U.ub;
-    for (int m = 0; m < U.nsteps; ++m) {
-        for (int tzi = 0; tzi < ntz; ++tzi) {
-            const int zt = tzi * TZ;
-            const bool rec_rows = (zt + TZ > U.rec_z0) && (zt <= U.rec_z1);
-            for (int txi = 0; txi < ntx; ++txi) {
-                const int x0 = txi * TX;
-                for (int i = tid; i < (TZ + 8) * SS; i += kLdsThreads) {
-                    const int r = i / SS, c = i - (i / SS) * SS;
-                    int gz = zt + r - 4;
-                    const int gx = x0 + c - 4;
-                    if (U.fs && gz < 0) gz = -gz;  // even mirror above a reflecting top
-                    lds[i] = (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) ? cur[gz * nxp + gx] : 0.f;
-                }
-                __syncthreads();
-                const int gx = x0 + tx;
-                if (gx < nxp) {
-                    const float axv = U.ax[gx];
+    const int G = (nxp + 63) / 64;
+    int S = 1;
+    while ((G * S) % NW != 0) ++S;  // panels a multiple of the wave count (S <= NW)
+    S *= SMUL;
+    const int seg = (nzp + S - 1) / S;
+    float* rb = lds + wave * 72;
+    const float* cur = ua;
+    float* nxt = ub;
+    for (int m = 0; m < nsteps; ++m) {
+        for (int pan = wave; pan < G * S; pan += NW) {
+            const int g = pan % G, sg = pan / G;
+            const int x0 = g * 64, x = x0 + lane;
+            const int za = sg * seg, zb = min(nzp, za + seg);
+            if (za >= zb) continue;
+            const bool xin = x < nxp;
+            const float axv = xin ? ax[x] : 0.f;
+            const int hx = lane < 4 ? x0 - 4 + lane : x0 + 64 + (lane - 4);  // halo column of lanes 0..7
+            const bool hin = lane < 8 && hx >= 0 && hx < nxp;
+            auto ld_u = [&](int z) {
+                const int zz = (fs && z < 0) ? -z : z;  // even mirror above a reflecting top
+                return (xin && zz >= 0 && zz < nzp) ? cur[zz * nxp + x] : 0.f;
+            };
+            auto ld_h = [&](int z) { return (hin && z >= 0 && z < nzp) ? cur[z * nxp + hx] : 0.f; };
+            float col[RB + 8];
 #pragma unroll
-                    for (int j = 0; j < RZ; ++j) {
-                        const int lz = tr * RZ + j;
-                        const int gz = zt + lz;
-                        if (gz < nzp) {
-                            const int p = gz * nxp + gx;
-                            const int li = (lz + 4) * SS + tx + 4;
-                            const float c = lds[li];
-                            const float lzs = FWI_LAPD(c, lds[li - 4 * SS], lds[li - 3 * SS], lds[li - 2 * SS],
-                                                       lds[li - SS], lds[li + SS], lds[li + 2 * SS], lds[li + 3 * SS],
-                                                       lds[li + 4 * SS]);
-                            const float lxs = FWI_LAPD(c, lds[li - 4], lds[li - 3], lds[li - 2], lds[li - 1],
-                                                       lds[li + 1], lds[li + 2], lds[li + 3], lds[li + 4]);
-                            float D = lzs * U.idz2 + lxs * U.idx2;
-                            if (p == U.src_pt) D += U.wavelet[m] * U.src_scale;
-                            const float wn = fmaf(U.K[p], D, (axv * U.az[gz]) * U.w[p]);
-                            const float un = c + wn;
-                            U.w[p] = wn;
-                            nxt[p] = un;
-                            if (rec_rows) {
-                                const int r = U.rec_map[p];
-                                if (r >= 0) U.traces[(size_t)r * U.nt + m + 1] = un;
-                            }
+            for (int k = 0; k < 8; ++k) col[k] = ld_u(za - 4 + k);
+            float cu[RB], ck[RB], cw[RB], chl[RB];
+#pragma unroll
+            for (int jj = 0; jj < RB; ++jj) {
+                const int z = za + jj;
+                const bool ok = xin && z < zb;
+                cu[jj] = ld_u(z + 4);
+                ck[jj] = ok ? K[z * nxp + x] : 0.f;
+                cw[jj] = ok ? wst[z * nxp + x] : 0.f;
+                chl[jj] = (z < zb) ? ld_h(z) : 0.f;
+            }
+            for (int z0 = za; z0 < zb; z0 += RB) {
+                float nu[RB], nk[RB], nw[RB], nh[RB];
+                const int z1 = z0 + RB;
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {  // the next block's loads go out first
+                    const int z = z1 + jj;
+                    const bool ok = xin && z < zb;
+                    nu[jj] = (z1 < zb) ? ld_u(z + 4) : 0.f;
+                    nk[jj] = ok ? K[z * nxp + x] : 0.f;
+                    nw[jj] = ok ? wst[z * nxp + x] : 0.f;
+                    nh[jj] = (z < zb) ? ld_h(z) : 0.f;
+                }
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) col[8 + jj] = cu[jj];
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {
+                    const int z = z0 + jj;
+                    if (z >= zb) break;
+                    const float c = col[jj + 4];
+                    rb[lane + 4] = c;
+                    if (lane < 8) rb[lane < 4 ? lane : 64 + lane] = chl[jj];
+                    __builtin_amdgcn_wave_barrier();
+                    float xr[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) xr[k] = rb[lane + k];
+                    __builtin_amdgcn_wave_barrier();
+                    const float lzs = FWI_LAPD(c, col[jj], col[jj + 1], col[jj + 2], col[jj + 3], col[jj + 5],
+                                               col[jj + 6], col[jj + 7], col[jj + 8]);
+                    const float lxs = FWI_LAPD(c, xr[0], xr[1], xr[2], xr[3], xr[5], xr[6], xr[7], xr[8]);
+                    float D = fmaf(lzs, idz2, lxs * idx2);
+                    const int p = z * nxp + x;
+                    if (xin) {
+                        if (p == src_pt) D = fmaf(wavelet[m], src_scale, D);
+                        const float wn = fmaf(ck[jj], D, (axv * az[z]) * cw[jj]);
+                        const float un = c + wn;
+                        wst[p] = wn;
+                        nxt[p] = un;
+                        if (z >= rec_z0 && z <= rec_z1) {
+                            const int r = rec_map[p];
+                            if (r >= 0) traces[(size_t)r * nt + m + 1] = un;
                         }
                     }
                 }
-                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 8; ++k) col[k] = col[RB + k];
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {
+                    cu[jj] = nu[jj];
+                    ck[jj] = nk[jj];
+                    cw[jj] = nw[jj];
+                    chl[jj] = nh[jj];
+                }
             }
         }
+        __syncthreads();
         float* t = const_cast<float*>(cur);
         cur = nxt;
         nxt = t;
     }
 }
 
-__device__ void run_unit_forward(const BatchUnit& U, float* lds) {
-    if (U.kind == 0) {
-#define FWI_LDS_CASE(ID, XX, PP, EX) \
-    if (U.variant == ID) {           \
-        lds_field<XX, PP, false, EX, false>(U.la, 0, U.ax, U.az, lds); \
-        return;                      \
+// One non-inlined entry per compiled variant: each gets its own register
+// allocation (the persistent kernel needs only the largest, not their sum);
+// the call happens once per unit.
+template <int X, int P, bool EX>
+__device__ __noinline__ void unit_lds_forward(const BatchUnit* __restrict__ U, float* lds) {
+    const LdsArgs a = U->la;
+    lds_field<X, P, false, EX, false>(a, 0, U->ax, U->az, lds);
+}
+
+template <int RB, int SM>
+__device__ __noinline__ void unit_glb_forward(const BatchUnit* __restrict__ U, float* lds) {
+    glb_field_forward<RB, SM>(*U, lds);
+}
+
+__device__ void run_unit_forward(const BatchUnit* U, float* lds) {
+    const int kind = U->kind, variant = U->variant;
+    if (kind == 0) {
+#define FWI_LDS_CASE(ID, XX, PP, EX)                 \
+    if (variant == ID) {                             \
+        unit_lds_forward<XX, PP, EX>(U, lds);        \
+        return;                                      \
     }
         FWI_BATCH_LDS(FWI_LDS_CASE)
 #undef FWI_LDS_CASE
     } else {
-#define FWI_GLB_CASE(ID, TXX, TZZ) \
-    if (U.variant == ID) {         \
-        glb_field_forward<TXX, TZZ>(U, lds); \
-        return;                    \
+#define FWI_GLB_CASE(ID, RBB, SM)                    \
+    if (variant == ID) {                             \
+        unit_glb_forward<RBB, SM>(U, lds);           \
+        return;                                      \
     }
         FWI_BATCH_GLB(FWI_GLB_CASE)
 #undef FWI_GLB_CASE
@@ -155,7 +232,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_batch_forward(const BatchUnit* 
         const int u = __builtin_amdgcn_readfirstlane(next);  // uniform: descriptor fields load as scalars
         __syncthreads();
         if (u >= nunits) break;  // every workgroup leaves once the queue is drained
-        run_unit_forward(units[u], lds);
+        run_unit_forward(units + u, lds);
         __syncthreads();
     }
 }
@@ -258,15 +335,16 @@ const LdsVar kLdsVar[kBatchLdsVariants] = {
 #undef FWI_V
 };
 struct GlbVar {
-    int TX, TZ;
+    int RB, SMUL;
 };
 const GlbVar kGlbVar[kBatchGlbVariants] = {
-#define FWI_V(ID, TXX, TZZ) {TXX, TZZ},
+#define FWI_V(ID, RBB, SM) {RBB, SM},
     FWI_BATCH_GLB(FWI_V)
 #undef FWI_V
 };
 
-size_t glb_lds(int v) { return (size_t)(kGlbVar[v].TZ + 8) * (kGlbVar[v].TX + 8) * sizeof(float); }
+// one 72-float row buffer per wave
+size_t glb_lds(int, int) { return (size_t)(kLdsThreads / 64) * 72 * sizeof(float); }
 
 bool lds_var_fits(int v, int nzp, int nxp, int* ncg, int* nstrip) {
     const LdsVar& L = kLdsVar[v];
@@ -295,7 +373,7 @@ int launch_units(BatchUnit* d_units, int nunits, int* counter, int grid, size_t 
                  const float* wavelets, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_bind, dim3((nunits + 255) / 256), dim3(256), 0, st, d_units, nunits, traces, wavelets);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-    hipFuncSetAttribute((const void*)k_batch_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_batch_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_batch_forward, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
     return hip_ok(hipGetLastError());
 }
@@ -492,9 +570,9 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                     lds_var_fits(v, nzp, nxp, &ncg, &nstrip);
                     c = (double)ncg * L.X * nstrip * L.P * ((L.P + 8.0) / L.P + 8.0 / L.X + 1.0);
                 } else {
+                    // deeper prefetch first, then fewer panel restarts (8 extra rows each)
                     const GlbVar& G = kGlbVar[v];
-                    c = (double)((nxp + G.TX - 1) / G.TX * G.TX) * ((nzp + G.TZ - 1) / G.TZ * G.TZ) *
-                        (1.0 + 8.0 / G.TZ + 8.0 / G.TX);
+                    c = 1.0 / G.RB + 0.01 * G.SMUL;
                 }
                 if (c < bc) {
                     bc = c;
@@ -543,7 +621,7 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                                   stt + (b->kind[r] == 1 ? (size_t)c * 3 * npts : 0), tune_steps);
             st = hip_ok(hipMemcpy(du, hu.data(), copies * sizeof(BatchUnit), hipMemcpyHostToDevice));
             const size_t lb =
-                b->kind[r] == 0 ? lds_bytes(kLdsVar[v].X, kLdsVar[v].P, hu[0].la.ncg, hu[0].la.nstrip) : glb_lds(v);
+                b->kind[r] == 0 ? lds_bytes(kLdsVar[v].X, kLdsVar[v].P, hu[0].la.ncg, hu[0].la.nstrip) : glb_lds(v, nzp);
             for (int rep = 0; rep < 2 && st == FWI_OK; ++rep) {  // first run warms up
                 st = hip_ok(hipEventRecord(e0, nullptr));
                 st = st ? st : launch_units(du, copies, b->counter, copies, lb, trt, wt, nullptr);
@@ -596,7 +674,7 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                                     tr_off, sp, b->g[r].nt - 1);
             b->units.push_back(U);
             b->unit_req.push_back(r);
-            const size_t lb = b->kind[r] == 0 ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip) : glb_lds(U.variant);
+            const size_t lb = b->kind[r] == 0 ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip) : glb_lds(U.variant, U.nzp);
             b->lds_bytes = std::max(b->lds_bytes, lb);
         }
         st = st ? st : balloc(b, &b->d_units, b->units.size());
@@ -641,8 +719,8 @@ int fwi_batch_get_info(const fwi_batch* b, int r, fwi_batch_request_info* info) 
         info->tile_x = kLdsVar[b->variant[r]].X;
         info->tile_z = kLdsVar[b->variant[r]].P;
     } else {
-        info->tile_x = kGlbVar[b->variant[r]].TX;
-        info->tile_z = kGlbVar[b->variant[r]].TZ;
+        info->tile_x = 64;
+        info->tile_z = kGlbVar[b->variant[r]].RB;
     }
     info->tuned = b->tuned[r];
     return FWI_OK;

@@ -21,10 +21,13 @@ namespace fwi {
 // 8th-order second difference of a 9-point window in difference form:
 // sum_k W_k [(u(+k) - u) + (u(-k) - u)].  Neighbouring values of a resolved
 // field are close, so each difference is (nearly) exact and the sum carries
-// no cancellation of the size of u.
-#define FWI_LAPD(c, m4, m3, m2, m1, p1, p2, p3, p4)                                     \
-    (FWI_W1 * (((m1) - (c)) + ((p1) - (c))) + FWI_W2 * (((m2) - (c)) + ((p2) - (c))) + \
-     FWI_W3 * (((m3) - (c)) + ((p3) - (c))) + FWI_W4 * (((m4) - (c)) + ((p4) - (c))))
+// no cancellation of the size of u.  The fused multiply-adds are written out
+// so every kernel using it rounds identically, accumulating from the smallest
+// weight to the largest.
+#define FWI_LAPD(c, m4, m3, m2, m1, p1, p2, p3, p4)                                \
+    fmaf(FWI_W1, ((m1) - (c)) + ((p1) - (c)),                                      \
+         fmaf(FWI_W2, ((m2) - (c)) + ((p2) - (c)),                                 \
+              fmaf(FWI_W3, ((m3) - (c)) + ((p3) - (c)), FWI_W4 * (((m4) - (c)) + ((p4) - (c))))))
 
 // Largest LDS allocation of one workgroup on gfx950.
 constexpr int kLdsBytes = 160 * 1024;

@@ -107,10 +107,10 @@ __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const floa
                                    tile[li + SS], tile[li + 2 * SS], tile[li + 3 * SS], tile[li + 4 * SS]);
         const float lxs = FWI_LAPD(c, tile[li - 4], tile[li - 3], tile[li - 2], tile[li - 1], tile[li + 1],
                                    tile[li + 2], tile[li + 3], tile[li + 4]);
-        float D = lzs * a.idz2 + lxs * a.idx2;
+        float D = fmaf(lzs, a.idz2, lxs * a.idx2);
         int r = -1;
         if (check_rec) r = a.rec_map[p];
-        if (!ADJ && p == sp) D += a.wavelet[m] * a.src_scale;
+        if (!ADJ && p == sp) D = fmaf(a.wavelet[m], a.src_scale, D);
         if (ADJ && r >= 0) D += a.rec_invw[r] * a.adj[((size_t)field * a.nr + r) * a.nt + (a.nt - 1 - m)];
         const float Kp = a.K[(size_t)b * a.npts + p];
         const float wn = fmaf(Kp, D, (axv * az_g[gz]) * wg[p]);

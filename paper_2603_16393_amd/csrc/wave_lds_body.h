@@ -10,7 +10,7 @@
 namespace fwi {
 
 template <int X, int P, bool ADJ, bool EXACT, bool STORE>
-__device__ __forceinline__ void lds_field(const LdsArgs& a, const int field, const float* __restrict__ ax_g,
+__device__ __forceinline__ void lds_field(const LdsArgs a, const int field, const float* __restrict__ ax_g,
                                           const float* __restrict__ az_g, float* lds) {
     const int S = a.S;
     const int R = a.nstrip * P + 8;
