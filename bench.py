@@ -69,7 +69,8 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
 # HBM bytes per sweep launch of the default workload from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by the same counters' reading for the library's plain copy kernel (profiles/
 # k_wave_lds_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
-TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/fwi_internal.h")
+TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
+                   "paper_2603_16393_amd/csrc/fwi_internal.h")
 TRAFFIC_SHA1 = "0aa2e863ef1181a1e12ba6f87ef4b029931a7c02"
 TRAFFIC_BYTES = {"forward": 5304064184.0, "adjoint": 5308392439.0}
 
