@@ -24,10 +24,13 @@ namespace fwi {
 // no cancellation of the size of u.  The fused multiply-adds are written out
 // so every kernel using it rounds identically, accumulating from the smallest
 // weight to the largest.
+// Each pair is written (u(+k) - u) - (u - u(-k)), equal bit for bit to
+// (u(-k) - u) + (u(+k) - u), so that a kernel sweeping along an axis can
+// share the first difference of one point with the point k cells further on.
 #define FWI_LAPD(c, m4, m3, m2, m1, p1, p2, p3, p4)                                \
-    fmaf(FWI_W1, ((m1) - (c)) + ((p1) - (c)),                                      \
-         fmaf(FWI_W2, ((m2) - (c)) + ((p2) - (c)),                                 \
-              fmaf(FWI_W3, ((m3) - (c)) + ((p3) - (c)), FWI_W4 * (((m4) - (c)) + ((p4) - (c))))))
+    fmaf(FWI_W1, ((p1) - (c)) - ((c) - (m1)),                                      \
+         fmaf(FWI_W2, ((p2) - (c)) - ((c) - (m2)),                                 \
+              fmaf(FWI_W3, ((p3) - (c)) - ((c) - (m3)), FWI_W4 * (((p4) - (c)) - ((c) - (m4))))))
 
 // Largest LDS allocation of one workgroup on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
