@@ -83,17 +83,39 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
 
     float* cur = lds;          // u^n
     float* nxt = lds + plane;  // receives u^{n+1}
+    // Adjoint: dc holds the tile's slice of D for the current step.  As soon as
+    // row j has been imaged its registers receive row j of the next step's
+    // slice, so every load has a whole step to arrive and no extra registers are
+    // needed.  The adjoint-source values of this thread's receivers (adjv) are
+    // likewise requested a step ahead.
+    float dc[P][X];
+    float adjv[X];
+    if (ADJ && active) {
+        const float* Dr = Drow0 + (size_t)(nsteps - 1) * npts;
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+#pragma unroll
+            for (int c = 0; c < X; ++c) dc[j][c] = (EXACT || (z0 + j < nzp && x0 + c < nxp)) ? Dr[j * nxp + c] : 0.f;
+#pragma unroll
+        for (int c = 0; c < X; ++c)
+            adjv[c] = (rec_j >= 0 && rr[c] >= 0) ? a.adj[trfield + (size_t)rr[c] * a.nt + nsteps] : 0.f;
+    }
     for (int m = 0; m < nsteps; ++m) {
         if (active) {
-            // D^{N-2-m} of the tile is requested first so its latency overlaps the LDS work
-            float dr[P][X];
-            if (ADJ) {
-                const float* Dr = Drow0 + (size_t)(nsteps - 1 - m) * npts;
+            const bool more = ADJ && m + 1 < nsteps;
+            // next step's slice (the last step re-reads slice 0: harmless, and the
+            // reload stays unconditional so old and new values never coexist)
+            const float* Dn = ADJ ? Drow0 + (size_t)max(nsteps - 2 - m, 0) * npts : nullptr;
+            float drec[X];  // D at this thread's receivers for the current step
+            if (ADJ && rec_j >= 0) {
+#pragma unroll
+                for (int c = 0; c < X; ++c) drec[c] = 0.f;
 #pragma unroll
                 for (int j = 0; j < P; ++j)
+                    if (j == rec_j) {
 #pragma unroll
-                    for (int c = 0; c < X; ++c)
-                        dr[j][c] = (EXACT || (z0 + j < nzp && x0 + c < nxp)) ? Dr[j * nxp + c] : 0.f;
+                        for (int c = 0; c < X; ++c) drec[c] = dc[j][c];
+                    }
             }
             float win[P + 8][X];
             const float* cb = cur + (z0 + 4) * S + x0 + 4;  // LDS cell of the tile corner
@@ -156,9 +178,18 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
                     const float un = u0 + wn;
                     wr[j][c] = wn;
                     nb_[j * S + c] = un;
+                    if (ADJ) acc[j][c] = fmaf(un, dc[j][c], acc[j][c]);  // imaging: psi^{N-1-m} D^{N-2-m}
                     if (STORE && !ADJ) {
                         if (EXACT || (z0 + j < nzp && x0 + c < nxp)) Dw[j * nxp + c] = D;
                     }
+                }
+                if (ADJ) {
+                    // keep the reload after the row that frees its registers
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int c = 0; c < X; ++c)
+                        dc[j][c] = (EXACT || (z0 + j < nzp && x0 + c < nxp)) ? Dn[j * nxp + c] : 0.f;
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             // point corrections of the owning threads
@@ -170,20 +201,17 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
 #pragma unroll
                         for (int c = 0; c < X; ++c)
                             if (rr[c] >= 0) {
-                                const float dv = Kr[j][c] * a.adj[trfield + (size_t)rr[c] * a.nt + (nsteps - m)] *
-                                                 a.rec_invw;
+                                const float dv = Kr[j][c] * adjv[c] * a.rec_invw;
                                 wr[j][c] += dv;
                                 nb_[j * S + c] += dv;
+                                acc[j][c] = fmaf(dv, drec[c], acc[j][c]);  // the injection's share of the imaging
                             }
                     }
-            }
-            if (ADJ) {
-                // imaging: psi^{N-1-m} (read back from this thread's own LDS writes) times
-                // D^{N-2-m}, whose loads were issued at the top of the step
+                if (more) {
 #pragma unroll
-                for (int j = 0; j < P; ++j)
-#pragma unroll
-                    for (int c = 0; c < X; ++c) acc[j][c] = fmaf(nb_[j * S + c], dr[j][c], acc[j][c]);
+                    for (int c = 0; c < X; ++c)
+                        adjv[c] = rr[c] >= 0 ? a.adj[trfield + (size_t)rr[c] * a.nt + (nsteps - m - 1)] : 0.f;
+                }
             }
             if (src_j >= 0) {
                 if (!ADJ) {
