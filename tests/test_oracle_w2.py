@@ -201,3 +201,32 @@ def test_adjoint_source_finite_differences(orc, squared):
         dm[idx] -= e
         fd = (orc.w2_misfit(o, dp, want_adjoint=False)[0] - orc.w2_misfit(o, dm, want_adjoint=False)[0]) / (2 * e)
         assert abs(adj[idx] - fd) <= 1e-5 * scale, (idx, adj[idx], fd)
+
+
+def test_gradient_is_the_local_slope_between_jumps(orc):
+    """Full-size batch acquisition (70 x 70, 5 shots, 1000 samples): synthetic
+    densities omega d + c' go negative (c' is fixed from the observations), so
+    the first-crossing quantile makes J jump at isolated points.  Along a
+    smooth direction J's slope over 0.01 m/s segments equals the reverse-mode
+    directional derivative on every segment but a few (the jumps)."""
+    from scipy.ndimage import gaussian_filter
+
+    import fwi_inputs as fi
+
+    acq = fi.surface_acquisition(70, 70, ns=5, nt=1000, nb=40)
+    w = fi.ricker(acq.nt, acq.dt, acq.f_peak)
+    obs = orc.w2_prepare(orc.forward(acq, fi.faulted_model(70, 70, 1000), w), acq.dt)
+    v0 = fi.faulted_model(70, 70, 0)
+    dsyn = orc.forward(acq, v0, w)
+    dens = obs["omega"].reshape(dsyn.shape) * dsyn + obs["cprime"].reshape(dsyn.shape[:-1])[..., None]
+    assert (dens < 0).any()  # the premise: the weighted synthetic density is not nonnegative
+    _, g, _, _ = orc.objective_and_gradient(acq, v0[None], w, obs)
+    blk = gaussian_filter(np.random.default_rng(0).standard_normal((16, 16)), 2.0)
+    d = np.zeros((70, 70))
+    d[4:20, 27:43] = blk / np.abs(blk).max()
+    an = float(np.sum(g[0] * d))
+    hs = np.linspace(-0.05, 0.05, 11)
+    J = orc.objective(acq, np.stack([v0 + h * d for h in hs]), w, obs)
+    slopes = np.diff(J) / np.diff(hs)
+    close = np.abs(slopes - an) <= 1e-3 * abs(an)
+    assert close.sum() >= len(slopes) - 2, (an, slopes)
