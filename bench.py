@@ -71,8 +71,8 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
 # k_wave_lds_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
                    "paper_2603_16393_amd/csrc/fwi_internal.h")
-TRAFFIC_SHA1 = "0aa2e863ef1181a1e12ba6f87ef4b029931a7c02"
-TRAFFIC_BYTES = {"forward": 5304064184.0, "adjoint": 5308392439.0}
+TRAFFIC_SHA1 = "4be7465d05314452babd971bfa0b22e5f2d8fb64"
+TRAFFIC_BYTES = {"forward": 5304131932.0, "adjoint": 5308455774.0}
 
 
 def kernel_sources_sha1():
@@ -253,6 +253,61 @@ def bench_uneven(args):
     print(json.dumps(out))
 
 
+# matrix-core FLOPs of the surrogate per sample (GEMMs only: the 4 encoder and 4 decoder MLPs, the depth->time
+# map, the 4 x-mixing products, the head and the time up-sampling)
+SUR_FWD_FLOP = 2.0 * (4 * 5184 * 2 * 64 * 128 + 256 * 72 * 4608 + 4 * (256 * 72 * 72 * 64 + 18432 * 2 * 64 * 128)
+                      + 18432 * 64 * 8 + 1000 * 256 * 576)
+
+
+def bench_surrogate(args):
+    """Learned surrogate alone (70 x 70 -> 5 x 70 x 1000 traces): forward, forward + input VJP, and one Adam
+    training step at batches of 16 and 64, with the matrix-core rate of the GEMM work against 2.5 PFLOP/s BF16."""
+    import torch
+
+    import fwi_inputs as fi
+    from paper_2603_16393_amd.surrogate import Surrogate
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sur = Surrogate(64, device=dev)
+    sur.set_params(np.load(SURROGATE_WEIGHTS))
+    res = {}
+    for B in (16, 64):
+        v = torch.tensor(np.stack([fi.faulted_model(NZ, NX, s) for s in range(B)]), dtype=torch.float32, device=dev)
+        tr = sur.forward(v)
+        dtr = torch.randn_like(tr)
+        dv = torch.empty_like(v)
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        reps = max(3, args.steps)
+        f = timed(lambda: sur.forward(v, out=tr), reps)
+        fb = timed(lambda: (sur.forward(v, out=tr), sur.backward(dtr, out=dv)), reps)
+        ts = timed(lambda: sur.train_step(v, tr, lr=1e-7), reps)
+        flop_f = SUR_FWD_FLOP * B
+        res[f"B{B}"] = {"forward_ms": round(f, 3), "forward_vjp_ms": round(fb, 3), "train_step_ms": round(ts, 3),
+                        "forward_tflops": round(flop_f / f / 1e9, 1),
+                        "forward_mfma_frac": round(flop_f / f / 1e9 / 2500.0, 4),
+                        "train_tflops": round(3 * flop_f / ts / 1e9, 1)}
+    out = {"metric": "surrogate forward samples/s (70x70 -> 5x70x1000 traces)",
+           "value": round(64 / (res["B64"]["forward_ms"] / 1e3), 1), "unit": "samples/s", "n_gpus": 1,
+           "steps": max(3, args.steps), "warmup": 1, "ms_per_step": res["B64"]["forward_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "trace surrogate, batches of 16 and 64, trained parameters"},
+           "flop_per_sample_forward": SUR_FWD_FLOP, "batches": res}
+    sur.close()
+    print(json.dumps(out))
+
+
 def bench_checkpointed(args):
     """Adjoint with checkpointing: 400 x 800 model (dx = 10 m) with a 50-cell sponge, 20 surface shots x 800
     receivers, 4000 samples at dt = 0.8 ms, 10 Hz Ricker, smooth-plus-layered model with a high-velocity lens
@@ -315,7 +370,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the library's plain copy kernel on 512 MiB three times "
                          "(the reference dispatch for HBM traffic counters) and exit")
-    ap.add_argument("--workload", choices=["guidance", "checkpointed", "uneven"], default="guidance")
+    ap.add_argument("--workload", choices=["guidance", "checkpointed", "uneven", "surrogate"], default="guidance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
@@ -326,6 +381,9 @@ def main():
         return
     if args.workload == "uneven":
         bench_uneven(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
 
     import torch
