@@ -25,6 +25,7 @@ constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;
 struct GemmDev {
     GemmArgs g;
     int vecA, vecB;
+    int vecC;        // ldc, strideC and every output / epilogue operand allow 16-byte accesses
     int ksteps;      // K steps per batch
     int total;       // total (batch, k) steps of one output tile
 };
@@ -45,6 +46,57 @@ __device__ inline void load8(const bf16_t* __restrict__ base, long ld, int row, 
     } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i) out[i] = (row < rows && col + i < cols) ? base[(long)row * ld + col + i] : 0;
+    }
+}
+
+// 8 consecutive elements, as one 16-byte (BF16) or two 16-byte (FP32) accesses when
+// `vec`, element-wise for the first n otherwise
+__device__ inline void ld8bf(const bf16_t* p, bool vec, int n, float o[8]) {
+    if (vec) {
+        const uint4 u = *reinterpret_cast<const uint4*>(p);
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            o[2 * e] = bf2f((bf16_t)(w[e] & 0xffff));
+            o[2 * e + 1] = bf2f((bf16_t)(w[e] >> 16));
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = e < n ? bf2f(p[e]) : 0.f;
+    }
+}
+__device__ inline void st8bf(bf16_t* p, bool vec, int n, const bf16_t h[8]) {
+    if (vec) {
+        uint4 u;
+        u.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        u.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        u.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+        u.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+        *reinterpret_cast<uint4*>(p) = u;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (e < n) p[e] = h[e];
+    }
+}
+__device__ inline void ld8f(const float* p, bool vec, int n, float o[8]) {
+    if (vec) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        const float4 b = *reinterpret_cast<const float4*>(p + 4);
+        o[0] = a.x, o[1] = a.y, o[2] = a.z, o[3] = a.w, o[4] = b.x, o[5] = b.y, o[6] = b.z, o[7] = b.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = e < n ? p[e] : 0.f;
+    }
+}
+__device__ inline void st8f(float* p, bool vec, int n, const float v[8]) {
+    if (vec) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (e < n) p[e] = v[e];
     }
 }
 
@@ -112,29 +164,105 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmDev d) {
     }
 
     const int col_l = lane & 15, row_l = (lane >> 4) * 4;
+    if (g.splitk > 1) {  // FP32 partials, added in split order by k_splitk_reduce
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = m0 + wm * 32 + i * 16 + row_l + q;
+                    const int col = n0 + wn * 32 + j * 16 + col_l;
+                    if (row < g.M && col < g.N) g.work[((long)split * g.M + row) * g.N + col] = acc[i][j][q];
+                }
+        return;
+    }
+    // Epilogue: the accumulator tile goes through LDS so that each thread then
+    // finishes 8 consecutive columns of one row and moves them with 16-byte
+    // loads and stores (an MFMA lane's own outputs span only 16 columns).
+    __shared__ float Ct[GBM][GBN + 4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = m0 + wm * 32 + i * 16 + row_l + q;
-                const int col = n0 + wn * 32 + j * 16 + col_l;
-                if (row >= g.M || col >= g.N) continue;
-                const float a = acc[i][j][q];
-                if (g.splitk > 1) {
-                    g.work[((long)split * g.M + row) * g.N + col] = a;
-                    continue;
+            for (int q = 0; q < 4; ++q) Ct[wm * 32 + i * 16 + row_l + q][wn * 32 + j * 16 + col_l] = acc[i][j][q];
+    __syncthreads();
+    const int cg = (tid & 7) * 8;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const int r = pass * 32 + (tid >> 3);
+        const int row = m0 + r, col0 = n0 + cg;
+        if (row >= g.M || col0 >= g.N) continue;
+        const int ncol = min(8, g.N - col0);
+        const bool vec = d.vecC && ncol == 8;
+        const long off = (long)bout * g.strideC + (long)row * g.ldc + col0;
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = g.alpha * Ct[r][cg + e];
+        if (g.beta != 0.f) {
+            float old[8];
+            if (g.C32)
+                ld8f(g.C32 + off, vec, ncol, old);
+            else
+                ld8bf(g.C16 + off, vec, ncol, old);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] += g.beta * old[e];
+        }
+        if (g.bias) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (e < ncol) v[e] += g.bias[col0 + e];
+        }
+        bf16_t h[8];
+        switch (g.epi) {
+            case kEpiGelu: {
+                bf16_t q16[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    h[e] = f2bf(v[e]);
+                    q16[e] = f2bf(gelu_f(bf2f(h[e])));
                 }
-                const long off = (long)bout * g.strideC + (long)row * g.ldc + col;
-                float val = g.alpha * a;
-                if (g.beta != 0.f) val += g.beta * (g.C32 ? g.C32[off] : bf2f(g.C16[off]));
-                if (g.bias) val += g.bias[col];
-                if (g.C32)
-                    g.C32[off] = val;
-                else
-                    g.C16[off] = f2bf(val);
+                st8bf(g.C16 + off, vec, ncol, h);
+                st8bf(g.aux16 + off, vec, ncol, q16);
+                break;
             }
+            case kEpiResid: {
+                float res[8];
+                ld8bf(g.res16 + off, vec, ncol, res);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = f2bf(res[e] + bf2f(f2bf(v[e])));
+                st8bf(g.C16 + off, vec, ncol, h);
+                break;
+            }
+            case kEpiGeluBwd: {
+                float pp[8];
+                ld8bf(g.p16 + off, vec, ncol, pp);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    v[e] *= gelu_d(pp[e]);
+                    h[e] = f2bf(v[e]);
+                }
+                st8f(g.C32 + off, vec, ncol, v);
+                st8bf(g.aux16 + off, vec, ncol, h);
+                break;
+            }
+            case kEpiDual:
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = f2bf(v[e]);
+                st8f(g.C32 + off, vec, ncol, v);
+                st8bf(g.aux16 + off, vec, ncol, h);
+                break;
+            default:
+                if (g.C32) {
+                    st8f(g.C32 + off, vec, ncol, v);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) h[e] = f2bf(v[e]);
+                    st8bf(g.C16 + off, vec, ncol, h);
+                }
+        }
+    }
 }
 
 __global__ void k_splitk_reduce(GemmArgs g) {
@@ -158,11 +286,21 @@ int gemm_bf16(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return FWI_OK;
     if (!g.A || !g.B || (!g.C32 == !g.C16)) return FWI_EINVAL;
     if (g.splitk > 1 && (!g.work || (g.batch > 1 && !g.reduce_batch))) return FWI_EINVAL;
+    if (g.epi != kEpiNone) {
+        if (g.splitk > 1 || g.reduce_batch) return FWI_EINVAL;
+        const bool c16 = g.C16 != nullptr, c32 = g.C32 != nullptr;
+        if ((g.epi == kEpiGelu && (!c16 || !g.aux16)) || (g.epi == kEpiResid && (!c16 || !g.res16)) ||
+            (g.epi == kEpiGeluBwd && (!c32 || !g.aux16 || !g.p16)) || (g.epi == kEpiDual && (!c32 || !g.aux16)))
+            return FWI_EINVAL;
+    }
     GemmDev d;
     d.g = g;
     if (d.g.splitk < 1) d.g.splitk = 1;
     d.vecA = (g.lda % 8 == 0) && (g.strideA % 8 == 0) && ((uintptr_t)g.A % 16 == 0);
     d.vecB = (g.ldb % 8 == 0) && (g.strideB % 8 == 0) && ((uintptr_t)g.B % 16 == 0);
+    auto al16 = [](const void* p) { return ((uintptr_t)p % 16) == 0; };
+    d.vecC = (g.ldc % 8 == 0) && (g.strideC % 8 == 0) && al16(g.C32) && al16(g.C16) && al16(g.aux16) &&
+             al16(g.res16) && al16(g.p16);
     d.ksteps = (g.K + GBK - 1) / GBK;
     const int nb = g.reduce_batch ? g.batch : 1;
     d.total = nb * d.ksteps;

@@ -119,9 +119,9 @@ __global__ void k_dw_fwd(int B, int H, int W, const bf16_t* __restrict__ in, con
     }
 }
 
-// din += transpose of the correlation applied to dout (FP32)
+// din += transpose of the correlation applied to dout (FP32), and its BF16 copy if din16
 __global__ void k_dw_bwd_input(int B, int H, int W, const float* __restrict__ dout, const float* __restrict__ k,
-                               float* __restrict__ din) {
+                               float* __restrict__ din, bf16_t* __restrict__ din16) {
     const long n = (long)B * H * W * kC;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const int c = (int)(i % kC);
@@ -140,7 +140,9 @@ __global__ void k_dw_bwd_input(int B, int H, int W, const float* __restrict__ do
                 acc += k[c * 9 + dy * 3 + dx] * dout[(base + (long)yy * W + xx) * kC + c];
             }
         }
-        din[i] += acc;
+        const float v = din[i] + acc;
+        din[i] = v;
+        if (din16) din16[i] = f2bf(v);
     }
 }
 
@@ -199,11 +201,6 @@ __global__ void k_dw_weight_finish(const float* __restrict__ part, int nparts, f
 }
 
 // ---------------------------------------------------------------------------
-__device__ inline float gelu_f(float p) { return 0.5f * p * (1.f + erff(p * 0.70710678118654752f)); }
-__device__ inline float gelu_d(float p) {
-    return 0.5f * (1.f + erff(p * 0.70710678118654752f)) + p * expf(-0.5f * p * p) * 0.39894228040143268f;
-}
-
 __global__ void k_gelu_fwd(long n, const bf16_t* __restrict__ p, bf16_t* __restrict__ q) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
         q[i] = f2bf(gelu_f(bf2f(p[i])));
@@ -420,6 +417,187 @@ __global__ void k_mf_predict(long n, const float* ga, const float* sn, const flo
 }
 
 // ---------------------------------------------------------------------------
+// Channel-vectorised forms (C = 64 channels, NHWC): 8 BF16 or 4 FP32 channels
+// per 16-byte access, taps in the same order as the scalar forms above.
+__device__ inline void unpack8(const uint4 u, float o[8]) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        o[2 * e] = bf2f((bf16_t)(w[e] & 0xffff));
+        o[2 * e + 1] = bf2f((bf16_t)(w[e] >> 16));
+    }
+}
+__device__ inline uint4 pack8(const float v[8]) {
+    uint4 u;
+    u.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+    u.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+    u.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
+    u.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
+    return u;
+}
+
+__global__ void k_dw_fwd8(int B, int H, int W, const bf16_t* __restrict__ in, const float* __restrict__ k,
+                          const float* __restrict__ b, bf16_t* __restrict__ out) {
+    __shared__ float ks[kC * 9], bs[kC];
+    for (int i = threadIdx.x; i < kC * 9; i += blockDim.x) ks[i] = k[i];
+    for (int i = threadIdx.x; i < kC; i += blockDim.x) bs[i] = b[i];
+    __syncthreads();
+    const long n = (long)B * H * W * (kC / 8);
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int c0 = (int)(i % (kC / 8)) * 8;
+        const long px = i / (kC / 8);
+        const int x = (int)(px % W), y = (int)((px / W) % H);
+        const long base = px - (long)y * W - x;
+        float acc[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] = bs[c0 + e];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yy = y + dy - 1;
+            if (yy < 0 || yy >= H) continue;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xx = x + dx - 1;
+                if (xx < 0 || xx >= W) continue;
+                float v[8];
+                unpack8(*reinterpret_cast<const uint4*>(in + (base + (long)yy * W + xx) * kC + c0), v);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[e] += ks[(c0 + e) * 9 + dy * 3 + dx] * v[e];
+            }
+        }
+        *reinterpret_cast<uint4*>(out + px * kC + c0) = pack8(acc);
+    }
+}
+
+__global__ void k_dw_bwd_input4(int B, int H, int W, const float* __restrict__ dout, const float* __restrict__ k,
+                                float* __restrict__ din, bf16_t* __restrict__ din16) {
+    __shared__ float ks[kC * 9];
+    for (int i = threadIdx.x; i < kC * 9; i += blockDim.x) ks[i] = k[i];
+    __syncthreads();
+    const long n = (long)B * H * W * (kC / 4);
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int c0 = (int)(i % (kC / 4)) * 4;
+        const long px = i / (kC / 4);
+        const int x = (int)(px % W), y = (int)((px / W) % H);
+        const long base = px - (long)y * W - x;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yy = y - dy + 1;
+            if (yy < 0 || yy >= H) continue;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xx = x - dx + 1;
+                if (xx < 0 || xx >= W) continue;
+                const float4 d = *reinterpret_cast<const float4*>(dout + (base + (long)yy * W + xx) * kC + c0);
+                const float dv[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[e] += ks[(c0 + e) * 9 + dy * 3 + dx] * dv[e];
+            }
+        }
+        float4* dp = reinterpret_cast<float4*>(din + px * kC + c0);
+        const float4 o = *dp;
+        const float4 r = make_float4(o.x + acc[0], o.y + acc[1], o.z + acc[2], o.w + acc[3]);
+        *dp = r;
+        if (din16) {
+            uint2 u;
+            u.x = (uint32_t)f2bf(r.x) | ((uint32_t)f2bf(r.y) << 16);
+            u.y = (uint32_t)f2bf(r.z) | ((uint32_t)f2bf(r.w) << 16);
+            *reinterpret_cast<uint2*>(din16 + px * kC + c0) = u;
+        }
+    }
+}
+
+// partials of dk [C][9] and db [C]: thread = (pixel lane, 8-channel group); 32 pixel
+// lanes per block summed by a fixed shuffle tree and a fixed pass over the 4 waves
+__global__ __launch_bounds__(256) void k_dw_bwd_weight_partial8(int B, int H, int W, const bf16_t* __restrict__ in,
+                                                                const float* __restrict__ dout,
+                                                                float* __restrict__ part, int nparts) {
+    const long npx = (long)B * H * W;
+    const int cgp = threadIdx.x & 7, pl = threadIdx.x >> 3;  // 8 channel groups x 32 pixel lanes
+    const int c0 = cgp * 8;
+    const long lo = npx * blockIdx.x / nparts, hi = npx * (blockIdx.x + 1) / nparts;
+    float acc[10][8];
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[q][e] = 0.f;
+    for (long px = lo + pl; px < hi; px += 32) {
+        const int x = (int)(px % W), y = (int)((px / W) % H);
+        const long base = px - (long)y * W - x;
+        const float4 da = *reinterpret_cast<const float4*>(dout + px * kC + c0);
+        const float4 db = *reinterpret_cast<const float4*>(dout + px * kC + c0 + 4);
+        const float d[8] = {da.x, da.y, da.z, da.w, db.x, db.y, db.z, db.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[9][e] += d[e];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yy = y + dy - 1;
+            if (yy < 0 || yy >= H) continue;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xx = x + dx - 1;
+                if (xx < 0 || xx >= W) continue;
+                float v[8];
+                unpack8(*reinterpret_cast<const uint4*>(in + (base + (long)yy * W + xx) * kC + c0), v);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[dy * 3 + dx][e] += d[e] * v[e];
+            }
+        }
+    }
+    // within a wave: lanes with the same channel group are 8 apart
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float t = acc[q][e];
+            t += __shfl_xor(t, 8);
+            t += __shfl_xor(t, 16);
+            t += __shfl_xor(t, 32);
+            acc[q][e] = t;
+        }
+    __shared__ float sh[4][10][kC];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < 8) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sh[wave][q][c0 + e] = acc[q][e];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < 10 * kC; j += blockDim.x) {
+        const int q = j / kC, c = j % kC;
+        part[((long)blockIdx.x * 10 + q) * kC + c] = ((sh[0][q][c] + sh[1][q][c]) + sh[2][q][c]) + sh[3][q][c];
+    }
+}
+
+// column sums of a [rows x cols] FP32 matrix (cols a multiple of 4 dividing 1024): 4 columns per thread
+__global__ void k_colsum_partial4(long rows, int cols, const float* __restrict__ a, float* __restrict__ part,
+                                  int nparts) {
+    const int g4 = cols / 4;                 // column groups
+    const int lanes = TPB / g4;              // row lanes
+    const int cg = threadIdx.x % g4, l = threadIdx.x / g4;
+    const long lo = rows * blockIdx.x / nparts, hi = rows * (blockIdx.x + 1) / nparts;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l < lanes)
+        for (long r = lo + l; r < hi; r += lanes) {
+            const float4 v = *reinterpret_cast<const float4*>(a + r * cols + cg * 4);
+            s.x += v.x, s.y += v.y, s.z += v.z, s.w += v.w;
+        }
+    __shared__ float4 sh[TPB];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (l == 0) {
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = 0; q < lanes; ++q) {
+            const float4 v = sh[q * g4 + cg];
+            t.x += v.x, t.y += v.y, t.z += v.z, t.w += v.w;
+        }
+        *reinterpret_cast<float4*>(part + (long)blockIdx.x * cols + cg * 4) = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 void lift_fwd(int B, const float* v, const float* W, const float* b, bf16_t* h, hipStream_t st) {
     hipLaunchKernelGGL(k_lift_fwd, dim3(blocks_for((long)B * kZ * kX * kC)), dim3(TPB), 0, st, B, v, W, b, h);
@@ -438,14 +616,16 @@ void lift_bwd(int B, const float* v, const float* dh, const float* W, float* dv,
     }
 }
 void dw_fwd(int B, int H, int W, const bf16_t* in, const float* k, const float* b, bf16_t* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_dw_fwd, dim3(blocks_for((long)B * H * W * kC)), dim3(TPB), 0, st, B, H, W, in, k, b, out);
+    hipLaunchKernelGGL(k_dw_fwd8, dim3(blocks_for((long)B * H * W * (kC / 8))), dim3(TPB), 0, st, B, H, W, in, k, b,
+                       out);
 }
-void dw_bwd(int B, int H, int W, const bf16_t* in, const float* dout, const float* k, float* din, float* dk, float* db,
-            float* part, hipStream_t st) {
-    hipLaunchKernelGGL(k_dw_bwd_input, dim3(blocks_for((long)B * H * W * kC)), dim3(TPB), 0, st, B, H, W, dout, k, din);
+void dw_bwd(int B, int H, int W, const bf16_t* in, const float* dout, const float* k, float* din, bf16_t* din16,
+            float* dk, float* db, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_dw_bwd_input4, dim3(blocks_for((long)B * H * W * (kC / 4))), dim3(TPB), 0, st, B, H, W, dout,
+                       k, din, din16);
     if (dk) {
         const int np = 512;
-        hipLaunchKernelGGL(k_dw_bwd_weight_partial, dim3(np), dim3(TPB), 0, st, B, H, W, in, dout, part, np);
+        hipLaunchKernelGGL(k_dw_bwd_weight_partial8, dim3(np), dim3(TPB), 0, st, B, H, W, in, dout, part, np);
         hipLaunchKernelGGL(k_dw_weight_finish, dim3((10 * kC + TPB - 1) / TPB), dim3(TPB), 0, st, part, np, dk, db);
     }
 }
@@ -466,7 +646,10 @@ void copy_f32(long n, const float* a, float* o, hipStream_t st) {
 }
 void colsum(long rows, int cols, const float* a, float* out, float* part, hipStream_t st) {
     const int np = 256;
-    hipLaunchKernelGGL(k_colsum_partial, dim3(np), dim3(TPB), 0, st, rows, cols, a, part, np);
+    if (cols % 4 == 0 && 1024 % cols == 0)
+        hipLaunchKernelGGL(k_colsum_partial4, dim3(np), dim3(TPB), 0, st, rows, cols, a, part, np);
+    else
+        hipLaunchKernelGGL(k_colsum_partial, dim3(np), dim3(TPB), 0, st, rows, cols, a, part, np);
     hipLaunchKernelGGL(k_sum_partials, dim3((cols + TPB - 1) / TPB), dim3(TPB), 0, st, part, np, cols, out, 0.f);
 }
 void out_fwd(int B, const float* out, const float* scale, float* tr, hipStream_t st) {

@@ -36,6 +36,23 @@ __host__ __device__ inline bf16_t f2bf(float f) {
     return (bf16_t)(r >> 16);
 }
 
+// GELU (erf form) and its derivative, shared by the element-wise kernels and
+// the GEMM epilogues.
+__device__ inline float gelu_f(float p) { return 0.5f * p * (1.f + erff(p * 0.70710678118654752f)); }
+__device__ inline float gelu_d(float p) {
+    return 0.5f * (1.f + erff(p * 0.70710678118654752f)) + p * expf(-0.5f * p * p) * 0.39894228040143268f;
+}
+
+// Epilogues of the GEMM (v = alpha acc + beta C + bias), each rounding exactly
+// as the separate passes they replace:
+enum GemmEpi {
+    kEpiNone = 0,
+    kEpiGelu = 1,     // C16 = R(v), aux16 = R(gelu(R(v)))
+    kEpiResid = 2,    // C16 = R(res16 + R(v))
+    kEpiGeluBwd = 3,  // v *= gelu'(p16); C32 = v, aux16 = R(v)
+    kEpiDual = 4      // C32 = v, aux16 = R(v)
+};
+
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b] (+ bias[n]) for b < batch,
 // or, with reduce_batch, C = alpha * sum_b op(A[b]) op(B[b]) + beta * C.
 // A, B are BF16; op(A)[m][k] = transA ? A[k * lda + m] : A[m * lda + k],
@@ -59,6 +76,11 @@ struct GemmArgs {
     // partial sums go to work[splitk][M][N] and are added in split order
     int splitk = 1;
     float* work = nullptr;
+    // epilogue (splitk == 1 only); aux16, res16 and p16 share C's ldc / strideC
+    int epi = kEpiNone;
+    bf16_t* aux16 = nullptr;
+    const bf16_t* res16 = nullptr;
+    const bf16_t* p16 = nullptr;
 };
 
 int gemm_bf16(const GemmArgs& g, hipStream_t st);

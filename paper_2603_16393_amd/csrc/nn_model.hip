@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "nn_internal.h"
 #include "nn_ops.h"
@@ -39,12 +40,12 @@ struct fwi_surrogate {
     // activations (BF16)
     fwi::bf16_t *hin[fwi::kNBLK + 1], *ae[fwi::kNBLK], *pe[fwi::kNBLK], *qe[fwi::kNBLK];
     fwi::bf16_t *gin[fwi::kNBLK + 1], *g1[fwi::kNBLK], *ad[fwi::kNBLK], *pd[fwi::kNBLK], *qd[fwi::kNBLK];
-    fwi::bf16_t *tmp = nullptr, *o = nullptr;
+    fwi::bf16_t* o = nullptr;
     float *out32 = nullptr, *vcache = nullptr;
     int cachedB = 0;
     // gradient streams
-    fwi::bf16_t *dout16 = nullptr, *do16 = nullptr, *dg16 = nullptr, *dp16 = nullptr;
-    float *do32 = nullptr, *dg32 = nullptr, *dq32 = nullptr, *dp32 = nullptr, *da32 = nullptr;
+    fwi::bf16_t *dout16 = nullptr, *do16 = nullptr, *dg16 = nullptr, *dg16b = nullptr, *dp16 = nullptr;
+    float *do32 = nullptr, *dg32 = nullptr, *dp32 = nullptr, *da32 = nullptr;
     float *part = nullptr, *work = nullptr;
     // training
     float *pred = nullptr, *dtr = nullptr, *mx = nullptr, *lpart = nullptr, *lval = nullptr;
@@ -102,13 +103,15 @@ struct Ctx {
 
     // C = op(A) op(B) (+ bias) per batch
     void mm(int M, int N, int K, int batch, const bf16_t* A, long lda, long sA, int tA, const bf16_t* B, long ldb,
-            long sB, int tB, float* C32, bf16_t* C16, long ldc, long sC, const float* bias, float beta = 0.f) {
+            long sB, int tB, float* C32, bf16_t* C16, long ldc, long sC, const float* bias, float beta = 0.f,
+            int epi = kEpiNone, bf16_t* aux16 = nullptr, const bf16_t* res16 = nullptr, const bf16_t* p16 = nullptr) {
         if (rc != FWI_OK) return;
         GemmArgs g;
         g.M = M, g.N = N, g.K = K, g.batch = batch;
         g.A = A, g.lda = lda, g.strideA = sA, g.transA = tA;
         g.B = B, g.ldb = ldb, g.strideB = sB, g.transB = tB;
         g.C32 = C32, g.C16 = C16, g.ldc = ldc, g.strideC = sC, g.beta = beta, g.bias = bias;
+        g.epi = epi, g.aux16 = aux16, g.res16 = res16, g.p16 = p16;
         rc = gemm_bf16(g, st);
     }
     // weight gradient C = sum over batch (and rows) of op(A) op(B), split-K
@@ -139,11 +142,12 @@ int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStre
     nn::lift_fwd(B, v, P + L.lift_w, P + L.lift_b, s->hin[0], st);
     for (int i = 0; i < kNBLK; ++i) {
         nn::dw_fwd(B, kZ, kX, s->hin[i], P + L.enc_dw_k[i], P + L.enc_dw_b[i], s->ae[i], st);
+        // p = R(a W1 + b1) and q = R(gelu(p)) from one GEMM epilogue
         c.mm(re, kCH, kC, 1, s->ae[i], kC, 0, 0, W + M.enc_w1[i], kCH, 0, 0, nullptr, s->pe[i], kCH, 0,
-             P + L.enc_b1[i]);
-        nn::gelu_fwd((long)re * kCH, s->pe[i], s->qe[i], st);
-        c.mm(re, kC, kCH, 1, s->qe[i], kCH, 0, 0, W + M.enc_w2[i], kC, 0, 0, nullptr, s->tmp, kC, 0, P + L.enc_b2[i]);
-        nn::add_bf16((long)re * kC, s->hin[i], s->tmp, s->hin[i + 1], st);
+             P + L.enc_b1[i], 0.f, kEpiGelu, s->qe[i]);
+        // h_next = R(h + R(q W2 + b2))
+        c.mm(re, kC, kCH, 1, s->qe[i], kCH, 0, 0, W + M.enc_w2[i], kC, 0, 0, nullptr, s->hin[i + 1], kC, 0,
+             P + L.enc_b2[i], 0.f, kEpiResid, nullptr, s->hin[i]);
     }
     // depth -> time: per sample [T][X C] = T[T][Z] h[Z][X C]
     const long xc = (long)kX * kC;
@@ -151,14 +155,14 @@ int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStre
          nullptr);
     for (int i = 0; i < kNBLK; ++i) {
         // mixing along x: per (sample, t) [X][C] = Xm[X][X] g[X][C]
-        c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 0, s->gin[i], kC, xc, 0, nullptr, s->tmp, kC, xc, nullptr);
-        nn::add_bf16((long)rd * kC, s->gin[i], s->tmp, s->g1[i], st);
+        // g1 = R(g + R(Xm g))
+        c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 0, s->gin[i], kC, xc, 0, nullptr, s->g1[i], kC, xc, nullptr,
+             0.f, kEpiResid, nullptr, s->gin[i]);
         nn::dw_fwd(B, kT, kX, s->g1[i], P + L.dec_dw_k[i], P + L.dec_dw_b[i], s->ad[i], st);
         c.mm(rd, kCH, kC, 1, s->ad[i], kC, 0, 0, W + M.dec_w1[i], kCH, 0, 0, nullptr, s->pd[i], kCH, 0,
-             P + L.dec_b1[i]);
-        nn::gelu_fwd((long)rd * kCH, s->pd[i], s->qd[i], st);
-        c.mm(rd, kC, kCH, 1, s->qd[i], kCH, 0, 0, W + M.dec_w2[i], kC, 0, 0, nullptr, s->tmp, kC, 0, P + L.dec_b2[i]);
-        nn::add_bf16((long)rd * kC, s->g1[i], s->tmp, s->gin[i + 1], st);
+             P + L.dec_b1[i], 0.f, kEpiGelu, s->qd[i]);
+        c.mm(rd, kC, kCH, 1, s->qd[i], kCH, 0, 0, W + M.dec_w2[i], kC, 0, 0, nullptr, s->gin[i + 1], kC, 0,
+             P + L.dec_b2[i], 0.f, kEpiResid, nullptr, s->g1[i]);
     }
     c.mm(rd, kS, kC, 1, s->gin[kNBLK], kC, 0, 0, W + M.proj_w, kS, 0, 0, nullptr, s->o, kS, 0, P + L.proj_b);
     // time up-sampling: per sample [NT][X S] = U[NT][T] o[T][X S] (FP32 out)
@@ -186,22 +190,24 @@ int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want
     if (want_w)  // dU = sum_n dout_n o_n^T
         c.wgrad(kNT, kT, (int)xs, B, s->dout16, xs, kNT * xs, 0, s->o, xs, kT * xs, 1, G + L.up, kT);
     // do_n = U^T dout_n
-    c.mm(kT, (int)xs, kNT, B, W + M.up, kT, 0, 1, s->dout16, xs, kNT * xs, 0, s->do32, nullptr, xs, kT * xs, nullptr);
-    nn::to_bf16((long)rd * kS, s->do32, s->do16, st);
+    c.mm(kT, (int)xs, kNT, B, W + M.up, kT, 0, 1, s->dout16, xs, kNT * xs, 0, s->do32, nullptr, xs, kT * xs, nullptr,
+         0.f, kEpiDual, s->do16);
     if (want_w) {
         c.wgrad(kC, kS, rd, 1, s->gin[kNBLK], kC, 0, 1, s->do16, kS, 0, 0, G + L.proj_w, kS);
         nn::colsum(rd, kS, s->do32, G + L.proj_b, s->part, st);
     }
-    c.mm(rd, kC, kS, 1, s->do16, kS, 0, 0, W + M.proj_w, kS, 0, 1, s->dg32, nullptr, kC, 0, nullptr);
+    c.mm(rd, kC, kS, 1, s->do16, kS, 0, 0, W + M.proj_w, kS, 0, 1, s->dg32, nullptr, kC, 0, nullptr, 0.f, kEpiDual,
+         s->dg16);
 
+    // every producer of dg32 also writes its BF16 copy dg16
     for (int i = kNBLK - 1; i >= 0; --i) {
-        nn::to_bf16((long)rd * kC, s->dg32, s->dg16, st);
         if (want_w) {
             c.wgrad(kCH, kC, rd, 1, s->qd[i], kCH, 0, 1, s->dg16, kC, 0, 0, G + L.dec_w2[i], kC);
             nn::colsum(rd, kC, s->dg32, G + L.dec_b2[i], s->part, st);
         }
-        c.mm(rd, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.dec_w2[i], kC, 0, 1, s->dq32, nullptr, kCH, 0, nullptr);
-        nn::gelu_bwd((long)rd * kCH, s->dq32, s->pd[i], s->dp32, s->dp16, st);
+        // dp = (dg W2^T) gelu'(p), FP32 and BF16, from one GEMM epilogue
+        c.mm(rd, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.dec_w2[i], kC, 0, 1, s->dp32, nullptr, kCH, 0, nullptr, 0.f,
+             kEpiGeluBwd, s->dp16, nullptr, s->pd[i]);
         if (want_w) {
             c.wgrad(kC, kCH, rd, 1, s->ad[i], kC, 0, 1, s->dp16, kCH, 0, 0, G + L.dec_w1[i], kCH);
             nn::colsum(rd, kCH, s->dp32, G + L.dec_b1[i], s->part, st);
@@ -209,38 +215,40 @@ int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want
         c.mm(rd, kC, kCH, 1, s->dp16, kCH, 0, 0, W + M.dec_w1[i], kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
         if (c.rc != FWI_OK) return c.rc;
         // dg1 = dg + dw^T(da)   (in place in dg32)
-        nn::dw_bwd(B, kT, kX, s->g1[i], s->da32, P + L.dec_dw_k[i], s->dg32, want_w ? G + L.dec_dw_k[i] : nullptr,
-                   G + L.dec_dw_b[i], s->part, st);
-        nn::to_bf16((long)rd * kC, s->dg32, s->dg16, st);
+        nn::dw_bwd(B, kT, kX, s->g1[i], s->da32, P + L.dec_dw_k[i], s->dg32, s->dg16,
+                   want_w ? G + L.dec_dw_k[i] : nullptr, G + L.dec_dw_b[i], s->part, st);
         if (want_w)  // dXm = sum_{n,t} dg1_{nt} g_{nt}^T
             c.wgrad(kX, kX, kC, B * kT, s->dg16, kC, xc, 0, s->gin[i], kC, xc, 1, G + L.dec_xm[i], kX);
         // dg = dg1 + Xm^T dg1
+        // the x-mixing's transpose accumulates into dg32; it reads dg16 (dg1) as its B operand,
+        // so its BF16 copy goes to the second buffer, which then becomes dg16
         c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 1, s->dg16, kC, xc, 0, s->dg32, nullptr, kC, xc, nullptr,
-             1.f);
+             1.f, kEpiDual, s->dg16b);
+        std::swap(s->dg16, s->dg16b);
     }
-    nn::to_bf16((long)rd * kC, s->dg32, s->dg16, st);
     if (want_w)  // dT = sum_n dy_n h_n^T
         c.wgrad(kT, kZ, (int)xc, B, s->dg16, xc, kT * xc, 0, s->hin[kNBLK], xc, kZ * xc, 1, G + L.d2t, kZ);
     // dh_n = T^T dy_n  (into dg32, whose FP32 contents are no longer needed)
     float* dh = s->dg32;
-    c.mm(kZ, (int)xc, kT, B, W + M.d2t, kZ, 0, 1, s->dg16, xc, kT * xc, 0, dh, nullptr, xc, kZ * xc, nullptr);
+    c.mm(kZ, (int)xc, kT, B, W + M.d2t, kZ, 0, 1, s->dg16, xc, kT * xc, 0, dh, nullptr, xc, kZ * xc, nullptr, 0.f,
+         kEpiDual, s->dg16b);
+    std::swap(s->dg16, s->dg16b);
 
     for (int i = kNBLK - 1; i >= 0; --i) {
-        nn::to_bf16((long)re * kC, dh, s->dg16, st);
         if (want_w) {
             c.wgrad(kCH, kC, re, 1, s->qe[i], kCH, 0, 1, s->dg16, kC, 0, 0, G + L.enc_w2[i], kC);
             nn::colsum(re, kC, dh, G + L.enc_b2[i], s->part, st);
         }
-        c.mm(re, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.enc_w2[i], kC, 0, 1, s->dq32, nullptr, kCH, 0, nullptr);
-        nn::gelu_bwd((long)re * kCH, s->dq32, s->pe[i], s->dp32, s->dp16, st);
+        c.mm(re, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.enc_w2[i], kC, 0, 1, s->dp32, nullptr, kCH, 0, nullptr, 0.f,
+             kEpiGeluBwd, s->dp16, nullptr, s->pe[i]);
         if (want_w) {
             c.wgrad(kC, kCH, re, 1, s->ae[i], kC, 0, 1, s->dp16, kCH, 0, 0, G + L.enc_w1[i], kCH);
             nn::colsum(re, kCH, s->dp32, G + L.enc_b1[i], s->part, st);
         }
         c.mm(re, kC, kCH, 1, s->dp16, kCH, 0, 0, W + M.enc_w1[i], kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
         if (c.rc != FWI_OK) return c.rc;
-        nn::dw_bwd(B, kZ, kX, s->hin[i], s->da32, P + L.enc_dw_k[i], dh, want_w ? G + L.enc_dw_k[i] : nullptr,
-                   G + L.enc_dw_b[i], s->part, st);
+        nn::dw_bwd(B, kZ, kX, s->hin[i], s->da32, P + L.enc_dw_k[i], dh, s->dg16,
+                   want_w ? G + L.enc_dw_k[i] : nullptr, G + L.enc_dw_b[i], s->part, st);
     }
     nn::lift_bwd(B, s->vcache, dh, P + L.lift_w, dv, want_w ? G + L.lift_w : nullptr, G + L.lift_b, s->part, st);
     return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
@@ -280,10 +288,10 @@ bool create_buffers(fwi_surrogate* s) {
              dalloc(s, &s->g1[i], pd * kC) && dalloc(s, &s->ad[i], pd * kC) && dalloc(s, &s->pd[i], pd * kCH) &&
              dalloc(s, &s->qd[i], pd * kCH);
     const long ntr = Bm * kNS * kNR * kNT;
-    ok = ok && dalloc(s, &s->tmp, pd * kC) && dalloc(s, &s->o, pd * kS) && dalloc(s, &s->out32, Bm * kNT * kX * kS) &&
+    ok = ok && dalloc(s, &s->o, pd * kS) && dalloc(s, &s->out32, Bm * kNT * kX * kS) &&
          dalloc(s, &s->vcache, Bm * kNZ * kNX) && dalloc(s, &s->dout16, Bm * kNT * kX * kS) &&
          dalloc(s, &s->do16, pd * kS) && dalloc(s, &s->do32, pd * kS) && dalloc(s, &s->dg16, pd * kC) &&
-         dalloc(s, &s->dg32, pd * kC) && dalloc(s, &s->dq32, pd * kCH) && dalloc(s, &s->dp32, pd * kCH) &&
+         dalloc(s, &s->dg32, pd * kC) && dalloc(s, &s->dg16b, pd * kC) && dalloc(s, &s->dp32, pd * kCH) &&
          dalloc(s, &s->dp16, pd * kCH) && dalloc(s, &s->da32, pd * kC) && dalloc(s, &s->part, kPartFloats) &&
          dalloc(s, &s->work, kWorkFloats) && dalloc(s, &s->pred, ntr) && dalloc(s, &s->dtr, ntr) &&
          dalloc(s, &s->mx, Bm) && dalloc(s, &s->lpart, 2048) && dalloc(s, &s->lval, 1);

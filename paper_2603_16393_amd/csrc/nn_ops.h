@@ -69,8 +69,8 @@ void lift_fwd(int B, const float* v, const float* W, const float* b, bf16_t* h, 
 void lift_bwd(int B, const float* v, const float* dh, const float* W, float* dv, float* dW, float* db, float* part,
               hipStream_t st);
 void dw_fwd(int B, int H, int W, const bf16_t* in, const float* k, const float* b, bf16_t* out, hipStream_t st);
-void dw_bwd(int B, int H, int W, const bf16_t* in, const float* dout, const float* k, float* din, float* dk, float* db,
-            float* part, hipStream_t st);
+void dw_bwd(int B, int H, int W, const bf16_t* in, const float* dout, const float* k, float* din, bf16_t* din16,
+            float* dk, float* db, float* part, hipStream_t st);
 void gelu_fwd(long n, const bf16_t* p, bf16_t* q, hipStream_t st);
 void gelu_bwd(long n, const float* dq, const bf16_t* p, float* dp, bf16_t* dp16, hipStream_t st);
 void add_bf16(long n, const bf16_t* a, const bf16_t* b, bf16_t* o, hipStream_t st);
