@@ -184,7 +184,8 @@ def bench_uneven(args):
     """64 requests (seeds 2000 + r): 70x70 / 140x140 / 256x256 grids with a 40-cell sponge, 1000 / 1500 / 2500
     samples at dt = 1 ms, 5-10 surface shots, faulted or layered models in 1500-4500 m/s; forward modelling of
     every (request, shot) field in one persistent launch with autotuned tiles.  Per-size rates come from
-    launches of the same kernel over each size class alone."""
+    launches of the same kernel over each size class alone; "gradient" times dJ/dv of the whole batch for given
+    adjoint sources (its forward_gpts_per_s counts the forward point-updates only)."""
     import torch
 
     import fwi_inputs as fi
@@ -230,6 +231,30 @@ def bench_uneven(args):
         per_size[f"{size}x{size}"] = {"requests": len(sel), "units": sum(reqs[r][0].ns for r in sel),
                                       "ms": round(m2, 3), "gpts_per_s": round(g2, 1),
                                       "hbm_frac_alg": round(16.0 * g2 / HBM_PEAK_GBS, 4)}
+    # gradients of the whole batch (forward with D history or checkpoints, then the adjoint sweep and
+    # imaging, every field in one persistent launch, then one fold launch) for band-limited adjoint sources
+    bg = FwiBatch([a for a, _, _ in reqs], autotune=True, device=dev, gradients=True)
+    v = bg.pack_velocity([m for _, m, _ in reqs])
+    w = bg.pack_wavelets([x for _, _, x in reqs])
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    adj = torch.randn(bg.trace_elems, generator=gen, device=dev) * 1e-3
+    g = bg.gradient(v, w, adj)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bg.gradient(v, w, adj, out=g)
+    e1.record()
+    torch.cuda.synchronize()
+    if bg.status() != 0 or not bool(torch.isfinite(g).all()):
+        print("gradient check failed", file=sys.stderr)
+        sys.exit(1)
+    gms = e0.elapsed_time(e1) / reps
+    bg.close()
+    gradient = {"ms": round(gms, 3), "requests_per_s": round(len(reqs) / (gms / 1e3), 2),
+                "fields_per_s": round(sum(a.ns for a, _, _ in reqs) / (gms / 1e3), 1),
+                "forward_gpts_per_s": round(upd / (gms / 1e3) / 1e9, 1), "cost_vs_forward": round(gms / ms, 3)}
     out = {
         "metric": "uneven batch forward GPts/s (64 requests, 70/140/256 grids, 1000-2500 steps)",
         "value": round(gpts, 1),
@@ -246,6 +271,7 @@ def bench_uneven(args):
         "config": {"workload": "uneven batch: 64 requests (seeds 2000+r), 461 (request, shot) fields, "
                                f"{upd / 1e9:.2f} G point-updates per launch, one persistent launch"},
         "per_size": per_size,
+        "gradient": gradient,
         "hbm_frac_alg": round(16.0 * gpts / HBM_PEAK_GBS, 4),
         "tiles": [{"padded": [t[0], t[1]], "kind": "lds" if t[2] == 0 else "hbm", "tile": [t[3], t[4]]} for t in tiles],
         "create_s": round(t_create, 3),

@@ -313,7 +313,7 @@ int fwi_plan_sweep_ms(fwi_plan* plan, float* forward_ms, float* adjoint_ms);
  * are kept for the process) or by a cost model (autotune = 0).
  *
  * Packed layouts (offsets from fwi_batch_get_info, in elements):
- *   v        request r: [nz_r][nx_r] at v_offset
+ *   v, grad  request r: [nz_r][nx_r] at v_offset
  *   wavelets request r: [nt_r] at wavelet_offset (one wavelet for its shots)
  *   traces   request r: [ns_r][nr_r][nt_r] at trace_offset
  * ------------------------------------------------------------------------ */
@@ -321,6 +321,9 @@ typedef struct fwi_batch fwi_batch;
 
 typedef struct {
     int autotune;   /* 1: time the candidate tiles per size class at creation; 0: cost model */
+    int gradients;  /* 1: also allocate what fwi_batch_gradient needs (per field: the full history of D for
+                       LDS-resident fields; checkpoints every ceil(sqrt(2 (nt - 1))) steps, one segment of D
+                       and the adjoint state for HBM-swept ones) */
 } fwi_batch_options;
 
 typedef struct {
@@ -344,6 +347,16 @@ int fwi_batch_sizes(const fwi_batch* batch, size_t* v_elems, size_t* wavelet_ele
  * = 0) in one persistent launch after one coefficient launch (asynchronous).
  * Velocities outside (0, v_max_r] raise the flag read by fwi_batch_status. */
 int fwi_batch_forward(fwi_batch* batch, const float* v, const float* wavelets, float* traces, void* stream);
+/* dJ/dv of every request for given adjoint sources a = dJ/dd (packed like the
+ * traces), as fwi_adjoint_gradient computes it for one plan (the transpose of
+ * the linearised forward map, Sec. 4, summed over shots and folded onto the
+ * model): grad packed like v.  Each field runs its forward sweep and its
+ * adjoint sweep in the same persistent launch (HBM-swept fields recompute
+ * each checkpoint segment), then one launch folds the imaging sums.
+ * FWI_ESTATE unless the batch was created with options.gradients = 1.
+ * Asynchronous. */
+int fwi_batch_gradient(fwi_batch* batch, const float* v, const float* wavelets, const float* adj, float* grad,
+                       void* stream);
 /* Synchronises; FWI_OK or FWI_EDEVICE (and clears the flag). */
 int fwi_batch_status(fwi_batch* batch);
 

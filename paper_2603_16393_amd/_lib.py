@@ -36,6 +36,7 @@ EXPORTED = (
     "fwi_batch_get_info",
     "fwi_batch_sizes",
     "fwi_batch_forward",
+    "fwi_batch_gradient",
     "fwi_batch_status",
     "fwi_error_string",
     "fwi_nn_gemm",
@@ -83,7 +84,7 @@ class PlanOptions(ctypes.Structure):
 
 
 class BatchOptions(ctypes.Structure):
-    _fields_ = [("autotune", c_int)]
+    _fields_ = [("autotune", c_int), ("gradients", c_int)]
 
 
 class BatchRequestInfo(ctypes.Structure):
@@ -133,6 +134,7 @@ def load():
     L.fwi_batch_get_info.argtypes = [P, c_int, ctypes.POINTER(BatchRequestInfo)]
     L.fwi_batch_sizes.argtypes = [P, ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t)]
     L.fwi_batch_forward.argtypes = [P, P, P, P, P]
+    L.fwi_batch_gradient.argtypes = [P, P, P, P, P, P]
     L.fwi_batch_status.argtypes = [P]
     L.fwi_error_string.argtypes = [c_int]
     L.fwi_error_string.restype = ctypes.c_char_p

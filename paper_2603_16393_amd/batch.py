@@ -21,7 +21,8 @@ __all__ = ["FwiBatch"]
 
 
 class FwiBatch:
-    def __init__(self, acqs: Sequence, autotune: bool = True, device: Optional[torch.device] = None):
+    def __init__(self, acqs: Sequence, autotune: bool = True, device: Optional[torch.device] = None,
+                 gradients: bool = False):
         L = _lib.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.acqs = list(acqs)
@@ -35,7 +36,7 @@ class FwiBatch:
                                      int(bool(a.free_surface)), float(a.v_max), len(idx[0]), ip[0], ip[1], len(idx[2]),
                                      ip[2], ip[3])
         h = ctypes.c_void_p()
-        opts = _lib.BatchOptions(int(bool(autotune)))
+        opts = _lib.BatchOptions(int(bool(autotune)), int(bool(gradients)))
         with torch.cuda.device(self.device):
             check(L.fwi_batch_create(len(self.acqs), geoms, ctypes.byref(opts), ctypes.byref(h)), "fwi_batch_create")
         self._h = h
@@ -88,6 +89,32 @@ class FwiBatch:
         _need(out, "traces", (self.trace_elems,), device=self.device)
         check(_lib.load().fwi_batch_forward(self._h, _ptr(v), _ptr(wavelets), _ptr(out), _stream()),
               "fwi_batch_forward")
+        return out
+
+    def pack_traces(self, traces: Sequence[np.ndarray]) -> torch.Tensor:
+        """Per-request [ns, nr, nt] arrays (e.g. adjoint sources) -> packed device buffer."""
+        out = np.empty(self.trace_elems, np.float32)
+        for r, t in enumerate(traces):
+            o = self.info[r]["trace_offset"]
+            out[o:o + t.size] = np.asarray(t, np.float32).reshape(-1)
+        return torch.tensor(out, device=self.device)
+
+    def model_of(self, packed: torch.Tensor, r: int) -> torch.Tensor:
+        a = self.acqs[r]
+        o = self.info[r]["v_offset"]
+        return packed[o:o + a.nz * a.nx].view(a.nz, a.nx)
+
+    def gradient(self, v: torch.Tensor, wavelets: torch.Tensor, adj: torch.Tensor,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dJ/dv of every request for adjoint sources adj (packed like the traces); packed like v."""
+        _need(v, "v", (self.v_elems,), device=self.device)
+        _need(wavelets, "wavelets", (self.wavelet_elems,), device=self.device)
+        _need(adj, "adj", (self.trace_elems,), device=self.device)
+        if out is None:
+            out = torch.empty(self.v_elems, dtype=torch.float32, device=self.device)
+        _need(out, "grad", (self.v_elems,), device=self.device)
+        check(_lib.load().fwi_batch_gradient(self._h, _ptr(v), _ptr(wavelets), _ptr(adj), _ptr(out), _stream()),
+              "fwi_batch_gradient")
         return out
 
     def status(self) -> int:

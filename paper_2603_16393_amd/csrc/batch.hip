@@ -52,6 +52,13 @@ struct BatchUnit {
     float* traces;  // [nr][nt] of this unit
     const float* ax;
     const float* az;
+    // gradients (fwi_batch_gradient): adjoint sources [nr][nt] (bound per call), imaging sum [npts]
+    const float* adj;
+    float* gpad;
+    const float* rec_invw;  // kind 1: [nr] 1/w per receiver
+    // kind 1: adjoint state (psi ping-pong, w_psi), checkpoints [nseg][2][npts], D of one segment [C][npts]
+    float *pa, *pb, *pw, *ckpt, *dseg;
+    int ckpt_every;
 };
 
 // HBM-swept field: wave w of the workgroup owns 64-column panels (column
@@ -187,6 +194,295 @@ __device__ void glb_field_forward(const BatchUnit& Ug, float* lds) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gradients of HBM-swept fields.  glb_steps runs steps n0 .. n1-1 of the
+// forward recursion (optionally saving (u^n, w^n) before every step n that is
+// a multiple of C, and D^n = L u^n + s^n into dseg[n - n0]) or, with ADJ, the
+// adjoint steps for n = n1-1 down to n0 (adjoint source a^{n+1}/w injected at
+// the receivers, imaging acc += psi^{n+1} D^n with D^n from dseg).  The field
+// is streamed column panel by column panel as in glb_field_forward; cur/nxt
+// are swapped after every step so that on return *cur holds the newest state.
+struct GlbCtx {
+    int nzp, nxp, nt, nr, fs, src_pt, rec_z0, rec_z1;
+    float idz2, idx2, src_scale;
+    const float* K;
+    const float* wavelet;
+    const int* rec_map;
+    const float* rec_invw;
+    const float* ax;
+    const float* az;
+    float* traces;      // forward: [nr][nt] or null
+    const float* adj;   // adjoint: [nr][nt]
+};
+
+template <int RB, int SMUL, bool ADJ>
+__device__ void glb_steps(const GlbCtx& c, float*& cur, float*& nxt, float* __restrict__ wst, int n0, int n1,
+                          float* __restrict__ ckpt, int C, float* __restrict__ dseg, float* __restrict__ acc,
+                          float* lds) {
+    constexpr int NW = kLdsThreads / 64;
+    const int nzp = c.nzp, nxp = c.nxp, npts = nzp * nxp;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int G = (nxp + 63) / 64;
+    int S = 1;
+    while ((G * S) % NW != 0) ++S;
+    S *= SMUL;
+    const int seg = (nzp + S - 1) / S;
+    float* rb = lds + wave * 72;
+    for (int it = 0; it < n1 - n0; ++it) {
+        const int n = ADJ ? n1 - 1 - it : n0 + it;
+        if (!ADJ && ckpt && n % C == 0) {  // state before step n
+            float* ck = ckpt + (size_t)(n / C) * 2 * npts;
+            for (int i = tid; i < npts; i += kLdsThreads) {
+                ck[i] = cur[i];
+                ck[npts + i] = wst[i];
+            }
+        }
+        float* dn = dseg ? dseg + (size_t)(n - n0) * npts : nullptr;
+        const float wm = ADJ ? 0.f : c.wavelet[n];
+        for (int pan = wave; pan < G * S; pan += NW) {
+            const int g = pan % G, sg = pan / G;
+            const int x0 = g * 64, x = x0 + lane;
+            const int za = sg * seg, zb = min(nzp, za + seg);
+            if (za >= zb) continue;
+            const bool xin = x < nxp;
+            const float axv = xin ? c.ax[x] : 0.f;
+            const int hx = lane < 4 ? x0 - 4 + lane : x0 + 64 + (lane - 4);
+            const bool hin = lane < 8 && hx >= 0 && hx < nxp;
+            auto ld_u = [&](int z) {
+                const int zz = (c.fs && z < 0) ? -z : z;
+                return (xin && zz >= 0 && zz < nzp) ? cur[zz * nxp + x] : 0.f;
+            };
+            auto ld_h = [&](int z) { return (hin && z >= 0 && z < nzp) ? cur[z * nxp + hx] : 0.f; };
+            float col[RB + 8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) col[k] = ld_u(za - 4 + k);
+            float cu[RB], ck[RB], cw[RB], chl[RB];
+#pragma unroll
+            for (int jj = 0; jj < RB; ++jj) {
+                const int z = za + jj;
+                const bool ok = xin && z < zb;
+                cu[jj] = ld_u(z + 4);
+                ck[jj] = ok ? c.K[z * nxp + x] : 0.f;
+                cw[jj] = ok ? wst[z * nxp + x] : 0.f;
+                chl[jj] = (z < zb) ? ld_h(z) : 0.f;
+            }
+            for (int z0 = za; z0 < zb; z0 += RB) {
+                float nu[RB], nk[RB], nw[RB], nh[RB];
+                const int z1 = z0 + RB;
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {
+                    const int z = z1 + jj;
+                    const bool ok = xin && z < zb;
+                    nu[jj] = (z1 < zb) ? ld_u(z + 4) : 0.f;
+                    nk[jj] = ok ? c.K[z * nxp + x] : 0.f;
+                    nw[jj] = ok ? wst[z * nxp + x] : 0.f;
+                    nh[jj] = (z < zb) ? ld_h(z) : 0.f;
+                }
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) col[8 + jj] = cu[jj];
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {
+                    const int z = z0 + jj;
+                    if (z >= zb) break;
+                    const float cc = col[jj + 4];
+                    rb[lane + 4] = cc;
+                    if (lane < 8) rb[lane < 4 ? lane : 64 + lane] = chl[jj];
+                    __builtin_amdgcn_wave_barrier();
+                    float xr[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) xr[k] = rb[lane + k];
+                    __builtin_amdgcn_wave_barrier();
+                    const float lzs = FWI_LAPD(cc, col[jj], col[jj + 1], col[jj + 2], col[jj + 3], col[jj + 5],
+                                               col[jj + 6], col[jj + 7], col[jj + 8]);
+                    const float lxs = FWI_LAPD(cc, xr[0], xr[1], xr[2], xr[3], xr[5], xr[6], xr[7], xr[8]);
+                    float D = fmaf(lzs, c.idz2, lxs * c.idx2);
+                    const int p = z * nxp + x;
+                    if (xin) {
+                        const bool recrow = z >= c.rec_z0 && z <= c.rec_z1;
+                        const int r = recrow ? c.rec_map[p] : -1;
+                        if (ADJ) {
+                            if (r >= 0) D = fmaf(c.rec_invw[r], c.adj[(size_t)r * c.nt + n + 1], D);
+                        } else if (p == c.src_pt) {
+                            D = fmaf(wm, c.src_scale, D);
+                        }
+                        const float wn = fmaf(ck[jj], D, (axv * c.az[z]) * cw[jj]);
+                        const float un = cc + wn;
+                        wst[p] = wn;
+                        nxt[p] = un;
+                        if (ADJ) {
+                            acc[p] = fmaf(un, dn[p], acc[p]);
+                        } else {
+                            if (dn) dn[p] = D;
+                            if (r >= 0 && c.traces) c.traces[(size_t)r * c.nt + n + 1] = un;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) col[k] = col[RB + k];
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {
+                    cu[jj] = nu[jj];
+                    ck[jj] = nk[jj];
+                    cw[jj] = nw[jj];
+                    chl[jj] = nh[jj];
+                }
+            }
+        }
+        __syncthreads();
+        float* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+__device__ inline GlbCtx glb_ctx(const BatchUnit* U) {
+    GlbCtx c;
+    c.nzp = U->nzp, c.nxp = U->nxp, c.nt = U->nt, c.nr = U->nr, c.fs = U->fs, c.src_pt = U->src_pt;
+    c.rec_z0 = U->rec_z0, c.rec_z1 = U->rec_z1;
+    c.idz2 = U->idz2, c.idx2 = U->idx2, c.src_scale = U->src_scale;
+    c.K = U->K, c.wavelet = U->wavelet, c.rec_map = U->rec_map, c.rec_invw = U->rec_invw;
+    c.ax = U->ax, c.az = U->az, c.traces = nullptr, c.adj = U->adj;
+    return c;
+}
+
+// dJ/dv_pad (before the 2 w / v factor) of one HBM-swept field: forward with
+// checkpoints every C steps, then per segment (last first) recomputation of
+// D from its checkpoint and the adjoint steps through it.
+template <int RB, int SM>
+__device__ __noinline__ void unit_glb_gradient(const BatchUnit* __restrict__ U, float* lds) {
+    const GlbCtx c = glb_ctx(U);
+    const int npts = c.nzp * c.nxp, nsteps = U->nsteps, C = U->ckpt_every;
+    const int nseg = (nsteps + C - 1) / C;
+    float* u0 = U->ua;
+    float* u1 = U->ub;
+    float* w = U->w;
+    float* p0 = U->pa;
+    float* p1 = U->pb;
+    float* pw = U->pw;
+    float* acc = U->gpad;
+    for (int i = threadIdx.x; i < npts; i += kLdsThreads) {
+        u0[i] = 0.f;
+        w[i] = 0.f;
+        p0[i] = 0.f;
+        pw[i] = 0.f;
+        acc[i] = 0.f;
+    }
+    __syncthreads();
+    glb_steps<RB, SM, false>(c, u0, u1, w, 0, nsteps, U->ckpt, C, nullptr, nullptr, lds);
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int n0 = sgi * C, n1 = min(n0 + C, nsteps);
+        const float* ck = U->ckpt + (size_t)sgi * 2 * npts;
+        for (int i = threadIdx.x; i < npts; i += kLdsThreads) {
+            u0[i] = ck[i];
+            w[i] = ck[npts + i];
+        }
+        __syncthreads();
+        glb_steps<RB, SM, false>(c, u0, u1, w, n0, n1, nullptr, C, U->dseg, nullptr, lds);
+        glb_steps<RB, SM, true>(c, p0, p1, pw, n0, n1, nullptr, C, U->dseg, acc, lds);
+    }
+}
+
+// LDS-resident field: forward sweep keeping the full history of D, then the
+// adjoint sweep (separate non-inlined entries: each gets its own registers).
+template <int X, int P, bool EX>
+__device__ __noinline__ void unit_lds_forward_store(const BatchUnit* __restrict__ U, float* lds) {
+    const LdsArgs a = U->la;
+    lds_field<X, P, false, EX, true>(a, 0, U->ax, U->az, lds);
+}
+
+template <int X, int P, bool EX>
+__device__ __noinline__ void unit_lds_adjoint(const BatchUnit* __restrict__ U, float* lds) {
+    LdsArgs a = U->la;
+    a.adj = U->adj;
+    a.gpad = U->gpad;
+    lds_field<X, P, true, EX, false>(a, 0, U->ax, U->az, lds);
+}
+
+template <int X, int P, bool EX>
+__device__ void unit_lds_gradient(const BatchUnit* __restrict__ U, float* lds) {
+    unit_lds_forward_store<X, P, EX>(U, lds);
+    __syncthreads();
+    unit_lds_adjoint<X, P, EX>(U, lds);
+}
+
+__device__ void run_unit_gradient(const BatchUnit* U, float* lds) {
+    const int kind = U->kind, variant = U->variant;
+    if (kind == 0) {
+#define FWI_LDS_CASE(ID, XX, PP, EX)              \
+    if (variant == ID) {                          \
+        unit_lds_gradient<XX, PP, EX>(U, lds);    \
+        return;                                   \
+    }
+        FWI_BATCH_LDS(FWI_LDS_CASE)
+#undef FWI_LDS_CASE
+    } else {
+#define FWI_GLB_CASE(ID, RBB, SM)                 \
+    if (variant == ID) {                          \
+        unit_glb_gradient<RBB, SM>(U, lds);       \
+        return;                                   \
+    }
+        FWI_BATCH_GLB(FWI_GLB_CASE)
+#undef FWI_GLB_CASE
+    }
+}
+
+__global__ __launch_bounds__(kLdsThreads) void k_batch_gradient(const BatchUnit* __restrict__ units, int nunits,
+                                                                int* __restrict__ counter) {
+    extern __shared__ float lds[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int u = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (u >= nunits) break;
+        run_unit_gradient(units + u, lds);
+        __syncthreads();
+    }
+}
+
+// grad_r[iz][ix] = sum over the padded cells replicating (iz, ix) (rows outer,
+// columns inner, as the plan's two-pass fold) of sum_s gpad * 2 w dt / sqrt(K)
+struct FoldReq {
+    long long v_off, pt_off, g_off;
+    int nz, nx, nzp, nxp, nb, ztop, ns;
+    float dt, w0;  // w0: row weight of padded row 0 (1/2 on a reflecting top)
+};
+
+__global__ void k_batch_fold(const FoldReq* __restrict__ req, int nreq, long long total, const float* __restrict__ K,
+                             const float* __restrict__ gpad, float* __restrict__ grad) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nreq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (req[mid].v_off <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const FoldReq& q = req[lo];
+        const int cell = (int)(i - q.v_off);
+        const int iz = cell / q.nx, ix = cell - (cell / q.nx) * q.nx;
+        const int zlo = (iz == 0) ? 0 : iz + q.ztop, zhi = (iz == q.nz - 1) ? q.nzp - 1 : iz + q.ztop;
+        const int xlo = (ix == 0) ? 0 : ix + q.nb, xhi = (ix == q.nx - 1) ? q.nxp - 1 : ix + q.nb;
+        const int npts = q.nzp * q.nxp;
+        float sum = 0.f;
+        for (int z = zlo; z <= zhi; ++z) {
+            const float wz = 2.f * (z == 0 ? q.w0 : 1.f) * q.dt;
+            float row = 0.f;
+            for (int x = xlo; x <= xhi; ++x) {
+                float gs = 0.f;
+                for (int s = 0; s < q.ns; ++s) gs += gpad[q.g_off + (long long)s * npts + z * q.nxp + x];
+                row += gs * (wz / sqrtf(K[q.pt_off + z * q.nxp + x]));
+            }
+            sum += row;
+        }
+        grad[i] = sum;
+    }
+}
+
 // One non-inlined entry per compiled variant: each gets its own register
 // allocation (the persistent kernel needs only the largest, not their sum);
 // the call happens once per unit.
@@ -237,15 +533,18 @@ __global__ __launch_bounds__(kLdsThreads) void k_batch_forward(const BatchUnit* 
     }
 }
 
-// Points the queued units at this call's packed traces and wavelets.
+// Points the queued units at this call's packed traces, wavelets and (for
+// gradients) adjoint sources.
 __global__ void k_batch_bind(BatchUnit* __restrict__ units, int nunits, float* __restrict__ traces,
-                             const float* __restrict__ wavelets) {
+                             const float* __restrict__ wavelets, const float* __restrict__ adj) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= nunits) return;
     BatchUnit& U = units[u];
+    U.adj = adj ? adj + U.tr_off : nullptr;
     if (U.kind == 0) {
         U.la.traces = traces + U.tr_off;
         U.la.wavelet = wavelets + U.w_off;
+        U.la.adj = U.adj;
     } else {
         U.traces = traces + U.tr_off;
         U.wavelet = wavelets + U.w_off;
@@ -312,6 +611,13 @@ struct fwi_batch {
     size_t lds_bytes = 0;
     std::vector<void*> allocs;
     std::vector<std::pair<int, int>> shape;      // (nzp, nxp) of each request
+    // gradients
+    int gradients = 0;
+    float* gpad = nullptr;         // per request [ns][npts] at g_off
+    float* tr_scratch = nullptr;   // traces of the gradient's forward sweeps
+    FoldReq* d_fold = nullptr;
+    std::vector<long long> g_off;
+    size_t grad_bytes = 0;
 };
 
 namespace {
@@ -370,8 +676,15 @@ void bfree(fwi_batch* b) {
 }
 
 int launch_units(BatchUnit* d_units, int nunits, int* counter, int grid, size_t lds, float* traces,
-                 const float* wavelets, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_bind, dim3((nunits + 255) / 256), dim3(256), 0, st, d_units, nunits, traces, wavelets);
+                 const float* wavelets, hipStream_t st, const float* adj = nullptr, bool gradient = false) {
+    hipLaunchKernelGGL(k_batch_bind, dim3((nunits + 255) / 256), dim3(256), 0, st, d_units, nunits, traces, wavelets,
+                       adj);
+    if (gradient) {
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+        (void)hipFuncSetAttribute((const void*)k_batch_gradient, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_batch_gradient, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
+        return hip_ok(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
     (void)hipFuncSetAttribute((const void*)k_batch_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_batch_forward, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
@@ -386,6 +699,7 @@ struct ReqDev {
     int* src_pt;
     int* rec_map;
     int* rec_of_col;
+    float* rec_invw;
     HostTables ht;
 };
 
@@ -439,6 +753,7 @@ BatchUnit make_unit(const fwi_batch* b, int r, int s, int kind, int variant, con
         U.src_scale = (float)(1.0 / (g.dx * g.dz));
         U.K = K;
         U.rec_map = rd.rec_map;
+        U.rec_invw = rd.rec_invw;
         const size_t npts = (size_t)nzp * nxp;
         U.ua = state;
         U.ub = state + npts;
@@ -454,9 +769,9 @@ extern "C" {
 int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_options* opt, fwi_batch** out) {
     if (!out || nreq < 1 || !geoms) return FWI_EINVAL;
     *out = nullptr;
-    fwi_batch_options o{1};
+    fwi_batch_options o{1, 0};
     if (opt) o = *opt;
-    if (o.autotune < 0 || o.autotune > 1) return FWI_EINVAL;
+    if (o.autotune < 0 || o.autotune > 1 || o.gradients < 0 || o.gradients > 1) return FWI_EINVAL;
     for (int r = 0; r < nreq; ++r) {
         const int st = validate_geometry(&geoms[r], 1);
         if (st) return st;
@@ -505,6 +820,7 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
         st = st ? st : balloc(b, &rd[r].src_pt, (size_t)g.ns);
         st = st ? st : balloc(b, &rd[r].rec_map, (size_t)nzp * nxp);
         st = st ? st : balloc(b, &rd[r].rec_of_col, (size_t)nxp);
+        st = st ? st : balloc(b, &rd[r].rec_invw, (size_t)g.nr);
         if (st) break;
         const HostTables& t = rd[r].ht;
         st = hip_ok(hipMemcpy(rd[r].ax, t.ax.data(), nxp * sizeof(float), hipMemcpyHostToDevice));
@@ -515,6 +831,8 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                                    hipMemcpyHostToDevice));
         st = st ? st
                 : hip_ok(hipMemcpy(rd[r].rec_of_col, t.rec_of_col.data(), nxp * sizeof(int), hipMemcpyHostToDevice));
+        st = st ? st
+                : hip_ok(hipMemcpy(rd[r].rec_invw, t.rec_invw.data(), g.nr * sizeof(float), hipMemcpyHostToDevice));
         if (st) break;
     }
     st = st ? st : balloc(b, &b->K, (size_t)b->pt_total);
@@ -677,6 +995,52 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             const size_t lb = b->kind[r] == 0 ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip) : glb_lds(U.variant, U.nzp);
             b->lds_bytes = std::max(b->lds_bytes, lb);
         }
+        if (st == FWI_OK && o.gradients) {
+            // per unit: LDS-resident -> full history of D; HBM-swept -> adjoint state,
+            // checkpoints every C = ceil(sqrt(2 (nt - 1))) steps and one segment of D
+            b->gradients = 1;
+            long long gtot = 0;
+            for (int r = 0; r < nreq; ++r) {
+                b->g_off.push_back(gtot);
+                gtot += (long long)b->g[r].ns * b->nzp[r] * b->nxp[r];
+            }
+            st = balloc(b, &b->gpad, (size_t)gtot);
+            st = st ? st : balloc(b, &b->tr_scratch, (size_t)b->tr_total);
+            b->grad_bytes = (size_t)(gtot + b->tr_total) * sizeof(float);
+            for (size_t ui = 0; ui < b->units.size() && st == FWI_OK; ++ui) {
+                BatchUnit& U = b->units[ui];
+                const int r = b->unit_req[ui];
+                const int shot = jobs[ui].s;
+                const size_t npts = (size_t)b->nzp[r] * b->nxp[r];
+                const int nsteps = b->g[r].nt - 1;
+                U.gpad = b->gpad + b->g_off[r] + (long long)shot * npts;
+                if (U.kind == 0) {
+                    float* dst = nullptr;
+                    st = balloc(b, &dst, (size_t)nsteps * npts);
+                    U.la.Dstore = dst;
+                    b->grad_bytes += (size_t)nsteps * npts * sizeof(float);
+                } else {
+                    const int C = std::max(1, std::min(nsteps, (int)std::ceil(std::sqrt(2.0 * nsteps))));
+                    const int nseg = (nsteps + C - 1) / C;
+                    float* buf = nullptr;
+                    const size_t n = (3 + 2 * (size_t)nseg + C) * npts;
+                    st = balloc(b, &buf, n);
+                    U.pa = buf;
+                    U.pb = buf + npts;
+                    U.pw = buf + 2 * npts;
+                    U.ckpt = buf + 3 * npts;
+                    U.dseg = buf + (3 + 2 * (size_t)nseg) * npts;
+                    U.ckpt_every = C;
+                    b->grad_bytes += n * sizeof(float);
+                }
+            }
+            std::vector<FoldReq> fr(nreq);
+            for (int r = 0; r < nreq; ++r)
+                fr[r] = {b->v_off[r], b->pt_off[r], b->g_off[r], b->g[r].nz, b->g[r].nx, b->nzp[r], b->nxp[r],
+                         b->g[r].nb, b->ztop[r], b->g[r].ns, (float)b->g[r].dt, b->g[r].free_surface ? 0.5f : 1.f};
+            st = st ? st : balloc(b, &b->d_fold, (size_t)nreq);
+            st = st ? st : hip_ok(hipMemcpy(b->d_fold, fr.data(), nreq * sizeof(FoldReq), hipMemcpyHostToDevice));
+        }
         st = st ? st : balloc(b, &b->d_units, b->units.size());
         st = st ? st
                 : hip_ok(hipMemcpy(b->d_units, b->units.data(), b->units.size() * sizeof(BatchUnit),
@@ -744,6 +1108,26 @@ int fwi_batch_forward(fwi_batch* b, const float* v, const float* wavelets, float
     if (hipGetLastError() != hipSuccess) return FWI_EHIP;
     const int grid = std::min<int>(b->n_cu, (int)b->units.size());
     return launch_units(b->d_units, (int)b->units.size(), b->counter, grid, b->lds_bytes, traces, wavelets, st);
+}
+
+int fwi_batch_gradient(fwi_batch* b, const float* v, const float* wavelets, const float* adj, float* grad,
+                       void* stream) {
+    if (!b || !v || !wavelets || !adj || !grad) return FWI_EINVAL;
+    if (!b->gradients) return FWI_ESTATE;
+    (void)hipSetDevice(b->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const long long total = b->pt_total;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_batch_prep, dim3(blocks), dim3(256), 0, st, b->d_prep, b->nreq, total, v, b->K, b->flags);
+    if (hipGetLastError() != hipSuccess) return FWI_EHIP;
+    const int grid = std::min<int>(b->n_cu, (int)b->units.size());
+    int rc = launch_units(b->d_units, (int)b->units.size(), b->counter, grid, b->lds_bytes, b->tr_scratch, wavelets,
+                          st, adj, true);
+    if (rc) return rc;
+    const long long cells = b->v_total;
+    hipLaunchKernelGGL(k_batch_fold, dim3((int)std::min<long long>((cells + 255) / 256, 65535)), dim3(256), 0, st,
+                       b->d_fold, b->nreq, cells, b->K, b->gpad, grad);
+    return hip_ok(hipGetLastError());
 }
 
 int fwi_batch_status(fwi_batch* b) {

@@ -1,10 +1,13 @@
 """Uneven batches in one persistent launch (fwi_batch_*) vs the FP64 oracle
 and vs the per-geometry plan, through the C ABI.
 
-Bars: seismograms relative L2 <= 1e-4 against the oracle (the FP32-stencil
-target); against the plan's own sweep for the same geometry the arithmetic
-per point is the same, so traces must agree bitwise (LDS-resident units vs
-the LDS path, HBM-swept units vs the tiled path).
+Bars: seismograms and gradients relative L2 <= 1e-4 against the oracle (the
+FP32-stencil target); against the plan's own sweep for the same geometry the
+arithmetic per point is the same, so traces must agree bitwise (LDS-resident
+units vs the LDS path, HBM-swept units vs the tiled path).  Gradients against
+the plan agree to 1e-6 (the injection and imaging sums are the same
+operations, the checkpoint schedules differ only in which steps are
+recomputed, which is exact).
 """
 import dataclasses
 import sys
@@ -133,4 +136,111 @@ def test_uneven_64_requests_sampled_vs_oracle(dev):
         _say(f"request {r} ({a.nz}x{a.nx}, nt {a.nt}, shot {s}/{a.ns}, kind {b.info[r]['kind']}): rel L2 {err:.2e}")
         assert err <= 1e-4
     assert seen == {70, 140, 256}
+    b.close()
+
+
+def _adjoint_sources(acq, seed):
+    """Band-limited adjoint sources [ns][nr][nt] (white noise filtered by the
+    request's Ricker wavelet); the gradient is linear in them."""
+    rng = np.random.default_rng(seed)
+    wav = fi.ricker(acq.nt, acq.dt, acq.f_peak)
+    k = wav[: min(acq.nt, int(np.argmax(np.abs(wav))) * 2 + 1)]
+    noise = rng.standard_normal((acq.ns, acq.nr, acq.nt))
+    out = np.apply_along_axis(lambda t: np.convolve(t, k, mode="same"), 2, noise)
+    return (out / np.abs(out).max()).astype(np.float32)
+
+
+@pytest.mark.parametrize("autotune", [True, False])
+def test_small_uneven_batch_gradient_vs_oracle_and_plans(dev, autotune):
+    import oracle
+    from paper_2603_16393_amd import FwiPlan
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = _small_requests()
+    b = FwiBatch([a for a, _, _ in reqs], autotune=autotune, device=dev, gradients=True)
+    kinds = [i["kind"] for i in b.info]
+    _say(f"gradient batch: kinds {kinds} tiles {[(i['tile_x'], i['tile_z']) for i in b.info]}")
+    v = b.pack_velocity([m for _, m, _ in reqs])
+    w = b.pack_wavelets([x for _, _, x in reqs])
+    adjs = [_adjoint_sources(a, 10 + r) for r, (a, _, _) in enumerate(reqs)]
+    adj = b.pack_traces(adjs)
+    tr = b.forward(v, w)
+    g1 = b.gradient(v, w, adj)
+    g2 = b.gradient(v, w, adj)
+    tr2 = b.forward(v, w)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    assert torch.equal(g1, g2), "gradient not reproducible"
+    assert torch.equal(tr, tr2), "forward changed by a gradient call"
+    for r, (a, m, wav) in enumerate(reqs):
+        got = b.model_of(g1, r).cpu().numpy()
+        m32 = np.asarray(m, np.float32)
+        ref = oracle.gradient(a, m32.astype(np.float64), np.asarray(wav, np.float32).astype(np.float64),
+                              adjs[r].astype(np.float64))
+        err = _rel(got, ref)
+        plan = FwiPlan(a, max_batch=1, device=dev, force_path=-1 if kinds[r] == 0 else 1)
+        vt = torch.tensor(m32[None], device=dev)
+        plan.forward(vt, torch.tensor(np.asarray(wav, np.float32), device=dev), keep_for_adjoint=True)
+        gp = plan.adjoint_gradient(vt, torch.tensor(adjs[r][None], device=dev))[0].cpu().numpy()
+        plan.close()
+        ep = _rel(got, gp)
+        _say(f"request {r} kind {kinds[r]}: gradient rel L2 vs oracle {err:.2e}, vs plan {ep:.2e}")
+        assert err <= 1e-4
+        assert np.array_equal(got, gp), f"request {r}: batch and plan gradients differ"
+    b.close()
+
+
+def test_gradient_needs_the_option(dev):
+    from paper_2603_16393_amd import _lib
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = _small_requests()[:1]
+    b = FwiBatch([a for a, _, _ in reqs], autotune=False, device=dev)
+    v = b.pack_velocity([reqs[0][1]])
+    w = b.pack_wavelets([reqs[0][2]])
+    adj = torch.zeros(b.trace_elems, dtype=torch.float32, device=dev)
+    with pytest.raises(_lib.FwiError) as e:
+        b.gradient(v, w, adj)
+    assert e.value.code == _lib.FWI_ESTATE
+    b.close()
+
+
+def test_uneven_64_requests_gradient_sampled_vs_oracle(dev):
+    """Gradients of the 64-request mixed batch in one launch: every request
+    gets band-limited adjoint sources, except that for one request per size
+    class (the shortest record) they are zero on all shots but the last, so
+    its gradient is that one shot's, which the oracle computes."""
+    import oracle
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = fi.uneven_requests()
+    picked = {}
+    for r, (a, _, _) in enumerate(reqs):
+        if a.nz not in picked or a.nt < reqs[picked[a.nz]][0].nt:
+            picked[a.nz] = r
+    b = FwiBatch([a for a, _, _ in reqs], autotune=True, device=dev, gradients=True)
+    v = b.pack_velocity([m for _, m, _ in reqs])
+    w = b.pack_wavelets([x for _, _, x in reqs])
+    adjs = []
+    for r, (a, _, _) in enumerate(reqs):
+        x = _adjoint_sources(a, 100 + r)
+        if r in picked.values():
+            x[:-1] = 0.0
+        adjs.append(x)
+    g = b.gradient(v, w, b.pack_traces(adjs))
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    assert bool(torch.isfinite(g).all())
+    for nz, r in sorted(picked.items()):
+        a, m, wav = reqs[r]
+        s = a.ns - 1
+        sub = a.subset_shots([s])
+        ref = oracle.gradient(sub, np.asarray(m, np.float32).astype(np.float64),
+                              np.asarray(wav, np.float32).astype(np.float64), adjs[r][s:].astype(np.float64))
+        got = b.model_of(g, r).cpu().numpy()
+        err = _rel(got, ref)
+        _say(f"request {r} ({a.nz}x{a.nx}, nt {a.nt}, shot {s}/{a.ns}, kind {b.info[r]['kind']}): "
+             f"gradient rel L2 {err:.2e}")
+        assert err <= 1e-4
+    assert set(picked) == {70, 140, 256}
     b.close()
