@@ -649,6 +649,10 @@ const GlbVar kGlbVar[kBatchGlbVariants] = {
 #undef FWI_V
 };
 
+// dynamic LDS of the persistent kernels: all of it but a little for their
+// static variables (the work-queue slot)
+constexpr int kBatchDynLds = kLdsBytes - 256;
+
 // one 72-float row buffer per wave
 size_t glb_lds(int, int) { return (size_t)(kLdsThreads / 64) * 72 * sizeof(float); }
 
@@ -658,7 +662,7 @@ bool lds_var_fits(int v, int nzp, int nxp, int* ncg, int* nstrip) {
     *nstrip = (nzp + L.P - 1) / L.P;
     const bool exact = *ncg * L.X == nxp && *nstrip * L.P == nzp;
     if (L.exact != exact) return false;
-    return *ncg * *nstrip <= kLdsThreads && lds_bytes(L.X, L.P, *ncg, *nstrip) <= (size_t)kLdsBytes;
+    return *ncg * *nstrip <= kLdsThreads && lds_bytes(L.X, L.P, *ncg, *nstrip) <= (size_t)kBatchDynLds;
 }
 
 template <class T>
@@ -681,12 +685,10 @@ int launch_units(BatchUnit* d_units, int nunits, int* counter, int grid, size_t 
                        adj);
     if (gradient) {
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-        (void)hipFuncSetAttribute((const void*)k_batch_gradient, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k_batch_gradient, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
         return hip_ok(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-    (void)hipFuncSetAttribute((const void*)k_batch_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_batch_forward, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
     return hip_ok(hipGetLastError());
 }
@@ -775,6 +777,16 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
     for (int r = 0; r < nreq; ++r) {
         const int st = validate_geometry(&geoms[r], 1);
         if (st) return st;
+    }
+    // the persistent kernels may use all of the LDS their static variables
+    // leave; set here so that the launches make no other runtime calls
+    for (const void* kern : {(const void*)k_batch_forward, (const void*)k_batch_gradient}) {
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, kern) != hipSuccess || (int)fa.sharedSizeBytes > kLdsBytes - kBatchDynLds ||
+            hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchDynLds) != hipSuccess) {
+            (void)hipGetLastError();
+            return FWI_EHIP;
+        }
     }
     fwi_batch* b = new (std::nothrow) fwi_batch();
     if (!b) return FWI_ENOMEM;

@@ -244,3 +244,45 @@ def test_uneven_64_requests_gradient_sampled_vs_oracle(dev):
         assert err <= 1e-4
     assert set(picked) == {70, 140, 256}
     b.close()
+
+
+def test_batch_launches_replay_from_a_captured_graph(dev):
+    """fwi_batch_forward / fwi_batch_gradient issue only kernels on the
+    caller's stream (the work-queue counter is cleared by a kernel), so a
+    caller can capture them into a graph; every replay, with eager calls in
+    between, matches the eager result bit for bit."""
+    from paper_2603_16393_amd.batch import FwiBatch
+
+    reqs = _small_requests()
+    b = FwiBatch([a for a, _, _ in reqs], autotune=False, device=dev, gradients=True)
+    v = b.pack_velocity([m for _, m, _ in reqs])
+    w = b.pack_wavelets([x for _, _, x in reqs])
+    adj = b.pack_traces([_adjoint_sources(a, 40 + r) for r, (a, _, _) in enumerate(reqs)])
+    tr_ref = b.forward(v, w).clone()
+    g_ref = b.gradient(v, w, adj).clone()
+    torch.cuda.synchronize()
+    tr = torch.zeros_like(tr_ref)
+    g = torch.zeros_like(g_ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        b.forward(v, w, out=tr)  # warm-up on the capture stream
+        b.gradient(v, w, adj, out=g)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            b.forward(v, w, out=tr)
+            b.gradient(v, w, adj, out=g)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        tr.zero_()
+        g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(tr, tr_ref), f"replay {rep}: traces differ"
+        assert torch.equal(g, g_ref), f"replay {rep}: gradient differs"
+        b.forward(v, w)  # eager work between replays
+        torch.cuda.synchronize()
+    assert b.status() == 0
+    del graph
+    b.close()
