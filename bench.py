@@ -503,7 +503,9 @@ def main():
     alg_bytes = 16.0 * updates + 4.0 * B * NS * (NT - 1) * NZ * NX
     adj_dominant = adj_sweep_ms >= fwd_sweep_ms
     dom_ms = max(fwd_sweep_ms, adj_sweep_ms)
-    dom = "k_wave_lds<ADJ> (adjoint sweep)" if adj_dominant else "k_wave_lds (forward sweep)"
+    split = plan.info.get("lds_split", 1) > 1
+    kname = "k_wave_split" if split else "k_wave_lds"
+    dom = f"{kname}<ADJ> (adjoint sweep)" if adj_dominant else f"{kname} (forward sweep)"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
     traffic = measured_traffic("adjoint" if adj_dominant else "forward")
     out = {
@@ -525,7 +527,9 @@ def main():
                         "adjoint gradient, preconditioned update",
             "batch": B,
             "padded_grid": [nzp, nxp],
-            "path": "lds-resident" if plan.info["path"] == 0 else "tiled",
+            "path": ("lds-resident" if plan.info["path"] == 0 else "tiled") +
+                    (f", {plan.info['lds_split']} workgroups per field" if split else ""),
+            "tile": [plan.info["lds_tile_x"], plan.info["lds_tile_z"]],
         },
         "stage_ms": {"forward": round(stage_ms[0], 4), "w2_misfit": round(stage_ms[1], 4),
                      "adjoint_gradient": round(stage_ms[2], 4), "guidance": round(stage_ms[3], 4)},

@@ -108,6 +108,8 @@ typedef struct {
     int max_batch;
     size_t device_bytes;       /* device memory held by the plan */
     int lds_tile_x, lds_tile_z;  /* register tile of the LDS-resident path (0 on the tiled path) */
+    int lds_split;             /* LDS-resident path: workgroups sharing one field (1: one per field; 0 on the
+                                  tiled path) */
 } fwi_plan_info;
 
 /* Creates a plan for up to `max_batch` velocity samples on the current device.
@@ -128,6 +130,10 @@ typedef struct {
     int lds_tile_z;     /* 0, 0 = the built-in cost model's choice; FWI_EINVAL if not available */
     int timing;         /* 1: record HIP events around each forward and adjoint sweep on the caller's
                            stream (read with fwi_plan_sweep_ms); 0: off */
+    int split;          /* LDS-resident path, when max_batch * ns fields leave CUs idle: 0 = split each field
+                           over several workgroups (row bands exchanging 4-row halos every step, launched
+                           cooperatively) if the cost model prefers it, and never with an explicit lds tile;
+                           1 = split whenever feasible (FWI_EINVAL if not); -1 = never */
 } fwi_plan_options;
 
 /* fwi_plan_create with explicit execution options (NULL = automatic). */

@@ -75,12 +75,13 @@ class GuidanceParams(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("nzp", c_int), ("nxp", c_int), ("path", c_int), ("store_mode", c_int), ("ckpt_every", c_int),
-                ("max_batch", c_int), ("device_bytes", c_size_t), ("lds_tile_x", c_int), ("lds_tile_z", c_int)]
+                ("max_batch", c_int), ("device_bytes", c_size_t), ("lds_tile_x", c_int), ("lds_tile_z", c_int),
+                ("lds_split", c_int)]
 
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("force_path", c_int), ("ckpt_every", c_int), ("lds_tile_x", c_int), ("lds_tile_z", c_int),
-                ("timing", c_int)]
+                ("timing", c_int), ("split", c_int)]
 
 
 class BatchOptions(ctypes.Structure):

@@ -130,9 +130,11 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     *out = nullptr;
     int st = validate_geometry(geom, max_batch);
     if (st) return st;
-    fwi_plan_options o{-1, 0, 0, 0, 0};
+    fwi_plan_options o{-1, 0, 0, 0, 0, 0};
     if (opt) o = *opt;
-    if (o.force_path < -1 || o.force_path > 1 || o.ckpt_every < 0 || o.timing < 0 || o.timing > 1) return FWI_EINVAL;
+    if (o.force_path < -1 || o.force_path > 1 || o.ckpt_every < 0 || o.timing < 0 || o.timing > 1 || o.split < -1 ||
+        o.split > 1)
+        return FWI_EINVAL;
 
     fwi_plan* pp = new (std::nothrow) fwi_plan();
     if (!pp) return FWI_ENOMEM;
@@ -219,8 +221,34 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         const size_t need = fixed + 6 * nf * npts * sizeof(float) +
                             nf * ((size_t)p.ckpt_every + 2 * (size_t)p.nseg) * npts * sizeof(float);
         if (need > avail) {
+            free_all(p);
             delete pp;
             return FWI_ENOMEM;
+        }
+    }
+
+    // LDS-resident path: several workgroups per field when the batch leaves CUs idle
+    if (o.split > 0 && p.path != 0) {
+        free_all(p);
+        delete pp;
+        return FWI_EINVAL;
+    }
+    if (p.path == 0) {
+        int ncu = 0, coop = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device) != hipSuccess ||
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p.device) != hipSuccess) {
+            (void)hipGetLastError();
+            ncu = coop = 0;
+        }
+        const int force = (o.split == 0 && (o.lds_tile_x > 0 || o.lds_tile_z > 0)) ? -1 : o.split;
+        if (coop && lds_choose_split(p.nzp, p.nxp, (int)nf, ncu, p.lds_X, p.lds_P, force, &p.split_X, &p.split_P,
+                                     &p.split_ncg, &p.split_nstrip, &p.split_G)) {
+        } else if (o.split > 0) {
+            free_all(p);
+            delete pp;
+            return FWI_EINVAL;
+        } else {
+            p.split_G = 1;
         }
     }
 
@@ -270,6 +298,8 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
     } else {
         st = st ? st : alloc_n(p, &p.rec_of_col, (size_t)p.nxp);
+        if (p.split_G > 1)
+            st = st ? st : alloc_n(p, &p.xchg, nf * p.split_G * 2 * 2 * 4 * (size_t)p.split_ncg * p.split_X);
     }
     if (p.store_mode == 0) {
         st = st ? st : alloc_n(p, &p.Dstore, nf * nsteps * npts);
@@ -337,8 +367,10 @@ int fwi_plan_get_info(const fwi_plan* plan, fwi_plan_info* info) {
     info->ckpt_every = plan->ckpt_every;
     info->max_batch = plan->max_batch;
     info->device_bytes = plan->device_bytes;
-    info->lds_tile_x = plan->path == 0 ? plan->lds_X : 0;
-    info->lds_tile_z = plan->path == 0 ? plan->lds_P : 0;
+    const bool split = plan->path == 0 && plan->split_G > 1;
+    info->lds_tile_x = plan->path == 0 ? (split ? plan->split_X : plan->lds_X) : 0;
+    info->lds_tile_z = plan->path == 0 ? (split ? plan->split_P : plan->lds_P) : 0;
+    info->lds_split = plan->path == 0 ? plan->split_G : 0;
     return FWI_OK;
 }
 

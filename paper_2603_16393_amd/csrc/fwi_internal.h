@@ -71,6 +71,24 @@ struct LdsArgs {
     int store;               // forward: write D
 };
 
+// Split LDS-resident sweep: G workgroups share one field, workgroup g owning
+// the padded rows [g H, g H + H), H = nstrip * P.  After each step a workgroup
+// publishes its first and last 4 rows of u^{n+1} and reads its neighbours'
+// into its 4-row halos.  Every published value carries its time level in the
+// upper half of a 64-bit word (relaxed device-scope stores and loads), so a
+// reader checks each value itself and no fences are needed; two slots per
+// boundary alternate with the step parity (a workgroup cannot publish level
+// n + 2 before its neighbour has read level n, because it first needs that
+// neighbour's level n + 1).  The buffer is cleared to level 0 before a sweep.
+struct SplitArgs {
+    int G;                       // workgroups per field
+    int W;                       // values per exchanged row (ncg * X)
+    unsigned long long* xchg;    // [fields][G][2: top, bottom rows][2: slot][4][W]
+    int* err;                    // |= 2 when a wait gave up (the sweep's results are then invalid)
+};
+constexpr int kSplitSpinMax = 1 << 18;  // polls of one value before a wait gives up
+constexpr int kSplitMaxHalo = 8;        // halo values received per thread per step (8 W <= 8 * 512)
+
 // Arguments of one tiled step (fields in HBM).
 struct TileArgs {
     int nzp, nxp, npts;
@@ -107,6 +125,9 @@ struct Plan {
     int ckpt_every;
     int nseg;
     int lds_X = 0, lds_P = 0, lds_ncg = 0, lds_nstrip = 0;
+    int split_G = 1;                     // LDS path: workgroups per field (1: whole field in one workgroup)
+    int split_X = 0, split_P = 0, split_ncg = 0, split_nstrip = 0;
+    unsigned long long* xchg = nullptr;  // split halo exchange [max_batch*ns][G][2][2][4][ncg*X]
     size_t device_bytes;
     std::vector<void*> allocs;
 
@@ -184,6 +205,12 @@ void build_host_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, HostTa
 // req_X, req_P > 0 restrict the choice to that tile.
 bool lds_choose_layout(int nzp, int nxp, int req_X, int req_P, int* X, int* P, int* ncg, int* nstrip);
 size_t lds_bytes(int X, int P, int ncg, int nstrip);
+// Split sweep for `nfields` fields on `ncu` CUs: picks the tile and the
+// workgroups per field when that beats the whole-field tile (X1, P1) by the
+// cost model (force > 0: whenever feasible; force < 0: never).
+bool lds_choose_split(int nzp, int nxp, int nfields, int ncu, int X1, int P1, int force, int* Xo, int* Po, int* ncgo,
+                      int* nstripo, int* Go);
+int launch_fill(float* x, size_t n, float v, hipStream_t st);
 
 // Launchers (return FWI_OK or FWI_EHIP).
 int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st);

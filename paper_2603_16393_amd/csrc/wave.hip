@@ -170,6 +170,11 @@ static void copy(float* dst, const float* src, size_t n, hipStream_t st) {
     if (n) hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
 }
 
+int launch_fill(float* x, size_t n, float v, hipStream_t st) {
+    fill(x, n, v, st);
+    return hip_ok(hipGetLastError());
+}
+
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t st) {
     copy(dst, src, n, st);
     return hip_ok(hipGetLastError());

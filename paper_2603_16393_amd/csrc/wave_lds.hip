@@ -34,6 +34,16 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
     lds_field<X, P, ADJ, EXACT, STORE>(a, blockIdx.x, ax_g, az_g, lds);
 }
 
+// Split sweep: workgroup b holds rows [g H, g H + H) of field b / G (g = b % G).
+// Launched cooperatively, so all F * G workgroups are resident together.
+template <int X, int P, bool ADJ, bool EXACT, bool STORE>
+__global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs sp, const float* __restrict__ ax_g,
+                                                            const float* __restrict__ az_g) {
+    extern __shared__ float lds[];
+    const int field = blockIdx.x / sp.G;
+    lds_field<X, P, ADJ, EXACT, STORE, true>(a, field, ax_g, az_g, lds, sp, blockIdx.x - field * sp.G);
+}
+
 // Instantiated tiles (X columns, P rows).  (3, 11) tiles the 110 x 150 padded
 // field of a 70 x 70 model with a 40-cell sponge exactly.
 #define FWI_LDS_TILES(M) \
@@ -41,6 +51,10 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
     M(2, 8) M(2, 12)                   \
     M(3, 8) M(3, 11) M(3, 12)          \
     M(4, 8)
+
+// Register tiles of the split sweep: rows per workgroup H = nstrip * P with
+// nstrip = 512 / ncg strips, so P sets how many workgroups share a field.
+#define FWI_SPLIT_TILES(M) M(3, 2) M(3, 4) M(3, 6)
 
 size_t lds_bytes(int X, int P, int ncg, int nstrip) {
     const size_t S = (size_t)ncg * X + 8;
@@ -74,6 +88,71 @@ bool lds_choose_layout(int nzp, int nxp, int req_X, int req_P, int* Xo, int* Po,
     FWI_LDS_TILES(FWI_TRY)
 #undef FWI_TRY
     return found;
+}
+
+// Cycles of one CU per time step: VALU issue (about 33 wave64 FP32
+// instructions per point, 4 cycles each, over 4 SIMDs), LDS traffic
+// ((P+8)/P + 8/X reads and one write per point, 128 bytes per cycle) and,
+// split, the latency of the halo exchange (about 0.6 us measured for one
+// tagged message between two workgroups).
+static double lds_step_cycles(int X, int P, int ncg, int H, bool split) {
+    const double pts = (double)ncg * X * H;
+    return pts * (33.0 / 64.0 + ((P + 8.0) / P + 8.0 / X + 1.0) / 32.0) + (split ? 1500.0 : 0.0);
+}
+
+bool lds_choose_split(int nzp, int nxp, int nfields, int ncu, int X1, int P1, int force, int* Xo, int* Po, int* ncgo,
+                      int* nstripo, int* Go) {
+    if (force < 0) return false;
+    const int ncg1 = (nxp + X1 - 1) / X1;
+    const double whole = lds_step_cycles(X1, P1, ncg1, ((nzp + P1 - 1) / P1) * P1, false);
+    double best = force > 0 ? 1e300 : 0.9 * whole;
+    bool found = false;
+#define FWI_TRY(XX, PP)                                                                                   \
+    {                                                                                                     \
+        const int ncg = (nxp + XX - 1) / XX;                                                              \
+        const int smax = kLdsThreads / ncg;                                                               \
+        if (smax >= 1) {                                                                                  \
+            const int G = (nzp + smax * PP - 1) / (smax * PP);                                            \
+            const int nstrip = (nzp + G * PP - 1) / (G * PP);                                             \
+            const int H = nstrip * PP;                                                                    \
+            if (G >= 2 && H >= 4 && (long long)nfields * G <= ncu && ncg * XX <= 512 &&                   \
+                lds_bytes(XX, PP, ncg, nstrip) <= (size_t)kLdsBytes) {                                    \
+                const double c = lds_step_cycles(XX, PP, ncg, H, true);                                   \
+                if (c < best) {                                                                           \
+                    best = c;                                                                             \
+                    *Xo = XX;                                                                             \
+                    *Po = PP;                                                                             \
+                    *ncgo = ncg;                                                                          \
+                    *nstripo = nstrip;                                                                    \
+                    *Go = G;                                                                              \
+                    found = true;                                                                         \
+                }                                                                                         \
+            }                                                                                             \
+        }                                                                                                 \
+    }
+    FWI_SPLIT_TILES(FWI_TRY)
+#undef FWI_TRY
+    return found;
+}
+
+template <bool ADJ, bool STORE>
+static int split_dispatch(const LdsArgs& a, SplitArgs sp, int nfields, hipStream_t st, const float* ax,
+                          const float* az) {
+    const size_t bytes = lds_bytes(a.X, a.P, a.ncg, a.nstrip);
+    const bool exact = a.ncg * a.X == a.nxp && sp.G * a.nstrip * a.P == a.nzp;
+    void* args[] = {(void*)&a, (void*)&sp, (void*)&ax, (void*)&az};
+#define FWI_CASE(XX, PP)                                                                                      \
+    if (a.X == XX && a.P == PP) {                                                                             \
+        auto kern = exact ? k_wave_split<XX, PP, ADJ, true, STORE> : k_wave_split<XX, PP, ADJ, false, STORE>; \
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != \
+            hipSuccess)                                                                                       \
+            return hip_ok(hipGetLastError());                                                                 \
+        return hip_ok(hipLaunchCooperativeKernel((const void*)kern, dim3(nfields * sp.G), dim3(kLdsThreads),   \
+                                                 args, (unsigned)bytes, st));                                 \
+    }
+    FWI_SPLIT_TILES(FWI_CASE)
+#undef FWI_CASE
+    return FWI_EINVAL;
 }
 
 template <bool ADJ, bool STORE>
@@ -119,20 +198,50 @@ static LdsArgs make_lds_args(const Plan& p) {
     return a;
 }
 
+// The split sweep's tile replaces the whole-field one; its exchange buffer is
+// cleared to level 0 first.
+static int split_args(const Plan& p, int nfields, LdsArgs& a, SplitArgs& sp, hipStream_t st) {
+    a.X = p.split_X;
+    a.P = p.split_P;
+    a.ncg = p.split_ncg;
+    a.nstrip = p.split_nstrip;
+    a.S = a.ncg * a.X + 8;
+    sp.G = p.split_G;
+    sp.W = a.ncg * a.X;
+    sp.xchg = p.xchg;
+    sp.err = p.flags;
+    return launch_fill(reinterpret_cast<float*>(p.xchg), (size_t)nfields * sp.G * 2 * 2 * 4 * sp.W * 2, 0.f, st);
+}
+
 int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st) {
     LdsArgs a = make_lds_args(p);
     a.traces = traces;
     a.wavelet = wavelet;
     a.store = store;
-    if (store) return lds_dispatch<false, true>(a, B * p.g.ns, st, p.ax, p.az);
-    return lds_dispatch<false, false>(a, B * p.g.ns, st, p.ax, p.az);
+    const int nf = B * p.g.ns;
+    if (p.split_G > 1) {
+        SplitArgs sp{};
+        const int rc = split_args(p, nf, a, sp, st);
+        if (rc) return rc;
+        if (store) return split_dispatch<false, true>(a, sp, nf, st, p.ax, p.az);
+        return split_dispatch<false, false>(a, sp, nf, st, p.ax, p.az);
+    }
+    if (store) return lds_dispatch<false, true>(a, nf, st, p.ax, p.az);
+    return lds_dispatch<false, false>(a, nf, st, p.ax, p.az);
 }
 
 int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wavelet, hipStream_t st) {
     LdsArgs a = make_lds_args(p);
     a.adj = adj;
     a.wavelet = wavelet;
-    return lds_dispatch<true, false>(a, B * p.g.ns, st, p.ax, p.az);
+    const int nf = B * p.g.ns;
+    if (p.split_G > 1) {
+        SplitArgs sp{};
+        const int rc = split_args(p, nf, a, sp, st);
+        if (rc) return rc;
+        return split_dispatch<true, false>(a, sp, nf, st, p.ax, p.az);
+    }
+    return lds_dispatch<true, false>(a, nf, st, p.ax, p.az);
 }
 
 }  // namespace fwi

@@ -55,7 +55,8 @@ class FwiPlan:
     """
 
     def __init__(self, acq, max_batch: int, mem_budget_bytes: int = 0, force_path: int = -1, ckpt_every: int = 0,
-                 device: Optional[torch.device] = None, lds_tile: tuple = (0, 0), timing: bool = False):
+                 device: Optional[torch.device] = None, lds_tile: tuple = (0, 0), timing: bool = False,
+                 split: int = 0):
         L = _lib.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.nz, self.nx, self.nt = int(acq.nz), int(acq.nx), int(acq.nt)
@@ -67,7 +68,8 @@ class FwiPlan:
                                    int(acq.nb), int(bool(acq.free_surface)), float(acq.v_max), self.ns, ip[0], ip[1],
                                    self.nr, ip[2], ip[3])
         self.max_batch = int(max_batch)
-        opts = _lib.PlanOptions(int(force_path), int(ckpt_every), int(lds_tile[0]), int(lds_tile[1]), int(bool(timing)))
+        opts = _lib.PlanOptions(int(force_path), int(ckpt_every), int(lds_tile[0]), int(lds_tile[1]), int(bool(timing)),
+                                int(split))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(L.fwi_plan_create_ex(ctypes.byref(self._geom), self.max_batch, int(mem_budget_bytes),
