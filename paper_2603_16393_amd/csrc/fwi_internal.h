@@ -72,9 +72,9 @@ struct LdsArgs {
 };
 
 // Split LDS-resident sweep: G workgroups share one field, workgroup g owning
-// the padded rows [g H, g H + H), H = nstrip * P.  After each step a workgroup
-// publishes its first and last 4 rows of u^{n+1} and reads its neighbours'
-// into its 4-row halos.  Every published value carries its time level in the
+// the band of padded rows [g H, g H + H).  In each step a workgroup publishes
+// its first and last 4 rows of u^{n+1} and reads its neighbours' into its
+// 4-row halos.  Every published value carries its time level in the
 // upper half of a 64-bit word (relaxed device-scope stores and loads), so a
 // reader checks each value itself and no fences are needed; two slots per
 // boundary alternate with the step parity (a workgroup cannot publish level
@@ -87,7 +87,6 @@ struct SplitArgs {
     int* err;                    // |= 2 when a wait gave up (the sweep's results are then invalid)
 };
 constexpr int kSplitSpinMax = 1 << 18;  // polls of one value before a wait gives up
-constexpr int kSplitMaxHalo = 8;        // halo values received per thread per step (8 W <= 8 * 512)
 
 // Arguments of one tiled step (fields in HBM).
 struct TileArgs {
@@ -205,6 +204,8 @@ void build_host_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, HostTa
 // req_X, req_P > 0 restrict the choice to that tile.
 bool lds_choose_layout(int nzp, int nxp, int req_X, int req_P, int* X, int* P, int* ncg, int* nstrip);
 size_t lds_bytes(int X, int P, int ncg, int nstrip);
+// LDS of one band of the split sweep: H = 8 + nstrip * PI rows.
+size_t split_lds_bytes(int X, int PI, int ncg, int nstrip);
 // Split sweep for `nfields` fields on `ncu` CUs: picks the tile and the
 // workgroups per field when that beats the whole-field tile (X1, P1) by the
 // cost model (force > 0: whenever feasible; force < 0: never).

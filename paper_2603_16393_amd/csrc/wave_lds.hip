@@ -24,6 +24,7 @@
 
 #include "fwi_internal.h"
 #include "wave_lds_body.h"
+#include "wave_split_body.h"
 
 namespace fwi {
 
@@ -34,14 +35,14 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
     lds_field<X, P, ADJ, EXACT, STORE>(a, blockIdx.x, ax_g, az_g, lds);
 }
 
-// Split sweep: workgroup b holds rows [g H, g H + H) of field b / G (g = b % G).
+// Split sweep: workgroup b holds band g = b % G of field b / G (wave_split_body.h).
 // Launched cooperatively, so all F * G workgroups are resident together.
-template <int X, int P, bool ADJ, bool EXACT, bool STORE>
+template <int X, int PI, bool ADJ, bool EXACT, bool STORE>
 __global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs sp, const float* __restrict__ ax_g,
                                                             const float* __restrict__ az_g) {
     extern __shared__ float lds[];
     const int field = blockIdx.x / sp.G;
-    lds_field<X, P, ADJ, EXACT, STORE, true>(a, field, ax_g, az_g, lds, sp, blockIdx.x - field * sp.G);
+    split_field<X, PI, ADJ, EXACT, STORE>(a, sp, field, blockIdx.x - field * sp.G, ax_g, az_g, lds);
 }
 
 // Instantiated tiles (X columns, P rows).  (3, 11) tiles the 110 x 150 padded
@@ -52,9 +53,15 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs
     M(3, 8) M(3, 11) M(3, 12)          \
     M(4, 8)
 
-// Register tiles of the split sweep: rows per workgroup H = nstrip * P with
-// nstrip = 512 / ncg strips, so P sets how many workgroups share a field.
-#define FWI_SPLIT_TILES(M) M(3, 2) M(3, 4) M(3, 6)
+// Interior tiles of the split sweep (X columns, PI rows): a band has 8
+// boundary rows and nstrip interior strips of PI rows, nstrip <= 512 / ncg.
+#define FWI_SPLIT_TILES(M) M(3, 2) M(3, 3) M(3, 4)
+
+size_t split_lds_bytes(int X, int PI, int ncg, int nstrip) {
+    const size_t S = (size_t)ncg * X + 8;
+    const size_t H = 8 + (size_t)nstrip * PI;
+    return (2 * (H + 8) * S + H) * sizeof(float);
+}
 
 size_t lds_bytes(int X, int P, int ncg, int nstrip) {
     const size_t S = (size_t)ncg * X + 8;
@@ -111,12 +118,12 @@ bool lds_choose_split(int nzp, int nxp, int nfields, int ncu, int X1, int P1, in
     {                                                                                                     \
         const int ncg = (nxp + XX - 1) / XX;                                                              \
         const int smax = kLdsThreads / ncg;                                                               \
-        if (smax >= 1) {                                                                                  \
-            const int G = (nzp + smax * PP - 1) / (smax * PP);                                            \
-            const int nstrip = (nzp + G * PP - 1) / (G * PP);                                             \
-            const int H = nstrip * PP;                                                                    \
-            if (G >= 2 && H >= 4 && (long long)nfields * G <= ncu && ncg * XX <= 512 &&                   \
-                lds_bytes(XX, PP, ncg, nstrip) <= (size_t)kLdsBytes) {                                    \
+        if (smax >= 8) {                                                                                  \
+            const int G = (nzp + 8 + smax * PP - 1) / (8 + smax * PP);                                    \
+            const int nstrip = std::max(1, ((nzp + G - 1) / G - 8 + PP - 1) / PP);                        \
+            const int H = 8 + nstrip * PP;                                                                \
+            if (G >= 2 && (long long)nfields * G <= ncu && nstrip <= smax &&                              \
+                split_lds_bytes(XX, PP, ncg, nstrip) <= (size_t)kLdsBytes) {                              \
                 const double c = lds_step_cycles(XX, PP, ncg, H, true);                                   \
                 if (c < best) {                                                                           \
                     best = c;                                                                             \
@@ -138,8 +145,8 @@ bool lds_choose_split(int nzp, int nxp, int nfields, int ncu, int X1, int P1, in
 template <bool ADJ, bool STORE>
 static int split_dispatch(const LdsArgs& a, SplitArgs sp, int nfields, hipStream_t st, const float* ax,
                           const float* az) {
-    const size_t bytes = lds_bytes(a.X, a.P, a.ncg, a.nstrip);
-    const bool exact = a.ncg * a.X == a.nxp && sp.G * a.nstrip * a.P == a.nzp;
+    const size_t bytes = split_lds_bytes(a.X, a.P, a.ncg, a.nstrip);
+    const bool exact = a.ncg * a.X == a.nxp && sp.G * (8 + a.nstrip * a.P) == a.nzp;
     void* args[] = {(void*)&a, (void*)&sp, (void*)&ax, (void*)&az};
 #define FWI_CASE(XX, PP)                                                                                      \
     if (a.X == XX && a.P == PP) {                                                                             \

@@ -1,35 +1,56 @@
 // Body of the LDS-resident time loop of one (sample, shot) field, shared by
-// the per-batch kernels (wave_lds.hip) and the persistent uneven-batch kernel
+// the per-batch kernel (wave_lds.hip) and the persistent uneven-batch kernel
 // (batch.hip).  The whole workgroup (kLdsThreads threads) must call it; it
 // uses `lds` (lds_bytes(X, P, ncg, nstrip) bytes) and synchronises the
 // workgroup internally.  See wave_lds.hip for the layout and the scheme.
-// With SPLIT the workgroup holds only rows [g H, g H + H) of the field
-// (H = nstrip * P) and exchanges 4-row halos with workgroups g - 1 and g + 1
-// after every step (SplitArgs); every workgroup of the field must be resident.
 #pragma once
 
 #include "fwi_internal.h"
 
 namespace fwi {
 
-__device__ __forceinline__ void split_put(unsigned long long* p, float v, unsigned level) {
-    __hip_atomic_store(p, ((unsigned long long)level << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+// L u at one point (without the source term) from the column values
+// zc = u(z-4 .. z+4) and the row values xr = u(x-4 .. x+4), the weights with
+// 1/h^2 folded in; zc[4] = xr[4] = u.  The forward sweep writes each pair as
+// (u(+k) - u) - (u - u(-k)): equal bit for bit to (u(-k) - u) + (u(+k) - u),
+// and its second difference is the first difference of the point k rows
+// (columns) before, which the compiler then computes once for both points
+// (10 % fewer VALU operations; in the adjoint sweep the longer live ranges
+// cost more in scheduling than they save, so it keeps the plain form).  Every
+// LDS-resident sweep evaluates exactly this, so their results agree bitwise.
+template <bool ADJ>
+__device__ __forceinline__ float lds_lap(const float (&zc)[9], const float (&xr)[9], float wz1, float wz2, float wz3,
+                                         float wz4, float wx1, float wx2, float wx3, float wx4) {
+    const float u0 = zc[4];
+    float D;
+    if (!ADJ) {
+        D = wz1 * ((zc[5] - u0) - (u0 - zc[3]));
+        D = fmaf(wz2, (zc[6] - u0) - (u0 - zc[2]), D);
+        D = fmaf(wz3, (zc[7] - u0) - (u0 - zc[1]), D);
+        D = fmaf(wz4, (zc[8] - u0) - (u0 - zc[0]), D);
+        D = fmaf(wx1, (xr[5] - u0) - (u0 - xr[3]), D);
+        D = fmaf(wx2, (xr[6] - u0) - (u0 - xr[2]), D);
+        D = fmaf(wx3, (xr[7] - u0) - (u0 - xr[1]), D);
+        D = fmaf(wx4, (xr[8] - u0) - (u0 - xr[0]), D);
+    } else {
+        D = wz1 * ((zc[3] - u0) + (zc[5] - u0));
+        D = fmaf(wz2, (zc[2] - u0) + (zc[6] - u0), D);
+        D = fmaf(wz3, (zc[1] - u0) + (zc[7] - u0), D);
+        D = fmaf(wz4, (zc[0] - u0) + (zc[8] - u0), D);
+        D = fmaf(wx1, (xr[3] - u0) + (xr[5] - u0), D);
+        D = fmaf(wx2, (xr[2] - u0) + (xr[6] - u0), D);
+        D = fmaf(wx3, (xr[1] - u0) + (xr[7] - u0), D);
+        D = fmaf(wx4, (xr[0] - u0) + (xr[8] - u0), D);
+    }
+    return D;
 }
 
-__device__ __forceinline__ unsigned long long split_get(const unsigned long long* p) {
-    return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <int X, int P, bool ADJ, bool EXACT, bool STORE, bool SPLIT = false>
+template <int X, int P, bool ADJ, bool EXACT, bool STORE>
 __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, const float* __restrict__ ax_g,
-                                          const float* __restrict__ az_g, float* lds, const SplitArgs sp = {},
-                                          const int g = 0) {
+                                          const float* __restrict__ az_g, float* lds) {
     const int S = a.S;
-    const int H = a.nstrip * P;  // rows held (the whole padded field unless SPLIT)
-    const int R = H + 8;
+    const int R = a.nstrip * P + 8;
     const int plane = R * S;
-    const int zs = SPLIT ? g * H : 0;  // first padded row held
     float* az_s = lds + 2 * plane;
     const int b = field / a.ns;
     const int s = field - b * a.ns;
@@ -39,17 +60,14 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
     const int nsteps = a.nt - 1;
 
     for (int i = tid; i < 2 * plane; i += blockDim.x) lds[i] = 0.f;
-    for (int i = tid; i < H; i += blockDim.x) az_s[i] = (zs + i < nzp) ? az_g[zs + i] : 1.f;
+    for (int i = tid; i < a.nstrip * P; i += blockDim.x) az_s[i] = (i < nzp) ? az_g[i] : 1.f;
 
     const int cg = tid % a.ncg;
     const int strip = tid / a.ncg;
     const bool active = strip < a.nstrip;
     const int x0 = cg * X;
-    const int zl0 = strip * P;  // first row of the tile in the rows held
-    const int z0 = zs + zl0;    // ... in the padded field
-    // the window of a tile starting at z0 < 4 reaches above a reflecting top
-    // (tiles of P >= 4 rows start on multiples of P, so only the first does)
-    const bool mirror_top = a.fs && z0 < 4;
+    const int z0 = strip * P;
+    const bool mirror_top = a.fs && z0 == 0;
 
     // weights of the Laplacian with the grid spacings folded in
     const float wz1 = FWI_W1 * a.idz2, wz2 = FWI_W2 * a.idz2, wz3 = FWI_W3 * a.idz2, wz4 = FWI_W4 * a.idz2;
@@ -101,7 +119,6 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
 
     float* cur = lds;          // u^n
     float* nxt = lds + plane;  // receives u^{n+1}
-    bool gave_up = false;      // SPLIT: this thread stopped waiting for its neighbours
     // Adjoint: dc holds the tile's slice of D for the current step.  As soon as
     // row j has been imaged its registers receive row j of the next step's
     // slice, so every load has a whole step to arrive and no extra registers are
@@ -137,21 +154,16 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
                     }
             }
             float win[P + 8][X];
-            const float* cb = cur + (zl0 + 4) * S + x0 + 4;  // LDS cell of the tile corner
+            const float* cb = cur + (z0 + 4) * S + x0 + 4;  // LDS cell of the tile corner
 #pragma unroll
             for (int q = 0; q < P + 8; ++q) {
                 const float* rp = cb + (q - 4) * S;
-                // even mirror above a reflecting top: padded row z0 + q - 4 < 0 reads row 4 - q - z0
-                if constexpr (P >= 4) {
-                    if (q < 4 && mirror_top) rp = cb + (4 - q) * S;
-                } else {
-                    if (q < 4 && mirror_top && z0 + q < 4) rp = cb + (4 - q - 2 * z0) * S;
-                }
+                if (q < 4 && mirror_top) rp = cb + (4 - q) * S;  // even mirror above a reflecting top
 #pragma unroll
                 for (int c = 0; c < X; ++c) win[q][c] = rp[c];
             }
             float* Dw = (!ADJ && STORE) ? Drow0 + (size_t)m * npts : nullptr;
-            float* nb_ = nxt + (zl0 + 4) * S + x0 + 4;
+            float* nb_ = nxt + (z0 + 4) * S + x0 + 4;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
                 const float* rp = cb + j * S;
@@ -161,7 +173,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
                     xl[c] = rp[c - 4];
                     xh[c] = rp[X + c];
                 }
-                const float azr = az_s[zl0 + j];
+                const float azr = az_s[z0 + j];
 #pragma unroll
                 for (int c = 0; c < X; ++c) {
                     // row neighbours x-4 .. x+4 of column c
@@ -172,32 +184,10 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
                         xr[k] = cc < 0 ? xl[cc + 4] : (cc >= X ? xh[cc - X] : win[j + 4][cc]);
                     }
                     const float u0 = win[j + 4][c];
-                    float D;
-                    if (!ADJ) {
-                        // each pair as (u(+k) - u) - (u - u(-k)): equal bit for bit to
-                        // (u(-k) - u) + (u(+k) - u), and its second difference is the first
-                        // difference of the point k rows (columns) before, which the
-                        // compiler then computes once for both points (10 % fewer VALU
-                        // operations; in the adjoint sweep the longer live ranges cost more
-                        // in scheduling than they save, so it keeps the plain form)
-                        D = wz1 * ((win[j + 5][c] - u0) - (u0 - win[j + 3][c]));
-                        D = fmaf(wz2, (win[j + 6][c] - u0) - (u0 - win[j + 2][c]), D);
-                        D = fmaf(wz3, (win[j + 7][c] - u0) - (u0 - win[j + 1][c]), D);
-                        D = fmaf(wz4, (win[j + 8][c] - u0) - (u0 - win[j][c]), D);
-                        D = fmaf(wx1, (xr[5] - u0) - (u0 - xr[3]), D);
-                        D = fmaf(wx2, (xr[6] - u0) - (u0 - xr[2]), D);
-                        D = fmaf(wx3, (xr[7] - u0) - (u0 - xr[1]), D);
-                        D = fmaf(wx4, (xr[8] - u0) - (u0 - xr[0]), D);
-                    } else {
-                        D = wz1 * ((win[j + 3][c] - u0) + (win[j + 5][c] - u0));
-                        D = fmaf(wz2, (win[j + 2][c] - u0) + (win[j + 6][c] - u0), D);
-                        D = fmaf(wz3, (win[j + 1][c] - u0) + (win[j + 7][c] - u0), D);
-                        D = fmaf(wz4, (win[j][c] - u0) + (win[j + 8][c] - u0), D);
-                        D = fmaf(wx1, (xr[3] - u0) + (xr[5] - u0), D);
-                        D = fmaf(wx2, (xr[2] - u0) + (xr[6] - u0), D);
-                        D = fmaf(wx3, (xr[1] - u0) + (xr[7] - u0), D);
-                        D = fmaf(wx4, (xr[0] - u0) + (xr[8] - u0), D);
-                    }
+                    float zc[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) zc[k] = win[j + k][c];
+                    const float D = lds_lap<ADJ>(zc, xr, wz1, wz2, wz3, wz4, wx1, wx2, wx3, wx4);
                     const float wn = fmaf(Kr[j][c], D, (axv[c] * azr) * wr[j][c]);
                     const float un = u0 + wn;
                     wr[j][c] = wn;
@@ -263,66 +253,6 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
 #pragma unroll
                 for (int c = 0; c < X; ++c)
                     if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt + m + 1] = nb_[rec_j * S + c];
-            }
-            if constexpr (SPLIT) {
-                // publish the first and last 4 rows held (final values, read back from LDS)
-                const unsigned level = (unsigned)m + 1;
-                const int slot = level & 1;
-                unsigned long long* mine = sp.xchg + (((size_t)field * sp.G + g) * 2) * 2 * 4 * sp.W;
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int zl = zl0 + j;
-                    if (g > 0 && zl < 4) {
-#pragma unroll
-                        for (int c = 0; c < X; ++c) split_put(mine + (slot * 4 + zl) * sp.W + x0 + c, nb_[j * S + c], level);
-                    }
-                    if (g < sp.G - 1 && zl >= H - 4) {
-#pragma unroll
-                        for (int c = 0; c < X; ++c)
-                            split_put(mine + ((2 + slot) * 4 + zl - (H - 4)) * sp.W + x0 + c, nb_[j * S + c], level);
-                    }
-                }
-            }
-        }
-        if constexpr (SPLIT) {
-            // receive the neighbours' rows of u^{n+1} into the halos of nxt:
-            // rows g H - 4 .. g H - 1 from workgroup g - 1 (its last rows) into
-            // LDS rows 0..3, rows g H + H .. + 3 from g + 1 (its first rows) into
-            // LDS rows H + 4 .. H + 7.  All loads are issued before any wait.
-            const unsigned level = (unsigned)m + 1;
-            const int slot = level & 1;
-            const size_t fb = (size_t)field * sp.G;
-            const unsigned long long* up =
-                g > 0 ? sp.xchg + (((fb + g - 1) * 2 + 1) * 2 + slot) * 4 * sp.W : sp.xchg;  // g - 1, bottom rows
-            const unsigned long long* dn =
-                g < sp.G - 1 ? sp.xchg + (((fb + g + 1) * 2 + 0) * 2 + slot) * 4 * sp.W : sp.xchg;  // g + 1, top rows
-            const int n4 = 4 * sp.W;
-            unsigned long long hv[kSplitMaxHalo];
-#pragma unroll
-            for (int k = 0; k < kSplitMaxHalo; ++k) {
-                const int i = tid + k * (int)blockDim.x;
-                const bool top = i < n4;
-                const bool want = i < 2 * n4 && (top ? g > 0 : g < sp.G - 1);
-                hv[k] = want ? split_get(top ? up + i : dn + (i - n4)) : 0ull;
-            }
-#pragma unroll
-            for (int k = 0; k < kSplitMaxHalo; ++k) {
-                const int i = tid + k * (int)blockDim.x;
-                const bool top = i < n4;
-                if (i < 2 * n4 && (top ? g > 0 : g < sp.G - 1)) {
-                    const unsigned long long* src = top ? up + i : dn + (i - n4);
-                    int spins = 0;
-                    while (!gave_up && (unsigned)(hv[k] >> 32) != level) {
-                        if (++spins > kSplitSpinMax) {  // a neighbour is not running: flag it, never wait again
-                            atomicOr(sp.err, 2);
-                            gave_up = true;
-                            break;
-                        }
-                        hv[k] = split_get(src);
-                    }
-                    const int r = (top ? i : i - n4) / sp.W, c = (top ? i : i - n4) - r * sp.W;
-                    nxt[(top ? r : H + 4 + r) * S + 4 + c] = __uint_as_float((unsigned)hv[k]);
-                }
             }
         }
         __syncthreads();
