@@ -70,7 +70,8 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
 # scaled by the same counters' reading for the library's plain copy kernel (profiles/
 # k_wave_lds_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
-                   "paper_2603_16393_amd/csrc/fwi_internal.h")
+                   "paper_2603_16393_amd/csrc/wave_split_body.h", "paper_2603_16393_amd/csrc/fwi_internal.h",
+                   "paper_2603_16393_amd/csrc/capi.hip")
 TRAFFIC_SHA1 = "4be7465d05314452babd971bfa0b22e5f2d8fb64"
 TRAFFIC_BYTES = {"forward": 5304131932.0, "adjoint": 5308455774.0}
 

@@ -83,7 +83,8 @@ struct LdsArgs {
 struct SplitArgs {
     int G;                       // workgroups per field
     int W;                       // values per exchanged row (ncg * X)
-    unsigned long long* xchg;    // [fields][G][2: top, bottom rows][2: slot][4][W]
+    unsigned long long* xchg;    // [fields][G][2: top, bottom rows][2: slot][4][W], a row as [X][ncg]
+                                 // (column x0 + c of column group cg at c * ncg + cg: coalesced)
     int* err;                    // |= 2 when a wait gave up (the sweep's results are then invalid)
 };
 constexpr int kSplitSpinMax = 1 << 18;  // polls of one value before a wait gives up

@@ -96,7 +96,8 @@ __device__ __forceinline__ void split_tile_init(SplitTile<R, X>& t, const LdsArg
 // Step m of one tile: its R rows of u^{n+1} into nxt, then the corrections
 // of the points it owns (as the whole-field body orders them).  `Dt` is the
 // tile corner in D slice 0; `mirror`: rows above padded row 0 reflect.  After
-// row `issue_after` (if `fetch`) the X halo values at `src` are requested
+// row `issue_after` (if `fetch`) the X halo values at `src` (column c at
+// src + c * ncg) are requested
 // into hv, so that their latency overlaps the remaining rows.
 template <int R, int X, bool ADJ, bool EXACT, bool STORE>
 __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArgs& a, const float* cur, float* nxt,
@@ -171,7 +172,7 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
         if (j == issue_after && fetch) {
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c = 0; c < X; ++c) hv[c] = split_get(src + c);
+            for (int c = 0; c < X; ++c) hv[c] = split_get(src + c * a.ncg);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -284,13 +285,13 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
     const unsigned long long* src0 = sp.xchg;
     if (recv) {
         const size_t nbr = row < 4 ? ((fb + g - 1) * 2 + 1) : ((fb + g + 1) * 2 + 0);
-        src0 = sp.xchg + nbr * 2 * 4 * sp.W + (size_t)(row & 3) * sp.W + x0;
+        src0 = sp.xchg + nbr * 2 * 4 * sp.W + (size_t)(row & 3) * sp.W + cg;
     }
     const int halo_row = row < 4 ? row : H + row;  // LDS row of the received values
     // where this thread's boundary row goes, if a neighbour reads it
     const bool pub = has_b && (row < 4 ? g > 0 : g < sp.G - 1);
     unsigned long long* dst0 =
-        sp.xchg + ((fb + g) * 2 + (row < 4 ? 0 : 1)) * 2 * 4 * sp.W + (size_t)(row & 3) * sp.W + x0;
+        sp.xchg + ((fb + g) * 2 + (row < 4 ? 0 : 1)) * 2 * 4 * sp.W + (size_t)(row & 3) * sp.W + cg;
     bool gave_up = false;
     __syncthreads();
 
@@ -304,18 +305,18 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
             if (pub) {
                 const float* nb = nxt + (lb + 4) * S + x0 + 4;
 #pragma unroll
-                for (int c = 0; c < X; ++c) split_put(dst0 + slot + c, nb[c], level);
+                for (int c = 0; c < X; ++c) split_put(dst0 + slot + c * ncg, nb[c], level);
             }
         }
-        // the neighbours' rows are requested part-way through the interior rows: by
-        // then they have published theirs (boundary rows come first everywhere)
+        // the neighbours' rows are requested after the first interior row: by then
+        // they have published theirs (boundary rows come first everywhere)
         unsigned long long hv[X];
         if (has_i) {
-            split_tile_step<PI, X, ADJ, EXACT, STORE>(ti, a, cur, nxt, az_s, x0, false, m, Di, trfield, wz, wx,
-                                                      (PI - 1) / 2, recv, src0 + slot, hv);
+            split_tile_step<PI, X, ADJ, EXACT, STORE>(ti, a, cur, nxt, az_s, x0, false, m, Di, trfield, wz, wx, 0,
+                                                      recv, src0 + slot, hv);
         } else if (recv) {
 #pragma unroll
-            for (int c = 0; c < X; ++c) hv[c] = split_get(src0 + slot + c);
+            for (int c = 0; c < X; ++c) hv[c] = split_get(src0 + slot + c * ncg);
         }
         if (recv) {
 #pragma unroll
@@ -327,7 +328,7 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
                         gave_up = true;
                         break;
                     }
-                    hv[c] = split_get(src0 + slot + c);
+                    hv[c] = split_get(src0 + slot + c * ncg);
                 }
                 nxt[halo_row * S + x0 + 4 + c] = __uint_as_float((unsigned)hv[c]);
             }
