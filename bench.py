@@ -68,12 +68,12 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
 
 # HBM bytes per sweep launch of the default workload from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by the same counters' reading for the library's plain copy kernel (profiles/
-# k_wave_lds_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
+# k_wave_split_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
                    "paper_2603_16393_amd/csrc/wave_split_body.h", "paper_2603_16393_amd/csrc/fwi_internal.h",
                    "paper_2603_16393_amd/csrc/capi.hip")
-TRAFFIC_SHA1 = "4be7465d05314452babd971bfa0b22e5f2d8fb64"
-TRAFFIC_BYTES = {"forward": 5304131932.0, "adjoint": 5308455774.0}
+TRAFFIC_SHA1 = "b5ff35cf5f420b660465f83b1cadc682493262bf"
+TRAFFIC_BYTES = {"forward": 8893773228.0, "adjoint": 8525571696.0}
 
 
 def kernel_sources_sha1():
@@ -453,6 +453,22 @@ def main():
         if record:
             ev[4].record()
 
+    if args.copy_calibration:
+        # three dispatches of the library's plain copy kernel on 512 MiB, before any sweep, whose counter
+        # readings scale FETCH_SIZE / WRITE_SIZE to bytes
+        from paper_2603_16393_amd import _lib
+
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            _lib.check(_lib.load().fwi_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "fwi_copy")
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+        del src, dst
+        print(f"copy calibration: 3 x {nbytes} bytes", file=sys.stderr)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -469,20 +485,6 @@ def main():
     # mean device time of the forward and adjoint sweep kernels over the timed steps (HIP events the
     # library records on the stream it launches them on)
     fwd_sweep_ms, adj_sweep_ms = plan.sweep_ms()
-    if args.copy_calibration:
-        from paper_2603_16393_amd import _lib
-
-        nbytes = 512 << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            _lib.check(_lib.load().fwi_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
-                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "fwi_copy")
-        torch.cuda.synchronize()
-        assert torch.equal(dst, src)
-        print(f"copy calibration: 3 x {nbytes} bytes", file=sys.stderr)
-        plan.close()
-        return
     # per-stage durations (HIP events on the stream the kernels run on), averaged over a few more steps
     reps = max(3, min(args.steps, 10))
     for _ in range(reps):
