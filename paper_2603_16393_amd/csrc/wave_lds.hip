@@ -37,12 +37,12 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
 
 // Split sweep: workgroup b holds band g = b % G of field b / G (wave_split_body.h).
 // Launched cooperatively, so all F * G workgroups are resident together.
-template <int X, int PI, bool ADJ, bool EXACT, bool STORE>
+template <int X, int PI, bool ADJ, bool XEXACT, bool STORE>
 __global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs sp, const float* __restrict__ ax_g,
                                                             const float* __restrict__ az_g) {
     extern __shared__ float lds[];
     const int field = blockIdx.x / sp.G;
-    split_field<X, PI, ADJ, EXACT, STORE>(a, sp, field, blockIdx.x - field * sp.G, ax_g, az_g, lds);
+    split_field<X, PI, ADJ, XEXACT, STORE>(a, sp, field, blockIdx.x - field * sp.G, ax_g, az_g, lds);
 }
 
 // Instantiated tiles (X columns, P rows).  (3, 11) tiles the 110 x 150 padded
@@ -146,7 +146,7 @@ template <bool ADJ, bool STORE>
 static int split_dispatch(const LdsArgs& a, SplitArgs sp, int nfields, hipStream_t st, const float* ax,
                           const float* az) {
     const size_t bytes = split_lds_bytes(a.X, a.P, a.ncg, a.nstrip);
-    const bool exact = a.ncg * a.X == a.nxp && sp.G * (8 + a.nstrip * a.P) == a.nzp;
+    const bool exact = a.ncg * a.X == a.nxp;  // columns; rows are always guarded
     void* args[] = {(void*)&a, (void*)&sp, (void*)&ax, (void*)&az};
 #define FWI_CASE(XX, PP)                                                                                      \
     if (a.X == XX && a.P == PP) {                                                                             \

@@ -99,7 +99,7 @@ __device__ __forceinline__ void split_tile_init(SplitTile<R, X>& t, const LdsArg
 // row `issue_after` (if `fetch`) the X halo values at `src` (column c at
 // src + c * ncg) are requested
 // into hv, so that their latency overlaps the remaining rows.
-template <int R, int X, bool ADJ, bool EXACT, bool STORE>
+template <int R, int X, bool ADJ, bool XEXACT, bool STORE>
 __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArgs& a, const float* cur, float* nxt,
                                                 const float* az_s, int x0, bool mirror, int m, float* Dt,
                                                 size_t trfield, const float (&wz)[4], const float (&wx)[4],
@@ -159,14 +159,14 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
             nb[j * S + c] = un;
             if (ADJ) t.acc[j][c] = fmaf(un, t.dc[j][c], t.acc[j][c]);
             if (STORE && !ADJ) {
-                if (EXACT || (t.z + j < nzp && x0 + c < nxp)) Dw[j * nxp + c] = D;
+                if (t.z + j < nzp && (XEXACT || x0 + c < nxp)) Dw[j * nxp + c] = D;
             }
         }
         if (ADJ) {
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < X; ++c)
-                t.dc[j][c] = (EXACT || (t.z + j < nzp && x0 + c < nxp)) ? Dn[j * nxp + c] : 0.f;
+                t.dc[j][c] = (t.z + j < nzp && (XEXACT || x0 + c < nxp)) ? Dn[j * nxp + c] : 0.f;
             __builtin_amdgcn_sched_barrier(0);
         }
         if (j == issue_after && fetch) {
@@ -237,7 +237,9 @@ __device__ __forceinline__ void split_tile_gpad(const SplitTile<R, X>& t, const 
 // The whole workgroup (kLdsThreads threads) calls this for band g of `field`;
 // a.nstrip is the number of interior strips of PI rows, so the band has
 // H = 8 + a.nstrip * PI rows and uses (2 (H + 8) S + H) floats of LDS.
-template <int X, int PI, bool ADJ, bool EXACT, bool STORE>
+// XEXACT: the column groups tile the padded width exactly (no column guards;
+// rows past the field, in the last band, are always guarded).
+template <int X, int PI, bool ADJ, bool XEXACT, bool STORE>
 __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp, const int field, const int g,
                                             const float* __restrict__ ax_g, const float* __restrict__ az_g,
                                             float* lds) {
@@ -301,7 +303,7 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
         const unsigned level = (unsigned)m + 1;
         const size_t slot = (size_t)(level & 1) * 4 * sp.W;
         if (has_b) {
-            split_tile_step<1, X, ADJ, EXACT, STORE>(tb, a, cur, nxt, az_s, x0, mirror, m, Db, trfield, wz, wx);
+            split_tile_step<1, X, ADJ, XEXACT, STORE>(tb, a, cur, nxt, az_s, x0, mirror, m, Db, trfield, wz, wx);
             if (pub) {
                 const float* nb = nxt + (lb + 4) * S + x0 + 4;
 #pragma unroll
@@ -312,7 +314,7 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
         // they have published theirs (boundary rows come first everywhere)
         unsigned long long hv[X];
         if (has_i) {
-            split_tile_step<PI, X, ADJ, EXACT, STORE>(ti, a, cur, nxt, az_s, x0, false, m, Di, trfield, wz, wx, 0,
+            split_tile_step<PI, X, ADJ, XEXACT, STORE>(ti, a, cur, nxt, az_s, x0, false, m, Di, trfield, wz, wx, 0,
                                                       recv, src0 + slot, hv);
         } else if (recv) {
 #pragma unroll
