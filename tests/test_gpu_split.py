@@ -91,6 +91,49 @@ def test_split_equals_whole_field_sweep(dev, case):
     pw.close()
 
 
+def test_sources_and_receivers_on_band_boundaries(dev):
+    """Receiver row and source on the published rows of a middle band (their
+    corrections must precede the publication); split vs whole field bitwise,
+    and vs the oracle."""
+    import math
+
+    import oracle
+    from paper_2603_16393_amd import FwiPlan
+
+    nz, nx, nb = 100, 60, 20
+    probe = fi.surface_acquisition(nz, nx, ns=2, nt=300, nb=nb, free_surface=False)
+    p0 = FwiPlan(probe, max_batch=2, device=dev, split=1)
+    G, PI = p0.info["lds_split"], p0.info["lds_tile_z"]
+    nzp = p0.info["nzp"]
+    p0.close()
+    H = 8 + max(1, math.ceil((math.ceil(nzp / G) - 8) / PI)) * PI
+    assert G >= 3, (G, H)
+    rec_pad, src_pad = H + 1, 2 * H - 2  # band 1: second row, next-to-last row
+    acq = fi.surface_acquisition(nz, nx, ns=2, nt=300, nb=nb, free_surface=False, rec_row=rec_pad - nb,
+                                 src_row=src_pad - nb)
+    ps = FwiPlan(acq, max_batch=2, device=dev, split=1)
+    pw = FwiPlan(acq, max_batch=2, device=dev, split=-1)
+    assert (ps.info["lds_split"], ps.info["lds_tile_z"]) == (G, PI)
+    _say(f"bands of {H} rows x {G}, receivers on padded row {rec_pad}, sources on row {src_pad}")
+    models = np.stack([fi.faulted_model(nz, nx, 70 + b) for b in range(2)]).astype(np.float32)
+    v = torch.tensor(models, device=dev)
+    wav = fi.ricker(acq.nt, acq.dt, acq.f_peak).astype(np.float32)
+    w = torch.tensor(wav, device=dev)
+    adj_np = _adjoint_sources((2, acq.ns, acq.nr, acq.nt), 5)
+    adj = torch.tensor(adj_np, device=dev)
+    ref = _run(pw, v, w, adj, 1)[0]
+    for i, (d, g) in enumerate(_run(ps, v, w, adj, 2)):
+        assert torch.equal(d, ref[0]), f"call {i}: traces differ"
+        assert torch.equal(g, ref[1]), f"call {i}: gradients differ"
+    dref = oracle.forward(acq, models[0].astype(np.float64), wav.astype(np.float64))
+    gref = oracle.gradient(acq, models[0].astype(np.float64), wav.astype(np.float64), adj_np[0].astype(np.float64))
+    et, eg = _rel(ref[0][0].cpu().numpy(), dref), _rel(ref[1][0].cpu().numpy(), gref)
+    _say(f"vs oracle: traces {et:.2e}, gradient {eg:.2e}")
+    assert et <= 1e-4 and eg <= 1e-4
+    ps.close()
+    pw.close()
+
+
 def test_split_vs_oracle_one_shot(dev):
     import oracle
     from paper_2603_16393_amd import FwiPlan
