@@ -142,10 +142,12 @@ __device__ inline double quantile(const double* F, const double* Fh, int nt, dou
 
 // ---------------------------------------------------------------------------
 // Observation side.
-__global__ __launch_bounds__(1024) void k_absmax(const float* __restrict__ d, long n, double* __restrict__ out) {
-    __shared__ float sh[16];
+// max |d| over n values: per-block maxima (grid-stride), then one block
+// reduces them (max is exact in any order).
+__global__ __launch_bounds__(256) void k_absmax_partial(const float* __restrict__ d, long n, double* __restrict__ part) {
+    __shared__ float sh[4];
     float m = 0.f;
-    for (long i = threadIdx.x; i < n; i += blockDim.x) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const float a = fabsf(d[i]);
         m = a > m ? a : m;
     }
@@ -158,7 +160,24 @@ __global__ __launch_bounds__(1024) void k_absmax(const float* __restrict__ d, lo
     if (threadIdx.x == 0) {
         float t = 0.f;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = sh[i] > t ? sh[i] : t;
-        *out = (double)t;
+        part[blockIdx.x] = (double)t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_absmax_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[4];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) m = part[i] > m ? part[i] : m;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(m, o);
+        m = t > m ? t : m;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = sh[i] > t ? sh[i] : t;
+        *out = t;
     }
 }
 
@@ -218,7 +237,10 @@ int launch_w2_obs(Plan& p, const float* d_obs, hipStream_t st) {
     const int nt = p.g.nt;
     const int nxi = p.w2p.n_xi;
     double* gmax = p.sobs + 1;  // scratch slot next to S_obs
-    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st, d_obs, (long)ntr * nt, gmax);
+    // per-block maxima in the misfit's pair buffer (max_batch * ns * nr >= ntr slots; the misfit overwrites it)
+    const int nb = std::min(ntr, 2048);
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, st, d_obs, (long)ntr * nt, p.w2pair);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, st, p.w2pair, nb, gmax);
     const size_t bytes = (size_t)3 * nt * sizeof(double);
     hipFuncSetAttribute((const void*)k_w2_obs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL(k_w2_obs, dim3(ntr), dim3(W2T), bytes, st, nt, nxi, p.g.dt, d_obs, gmax, p.w2p.k,
