@@ -353,7 +353,7 @@ def bench_checkpointed(args):
     vt = fi.large_lens_model(nz, nx, seed=1)
     w = fi.ricker(nt, acq.dt, acq.f_peak)
     budget = 16 << 30
-    plan = FwiPlan(acq, max_batch=1, device=dev, mem_budget_bytes=budget, ckpt_every=100)
+    plan = FwiPlan(acq, max_batch=1, device=dev, mem_budget_bytes=budget, ckpt_every=100, timing=True)
     wt = torch.tensor(w, dtype=torch.float32, device=dev)
     dobs = plan.forward(torch.tensor(vt[None], dtype=torch.float32, device=dev), wt, keep_for_adjoint=False)
     plan.set_obs(dobs[0].contiguous())
@@ -367,6 +367,7 @@ def bench_checkpointed(args):
     for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
+    plan.sweep_ms()  # restart the sweep event averages at the timed region
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
@@ -375,12 +376,23 @@ def bench_checkpointed(args):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
+    fwd_ms, adj_ms = plan.sweep_ms()  # whole forward sweep; recomputation + adjoint steps
     nzp, nxp = acq.padded_shape
-    updates = 3 * ns * (nt - 1) * nzp * nxp  # forward, recomputation, adjoint
+    per_sweep = ns * (nt - 1) * nzp * nxp
+    updates = 3 * per_sweep  # forward, recomputation, adjoint
+    # algorithmic bytes of the adjoint phase (the dominant one): per point-update 16 B (u^n, w^n, K read,
+    # u^{n+1} written) in both the recomputation and the adjoint steps, plus D written by the recomputation and
+    # read back by the adjoint (4 B each)
+    alg = per_sweep * (16.0 + 4.0) * 2
+    achieved = alg / (adj_ms / 1e3) / 1e9
     print(json.dumps({
         "metric": "checkpointed guidance gradient (400x800, 20 shots, 4k steps)",
         "value": round(1e3 / ms, 4), "unit": "grads/s", "ms_per_gradient": round(ms, 2), "steps": args.steps,
         "gpts_per_s": round(updates / (ms / 1e3) / 1e9, 2),
+        "sweep_ms": {"forward": round(fwd_ms, 2), "recompute_and_adjoint": round(adj_ms, 2)},
+        "roofline": {"bound": "hbm", "kernel": "k_wave_tile (recomputation + adjoint steps, one launch per step)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_phase": alg},
         "plan": {k: plan.info[k] for k in ("path", "store_mode", "ckpt_every", "device_bytes")},
         "memory_budget_bytes": budget, "dtype": "f32", "data": "synthetic",
     }))

@@ -321,19 +321,25 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
             for (int c = 0; c < X; ++c) hv[c] = split_get(src0 + slot + c * ncg);
         }
         if (recv) {
+            // values that were not yet there are requested again together, so each
+            // round costs one round trip whatever the number of stale values
+            int spins = 0;
+            for (;;) {
+                bool stale = false;
 #pragma unroll
-            for (int c = 0; c < X; ++c) {
-                int spins = 0;
-                while (!gave_up && (unsigned)(hv[c] >> 32) != level) {
-                    if (++spins > kSplitSpinMax) {  // a neighbour is not running: flag it, never wait again
-                        atomicOr(sp.err, 2);
-                        gave_up = true;
-                        break;
-                    }
-                    hv[c] = split_get(src0 + slot + c * ncg);
+                for (int c = 0; c < X; ++c) stale |= (unsigned)(hv[c] >> 32) != level;
+                if (!stale || gave_up) break;
+                if (++spins > kSplitSpinMax) {  // a neighbour is not running: flag it, never wait again
+                    atomicOr(sp.err, 2);
+                    gave_up = true;
+                    break;
                 }
-                nxt[halo_row * S + x0 + 4 + c] = __uint_as_float((unsigned)hv[c]);
+#pragma unroll
+                for (int c = 0; c < X; ++c)
+                    if ((unsigned)(hv[c] >> 32) != level) hv[c] = split_get(src0 + slot + c * ncg);
             }
+#pragma unroll
+            for (int c = 0; c < X; ++c) nxt[halo_row * S + x0 + 4 + c] = __uint_as_float((unsigned)hv[c]);
         }
         __syncthreads();
         float* tmp = cur;
