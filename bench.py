@@ -390,7 +390,7 @@ def bench_checkpointed(args):
         "value": round(1e3 / ms, 4), "unit": "grads/s", "ms_per_gradient": round(ms, 2), "steps": args.steps,
         "gpts_per_s": round(updates / (ms / 1e3) / 1e9, 2),
         "sweep_ms": {"forward": round(fwd_ms, 2), "recompute_and_adjoint": round(adj_ms, 2)},
-        "roofline": {"bound": "hbm", "kernel": "k_wave_tile (recomputation + adjoint steps, one launch per step)",
+        "roofline": {"bound": "hbm", "kernel": "k_wave_tile2 (recomputation + adjoint steps, two steps per launch)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_phase": alg},
         "plan": {k: plan.info[k] for k in ("path", "store_mode", "ckpt_every", "device_bytes")},

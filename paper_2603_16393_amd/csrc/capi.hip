@@ -193,7 +193,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // fixed-size buffers
     size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
                    nf * nr * 8 + (size_t)ns * nr * 1000 * 8;
-    if (p.path == 1) fixed += (6 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
+    if (p.path == 1) fixed += (8 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
     const size_t full_store = nf * nsteps * npts * sizeof(float);
     size_t avail = budget;
     if (avail == 0) {
@@ -218,7 +218,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     }
     if (p.store_mode == 1) {
         p.nseg = (int)((nsteps + p.ckpt_every - 1) / p.ckpt_every);
-        const size_t need = fixed + 6 * nf * npts * sizeof(float) +
+        const size_t need = fixed + 8 * nf * npts * sizeof(float) +
                             nf * ((size_t)p.ckpt_every + 2 * (size_t)p.nseg) * npts * sizeof(float);
         if (need > avail) {
             free_all(p);
@@ -291,8 +291,8 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     st = st ? st : alloc_n(p, &p.w2pair, nf * nr);
     if (p.path == 1) {
         st = st ? st : alloc_n(p, &p.rec_map, npts);
-        st = st ? st : alloc_n(p, &p.state, 3 * nf * npts);
-        st = st ? st : alloc_n(p, &p.astate, 3 * nf * npts);
+        st = st ? st : alloc_n(p, &p.state, 4 * nf * npts);   // u, u, w, w (two-step launches do not update w in place)
+        st = st ? st : alloc_n(p, &p.astate, 4 * nf * npts);
         st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;

@@ -144,8 +144,8 @@ struct Plan {
     float* rec_invw = nullptr;   // [nr]
     float* Dstore = nullptr;     // full: [max_batch*ns][nt-1][npts]; ckpt: [max_batch*ns][ckpt_every][npts]
     float* ckpt = nullptr;       // ckpt: [max_batch*ns][nseg][2][npts] (u^n, w^n)
-    float* state = nullptr;      // tiled: [3][max_batch*ns][npts] u (ping-pong) and w
-    float* astate = nullptr;     // tiled adjoint: [3][max_batch*ns][npts]
+    float* state = nullptr;      // tiled: [4][max_batch*ns][npts] u and w, each ping-pong
+    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]
     float* acc = nullptr;        // tiled adjoint: [max_batch*ns][npts]
     float* gpad = nullptr;       // [max_batch*ns][npts]
     float* fold_tmp = nullptr;   // [max_batch][nzp][nx] column-folded gradient

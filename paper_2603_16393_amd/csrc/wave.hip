@@ -111,17 +111,143 @@ __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const floa
         int r = -1;
         if (check_rec) r = a.rec_map[p];
         if (!ADJ && p == sp) D = fmaf(a.wavelet[m], a.src_scale, D);
-        if (ADJ && r >= 0) D += a.rec_invw[r] * a.adj[((size_t)field * a.nr + r) * a.nt + (a.nt - 1 - m)];
+        if (ADJ && r >= 0) D = fmaf(a.rec_invw[r], a.adj[((size_t)field * a.nr + r) * a.nt + (a.nt - 1 - m)], D);
         const float Kp = a.K[(size_t)b * a.npts + p];
         const float wn = fmaf(Kp, D, (axv * az_g[gz]) * wg[p]);
         const float un = c + wn;
         wg[p] = wn;
         un_g[p] = un;
         if (ADJ) {
-            if (a.Din) a.acc[(size_t)field * a.npts + p] += un * a.Din[(size_t)field * a.dstride + p];
+            if (a.Din) {
+                float* acc = a.acc + (size_t)field * a.npts + p;
+                *acc = fmaf(un, a.Din[(size_t)field * a.dstride + p], *acc);
+            }
         } else {
             if (a.Dout) a.Dout[(size_t)field * a.dstride + p] = D;
             if (r >= 0 && a.traces) a.traces[((size_t)field * a.nr + r) * a.nt + m + 1] = un;
+        }
+    }
+}
+
+// Two time steps per launch (temporal blocking): the block computes step 1
+// on its 64 x 16 tile plus a 4-cell ring (72 x 24 points, from u^n staged with
+// an 8-cell ring), keeps u^{n+1} of that region in LDS and w^{n+1} of the tile,
+// then computes step 2 on the tile.  Every point is updated with the same
+// operations as in k_wave_tile (the ring points again by each block that
+// needs them), so two launches of k_wave_tile and one of this kernel agree
+// bitwise; u, w and K pass through HBM once per two steps and, in the adjoint,
+// the imaging sum is read and written once per two steps.  w is not updated in
+// place (a neighbour still reads w^n of the ring): w^n from a.wst, w^{n+2} to
+// wout.  Step 1 is step m (forward: time index m; adjoint: step m of the
+// reversed recursion), step 2 is m + 1; Dout / Din belong to step 1, Dout2 /
+// Din2 to step 2.
+constexpr int EX = TX + 8, EZ = TZ + 8;   // step-1 region: the tile and a 4-cell ring
+constexpr int AX = TX + 16, AZ = TZ + 16; // u^n window: the tile and an 8-cell ring
+
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const float* __restrict__ ax_g,
+                                                    const float* __restrict__ az_g, float* __restrict__ wout,
+                                                    float* __restrict__ Dout2, const float* __restrict__ Din2) {
+    __shared__ float A[AZ * AX];   // u^n
+    __shared__ float Bt[EZ * EX];  // u^{n+1}
+    __shared__ float W1[TZ * TX];  // w^{n+1} of the tile
+    const int field = blockIdx.z;
+    const int b = field / a.ns;
+    const int s = field - b * a.ns;
+    const int x0 = blockIdx.x * TX, zt = blockIdx.y * TZ;
+    const int nxp = a.nxp, nzp = a.nzp;
+    const float* uc = a.ucur + (size_t)field * a.npts;
+    const float* wg = a.wst + (size_t)field * a.npts;
+    const float* Kb = a.K + (size_t)b * a.npts;
+    const int sp = a.src_pt[s];
+    const size_t trf = (size_t)field * a.nr;
+
+    for (int i = threadIdx.x; i < AZ * AX; i += 256) {
+        const int r = i / AX, c = i - (i / AX) * AX;
+        int gz = zt + r - 8;
+        const int gx = x0 + c - 8;
+        if (a.fs && gz < 0) gz = -gz;
+        A[i] = (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) ? uc[gz * nxp + gx] : 0.f;
+    }
+    __syncthreads();
+
+    // step 1 on the tile and its ring
+    const bool rec1 = (zt + TZ + 4 > a.rec_z0) && (zt - 4 <= a.rec_z1);
+    for (int i = threadIdx.x; i < EZ * EX; i += 256) {
+        const int r = i / EX, c = i - (i / EX) * EX;
+        const int gz = zt + r - 4, gx = x0 + c - 4;
+        float un = 0.f;
+        if (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) {
+            const int p = gz * nxp + gx;
+            const int li = (r + 4) * AX + c + 4;
+            const float cc = A[li];
+            const float lzs = FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX], A[li + AX],
+                                       A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
+            const float lxs = FWI_LAPD(cc, A[li - 4], A[li - 3], A[li - 2], A[li - 1], A[li + 1], A[li + 2], A[li + 3],
+                                       A[li + 4]);
+            float D = fmaf(lzs, a.idz2, lxs * a.idx2);
+            const int rr = rec1 ? a.rec_map[p] : -1;
+            if (!ADJ && p == sp) D = fmaf(a.wavelet[m], a.src_scale, D);
+            if (ADJ && rr >= 0) D = fmaf(a.rec_invw[rr], a.adj[(trf + rr) * a.nt + (a.nt - 1 - m)], D);
+            const float wn = fmaf(Kb[p], D, (ax_g[gx] * az_g[gz]) * wg[p]);
+            un = cc + wn;
+            const bool own = r >= 4 && r < 4 + TZ && c >= 4 && c < 4 + TX;
+            if (own) {
+                W1[(r - 4) * TX + c - 4] = wn;
+                if (!ADJ) {
+                    if (a.Dout) a.Dout[(size_t)field * a.dstride + p] = D;
+                    if (rr >= 0 && a.traces) a.traces[(trf + rr) * a.nt + m + 1] = un;
+                }
+            }
+        }
+        Bt[i] = un;
+    }
+    __syncthreads();
+    if (a.fs && zt == 0) {  // rows above a reflecting top mirror rows 1..4 of u^{n+1}
+        for (int i = threadIdx.x; i < 4 * EX; i += 256) {
+            const int r = i / EX, c = i - (i / EX) * EX;
+            Bt[i] = Bt[(8 - r) * EX + c];
+        }
+        __syncthreads();
+    }
+
+    // step 2 on the tile (the mapping of k_wave_tile)
+    const int tx = threadIdx.x % TX, ts = threadIdx.x / TX;
+    const int gx = x0 + tx;
+    if (gx >= nxp) return;
+    const float axv = ax_g[gx];
+    const bool rec2 = (zt + TZ > a.rec_z0) && (zt <= a.rec_z1);
+    float* un_g = a.unxt + (size_t)field * a.npts;
+    float* wo = wout + (size_t)field * a.npts;
+#pragma unroll
+    for (int j = 0; j < TROWS; ++j) {
+        const int lz = ts * TROWS + j;
+        const int gz = zt + lz;
+        if (gz >= nzp) break;
+        const int p = gz * nxp + gx;
+        const int li = (lz + 4) * EX + tx + 4;
+        const float cc = Bt[li];
+        const float lzs = FWI_LAPD(cc, Bt[li - 4 * EX], Bt[li - 3 * EX], Bt[li - 2 * EX], Bt[li - EX], Bt[li + EX],
+                                   Bt[li + 2 * EX], Bt[li + 3 * EX], Bt[li + 4 * EX]);
+        const float lxs = FWI_LAPD(cc, Bt[li - 4], Bt[li - 3], Bt[li - 2], Bt[li - 1], Bt[li + 1], Bt[li + 2],
+                                   Bt[li + 3], Bt[li + 4]);
+        float D = fmaf(lzs, a.idz2, lxs * a.idx2);
+        const int rr = rec2 ? a.rec_map[p] : -1;
+        if (!ADJ && p == sp) D = fmaf(a.wavelet[m + 1], a.src_scale, D);
+        if (ADJ && rr >= 0) D = fmaf(a.rec_invw[rr], a.adj[(trf + rr) * a.nt + (a.nt - 2 - m)], D);
+        const float wn = fmaf(Kb[p], D, (axv * az_g[gz]) * W1[lz * TX + tx]);
+        const float un = cc + wn;
+        wo[p] = wn;
+        un_g[p] = un;
+        if (ADJ) {
+            if (a.Din) {
+                float* acc = a.acc + (size_t)field * a.npts + p;
+                const float s1 = fmaf(cc, a.Din[(size_t)field * a.dstride + p], *acc);
+                *acc = fmaf(un, Din2[(size_t)field * a.dstride + p], s1);
+            }
+        } else {
+            if (Dout2) Dout2[(size_t)field * a.dstride + p] = D;
+            if (rr >= 0 && a.traces) a.traces[(trf + rr) * a.nt + m + 2] = un;
         }
     }
 }
@@ -229,33 +355,69 @@ static dim3 tile_grid(const Plan& p, int nfields) {
     return dim3((p.nxp + TX - 1) / TX, (p.nzp + TZ - 1) / TZ, nfields);
 }
 
+// One or two forward steps from (u0, w0) to u1 and, for two steps, w1 (one
+// step updates w0 in place).  Returns the number of steps taken.
+static int forward_steps(TileArgs a, const dim3& grid, int n, bool two, float* u0, float* u1, float* w0, float* w1,
+                         float* D0, float* D1, const Plan& p, hipStream_t st) {
+    a.ucur = u0;
+    a.unxt = u1;
+    a.wst = w0;
+    a.Dout = D0;
+    if (two) {
+        hipLaunchKernelGGL(k_wave_tile2<false>, grid, dim3(256), 0, st, a, n, p.ax, p.az, w1, D1, nullptr);
+        return 2;
+    }
+    hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, a, n, p.ax, p.az);
+    return 1;
+}
+
 // Enqueues the whole forward sweep of B samples on st (reads p.wav, writes p.trace_buf).
+// State: p.state = [u][u][w][w] per field, (u, w) ping-pong.
 static void enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
     const int nf = B * p.g.ns;
     const size_t fs = (size_t)nf * p.npts;
     float* u0 = p.state;
     float* u1 = p.state + fs;
-    float* w = p.state + 2 * fs;
-    fill(p.state, 3 * fs, 0.f, st);
+    float* w0 = p.state + 2 * fs;
+    float* w1 = p.state + 3 * fs;
+    fill(p.state, 4 * fs, 0.f, st);
     hipLaunchKernelGGL(k_zero_first_sample, dim3((nf * p.g.nr + 255) / 256), dim3(256), 0, st, p.trace_buf,
                        nf * p.g.nr, p.g.nt);
     TileArgs a = make_tile_args(p, B);
     a.traces = p.trace_buf;
     a.wavelet = p.wav;
-    a.wst = w;
     const dim3 grid = tile_grid(p, nf);
     const int nsteps = p.g.nt - 1;
     a.dstride = (size_t)nsteps * p.npts;
-    for (int n = 0; n < nsteps; ++n) {
-        if (keep && p.store_mode == 1 && n % p.ckpt_every == 0)
-            hipLaunchKernelGGL(k_ckpt<true>, dim3(grid_for(fs)), dim3(256), 0, st, p.ckpt, u0, w, nf, p.nseg,
+    const bool ck = keep && p.store_mode == 1;
+    for (int n = 0; n < nsteps;) {
+        if (ck && n % p.ckpt_every == 0)
+            hipLaunchKernelGGL(k_ckpt<true>, dim3(grid_for(fs)), dim3(256), 0, st, p.ckpt, u0, w0, nf, p.nseg,
                                n / p.ckpt_every, p.npts);
-        a.ucur = u0;
-        a.unxt = u1;
-        a.Dout = (keep && p.store_mode == 0) ? p.Dstore + (size_t)n * p.npts : nullptr;
-        hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, a, n, p.ax, p.az);
+        // a pair never straddles a checkpoint
+        const bool two = n + 1 < nsteps && !(ck && (n + 1) % p.ckpt_every == 0);
+        const bool full = keep && p.store_mode == 0;
+        const int k = forward_steps(a, grid, n, two, u0, u1, w0, w1, full ? p.Dstore + (size_t)n * p.npts : nullptr,
+                                    full ? p.Dstore + (size_t)(n + 1) * p.npts : nullptr, p, st);
         std::swap(u0, u1);
+        if (k == 2) std::swap(w0, w1);
+        n += k;
     }
+}
+
+// One or two adjoint steps (m, m + 1) with D slices Da (step m) and Db (step m + 1).
+static int adjoint_steps(TileArgs a, const dim3& grid, int m, bool two, float* u0, float* u1, float* w0, float* w1,
+                         const float* Da, const float* Db, const Plan& p, hipStream_t st) {
+    a.ucur = u0;
+    a.unxt = u1;
+    a.wst = w0;
+    a.Din = Da;
+    if (two) {
+        hipLaunchKernelGGL(k_wave_tile2<true>, grid, dim3(256), 0, st, a, m, p.ax, p.az, w1, nullptr, Db);
+        return 2;
+    }
+    hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, a, m, p.ax, p.az);
+    return 1;
 }
 
 // Enqueues the whole adjoint sweep (reads p.adj_buf, p.wav; writes p.gpad).
@@ -265,23 +427,24 @@ static void enqueue_adjoint(Plan& p, int B, hipStream_t st) {
     const int nsteps = p.g.nt - 1;
     float* a0 = p.astate;
     float* a1 = p.astate + fs;
-    float* aw = p.astate + 2 * fs;
-    fill(p.astate, 3 * fs, 0.f, st);
+    float* aw0 = p.astate + 2 * fs;
+    float* aw1 = p.astate + 3 * fs;
+    fill(p.astate, 4 * fs, 0.f, st);
     fill(p.gpad, fs, 0.f, st);
     TileArgs aa = make_tile_args(p, B);
     aa.adj = p.adj_buf;
     aa.acc = p.gpad;
     aa.wavelet = p.wav;
-    aa.wst = aw;
     const dim3 grid = tile_grid(p, nf);
     if (p.store_mode == 0) {
         aa.dstride = (size_t)nsteps * p.npts;
-        for (int m = 0; m < nsteps; ++m) {
-            aa.ucur = a0;
-            aa.unxt = a1;
-            aa.Din = p.Dstore + (size_t)(nsteps - 1 - m) * p.npts;
-            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ax, p.az);
+        for (int m = 0; m < nsteps;) {
+            const bool two = m + 1 < nsteps;
+            const int k = adjoint_steps(aa, grid, m, two, a0, a1, aw0, aw1, p.Dstore + (size_t)(nsteps - 1 - m) * p.npts,
+                                        two ? p.Dstore + (size_t)(nsteps - 2 - m) * p.npts : nullptr, p, st);
             std::swap(a0, a1);
+            if (k == 2) std::swap(aw0, aw1);
+            m += k;
         }
         return;
     }
@@ -294,29 +457,33 @@ static void enqueue_adjoint(Plan& p, int B, hipStream_t st) {
     aa.dstride = (size_t)K * p.npts;
     float* f0 = p.state;
     float* f1 = p.state + fs;
-    float* fw = p.state + 2 * fs;
-    fa.wst = fw;
+    float* fw0 = p.state + 2 * fs;
+    float* fw1 = p.state + 3 * fs;
     for (int c = p.nseg - 1; c >= 0; --c) {
         const int n0 = c * K;
         const int n1 = std::min(n0 + K, nsteps);
-        hipLaunchKernelGGL(k_ckpt<false>, dim3(grid_for(fs)), dim3(256), 0, st, p.ckpt, p.state, fw, nf, p.nseg, c,
-                           p.npts);
         float* g0 = f0;
         float* g1 = f1;
-        for (int n = n0; n < n1; ++n) {
-            fa.ucur = g0;
-            fa.unxt = g1;
-            fa.Dout = p.Dstore + (size_t)(n - n0) * p.npts;
-            hipLaunchKernelGGL(k_wave_tile<false>, grid, dim3(256), 0, st, fa, n, p.ax, p.az);
+        float* gw0 = fw0;
+        float* gw1 = fw1;
+        hipLaunchKernelGGL(k_ckpt<false>, dim3(grid_for(fs)), dim3(256), 0, st, p.ckpt, g0, gw0, nf, p.nseg, c,
+                           p.npts);
+        for (int n = n0; n < n1;) {
+            const bool two = n + 1 < n1;
+            const int k = forward_steps(fa, grid, n, two, g0, g1, gw0, gw1, p.Dstore + (size_t)(n - n0) * p.npts,
+                                        p.Dstore + (size_t)(n + 1 - n0) * p.npts, p, st);
             std::swap(g0, g1);
+            if (k == 2) std::swap(gw0, gw1);
+            n += k;
         }
-        for (int n = n1 - 1; n >= n0; --n) {
+        for (int n = n1 - 1; n >= n0;) {
             const int m = nsteps - 1 - n;
-            aa.ucur = a0;
-            aa.unxt = a1;
-            aa.Din = p.Dstore + (size_t)(n - n0) * p.npts;
-            hipLaunchKernelGGL(k_wave_tile<true>, grid, dim3(256), 0, st, aa, m, p.ax, p.az);
+            const bool two = n - 1 >= n0;
+            const int k = adjoint_steps(aa, grid, m, two, a0, a1, aw0, aw1, p.Dstore + (size_t)(n - n0) * p.npts,
+                                        two ? p.Dstore + (size_t)(n - 1 - n0) * p.npts : nullptr, p, st);
             std::swap(a0, a1);
+            if (k == 2) std::swap(aw0, aw1);
+            n -= k;
         }
     }
 }
