@@ -100,8 +100,9 @@ typedef struct fwi_plan fwi_plan;
 /* Read-only description of a plan's layout. */
 typedef struct {
     int nzp, nxp;              /* padded grid */
-    int path;                  /* 0: whole field resident in LDS, one workgroup per (sample, shot);
-                                  1: tiled sweep from HBM, one launch per time step */
+    int path;                  /* 0: field resident in LDS (one workgroup per (sample, shot), or lds_split
+                                  workgroups per field each holding a band of rows);
+                                  1: tiled sweep from HBM, two time steps per launch */
     int store_mode;            /* 0: full history of D = L u + s kept for the adjoint;
                                   1: checkpoints every `ckpt_every` steps plus recomputation */
     int ckpt_every;
@@ -133,7 +134,8 @@ typedef struct {
     int split;          /* LDS-resident path, when max_batch * ns fields leave CUs idle: 0 = split each field
                            over several workgroups (row bands exchanging 4-row halos every step, launched
                            cooperatively) if the cost model prefers it, and never with an explicit lds tile;
-                           1 = split whenever feasible (FWI_EINVAL if not); -1 = never */
+                           1 = split whenever feasible (FWI_EINVAL if not); -1 = never.  While the caller's
+                           stream is capturing a graph the unsplit kernels run (same results bit for bit). */
 } fwi_plan_options;
 
 /* fwi_plan_create with explicit execution options (NULL = automatic). */

@@ -205,6 +205,18 @@ static LdsArgs make_lds_args(const Plan& p) {
     return a;
 }
 
+// A cooperative launch cannot be recorded into a graph: while the caller's
+// stream is capturing, the whole-field kernels run instead (same results, bit
+// for bit).
+static bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
 // The split sweep's tile replaces the whole-field one; its exchange buffer is
 // cleared to level 0 first.
 static int split_args(const Plan& p, int nfields, LdsArgs& a, SplitArgs& sp, hipStream_t st) {
@@ -226,7 +238,7 @@ int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet
     a.wavelet = wavelet;
     a.store = store;
     const int nf = B * p.g.ns;
-    if (p.split_G > 1) {
+    if (p.split_G > 1 && !capturing(st)) {
         SplitArgs sp{};
         const int rc = split_args(p, nf, a, sp, st);
         if (rc) return rc;
@@ -242,7 +254,7 @@ int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wave
     a.adj = adj;
     a.wavelet = wavelet;
     const int nf = B * p.g.ns;
-    if (p.split_G > 1) {
+    if (p.split_G > 1 && !capturing(st)) {
         SplitArgs sp{};
         const int rc = split_args(p, nf, a, sp, st);
         if (rc) return rc;

@@ -169,3 +169,52 @@ def test_split_option_errors(dev):
     p = FwiPlan(acq, max_batch=1, device=dev, lds_tile=(3, 11))
     assert p.info["lds_split"] == 1  # an explicit tile keeps one workgroup per field
     p.close()
+
+
+def test_split_plan_under_graph_capture(dev):
+    """A plan that splits its fields runs the whole-field kernels while the
+    caller's stream is capturing (a cooperative launch is not recorded); the
+    captured forward + misfit + adjoint replays equal the eager (split) calls
+    bit for bit."""
+    from paper_2603_16393_amd import FwiPlan
+
+    acq = fi.surface_acquisition(70, 70, ns=2, nt=300, nb=40)
+    plan = FwiPlan(acq, max_batch=2, device=dev)
+    assert plan.info["lds_split"] >= 2
+    vt = torch.tensor(fi.faulted_model(70, 70, 9)[None].astype(np.float32), device=dev)
+    w = torch.tensor(fi.ricker(acq.nt, acq.dt, acq.f_peak), dtype=torch.float32, device=dev)
+    plan.set_obs(plan.forward(vt, w, keep_for_adjoint=False)[0].contiguous())
+    v = torch.tensor(np.stack([fi.faulted_model(70, 70, 80 + b) for b in range(2)]).astype(np.float32), device=dev)
+    d = torch.empty((2, acq.ns, acq.nr, acq.nt), dtype=torch.float32, device=dev)
+    J = torch.empty(2, dtype=torch.float64, device=dev)
+    adj = torch.empty_like(d)
+    g = torch.empty((2, 70, 70), dtype=torch.float32, device=dev)
+
+    def step():
+        plan.forward(v, w, keep_for_adjoint=True, out=d)
+        plan.w2_misfit(d, J_out=J, adj_out=adj)
+        plan.adjoint_gradient(v, adj, out=g)
+
+    step()
+    torch.cuda.synchronize()
+    ref = (d.clone(), J.clone(), g.clone())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        step()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        d.zero_()
+        g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(d, ref[0]) and torch.equal(J, ref[1]) and torch.equal(g, ref[2]), f"replay {rep}"
+        step()  # eager (split) work between replays
+        torch.cuda.synchronize()
+    assert plan.status() == 0
+    del graph
+    plan.close()
