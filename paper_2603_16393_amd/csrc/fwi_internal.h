@@ -88,6 +88,7 @@ struct SplitArgs {
     int* err;                    // |= 2 when a wait gave up (the sweep's results are then invalid)
 };
 constexpr int kSplitSpinMax = 1 << 18;  // polls of one value before a wait gives up
+constexpr int kBufferRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit accesses (gfx9 data format)
 
 // Arguments of one tiled step (fields in HBM).
 struct TileArgs {

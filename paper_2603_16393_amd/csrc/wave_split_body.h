@@ -95,13 +95,14 @@ __device__ __forceinline__ void split_tile_init(SplitTile<R, X>& t, const LdsArg
 
 // Step m of one tile: its R rows of u^{n+1} into nxt, then the corrections
 // of the points it owns (as the whole-field body orders them).  `Dt` is the
-// tile corner in D slice 0; `mirror`: rows above padded row 0 reflect.  After
+// tile corner in D slice 0 (Df: the field's slice 0); `mirror`: rows above
+// padded row 0 reflect.  After
 // row `issue_after` (if `fetch`) the X halo values at `src` (column c at
 // src + c * ncg) are requested
 // into hv, so that their latency overlaps the remaining rows.
 template <int R, int X, bool ADJ, bool XEXACT, bool STORE>
 __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArgs& a, const float* cur, float* nxt,
-                                                const float* az_s, int x0, bool mirror, int m, float* Dt,
+                                                const float* az_s, int x0, bool mirror, int m, float* Dt, float* Df,
                                                 size_t trfield, const float (&wz)[4], const float (&wx)[4],
                                                 int issue_after = -1, bool fetch = false,
                                                 const unsigned long long* src = nullptr,
@@ -112,6 +113,13 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
     float* nb = nxt + (t.lz + 4) * S + x0 + 4;
     const float* Dn = ADJ ? Dt + (size_t)max(nsteps - 2 - m, 0) * npts : nullptr;
     float* Dw = (!ADJ && STORE) ? Dt + (size_t)m * npts : nullptr;
+    // with exact columns, D goes through buffer accesses bounded by the field's
+    // slice: rows past the field (last band) are dropped on store and read as 0,
+    // so no per-point guard is needed
+    float* sliceD = Df + (size_t)(ADJ ? max(nsteps - 2 - m, 0) : m) * npts;
+    const __amdgpu_buffer_rsrc_t rsD =
+        __builtin_amdgcn_make_buffer_rsrc(sliceD, (short)0, npts * (int)sizeof(float), kBufferRsrcWord3);
+    const int offD = (t.z * nxp + x0) * (int)sizeof(float);
     float drec[X];
     if (ADJ && t.rec_j >= 0) {
 #pragma unroll
@@ -159,14 +167,22 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
             nb[j * S + c] = un;
             if (ADJ) t.acc[j][c] = fmaf(un, t.dc[j][c], t.acc[j][c]);
             if (STORE && !ADJ) {
-                if (t.z + j < nzp && (XEXACT || x0 + c < nxp)) Dw[j * nxp + c] = D;
+                if constexpr (XEXACT)
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D), rsD,
+                                                          offD + (j * nxp + c) * (int)sizeof(float), 0, 0);
+                else if (t.z + j < nzp && x0 + c < nxp)
+                    Dw[j * nxp + c] = D;
             }
         }
         if (ADJ) {
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < X; ++c)
-                t.dc[j][c] = (t.z + j < nzp && (XEXACT || x0 + c < nxp)) ? Dn[j * nxp + c] : 0.f;
+                if constexpr (XEXACT)
+                    t.dc[j][c] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(rsD, offD + (j * nxp + c) * (int)sizeof(float), 0, 0));
+                else
+                    t.dc[j][c] = (t.z + j < nzp && x0 + c < nxp) ? Dn[j * nxp + c] : 0.f;
             __builtin_amdgcn_sched_barrier(0);
         }
         if (j == issue_after && fetch) {
@@ -303,7 +319,8 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
         const unsigned level = (unsigned)m + 1;
         const size_t slot = (size_t)(level & 1) * 4 * sp.W;
         if (has_b) {
-            split_tile_step<1, X, ADJ, XEXACT, STORE>(tb, a, cur, nxt, az_s, x0, mirror, m, Db, trfield, wz, wx);
+            split_tile_step<1, X, ADJ, XEXACT, STORE>(tb, a, cur, nxt, az_s, x0, mirror, m, Db, Dfield, trfield, wz,
+                                                      wx);
             if (pub) {
                 const float* nb = nxt + (lb + 4) * S + x0 + 4;
 #pragma unroll
@@ -314,7 +331,7 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
         // they have published theirs (boundary rows come first everywhere)
         unsigned long long hv[X];
         if (has_i) {
-            split_tile_step<PI, X, ADJ, XEXACT, STORE>(ti, a, cur, nxt, az_s, x0, false, m, Di, trfield, wz, wx, 0,
+            split_tile_step<PI, X, ADJ, XEXACT, STORE>(ti, a, cur, nxt, az_s, x0, false, m, Di, Dfield, trfield, wz, wx, 0,
                                                       recv, src0 + slot, hv);
         } else if (recv) {
 #pragma unroll
