@@ -340,6 +340,8 @@ typedef struct {
     int kind;               /* 0: LDS-resident, 1: swept from HBM */
     int tile_x, tile_z;     /* kind 0: register tile (columns, rows); kind 1: sweep tile */
     int tuned;              /* 1 if the tile was picked by timing */
+    int parts;              /* HBM-swept fields: row parts per field, each swept by its own workgroup in lockstep
+                               with the others (1: one workgroup per field) */
 } fwi_batch_request_info;
 
 /* Validates every geometry (FWI_EINVAL / FWI_ECFL as fwi_plan_create), builds

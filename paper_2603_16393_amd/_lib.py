@@ -90,7 +90,8 @@ class BatchOptions(ctypes.Structure):
 
 class BatchRequestInfo(ctypes.Structure):
     _fields_ = [("v_offset", c_size_t), ("wavelet_offset", c_size_t), ("trace_offset", c_size_t), ("nzp", c_int),
-                ("nxp", c_int), ("kind", c_int), ("tile_x", c_int), ("tile_z", c_int), ("tuned", c_int)]
+                ("nxp", c_int), ("kind", c_int), ("tile_x", c_int), ("tile_z", c_int), ("tuned", c_int),
+                ("parts", c_int)]
 
 
 class SurTrainParams(ctypes.Structure):

@@ -59,7 +59,55 @@ struct BatchUnit {
     // kind 1: adjoint state (psi ping-pong, w_psi), checkpoints [nseg][2][npts], D of one segment [C][npts]
     float *pa, *pb, *pw, *ckpt, *dseg;
     int ckpt_every;
+    // kind 1 split into parts: this unit sweeps rows [z_lo, z_hi) of the field;
+    // the nparts units of one field meet at a barrier (counter *bar, cleared
+    // before each launch) after every step.  nparts = 1: the whole field.
+    int z_lo, z_hi, part, nparts;
+    int* bar;
+    int* flags;     // the batch's device flag (a barrier that gave up sets kFlagPartTimeout)
 };
+
+// Barrier of the nparts units of one field (all resident: the launch holds
+// at most one workgroup per compute unit, and the parts of a field are
+// queued next to each other, so a part waits at most until the next
+// workgroup frees up).  Release / acquire at device scope around a counter;
+// a wait that exceeds the spin limit raises the batch flag and the part stops
+// waiting from then on (its results are then invalid, never a hang).
+constexpr int kPartSpinMax = 1 << 22;
+constexpr int kFlagPartTimeout = 4;
+
+struct PartSync {
+    int nparts;
+    int* bar;
+    int* flags;
+    int k;          // barriers passed
+    bool gave_up;   // thread 0 only
+};
+
+__device__ inline void part_barrier(PartSync& ps) {
+    // every wave's stores complete (reach L2) before the barrier, so that the
+    // L2 write-back of thread 0's release fence covers the whole part's writes
+    if (ps.nparts > 1) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (ps.nparts > 1) {
+        ++ps.k;
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicAdd(ps.bar, 1);
+            int spins = 0;
+            while (!ps.gave_up &&
+                   __hip_atomic_load(ps.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ps.nparts * ps.k) {
+                if (++spins > kPartSpinMax) {
+                    atomicOr(ps.flags, kFlagPartTimeout);
+                    ps.gave_up = true;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __threadfence();
+        }
+        __syncthreads();
+    }
+}
 
 // HBM-swept field: wave w of the workgroup owns 64-column panels (column
 // group, row segment) and walks down each panel's rows.  Each lane keeps the
@@ -90,18 +138,19 @@ __device__ void glb_field_forward(const BatchUnit& Ug, float* lds) {
     // the wave index is uniform across the wave: made explicit so that panel
     // rows, bounds and clamps derived from it are scalar (SALU) arithmetic
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int npts = nzp * nxp;
-    for (int i = tid; i < npts; i += kLdsThreads) {
+    const int z_lo = Ug.z_lo, z_hi = Ug.z_hi;
+    PartSync ps{Ug.nparts, Ug.bar, Ug.flags, 0, false};
+    for (int i = z_lo * nxp + tid; i < z_hi * nxp; i += kLdsThreads) {
         ua[i] = 0.f;
         wst[i] = 0.f;
     }
     for (int r = tid; r < nr; r += kLdsThreads) traces[(size_t)r * nt] = 0.f;
-    __syncthreads();
+    part_barrier(ps);
     const int G = (nxp + 63) / 64;
     int S = 1;
     while ((G * S) % NW != 0) ++S;  // panels a multiple of the wave count (S <= NW)
     S *= SMUL;
-    const int seg = (nzp + S - 1) / S;
+    const int seg = (z_hi - z_lo + S - 1) / S;
     float* rb = lds + wave * 72;
     const float* cur = ua;
     float* nxt = ub;
@@ -109,7 +158,7 @@ __device__ void glb_field_forward(const BatchUnit& Ug, float* lds) {
         for (int pan = wave; pan < G * S; pan += NW) {
             const int g = pan % G, sg = pan / G;
             const int x0 = g * 64, x = x0 + lane;
-            const int za = sg * seg, zb = min(nzp, za + seg);
+            const int za = z_lo + sg * seg, zb = min(z_hi, za + seg);
             if (za >= zb) continue;
             const bool xin = x < nxp;
             const float axv = xin ? ax[x] : 0.f;
@@ -187,7 +236,7 @@ __device__ void glb_field_forward(const BatchUnit& Ug, float* lds) {
                 }
             }
         }
-        __syncthreads();
+        part_barrier(ps);
         float* t = const_cast<float*>(cur);
         cur = nxt;
         nxt = t;
@@ -204,6 +253,7 @@ __device__ void glb_field_forward(const BatchUnit& Ug, float* lds) {
 // are swapped after every step so that on return *cur holds the newest state.
 struct GlbCtx {
     int nzp, nxp, nt, nr, fs, src_pt, rec_z0, rec_z1;
+    int z_lo, z_hi;     // rows of this part
     float idz2, idx2, src_scale;
     const float* K;
     const float* wavelet;
@@ -218,7 +268,7 @@ struct GlbCtx {
 template <int RB, int SMUL, bool ADJ>
 __device__ void glb_steps(const GlbCtx& c, float*& cur, float*& nxt, float* __restrict__ wst, int n0, int n1,
                           float* __restrict__ ckpt, int C, float* __restrict__ dseg, float* __restrict__ acc,
-                          float* lds) {
+                          float* lds, PartSync& ps) {
     constexpr int NW = kLdsThreads / 64;
     const int nzp = c.nzp, nxp = c.nxp, npts = nzp * nxp;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -227,13 +277,13 @@ __device__ void glb_steps(const GlbCtx& c, float*& cur, float*& nxt, float* __re
     int S = 1;
     while ((G * S) % NW != 0) ++S;
     S *= SMUL;
-    const int seg = (nzp + S - 1) / S;
+    const int seg = (c.z_hi - c.z_lo + S - 1) / S;
     float* rb = lds + wave * 72;
     for (int it = 0; it < n1 - n0; ++it) {
         const int n = ADJ ? n1 - 1 - it : n0 + it;
-        if (!ADJ && ckpt && n % C == 0) {  // state before step n
+        if (!ADJ && ckpt && n % C == 0) {  // state before step n (this part's rows)
             float* ck = ckpt + (size_t)(n / C) * 2 * npts;
-            for (int i = tid; i < npts; i += kLdsThreads) {
+            for (int i = c.z_lo * nxp + tid; i < c.z_hi * nxp; i += kLdsThreads) {
                 ck[i] = cur[i];
                 ck[npts + i] = wst[i];
             }
@@ -243,7 +293,7 @@ __device__ void glb_steps(const GlbCtx& c, float*& cur, float*& nxt, float* __re
         for (int pan = wave; pan < G * S; pan += NW) {
             const int g = pan % G, sg = pan / G;
             const int x0 = g * 64, x = x0 + lane;
-            const int za = sg * seg, zb = min(nzp, za + seg);
+            const int za = c.z_lo + sg * seg, zb = min(c.z_hi, za + seg);
             if (za >= zb) continue;
             const bool xin = x < nxp;
             const float axv = xin ? c.ax[x] : 0.f;
@@ -329,7 +379,7 @@ __device__ void glb_steps(const GlbCtx& c, float*& cur, float*& nxt, float* __re
                 }
             }
         }
-        __syncthreads();
+        part_barrier(ps);
         float* t = cur;
         cur = nxt;
         nxt = t;
@@ -340,6 +390,7 @@ __device__ inline GlbCtx glb_ctx(const BatchUnit* U) {
     GlbCtx c;
     c.nzp = U->nzp, c.nxp = U->nxp, c.nt = U->nt, c.nr = U->nr, c.fs = U->fs, c.src_pt = U->src_pt;
     c.rec_z0 = U->rec_z0, c.rec_z1 = U->rec_z1;
+    c.z_lo = U->z_lo, c.z_hi = U->z_hi;
     c.idz2 = U->idz2, c.idx2 = U->idx2, c.src_scale = U->src_scale;
     c.K = U->K, c.wavelet = U->wavelet, c.rec_map = U->rec_map, c.rec_invw = U->rec_invw;
     c.ax = U->ax, c.az = U->az, c.traces = nullptr, c.adj = U->adj;
@@ -361,25 +412,27 @@ __device__ __noinline__ void unit_glb_gradient(const BatchUnit* __restrict__ U, 
     float* p1 = U->pb;
     float* pw = U->pw;
     float* acc = U->gpad;
-    for (int i = threadIdx.x; i < npts; i += kLdsThreads) {
+    PartSync ps{U->nparts, U->bar, U->flags, 0, false};
+    const int i0 = c.z_lo * c.nxp, i1 = c.z_hi * c.nxp;  // this part's points
+    for (int i = i0 + threadIdx.x; i < i1; i += kLdsThreads) {
         u0[i] = 0.f;
         w[i] = 0.f;
         p0[i] = 0.f;
         pw[i] = 0.f;
         acc[i] = 0.f;
     }
-    __syncthreads();
-    glb_steps<RB, SM, false>(c, u0, u1, w, 0, nsteps, U->ckpt, C, nullptr, nullptr, lds);
+    part_barrier(ps);
+    glb_steps<RB, SM, false>(c, u0, u1, w, 0, nsteps, U->ckpt, C, nullptr, nullptr, lds, ps);
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int n0 = sgi * C, n1 = min(n0 + C, nsteps);
         const float* ck = U->ckpt + (size_t)sgi * 2 * npts;
-        for (int i = threadIdx.x; i < npts; i += kLdsThreads) {
+        for (int i = i0 + threadIdx.x; i < i1; i += kLdsThreads) {
             u0[i] = ck[i];
             w[i] = ck[npts + i];
         }
-        __syncthreads();
-        glb_steps<RB, SM, false>(c, u0, u1, w, n0, n1, nullptr, C, U->dseg, nullptr, lds);
-        glb_steps<RB, SM, true>(c, p0, p1, pw, n0, n1, nullptr, C, U->dseg, acc, lds);
+        part_barrier(ps);
+        glb_steps<RB, SM, false>(c, u0, u1, w, n0, n1, nullptr, C, U->dseg, nullptr, lds, ps);
+        glb_steps<RB, SM, true>(c, p0, p1, pw, n0, n1, nullptr, C, U->dseg, acc, lds, ps);
     }
 }
 
@@ -541,6 +594,7 @@ __global__ void k_batch_bind(BatchUnit* __restrict__ units, int nunits, float* _
     if (u >= nunits) return;
     BatchUnit& U = units[u];
     U.adj = adj ? adj + U.tr_off : nullptr;
+    if (U.kind == 1 && U.nparts > 1 && U.part == 0) *U.bar = 0;
     if (U.kind == 0) {
         U.la.traces = traces + U.tr_off;
         U.la.wavelet = wavelets + U.w_off;
@@ -603,6 +657,8 @@ struct fwi_batch {
     long long v_total = 0, w_total = 0, tr_total = 0, pt_total = 0;
     std::vector<BatchUnit> units;                // queue order
     std::vector<int> unit_req;                   // request of each queued unit
+    std::vector<int> unit_shot;                  // shot of each queued unit
+    int* bars = nullptr;                         // barrier counters of the fields cut into parts
     BatchUnit* d_units = nullptr;
     PrepReq* d_prep = nullptr;
     int* counter = nullptr;
@@ -648,6 +704,9 @@ const GlbVar kGlbVar[kBatchGlbVariants] = {
     FWI_BATCH_GLB(FWI_V)
 #undef FWI_V
 };
+
+constexpr int kMaxParts = 4;     // row parts of one HBM-swept field
+constexpr int kMinPartRows = 16;
 
 // dynamic LDS of the persistent kernels: all of it but a little for their
 // static variables (the work-queue slot)
@@ -760,6 +819,12 @@ BatchUnit make_unit(const fwi_batch* b, int r, int s, int kind, int variant, con
         U.ua = state;
         U.ub = state + npts;
         U.w = state + 2 * npts;
+        U.z_lo = 0;
+        U.z_hi = nzp;
+        U.part = 0;
+        U.nparts = 1;
+        U.bar = nullptr;
+        U.flags = b->flags;
     }
     return U;
 }
@@ -974,36 +1039,70 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
         g_tune[key] = best;
     }
 
-    // units, longest first
+    // units, longest first.  An HBM-swept field whose time loop alone would
+    // outlast the batch's share per compute unit is cut into row parts swept
+    // by as many workgroups in lockstep (queued next to each other).
     if (st == FWI_OK) {
         struct Job {
-            double cost;
-            int r, s;
+            double cost;  // of one part
+            int r, s, part, nparts;
         };
+        double total = 0.0;
+        for (int r = 0; r < nreq; ++r)
+            total += (double)b->g[r].ns * b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1) * (b->kind[r] == 0 ? 0.2 : 1.0);
+        const double share = total / std::max(1, b->n_cu);
         std::vector<Job> jobs;
         size_t state_elems = 0;
+        int nsplit = 0;
         for (int r = 0; r < nreq; ++r)
             for (int s = 0; s < b->g[r].ns; ++s) {
-                jobs.push_back({(double)b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1), r, s});
+                const double cost = (double)b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1) * (b->kind[r] == 0 ? 0.2 : 1.0);
+                int np = 1;
+                if (b->kind[r] == 1 && cost > 1.25 * share)
+                    np = std::max(1, std::min({kMaxParts, (int)std::ceil(cost / share), b->nzp[r] / kMinPartRows}));
+                for (int q = 0; q < np; ++q) jobs.push_back({cost / np, r, s, q, np});
+                if (np > 1) ++nsplit;
                 if (b->kind[r] == 1) state_elems += 3 * (size_t)b->nzp[r] * b->nxp[r];
             }
         std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& c) { return a.cost > c.cost; });
         float* state = nullptr;
         st = balloc(b, &state, state_elems);
+        st = st ? st : balloc(b, &b->bars, (size_t)std::max(nsplit, 1));
         size_t so = 0;
+        int nb = 0;
+        std::map<std::pair<int, int>, std::pair<float*, int*>> field;  // (r, s) -> state, barrier
         for (const Job& j : jobs) {
             if (st) break;
             const int r = j.r;
             const long long tr_off = b->tr_off[r] + (long long)j.s * b->g[r].nr * b->g[r].nt;
             float* sp = nullptr;
+            int* bar = nullptr;
             if (b->kind[r] == 1) {
-                sp = state + so;
-                so += 3 * (size_t)b->nzp[r] * b->nxp[r];
+                auto it = field.find({r, j.s});
+                if (it == field.end()) {
+                    sp = state + so;
+                    so += 3 * (size_t)b->nzp[r] * b->nxp[r];
+                    bar = j.nparts > 1 ? b->bars + nb++ : nullptr;
+                    field[{r, j.s}] = {sp, bar};
+                } else {
+                    sp = it->second.first;
+                    bar = it->second.second;
+                }
             }
             BatchUnit U = make_unit(b, r, j.s, b->kind[r], b->variant[r], rd[r], b->K + b->pt_off[r], b->w_off[r],
                                     tr_off, sp, b->g[r].nt - 1);
+            if (j.nparts > 1) {
+                // rows split evenly; every part takes part of the sweep's panels
+                const int nzp = b->nzp[r];
+                U.part = j.part;
+                U.nparts = j.nparts;
+                U.z_lo = (int)((long long)nzp * j.part / j.nparts);
+                U.z_hi = (int)((long long)nzp * (j.part + 1) / j.nparts);
+                U.bar = bar;
+            }
             b->units.push_back(U);
             b->unit_req.push_back(r);
+            b->unit_shot.push_back(j.s);
             const size_t lb = b->kind[r] == 0 ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip) : glb_lds(U.variant, U.nzp);
             b->lds_bytes = std::max(b->lds_bytes, lb);
         }
@@ -1019,10 +1118,25 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             st = balloc(b, &b->gpad, (size_t)gtot);
             st = st ? st : balloc(b, &b->tr_scratch, (size_t)b->tr_total);
             b->grad_bytes = (size_t)(gtot + b->tr_total) * sizeof(float);
+            std::map<std::pair<int, int>, size_t> first;  // (r, s) -> its first unit: parts share the buffers
             for (size_t ui = 0; ui < b->units.size() && st == FWI_OK; ++ui) {
                 BatchUnit& U = b->units[ui];
                 const int r = b->unit_req[ui];
-                const int shot = jobs[ui].s;
+                const int shot = b->unit_shot[ui];
+                auto f = first.find({r, shot});
+                if (f != first.end()) {
+                    const BatchUnit& F = b->units[f->second];
+                    U.gpad = F.gpad;
+                    U.la.Dstore = F.la.Dstore;
+                    U.pa = F.pa;
+                    U.pb = F.pb;
+                    U.pw = F.pw;
+                    U.ckpt = F.ckpt;
+                    U.dseg = F.dseg;
+                    U.ckpt_every = F.ckpt_every;
+                    continue;
+                }
+                first[{r, shot}] = ui;
                 const size_t npts = (size_t)b->nzp[r] * b->nxp[r];
                 const int nsteps = b->g[r].nt - 1;
                 U.gpad = b->gpad + b->g_off[r] + (long long)shot * npts;
@@ -1099,6 +1213,9 @@ int fwi_batch_get_info(const fwi_batch* b, int r, fwi_batch_request_info* info) 
         info->tile_z = kGlbVar[b->variant[r]].RB;
     }
     info->tuned = b->tuned[r];
+    info->parts = 1;
+    for (size_t i = 0; i < b->units.size(); ++i)
+        if (b->unit_req[i] == r && b->units[i].kind == 1) info->parts = std::max(info->parts, b->units[i].nparts);
     return FWI_OK;
 }
 

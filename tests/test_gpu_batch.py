@@ -1,5 +1,6 @@
 """Uneven batches in one persistent launch (fwi_batch_*) vs the FP64 oracle
-and vs the per-geometry plan, through the C ABI.
+and vs the per-geometry plan, through the C ABI (HBM-swept fields that
+outlast the batch's share per compute unit run as row parts in lockstep).
 
 Bars: seismograms and gradients relative L2 <= 1e-4 against the oracle (the
 FP32-stencil target); against the plan's own sweep for the same geometry the
@@ -66,8 +67,10 @@ def test_small_uneven_batch_vs_oracle_and_plans(dev, autotune):
     reqs = _small_requests()
     b = FwiBatch([a for a, _, _ in reqs], autotune=autotune, device=dev)
     kinds = [i["kind"] for i in b.info]
-    _say(f"kinds {kinds} tiles {[(i['tile_x'], i['tile_z'], i['tuned']) for i in b.info]}")
+    parts = [i["parts"] for i in b.info]
+    _say(f"kinds {kinds} tiles {[(i['tile_x'], i['tile_z'], i['tuned']) for i in b.info]} parts {parts}")
     assert kinds[0] == 0 and kinds[1] == 0 and kinds[2] == 1 and kinds[3] == 1
+    assert parts[3] >= 2  # the 100 x 120 field outlasts the batch's share: swept in row parts
     v = b.pack_velocity([m for _, m, _ in reqs])
     w = b.pack_wavelets([x for _, _, x in reqs])
     tr = b.forward(v, w)
