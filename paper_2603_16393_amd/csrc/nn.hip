@@ -282,18 +282,28 @@ __global__ void k_out_bwd(int B, const float* __restrict__ dtr, const float* __r
 
 // ---------------------------------------------------------------------------
 // Weighted trace loss L = sum_b sum (w (pred - tgt))^2 / count, w = 1/(1 + kw |tgt| / max_b |tgt|).
+// max |t| per sample: grid (chunks, B); each block folds its maximum into
+// mx[b] with an integer atomic max (non-negative floats order like their bit
+// patterns), so the result is exact and independent of the order.  mx is
+// cleared first by k_zero_f32.
+__global__ void k_zero_f32(float* __restrict__ x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.f;
+}
+
 __global__ void k_absmax_per_sample(int B, long per, const float* __restrict__ t, float* __restrict__ mx) {
     __shared__ float sh[TPB];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y;
     float m = 0.f;
-    for (long i = threadIdx.x; i < per; i += TPB) m = fmaxf(m, fabsf(t[b * per + i]));
+    for (long i = blockIdx.x * (long)TPB + threadIdx.x; i < per; i += (long)gridDim.x * TPB)
+        m = fmaxf(m, fabsf(t[b * per + i]));
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int s = TPB / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) mx[b] = sh[0];
+    if (threadIdx.x == 0) atomicMax(reinterpret_cast<int*>(mx + b), __float_as_int(sh[0]));
 }
 
 __global__ void k_loss(int B, long per, const float* __restrict__ pred, const float* __restrict__ tgt,
@@ -661,7 +671,8 @@ void out_bwd(int B, const float* dtr, const float* scale, bf16_t* dout, hipStrea
 void loss(int B, const float* pred, const float* tgt, float kw, float pair_w, float* dpred, float* loss_out, float* mx,
           float* part, hipStream_t st) {
     const long per = (long)kNS * kNR * kNT;
-    hipLaunchKernelGGL(k_absmax_per_sample, dim3(B), dim3(TPB), 0, st, B, per, tgt, mx);
+    hipLaunchKernelGGL(k_zero_f32, dim3((B + TPB - 1) / TPB), dim3(TPB), 0, st, mx, B);
+    hipLaunchKernelGGL(k_absmax_per_sample, dim3(32, B), dim3(TPB), 0, st, B, per, tgt, mx);
     const int np = 512;
     hipLaunchKernelGGL(k_loss, dim3(np), dim3(TPB), 0, st, B, per, pred, tgt, mx, kw, 1.f / (float)(B * per), dpred,
                        part, np);

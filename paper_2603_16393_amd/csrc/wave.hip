@@ -16,9 +16,12 @@
 //
 // Two execution paths:
 //  * LDS-resident (wave_lds.hip): one workgroup per (sample, shot) keeps the
-//    whole padded field in LDS for all nt-1 steps.
-//  * tiled (this file): fields too large for LDS are swept one time step per
-//    launch in 64 x 16 tiles staged through LDS with a 4-cell halo.  Each
+//    whole padded field in LDS for all nt-1 steps, or, when the batch leaves
+//    compute units idle, several workgroups each keep a band of its rows and
+//    exchange halos every step (wave_split_body.h).
+//  * tiled (this file): fields too large for LDS are swept two time steps per
+//    launch in 64 x 16 tiles staged through LDS (k_wave_tile2; k_wave_tile for
+//    a single step).  Each
 //    sweep's launches are captured once into a hipGraph on a plan-owned
 //    stream and replayed on the caller's stream; the graph touches only
 //    plan-owned buffers (traces and adjoint sources are staged through them).
@@ -61,8 +64,8 @@ int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Tiled sweep: one launch per time step.  Block = 64 columns x 4 strips of 4
-// rows (a 64 x 16 tile); the tile of u^n plus a 4-cell halo is staged in LDS.
+// Tiled sweep, one time step: block = 64 columns x 4 strips of 4 rows (a
+// 64 x 16 tile); the tile of u^n plus a 4-cell halo is staged in LDS.
 constexpr int TX = 64, TZ = 16, TSTRIP = 4, TROWS = TZ / TSTRIP;
 
 template <bool ADJ>
