@@ -218,6 +218,25 @@ int fwi_nn_gemm(int M, int N, int K, int batch, const void* A, long lda, long st
                 long ldb, long strideB, int transB, float* C32, void* C16, long ldc, long strideC, float alpha,
                 float beta, const float* bias, int reduce_batch, int splitk, float* work, void* stream);
 
+/* Fused pointwise MLP of the surrogate's blocks (64 -> 128 GELU -> 64 per row,
+ * the 1x1 convolutions of the encoder and decoder blocks), R rows, BF16
+ * row-major operands: a, res, h, dg [R][64]; W1 [64][128]; W2 [128][64]; FP32
+ * b1 [128], b2 [64], da [R][64].  With R() rounding to BF16 and
+ * p = R(a W1 + b1):
+ *   forward  h  = R(res + R(R(gelu(p)) W2 + b2))          (gelu: erf form)
+ *   VJP      da = R((dg W2^T) gelu'(p)) W1^T              (p recomputed from a)
+ * One kernel each; the 128-wide hidden activation never leaves the chip.
+ * Results equal, bit for bit, those of the same block as two fwi_nn_gemm-style
+ * GEMMs with the roundings above.  BF16 and FP32 arrays 16-byte aligned, else
+ * FWI_EINVAL; h must not overlap a or res, nor da dg or a.  Asynchronous,
+ * except that the first call on a device fills a 384 KB table of GELU values
+ * and waits for it on `stream` (FWI_ESTATE if `stream` is capturing a graph
+ * then; fwi_sur_create fills it too). */
+int fwi_nn_mlp_forward(long R, const void* a, const void* W1, const float* b1, const void* W2, const float* b2,
+                       const void* res, void* h, void* stream);
+int fwi_nn_mlp_vjp(long R, const void* dg, const void* a, const void* W1, const float* b1, const void* W2, float* da,
+                   void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate of the forward map (Sec. 7, future work: a cheaper stand-in for
  * the wave solver inside guidance), fixed shapes: v [B][70][70] m/s ->
@@ -264,6 +283,12 @@ int fwi_sur_get_params(fwi_surrogate* s, float* host_params);
 /* Weight gradients of the last fwi_sur_backward(want_weight_grads = 1) or
  * training step (synchronous). */
 int fwi_sur_get_grads(fwi_surrogate* s, float* host_grads);
+/* fused = 1 (the default): each block's pointwise MLP runs as one kernel
+ * (fwi_nn_mlp_forward / fwi_nn_mlp_vjp) and the forward keeps no 128-wide
+ * hidden activations; a backward with want_weight_grads recomputes them.
+ * fused = 0: two GEMMs per MLP, hidden activations kept.  Both give identical
+ * results; the setting applies from the next forward.  FWI_EINVAL unless 0 or 1. */
+int fwi_sur_set_fused_mlp(fwi_surrogate* s, int fused);
 /* traces = S(v) for B <= max_batch samples (asynchronous).  Keeps the
  * activations for fwi_sur_backward. */
 int fwi_sur_forward(fwi_surrogate* s, int B, const float* v, float* traces, void* stream);

@@ -40,6 +40,8 @@ EXPORTED = (
     "fwi_batch_status",
     "fwi_error_string",
     "fwi_nn_gemm",
+    "fwi_nn_mlp_forward",
+    "fwi_nn_mlp_vjp",
     "fwi_sur_shape",
     "fwi_sur_param_count",
     "fwi_sur_create",
@@ -47,6 +49,7 @@ EXPORTED = (
     "fwi_sur_set_params",
     "fwi_sur_get_params",
     "fwi_sur_get_grads",
+    "fwi_sur_set_fused_mlp",
     "fwi_sur_forward",
     "fwi_sur_backward",
     "fwi_sur_train_step",
@@ -143,6 +146,9 @@ def load():
     cl, cf = ctypes.c_long, ctypes.c_float
     L.fwi_nn_gemm.argtypes = [c_int, c_int, c_int, c_int, P, cl, cl, c_int, P, cl, cl, c_int, P, P, cl, cl, cf, cf, P,
                               c_int, c_int, P, P]
+    L.fwi_nn_mlp_forward.argtypes = [cl, P, P, P, P, P, P, P, P]
+    L.fwi_nn_mlp_vjp.argtypes = [cl, P, P, P, P, P, P, P]
+    L.fwi_sur_set_fused_mlp.argtypes = [P, c_int]
     L.fwi_sur_shape.argtypes = [P]
     L.fwi_sur_param_count.argtypes = []
     L.fwi_sur_create.argtypes = [c_int, ctypes.POINTER(P)]

@@ -31,6 +31,10 @@ struct BfMap {  // offsets of the BF16 copies
 
 struct fwi_surrogate {
     int device = 0, max_batch = 0, step = 0;
+    // fused: each pointwise MLP runs as one kernel (forward and input VJP); the
+    // forward then keeps no hidden activations (pq_valid false) and a weight
+    // gradient recomputes them
+    bool fused = true, pq_valid = false;
     fwi::SurLayout L;
     fwi::BfMap M;
     std::vector<void*> allocs;
@@ -130,6 +134,23 @@ struct Ctx {
     }
 };
 
+// pre-activation p = R(a W1 + b1) and q = R(gelu(p)) of one pointwise MLP
+void mlp_hidden(Ctx& c, int rows, const bf16_t* a, const bf16_t* W1, const float* b1, bf16_t* p, bf16_t* q) {
+    c.mm(rows, kCH, kC, 1, a, kC, 0, 0, W1, kCH, 0, 0, nullptr, p, kCH, 0, b1, 0.f, kEpiGelu, q);
+}
+
+// h = R(res + R(q W2 + b2)) for one pointwise MLP of the forward, fused or as two GEMMs
+void mlp_forward(Ctx& c, bool fused, int rows, const bf16_t* a, const bf16_t* W1, const float* b1, const bf16_t* W2,
+                 const float* b2, const bf16_t* res, bf16_t* h, bf16_t* p, bf16_t* q) {
+    if (c.rc != FWI_OK) return;
+    if (fused) {
+        c.rc = nn::mlp_fwd(rows, a, W1, b1, W2, b2, res, h, c.st);
+        return;
+    }
+    mlp_hidden(c, rows, a, W1, b1, p, q);
+    c.mm(rows, kC, kCH, 1, q, kCH, 0, 0, W2, kC, 0, 0, nullptr, h, kC, 0, b2, 0.f, kEpiResid, nullptr, res);
+}
+
 // ---------------------------------------------------------------------------
 int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStream_t st) {
     Ctx c{s, st};
@@ -140,14 +161,12 @@ int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStre
     const int re = B * kZ * kX, rd = B * kT * kX;
     nn::copy_f32((long)B * kNZ * kNX, v, s->vcache, st);
     nn::lift_fwd(B, v, P + L.lift_w, P + L.lift_b, s->hin[0], st);
+    const bool fused = s->fused;
     for (int i = 0; i < kNBLK; ++i) {
         nn::dw_fwd(B, kZ, kX, s->hin[i], P + L.enc_dw_k[i], P + L.enc_dw_b[i], s->ae[i], st);
-        // p = R(a W1 + b1) and q = R(gelu(p)) from one GEMM epilogue
-        c.mm(re, kCH, kC, 1, s->ae[i], kC, 0, 0, W + M.enc_w1[i], kCH, 0, 0, nullptr, s->pe[i], kCH, 0,
-             P + L.enc_b1[i], 0.f, kEpiGelu, s->qe[i]);
-        // h_next = R(h + R(q W2 + b2))
-        c.mm(re, kC, kCH, 1, s->qe[i], kCH, 0, 0, W + M.enc_w2[i], kC, 0, 0, nullptr, s->hin[i + 1], kC, 0,
-             P + L.enc_b2[i], 0.f, kEpiResid, nullptr, s->hin[i]);
+        // h_next = R(h + R(R(gelu(R(a W1 + b1))) W2 + b2))
+        mlp_forward(c, fused, re, s->ae[i], W + M.enc_w1[i], P + L.enc_b1[i], W + M.enc_w2[i], P + L.enc_b2[i],
+                    s->hin[i], s->hin[i + 1], s->pe[i], s->qe[i]);
     }
     // depth -> time: per sample [T][X C] = T[T][Z] h[Z][X C]
     const long xc = (long)kX * kC;
@@ -159,10 +178,8 @@ int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStre
         c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 0, s->gin[i], kC, xc, 0, nullptr, s->g1[i], kC, xc, nullptr,
              0.f, kEpiResid, nullptr, s->gin[i]);
         nn::dw_fwd(B, kT, kX, s->g1[i], P + L.dec_dw_k[i], P + L.dec_dw_b[i], s->ad[i], st);
-        c.mm(rd, kCH, kC, 1, s->ad[i], kC, 0, 0, W + M.dec_w1[i], kCH, 0, 0, nullptr, s->pd[i], kCH, 0,
-             P + L.dec_b1[i], 0.f, kEpiGelu, s->qd[i]);
-        c.mm(rd, kC, kCH, 1, s->qd[i], kCH, 0, 0, W + M.dec_w2[i], kC, 0, 0, nullptr, s->gin[i + 1], kC, 0,
-             P + L.dec_b2[i], 0.f, kEpiResid, nullptr, s->g1[i]);
+        mlp_forward(c, fused, rd, s->ad[i], W + M.dec_w1[i], P + L.dec_b1[i], W + M.dec_w2[i], P + L.dec_b2[i],
+                    s->g1[i], s->gin[i + 1], s->pd[i], s->qd[i]);
     }
     c.mm(rd, kS, kC, 1, s->gin[kNBLK], kC, 0, 0, W + M.proj_w, kS, 0, 0, nullptr, s->o, kS, 0, P + L.proj_b);
     // time up-sampling: per sample [NT][X S] = U[NT][T] o[T][X S] (FP32 out)
@@ -171,7 +188,37 @@ int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStre
     if (c.rc != FWI_OK) return c.rc;
     nn::out_fwd(B, s->out32, P + L.out_scale, traces, st);
     s->cachedB = B;
+    s->pq_valid = !fused;
     return hipGetLastError() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
+// Through one pointwise MLP: s->da32 = dL/da from dL/dh (s->dg16, BF16, and
+// dg32, FP32, the latter read only for the bias gradient), and with want_w
+// the gradients of W1, b1, W2, b2.  The input VJP alone runs fused; the
+// weight gradients take the GEMM path and need p and q, which are recomputed
+// when the forward did not keep them.
+void mlp_backward(Ctx& c, int want_w, int rows, const bf16_t* a, bf16_t* p, bf16_t* q, const bf16_t* W1,
+                  const float* b1, const bf16_t* W2, float* gW1, float* gb1, float* gW2, float* gb2,
+                  const float* dg32) {
+    fwi_surrogate* s = c.s;
+    if (c.rc != FWI_OK) return;
+    if (!want_w && (s->fused || !s->pq_valid)) {
+        c.rc = nn::mlp_vjp(rows, s->dg16, a, W1, b1, W2, s->da32, c.st);
+        return;
+    }
+    if (!s->pq_valid) mlp_hidden(c, rows, a, W1, b1, p, q);
+    if (want_w) {
+        c.wgrad(kCH, kC, rows, 1, q, kCH, 0, 1, s->dg16, kC, 0, 0, gW2, kC);
+        nn::colsum(rows, kC, dg32, gb2, s->part, c.st);
+    }
+    // dp = (dg W2^T) gelu'(p), FP32 and BF16, from one GEMM epilogue
+    c.mm(rows, kCH, kC, 1, s->dg16, kC, 0, 0, W2, kC, 0, 1, s->dp32, nullptr, kCH, 0, nullptr, 0.f, kEpiGeluBwd,
+         s->dp16, nullptr, p);
+    if (want_w) {
+        c.wgrad(kC, kCH, rows, 1, a, kC, 0, 1, s->dp16, kCH, 0, 0, gW1, kCH);
+        nn::colsum(rows, kCH, s->dp32, gb1, s->part, c.st);
+    }
+    c.mm(rows, kC, kCH, 1, s->dp16, kCH, 0, 0, W1, kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
 }
 
 // Chain rule through the last forward_impl (same B).  dv may be NULL; with
@@ -201,18 +248,8 @@ int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want
 
     // every producer of dg32 also writes its BF16 copy dg16
     for (int i = kNBLK - 1; i >= 0; --i) {
-        if (want_w) {
-            c.wgrad(kCH, kC, rd, 1, s->qd[i], kCH, 0, 1, s->dg16, kC, 0, 0, G + L.dec_w2[i], kC);
-            nn::colsum(rd, kC, s->dg32, G + L.dec_b2[i], s->part, st);
-        }
-        // dp = (dg W2^T) gelu'(p), FP32 and BF16, from one GEMM epilogue
-        c.mm(rd, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.dec_w2[i], kC, 0, 1, s->dp32, nullptr, kCH, 0, nullptr, 0.f,
-             kEpiGeluBwd, s->dp16, nullptr, s->pd[i]);
-        if (want_w) {
-            c.wgrad(kC, kCH, rd, 1, s->ad[i], kC, 0, 1, s->dp16, kCH, 0, 0, G + L.dec_w1[i], kCH);
-            nn::colsum(rd, kCH, s->dp32, G + L.dec_b1[i], s->part, st);
-        }
-        c.mm(rd, kC, kCH, 1, s->dp16, kCH, 0, 0, W + M.dec_w1[i], kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
+        mlp_backward(c, want_w, rd, s->ad[i], s->pd[i], s->qd[i], W + M.dec_w1[i], P + L.dec_b1[i], W + M.dec_w2[i],
+                     G + L.dec_w1[i], G + L.dec_b1[i], G + L.dec_w2[i], G + L.dec_b2[i], s->dg32);
         if (c.rc != FWI_OK) return c.rc;
         // dg1 = dg + dw^T(da)   (in place in dg32)
         nn::dw_bwd(B, kT, kX, s->g1[i], s->da32, P + L.dec_dw_k[i], s->dg32, s->dg16,
@@ -235,17 +272,8 @@ int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want
     std::swap(s->dg16, s->dg16b);
 
     for (int i = kNBLK - 1; i >= 0; --i) {
-        if (want_w) {
-            c.wgrad(kCH, kC, re, 1, s->qe[i], kCH, 0, 1, s->dg16, kC, 0, 0, G + L.enc_w2[i], kC);
-            nn::colsum(re, kC, dh, G + L.enc_b2[i], s->part, st);
-        }
-        c.mm(re, kCH, kC, 1, s->dg16, kC, 0, 0, W + M.enc_w2[i], kC, 0, 1, s->dp32, nullptr, kCH, 0, nullptr, 0.f,
-             kEpiGeluBwd, s->dp16, nullptr, s->pe[i]);
-        if (want_w) {
-            c.wgrad(kC, kCH, re, 1, s->ae[i], kC, 0, 1, s->dp16, kCH, 0, 0, G + L.enc_w1[i], kCH);
-            nn::colsum(re, kCH, s->dp32, G + L.enc_b1[i], s->part, st);
-        }
-        c.mm(re, kC, kCH, 1, s->dp16, kCH, 0, 0, W + M.enc_w1[i], kCH, 0, 1, s->da32, nullptr, kC, 0, nullptr);
+        mlp_backward(c, want_w, re, s->ae[i], s->pe[i], s->qe[i], W + M.enc_w1[i], P + L.enc_b1[i], W + M.enc_w2[i],
+                     G + L.enc_w1[i], G + L.enc_b1[i], G + L.enc_w2[i], G + L.enc_b2[i], dh);
         if (c.rc != FWI_OK) return c.rc;
         nn::dw_bwd(B, kZ, kX, s->hin[i], s->da32, P + L.enc_dw_k[i], dh, s->dg16,
                    want_w ? G + L.enc_dw_k[i] : nullptr, G + L.enc_dw_b[i], s->part, st);
@@ -337,6 +365,7 @@ int fwi_sur_create(int max_batch, fwi_surrogate** out) {
          hipMemset(s->Am, 0, pb) != hipSuccess || hipMemset(s->Av, 0, pb) != hipSuccess ||
          hipMemset(s->W, 0, (size_t)s->M.total * sizeof(bf16_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
         rc = FWI_EHIP;
+    if (rc == FWI_OK) rc = nn::mlp_prepare(nullptr);  // the fused MLP's GELU tables, once per device
     if (rc != FWI_OK) {
         free_all(s);
         delete s;
@@ -376,6 +405,12 @@ static int copy_out(fwi_surrogate* s, const float* src, float* host) {
 
 int fwi_sur_get_params(fwi_surrogate* s, float* host) { return copy_out(s, s ? s->P : nullptr, host); }
 int fwi_sur_get_grads(fwi_surrogate* s, float* host) { return copy_out(s, s ? s->G : nullptr, host); }
+
+int fwi_sur_set_fused_mlp(fwi_surrogate* s, int fused) {
+    if (!s || (fused != 0 && fused != 1)) return FWI_EINVAL;
+    s->fused = fused == 1;
+    return FWI_OK;
+}
 
 int fwi_sur_forward(fwi_surrogate* s, int B, const float* v, float* traces, void* stream) {
     if (!s || !v || !traces || B < 0 || B > s->max_batch) return FWI_EINVAL;

@@ -78,6 +78,16 @@ void to_bf16(long n, const float* a, bf16_t* o, hipStream_t st);
 void copy_f32(long n, const float* a, float* o, hipStream_t st);
 void colsum(long rows, int cols, const float* a, float* out, float* part, hipStream_t st);
 void out_fwd(int B, const float* out, const float* scale, float* tr, hipStream_t st);
+// fused pointwise MLP (64 -> 128 GELU -> 64) over R rows: forward with residual,
+// and the input VJP recomputing the pre-activation (FWI_EINVAL on NULL or
+// misaligned operands).  mlp_prepare fills the device's GELU tables once
+// (synchronous on st; FWI_ESTATE if st is capturing a graph at that point);
+// both entry points call it.
+int mlp_prepare(hipStream_t st);
+int mlp_fwd(long R, const bf16_t* a, const bf16_t* W1, const float* b1, const bf16_t* W2, const float* b2,
+            const bf16_t* res, bf16_t* h, hipStream_t st);
+int mlp_vjp(long R, const bf16_t* dg, const bf16_t* a, const bf16_t* W1, const float* b1, const bf16_t* W2, float* da,
+            hipStream_t st);
 void out_bwd(int B, const float* dtr, const float* scale, bf16_t* dout, hipStream_t st);
 void loss(int B, const float* pred, const float* tgt, float kw, float pair_w, float* dpred, float* loss_out, float* mx,
           float* part, hipStream_t st);

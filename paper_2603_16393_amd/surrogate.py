@@ -120,6 +120,10 @@ class Surrogate:
         except Exception:
             pass
 
+    def set_fused_mlp(self, fused: bool) -> None:
+        """One kernel per pointwise MLP (default) or two GEMMs; identical results."""
+        check(_lib.load().fwi_sur_set_fused_mlp(self._h, int(bool(fused))), "fwi_sur_set_fused_mlp")
+
     # parameters ---------------------------------------------------------
     def set_params(self, params) -> None:
         vec = pack(params) if isinstance(params, dict) else np.ascontiguousarray(params, np.float32)

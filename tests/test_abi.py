@@ -72,6 +72,21 @@ def test_guidance_validation():
     assert L.fwi_guidance_step(0, 4, 4, None, None, None, None, ctypes.byref(ok), None, None, None) == 0
 
 
+def test_mlp_and_surrogate_option_validation():
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    x = ctypes.c_void_p(256)
+    assert L.fwi_nn_mlp_forward(-1, x, x, x, x, x, x, x, None) == -1
+    assert L.fwi_nn_mlp_forward(0, None, None, None, None, None, None, None, None) == 0
+    assert L.fwi_nn_mlp_forward(16, x, x, None, x, x, x, x, None) == -1
+    assert L.fwi_nn_mlp_forward(16, ctypes.c_void_p(258), x, x, x, x, x, x, None) == -1  # not 16-byte aligned
+    assert L.fwi_nn_mlp_vjp(-5, x, x, x, x, x, x, None) == -1
+    assert L.fwi_nn_mlp_vjp(0, None, None, None, None, None, None, None) == 0
+    assert L.fwi_nn_mlp_vjp(16, x, x, x, x, x, None, None) == -1
+    assert L.fwi_sur_set_fused_mlp(None, 1) == -1
+
+
 def test_product_has_no_oracle_or_cpu_path():
     """The product package never imports the oracle, and the HIP library is required."""
     pkg = os.path.join(ROOT, "paper_2603_16393_amd")
