@@ -13,6 +13,9 @@ arrays through ctypes.  Functions and the passages they follow:
 * :func:`w2_prepare`   -- omega, c', Q_obs, S_obs (Sec. 5.1 (I)-(III), Sec. 6.2)
 * :func:`w2_misfit`    -- J (Eq. final_objective) and dJ/dd_syn
 * :func:`guidance`     -- TV, rho, kappa and the update (Sec. 5.2, Algorithm 2)
+* :func:`l2_misfit`    -- least-squares potential Phi_l2 of baseline DPS (Sec. 4,
+                          Algorithm 1) and its weighted / normalised ablation form
+* :func:`tv_subgradient` -- g + alpha dTV (Eq. tv) for the TV-regularised baselines (Sec. 6)
 
 Every function is pinned by the CPU tests in ``tests/test_oracle_*.py``.
 """
@@ -59,6 +62,8 @@ def lib():
         L.orc_w2_misfit.argtypes = [i, i, i, d, _dp, _dp, _dp, _dp, d, d, i, i, i, _dp, _dp, _dp]
         L.orc_quantiles.argtypes = [i, d, _dp, d, i, _dp, _dp]
         L.orc_guidance.argtypes = [i, i, i, _dp, _dp, _dp, _dp, d, d, d, d, d, d, d, _dp, _dp, _dp, _dp]
+        L.orc_l2_misfit.argtypes = [i, i, i, _dp, _dp, d, d, i, _dp, _dp]
+        L.orc_tv_subgradient.argtypes = [i, i, i, _dp, _dp, d, _dp]
         L.orc_stencil_weights.argtypes = [_dp]
         L.orc_stencil_weights.restype = None
         L.orc_apply_laplacian.argtypes = [i, i, d, d, i, _dp, _dp, i]
@@ -220,6 +225,44 @@ def guidance(v_prop, h, g, v0hat, rho0=1.15, c=0.1, tau=0.0, gamma=0.55, eps=1e-
     if single:
         return vn[0], rho[0], tv[0], kap[0]
     return vn, rho, tv, kap
+
+
+def l2_misfit(d_syn: np.ndarray, d_obs: np.ndarray, sigma: float = 0.05, k: float = 0.0, normalize: bool = False,
+              want_adjoint: bool = True):
+    """J per sample and dJ/dd_syn of (1/2) sum (w (d_syn - d_obs))^2 / S, with
+    w = 1/(1 + k |d_obs| / max|d_obs|) and S = sigma^2 or sum (w d_obs)^2."""
+    o = _d(d_obs)
+    d = _d(d_syn)
+    single = d.ndim == o.ndim
+    if single:
+        d = d[None]
+    B = d.shape[0]
+    assert d.shape[1:] == o.shape
+    nt = o.shape[-1]
+    ntr = int(np.prod(o.shape[:-1]))
+    J = np.zeros(B)
+    adj = np.zeros(d.shape) if want_adjoint else None
+    _chk(lib().orc_l2_misfit(B, ntr, nt, _p(d), _p(o), float(sigma), float(k), int(bool(normalize)), _p(J),
+                             _p(adj) if adj is not None else None), "orc_l2_misfit")
+    if single:
+        return J[0], (adj[0] if adj is not None else None)
+    return J, adj
+
+
+def tv_subgradient(x: np.ndarray, g: np.ndarray | None = None, alpha: float = 1.0) -> np.ndarray:
+    """g + alpha q with q a subgradient of TV (Eq. tv) at x (sign(0) = 0)."""
+    xx = _d(x)
+    single = xx.ndim == 2
+    if single:
+        xx = xx[None]
+    B, nz, nx = xx.shape
+    gg = None
+    if g is not None:
+        gg = _d(g).reshape(B, nz, nx)
+    out = np.zeros_like(xx)
+    _chk(lib().orc_tv_subgradient(B, nz, nx, _p(xx), _p(gg) if gg is not None else None, float(alpha), _p(out)),
+         "orc_tv_subgradient")
+    return out[0] if single else out
 
 
 def stencil_weights() -> np.ndarray:

@@ -690,6 +690,86 @@ int orc_guidance(int B, int nz, int nx, const double* vprop, const double* h, co
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Least-squares potential of baseline DPS (Sec. 4, Phi_l2 with Sigma =       */
+/* sigma^2 I; Sec. 6 ablation: MSE guidance, optionally with the wavefield    */
+/* enhancement of Sec. 5.1 (I) and a misfit-scale normalisation)              */
+/* ------------------------------------------------------------------------ */
+
+/* Observations dobs [ntr][nt] shared by the B samples dsyn [B][ntr][nt]:
+ *   w = 1/(1 + k |dobs| / max|dobs|)                      Eq. omega_def
+ *       (w = 1 when k = 0 or every observation is zero)
+ *   r = dsyn_b - dobs
+ *   S = sigma^2                   (normalize = 0: Phi_l2 = |r|^2_{Sigma^-1} / 2)
+ *     = sum (w dobs)^2            (normalize = 1; 1 if that sum is 0)
+ *   J_b   = (1/2) sum (w r)^2 / S
+ *   adj_b = dJ_b / d dsyn_b = w^2 r / S                                     */
+int orc_l2_misfit(int B, int ntr, int nt, const double* dsyn, const double* dobs, double sigma, double k,
+                  int normalize, double* J, double* adj) {
+    if (B < 0 || ntr < 1 || nt < 1 || !(k >= 0) || (!normalize && !(sigma > 0))) return ORC_EINVAL;
+    size_t n = (size_t)ntr * nt;
+    double amax = 0.0;
+    for (size_t j = 0; j < n; ++j)
+        if (fabs(dobs[j]) > amax) amax = fabs(dobs[j]);
+    double* w = (double*)malloc(n * sizeof(double));
+    if (!w) return ORC_ENOMEM;
+    for (size_t j = 0; j < n; ++j) w[j] = (k > 0.0 && amax > 0.0) ? 1.0 / (1.0 + k * fabs(dobs[j]) / amax) : 1.0;
+    double S = sigma * sigma;
+    if (normalize) {
+        S = 0.0;
+        for (size_t j = 0; j < n; ++j) S += (w[j] * dobs[j]) * (w[j] * dobs[j]);
+        if (S == 0.0) S = 1.0;
+    }
+    for (int b = 0; b < B; ++b) {
+        double acc = 0.0;
+        for (size_t j = 0; j < n; ++j) {
+            double r = dsyn[(size_t)b * n + j] - dobs[j];
+            acc += (w[j] * r) * (w[j] * r);
+            if (adj) adj[(size_t)b * n + j] = w[j] * w[j] * r / S;
+        }
+        J[b] = 0.5 * acc / S;
+    }
+    free(w);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Total-variation subgradient (Eq. tv; the TV-regularised descent baselines  */
+/* W2+TV and OT-WE+TV of Sec. 6)                                              */
+/* ------------------------------------------------------------------------ */
+
+/* For each sample b, x and g [nz][nx]:
+ *   out = g + alpha q,  q a subgradient of TV(x) = (1/(nz nx)) sum |x_m - x_l|
+ *   over the forward differences (l -> m = right or lower neighbour) that exist:
+ *   each difference adds sign(x_m - x_l) / (nz nx) to q_m and subtracts it from
+ *   q_l, with sign(0) = 0.  g may be NULL (zero).                            */
+int orc_tv_subgradient(int B, int nz, int nx, const double* x, const double* g, double alpha, double* out) {
+    if (B < 0 || nz < 1 || nx < 1) return ORC_EINVAL;
+    size_t n = (size_t)nz * nx;
+    for (int b = 0; b < B; ++b) {
+        const double* xb = x + (size_t)b * n;
+        double* ob = out + (size_t)b * n;
+        for (size_t j = 0; j < n; ++j) ob[j] = g ? g[(size_t)b * n + j] : 0.0;
+        for (int iz = 0; iz < nz; ++iz)
+            for (int ix = 0; ix < nx; ++ix) {
+                int l = iz * nx + ix;
+                if (ix + 1 < nx) {
+                    double d = xb[l + 1] - xb[l];
+                    double s = (d > 0.0) - (d < 0.0);
+                    ob[l + 1] += alpha * s / (double)n;
+                    ob[l] -= alpha * s / (double)n;
+                }
+                if (iz + 1 < nz) {
+                    double d = xb[l + nx] - xb[l];
+                    double s = (d > 0.0) - (d < 0.0);
+                    ob[l + nx] += alpha * s / (double)n;
+                    ob[l] -= alpha * s / (double)n;
+                }
+            }
+    }
+    return ORC_OK;
+}
+
 /* Small helpers exposed for the self-checks. */
 void orc_stencil_weights(double* w) {
     for (int i = 0; i < 5; ++i) w[i] = W8[i];
