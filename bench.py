@@ -72,8 +72,8 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
 TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
                    "paper_2603_16393_amd/csrc/wave_split_body.h", "paper_2603_16393_amd/csrc/fwi_internal.h",
                    "paper_2603_16393_amd/csrc/capi.hip")
-TRAFFIC_SHA1 = "6892e48d442c8efee815145a90ad27327817a08f"
-TRAFFIC_BYTES = {"forward": 8995147736.0, "adjoint": 8532720292.0}
+TRAFFIC_SHA1 = "c95be2ae0aebb210e7ceebc38a43e4eef5cec4e9"
+TRAFFIC_BYTES = {"forward": 8991429507.0, "adjoint": 8532635784.0}
 
 
 def kernel_sources_sha1():
@@ -178,6 +178,76 @@ def surrogate_guidance(plan, wt, v_true):
                        "t > 0.5: anchor + surrogate change, solver judge (cos >= 0.95, misfit error <= 5%) with an "
                        "adaptive interval (4, x2 on pass up to 32, /2 on fail); t <= 0.5: solver")
     sur.close()
+    return res
+
+
+def comparison_variants(plan, acq, wt, dobs, v, x0, steps=10, warmup=2):
+    """Whole guidance steps of the comparison and ablation variants on the same batch:
+    baseline DPS with the least-squares potential (Algorithm 1, sigma = 0.05, scalar step), its MSE-All
+    ablation form (amplitude weight k = 100, misfit-scale normalisation, preconditioned step), and the
+    TV-regularised descent baselines W2+TV (raw-trace squared W2, fixed step) and OT-WE+TV (enhanced
+    W2, preconditioned step).  Each: forward, misfit, adjoint gradient, [TV subgradient,] update."""
+    import torch
+
+    from paper_2603_16393_amd import FwiPlan, guidance_step, tv_subgradient
+
+    dev = plan.device
+    plan_raw = FwiPlan(acq, max_batch=B, device=dev)
+    plan_raw.set_obs(dobs, k=0.0, squared=True)
+    d = torch.empty((B, NS, acq.nr, NT), dtype=torch.float32, device=dev)
+    J = torch.empty(B, dtype=torch.float64, device=dev)
+    adj = torch.empty_like(d)
+    g = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
+    h = torch.empty_like(g)
+    xn = torch.empty_like(g)
+    rho = torch.empty(B, dtype=torch.float32, device=dev)
+    alpha = 1e-6  # TV weight per m/s of gradient (a fixed setting for timing)
+
+    def lsq(kw, precond):
+        def step():
+            plan.forward(v, wt, keep_for_adjoint=True, out=d)
+            plan.l2_misfit(d, dobs, J_out=J, adj_out=adj, **kw)
+            plan.adjoint_gradient(v, adj, out=g)
+            extra = {} if precond else dict(gamma=0.0, tau=1e30)
+            guidance_step(x0, g, g, x0, unit_scale=1500.0, out=xn, rho_out=rho, **extra)
+        return step
+
+    def tv(p, precond):
+        def step():
+            p.forward(v, wt, keep_for_adjoint=True, out=d)
+            p.w2_misfit(d, want_adjoint=True, J_out=J, adj_out=adj)
+            p.adjoint_gradient(v, adj, out=g)
+            tv_subgradient(v, g, alpha, out=h)
+            extra = {} if precond else dict(gamma=0.0, tau=1e30)
+            guidance_step(x0, h, g, x0, unit_scale=1500.0, out=xn, rho_out=rho, **extra)
+        return step
+
+    variants = {
+        "dps_l2": lsq(dict(sigma=0.05), False),
+        "mse_all": lsq(dict(sigma=1.0, k=100.0, normalize=True), True),
+        "w2_tv": tv(plan_raw, False),
+        "ot_we_tv": tv(plan, True),
+    }
+    res = {}
+    for name, step in variants.items():
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"grads_per_s": round(B / (ms / 1e3), 2), "ms_per_step": round(ms, 4)}
+    ok = plan.status() == 0 and plan_raw.status() == 0
+    plan_raw.close()
+    if not ok:
+        return {"error": "device-side check failed"}
+    res["protocol"] = (f"{B} samples x one step each, {steps} timed steps after {warmup} warm-up: forward, misfit "
+                       "(least squares or W2), adjoint gradient, [TV subgradient,] update; same batch and "
+                       "observations as the plain line")
     return res
 
 
@@ -406,6 +476,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the library's plain copy kernel on 512 MiB three times "
                          "(the reference dispatch for HBM traffic counters) and exit")
@@ -561,9 +632,12 @@ def main():
             "launch_ms": round(dom_ms, 4),
         },
         "sweep_ms": {"forward": round(fwd_sweep_ms, 4), "adjoint": round(adj_sweep_ms, 4)},
+        "variants": None,
         "surrogate": None,
         "cpu_baseline": None,
     }
+    if not args.no_variants:
+        out["variants"] = comparison_variants(plan, acq, wt, dobs[0].contiguous(), v, x0)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_guidance(plan, wt, v_true)
     if not args.no_cpu_baseline:

@@ -12,7 +12,10 @@
  *     fwi_guidance_step      v_{i-1} = v'_{i-1} - rho_i D_i h (Sec. 5.2, Eqs. tv, rho, kappa, precond_step)
  *
  * after a one-time fwi_set_obs (weights, shift constants, observed quantiles
- * and S_obs of Sec. 5.1 (I)-(III)).
+ * and S_obs of Sec. 5.1 (I)-(III)).  The comparison variants of Sec. 6 swap
+ * single calls: fwi_l2_misfit for fwi_w2_misfit (baseline DPS, Algorithm 1,
+ * and the MSE ablations), and fwi_tv_subgradient before fwi_guidance_step
+ * (the TV-regularised descent baselines).
  *
  * Conventions shared by every entry point
  *   - Array arguments are DEVICE pointers unless marked HOST; they are owned by
@@ -81,6 +84,16 @@ typedef struct {
                           1: sum W2^2 / sum ||Q_obs||^2 (raw-trace W2 baseline, Sec. 6) */
     int reduction;     /* 0: divide by the observation scale S_obs; 1: average over pairs */
 } fwi_w2_params;
+
+/* Least-squares misfit settings: the potential Phi_l2 of baseline DPS (Sec. 4,
+ * Algorithm 1; Sigma = sigma^2 I, paper sigma = 0.05) and the ablation's MSE
+ * guidance with wavefield enhancement (Sec. 6: the amplitude weight of
+ * Sec. 5.1 (I) and a misfit-scale normalisation). */
+typedef struct {
+    double sigma;   /* noise standard deviation; S = sigma^2 when normalize = 0 (> 0 then) */
+    double k;       /* amplitude weight w = 1/(1 + k |d_obs| / max|d_obs|) (Eq. omega_def); 0: w = 1 */
+    int normalize;  /* 1: S = sum (w d_obs)^2 over all traces (1 if that is 0) instead of sigma^2 */
+} fwi_l2_params;
 
 /* Guidance-update settings (Sec. 5.2).  Paper fixed values: c = 0.1,
  * tau = 0, eps = 1e-4 (Sec. 6.3); gamma and rho0 per dataset (Table 'parameter'). */
@@ -174,6 +187,16 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
  *   adj_src  [B][ns][nr][nt] output dJ/dd_syn, or NULL to skip the adjoint. */
 int fwi_w2_misfit(fwi_plan* plan, int B, const float* d_syn, double* J, float* adj_src, void* stream);
 
+/* Least-squares misfit and its adjoint source (fwi_l2_params), per sample b:
+ *   J[b]        = (1/2) sum (w (d_syn[b] - d_obs))^2 / S
+ *   adj_src[b]  = dJ[b]/dd_syn[b] = w^2 (d_syn[b] - d_obs) / S
+ *   d_obs [ns][nr][nt] (shared by the batch), d_syn and adj_src [B][ns][nr][nt],
+ *   J [B] FP64; adj_src may be NULL.  w and S come from d_obs on every call
+ *   (no fwi_set_obs needed).  FP64 sums in a fixed order (deterministic).
+ *   Uses the plan's scratch: not concurrent with fwi_w2_misfit on the plan. */
+int fwi_l2_misfit(fwi_plan* plan, int B, const float* d_syn, const float* d_obs, const fwi_l2_params* params,
+                  double* J, float* adj_src, void* stream);
+
 /* Adjoint-state gradient (the transpose of the linearised forward map
  * applied to the adjoint source): the adjoint field is stepped backward in
  * time with the receivers as sources and correlated at zero lag with the
@@ -199,6 +222,17 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
 int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h, const float* g,
                       const float* v0hat, const fwi_guidance_params* params, float* v_next, float* rho_out,
                       void* stream);
+
+/* Total-variation subgradient for the TV-regularised descent baselines
+ * (Sec. 6: W2+TV and OT-WE+TV, with TV of Eq. tv), per sample of [B][nz][nx]:
+ *   out = g + alpha q,  q_l = (1/(nz nx)) sum over the forward differences
+ *   x_m - x_l' (m the right or lower neighbour of l') that contain l of
+ *   sign(x_m - x_l') (+ at the head m, - at the tail l'), sign(0) = 0.
+ * g may be NULL (zero) and may equal out; out must not alias v.  Needs no
+ * plan.  The descent steps are then fwi_guidance_step with h = out:
+ * W2+TV is gamma = 0 and tau above any TV (rho = rho0), OT-WE+TV uses the
+ * preconditioner evaluated at v (v_prop = v0hat = v). */
+int fwi_tv_subgradient(int B, int nz, int nx, const float* v, const float* g, double alpha, float* out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Building blocks of the learned surrogate (BF16 storage, FP32 accumulation).

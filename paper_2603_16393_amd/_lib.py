@@ -28,6 +28,8 @@ EXPORTED = (
     "fwi_w2_misfit",
     "fwi_adjoint_gradient",
     "fwi_guidance_step",
+    "fwi_l2_misfit",
+    "fwi_tv_subgradient",
     "fwi_status",
     "fwi_plan_sweep_ms",
     "fwi_copy",
@@ -69,6 +71,10 @@ class Geometry(ctypes.Structure):
 class W2Params(ctypes.Structure):
     _fields_ = [("k", c_double), ("eps_prime", c_double), ("n_xi", c_int), ("c_factor", c_double),
                 ("squared", c_int), ("reduction", c_int)]
+
+
+class L2Params(ctypes.Structure):
+    _fields_ = [("sigma", c_double), ("k", c_double), ("normalize", c_int)]
 
 
 class GuidanceParams(ctypes.Structure):
@@ -130,6 +136,8 @@ def load():
     L.fwi_forward.argtypes = [P, c_int, P, P, P, c_int, P]
     L.fwi_w2_misfit.argtypes = [P, c_int, P, P, P, P]
     L.fwi_adjoint_gradient.argtypes = [P, c_int, P, P, P, P, P]
+    L.fwi_l2_misfit.argtypes = [P, c_int, P, P, ctypes.POINTER(L2Params), P, P, P]
+    L.fwi_tv_subgradient.argtypes = [c_int, c_int, c_int, P, P, c_double, P, P]
     L.fwi_guidance_step.argtypes = [c_int, c_int, c_int, P, P, P, P, ctypes.POINTER(GuidanceParams), P, P, P]
     L.fwi_status.argtypes = [P]
     L.fwi_plan_sweep_ms.argtypes = [P, P, P]

@@ -289,6 +289,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     st = st ? st : alloc_n(p, &p.qnorm, (size_t)ns * nr);
     st = st ? st : alloc_n(p, &p.sobs, 2);
     st = st ? st : alloc_n(p, &p.w2pair, nf * nr);
+    st = st ? st : alloc_n(p, &p.l2stat, (size_t)2 * ns * nr + 2);
     if (p.path == 1) {
         st = st ? st : alloc_n(p, &p.rec_map, npts);
         st = st ? st : alloc_n(p, &p.state, 4 * nf * npts);   // u, u, w, w (two-step launches do not update w in place)
@@ -465,6 +466,26 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
         ++p.n_adj_rec;
     }
     return launch_fold_gradient(p, B, scale, grad, st);
+}
+
+int fwi_l2_misfit(fwi_plan* plan, int B, const float* d_syn, const float* d_obs, const fwi_l2_params* params,
+                  double* J, float* adj_src, void* stream) {
+    if (!plan || !params || B < 0 || B > plan->max_batch) return FWI_EINVAL;
+    const fwi_l2_params& lp = *params;
+    if (!(lp.k >= 0) || !std::isfinite(lp.k) || (lp.normalize != 0 && lp.normalize != 1) ||
+        (lp.normalize == 0 && !(lp.sigma > 0 && std::isfinite(lp.sigma))))
+        return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (!d_syn || !d_obs || !J) return FWI_EINVAL;
+    (void)hipSetDevice(plan->device);
+    return launch_l2_misfit(*plan, B, d_syn, d_obs, lp, J, adj_src, as_stream(stream));
+}
+
+int fwi_tv_subgradient(int B, int nz, int nx, const float* v, const float* g, double alpha, float* out, void* stream) {
+    if (B < 0 || nz < 1 || nx < 1 || !std::isfinite(alpha)) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (!v || !out || out == v) return FWI_EINVAL;
+    return launch_tv_subgradient(B, nz, nx, v, g, alpha, out, as_stream(stream));
 }
 
 int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h, const float* g, const float* v0hat,

@@ -162,7 +162,8 @@ struct Plan {
     double* qobs = nullptr;      // [ns*nr*n_xi]
     double* qnorm = nullptr;     // [ns*nr] per-trace (int Q_obs^2) (squared) or its root
     double* sobs = nullptr;      // [1]
-    double* w2pair = nullptr;    // [max_batch*ns*nr]
+    double* w2pair = nullptr;    // [max_batch*ns*nr] per-pair terms (W2 and least-squares misfits)
+    double* l2stat = nullptr;    // [2*ns*nr + 2] least squares: per-trace max|d_obs|, weighted energies; max, S
     int qobs_cap = 0;            // n_xi capacity of qobs
 
     int stored_B = 0;            // batch of the forward state kept for the adjoint (0 = none)
@@ -226,6 +227,10 @@ int launch_fold_gradient(const Plan& p, int B, const float* scale, float* grad, 
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
 int launch_w2_obs(Plan& p, const float* d_obs, hipStream_t st);
 int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st);
+int launch_l2_misfit(const Plan& p, int B, const float* d_syn, const float* d_obs, const fwi_l2_params& lp, double* J,
+                     float* adj, hipStream_t st);
+int launch_tv_subgradient(int B, int nz, int nx, const float* v, const float* g, double alpha, float* out,
+                          hipStream_t st);
 int launch_guidance(int B, int nz, int nx, const float* v_prop, const float* h, const float* g, const float* v0hat,
                     const fwi_guidance_params& gp, float* v_next, float* rho_out, hipStream_t st);
 

@@ -123,6 +123,24 @@ class FwiPlan:
         check(_lib.load().fwi_w2_misfit(self._h, B, _ptr(d_syn), _ptr(J), _ptr(adj), _stream()), "fwi_w2_misfit")
         return J, adj
 
+    def l2_misfit(self, d_syn: torch.Tensor, d_obs: torch.Tensor, sigma: float = 0.05, k: float = 0.0,
+                  normalize: bool = False, want_adjoint: bool = True, J_out=None, adj_out=None):
+        """Least-squares potential (1/2) sum (w (d_syn - d_obs))^2 / S per sample and dJ/dd_syn
+        (baseline DPS: k = 0, S = sigma^2; the ablation's enhanced form: k > 0, normalize)."""
+        B = d_syn.shape[0]
+        _need(d_syn, "d_syn", (B, self.ns, self.nr, self.nt), device=self.device)
+        _need(d_obs, "d_obs", self.obs_shape, device=self.device)
+        J = J_out if J_out is not None else torch.empty(B, dtype=torch.float64, device=self.device)
+        _need(J, "J", (B,), dtype=torch.float64, device=self.device)
+        adj = None
+        if want_adjoint:
+            adj = adj_out if adj_out is not None else torch.empty_like(d_syn)
+            _need(adj, "adj", tuple(d_syn.shape), device=self.device)
+        p = _lib.L2Params(float(sigma), float(k), int(bool(normalize)))
+        check(_lib.load().fwi_l2_misfit(self._h, B, _ptr(d_syn), _ptr(d_obs), ctypes.byref(p), _ptr(J), _ptr(adj),
+                                        _stream()), "fwi_l2_misfit")
+        return J, adj
+
     def adjoint_gradient(self, v: torch.Tensor, adj: torch.Tensor, scale: Optional[torch.Tensor] = None,
                          out: Optional[torch.Tensor] = None) -> torch.Tensor:
         B = v.shape[0]
@@ -189,3 +207,18 @@ def guidance_step(v_prop, h, g, v0hat, rho0=1.15, c=0.1, tau=0.0, gamma=0.55, ep
     check(_lib.load().fwi_guidance_step(B, nz, nx, _ptr(v_prop), _ptr(h), _ptr(g), _ptr(v0hat), ctypes.byref(p),
                                         _ptr(out), _ptr(rho_out), _stream()), "fwi_guidance_step")
     return out, rho_out
+
+
+def tv_subgradient(v: torch.Tensor, g: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g + alpha q with q a subgradient of TV(v) (Eq. tv, sign(0) = 0), per sample of [B, nz, nx]."""
+    B, nz, nx = v.shape
+    _need(v, "v", (B, nz, nx), device=v.device)
+    if g is not None:
+        _need(g, "g", (B, nz, nx), device=v.device)
+    if out is None:
+        out = torch.empty_like(v)
+    _need(out, "out", (B, nz, nx), device=v.device)
+    check(_lib.load().fwi_tv_subgradient(B, nz, nx, _ptr(v), _ptr(g), float(alpha), _ptr(out), _stream()),
+          "fwi_tv_subgradient")
+    return out

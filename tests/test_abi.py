@@ -87,6 +87,20 @@ def test_mlp_and_surrogate_option_validation():
     assert L.fwi_sur_set_fused_mlp(None, 1) == -1
 
 
+def test_variant_entry_point_validation():
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    x = ctypes.c_void_p(256)
+    lp = _lib.L2Params(0.05, 0.0, 0)
+    assert L.fwi_l2_misfit(None, 1, x, x, ctypes.byref(lp), x, x, None) == -1
+    assert L.fwi_tv_subgradient(-1, 4, 4, x, None, 1.0, ctypes.c_void_p(512), None) == -1
+    assert L.fwi_tv_subgradient(1, 4, 0, x, None, 1.0, ctypes.c_void_p(512), None) == -1
+    assert L.fwi_tv_subgradient(1, 4, 4, x, None, 1.0, x, None) == -1          # out aliases v
+    assert L.fwi_tv_subgradient(1, 4, 4, x, None, float("inf"), ctypes.c_void_p(512), None) == -1
+    assert L.fwi_tv_subgradient(0, 4, 4, None, None, 1.0, None, None) == 0
+
+
 def test_product_has_no_oracle_or_cpu_path():
     """The product package never imports the oracle, and the HIP library is required."""
     pkg = os.path.join(ROOT, "paper_2603_16393_amd")
