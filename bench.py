@@ -251,6 +251,58 @@ def comparison_variants(plan, acq, wt, dobs, v, x0, steps=10, warmup=2):
     return res
 
 
+def perturbed_operators(v0hat, v_true, x0, steps=5, warmup=1):
+    """The plain guidance step (forward, W2, adjoint gradient, update) of the same 16 models under the
+    forward-operator configurations of the robustness study and the anisotropic Marmousi2-crop grids
+    (fwi_inputs.operator_acquisition): grads/s of each."""
+    import torch
+
+    import fwi_inputs as fi
+    from paper_2603_16393_amd import FwiPlan, guidance_step
+
+    dev = torch.device("cuda:0")
+    v = torch.tensor(v0hat, dtype=torch.float32, device=dev)
+    res = {}
+    for name in fi.OPERATORS:
+        acq = fi.operator_acquisition(name)
+        w = torch.tensor(fi.ricker(acq.nt, acq.dt, acq.f_peak), dtype=torch.float32, device=dev)
+        plan = FwiPlan(acq, max_batch=B, device=dev)
+        dobs = plan.forward(torch.tensor(v_true[None], dtype=torch.float32, device=dev), w, keep_for_adjoint=False)
+        plan.set_obs(dobs[0].contiguous())
+        d = torch.empty((B, acq.ns, acq.nr, acq.nt), dtype=torch.float32, device=dev)
+        J = torch.empty(B, dtype=torch.float64, device=dev)
+        adj = torch.empty_like(d)
+        g = torch.empty_like(v)
+        xn = torch.empty_like(v)
+
+        def step():
+            plan.forward(v, w, keep_for_adjoint=True, out=d)
+            plan.w2_misfit(d, want_adjoint=True, J_out=J, adj_out=adj)
+            plan.adjoint_gradient(v, adj, out=g)
+            guidance_step(x0, g, g, x0, unit_scale=1500.0, out=xn)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ok = plan.status() == 0
+        info = dict(plan.info)
+        plan.close()
+        res[name] = {"grads_per_s": round(B / (ms / 1e3), 2) if ok else None, "ms_per_step": round(ms, 3),
+                     "shots": acq.ns, "samples": acq.nt, "f_peak": acq.f_peak, "dz": acq.dz, "dx": round(acq.dx, 4),
+                     "dt": acq.dt, "src_row": int(acq.src_iz[0]), "lds_split": info.get("lds_split")}
+        print(f"operator {name}: {ms:.2f} ms per batch of {B}", file=sys.stderr, flush=True)
+    res["protocol"] = (f"{B} faulted 70x70 models, 40-cell sponge, W2 misfit (k = 100); {steps} timed steps after "
+                       f"{warmup} warm-up per configuration")
+    return res
+
+
 def bench_uneven(args):
     """64 requests (seeds 2000 + r): 70x70 / 140x140 / 256x256 grids with a 40-cell sponge, 1000 / 1500 / 2500
     samples at dt = 1 ms, 5-10 surface shots, faulted or layered models in 1500-4500 m/s; forward modelling of
@@ -633,11 +685,13 @@ def main():
         },
         "sweep_ms": {"forward": round(fwd_sweep_ms, 4), "adjoint": round(adj_sweep_ms, 4)},
         "variants": None,
+        "operators": None,
         "surrogate": None,
         "cpu_baseline": None,
     }
     if not args.no_variants:
         out["variants"] = comparison_variants(plan, acq, wt, dobs[0].contiguous(), v, x0)
+        out["operators"] = perturbed_operators(v0hat, v_true, x0)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_guidance(plan, wt, v_true)
     if not args.no_cpu_baseline:

@@ -267,6 +267,28 @@ def surrogate_training_pair(seed: int, nz: int = 70, nx: int = 70):
     return v, np.clip(v + d, V_LO, V_HI)
 
 
+OPERATORS = ("Init", "Freq10", "Depth2", "Shot17", "AllChange", "Marmousi-P1", "Marmousi-P3")
+
+
+def operator_acquisition(name: str, nz: int = 70, nx: int = 70, nb: int = 40) -> Acquisition:
+    """Forward-operator configurations of the robustness study (Sec. 6.5, on a 70 x 70 grid with ten
+    sources at columns 7k as Init): Freq10 (10 Hz Ricker), Depth2 (sources and receivers two grid
+    intervals below the surface), Shot17 (17 evenly placed sources), AllChange (all three); and the
+    anisotropic grids of the Marmousi2 crops (table of local models: dx = 10 m or 100/7 m, dz = 2.5 m),
+    whose dz needs dt = 0.4 ms (2500 samples for 1 s) by the CFL bound."""
+    base = dict(ns=10, shot_cols=even_shot_columns(nx, 10), nt=1000, nb=nb)
+    cfg = {
+        "Init": {},
+        "Freq10": dict(f_peak=10.0),
+        "Depth2": dict(src_row=2, rec_row=2),
+        "Shot17": dict(ns=17, shot_cols=even_shot_columns(nx, 17)),
+        "AllChange": dict(f_peak=10.0, src_row=2, rec_row=2, ns=17, shot_cols=even_shot_columns(nx, 17)),
+        "Marmousi-P1": dict(dx=10.0, dz=2.5, dt=4e-4, nt=2500),
+        "Marmousi-P3": dict(dx=100.0 / 7.0, dz=2.5, dt=4e-4, nt=2500),
+    }[name]
+    return surface_acquisition(nz, nx, **{**base, **cfg})
+
+
 def uneven_requests(n: int = 64, seed0: int = 2000, nb: int = 40, sizes=(70, 140, 256), nts=(1000, 1500, 2500),
                     shots=(5, 10)):
     """Requests of an uneven guidance batch: request r (seed seed0 + r) draws a

@@ -80,7 +80,16 @@ def _small(seed, nz=23, nx=37, nb=5, fs=True, ns=3, nt=350, one_row=None):
     return acq, v, vt
 
 
-def _run_gpu(acq, v, vt, dev, force_path=-1, ckpt_every=0, budget=0):
+def _oracle_obs(acq, vt):
+    """Observations from the true model by the oracle (FP32-rounded), given to both sides."""
+    import oracle
+
+    w = fi.ricker(acq.nt, acq.dt, acq.f_peak)
+    return oracle.forward(acq, _f32(vt[None]), _f32(w))[0].astype(np.float32)
+
+
+def _run_gpu(acq, v, vt, dev, force_path=-1, ckpt_every=0, budget=0, dobs=None):
+    """dobs: the observations (the oracle's for gradient parity); None models them on the GPU."""
     from paper_2603_16393_amd import FwiPlan
 
     w = fi.ricker(acq.nt, acq.dt, acq.f_peak)
@@ -88,7 +97,10 @@ def _run_gpu(acq, v, vt, dev, force_path=-1, ckpt_every=0, budget=0):
     plan = FwiPlan(acq, max_batch=B, device=dev, force_path=force_path, ckpt_every=ckpt_every,
                    mem_budget_bytes=budget)
     wt = _t(w, dev)
-    dobs = plan.forward(_t(vt[None], dev), wt, keep_for_adjoint=False)[0].contiguous()
+    if dobs is None:
+        dobs = plan.forward(_t(vt[None], dev), wt, keep_for_adjoint=False)[0].contiguous()
+    else:
+        dobs = _t(dobs, dev)
     plan.set_obs(dobs)
     vg = _t(v, dev)
     d = plan.forward(vg, wt, keep_for_adjoint=True)
@@ -102,10 +114,10 @@ def _run_gpu(acq, v, vt, dev, force_path=-1, ckpt_every=0, budget=0):
     return out
 
 
-def _run_oracle(acq, v, dobs_gpu, w, d_gpu=None):
+def _run_oracle(acq, v, dobs, w):
     import oracle
 
-    obs = oracle.w2_prepare(_f32(dobs_gpu), acq.dt)
+    obs = oracle.w2_prepare(_f32(dobs), acq.dt)
     J, g, d, adj = oracle.objective_and_gradient(acq, _f32(v), _f32(w), obs)
     return dict(J=J, g=g, d=d, adj=adj, obs=obs)
 
@@ -168,8 +180,9 @@ def test_w2_stage_identical_inputs(dev):
 def test_gradient_config0(dev):
     """Full chain on the one-shot configuration: J to 1e-5, dJ/dv to 1e-4."""
     acq, v, vt = _config0()
-    r = _run_gpu(acq, v, vt, dev)
-    o = _run_oracle(acq, v, r["dobs"], r["w"])
+    dobs = _oracle_obs(acq, vt)
+    r = _run_gpu(acq, v, vt, dev, dobs=dobs)
+    o = _run_oracle(acq, v, dobs, r["w"])
     eJ = abs(r["J"][0] - o["J"][0]) / abs(o["J"][0])
     eg = _rel(r["g"], o["g"])
     ea = _rel(r["adj"], o["adj"])
@@ -184,9 +197,10 @@ def test_gradient_ragged_paths(dev, path, ckpt):
     the full history, tiled with checkpoints every 7 steps (ragged last
     segment) and with a single segment."""
     acq, v, vt = _small(11, one_row=(0 if path == 0 else None))
-    r = _run_gpu(acq, v, vt, dev, force_path=path, ckpt_every=ckpt)
+    dobs = _oracle_obs(acq, vt)
+    r = _run_gpu(acq, v, vt, dev, force_path=path, ckpt_every=ckpt, dobs=dobs)
     assert r["info"]["path"] == path and r["info"]["store_mode"] == (1 if ckpt else 0)
-    o = _run_oracle(acq, v, r["dobs"], r["w"])
+    o = _run_oracle(acq, v, dobs, r["w"])
     eJ = np.max(np.abs(r["J"] - o["J"]) / np.abs(o["J"]))
     eg = _rel(r["g"], o["g"])
     _say(f"gradient ragged path={path} ckpt={ckpt}: J rel {eJ:.2e}, grad rel L2 {eg:.2e}")
