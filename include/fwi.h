@@ -252,6 +252,17 @@ int fwi_nn_gemm(int M, int N, int K, int batch, const void* A, long lda, long st
                 long ldb, long strideB, int transB, float* C32, void* C16, long ldc, long strideC, float alpha,
                 float beta, const float* bias, int reduce_batch, int splitk, float* work, void* stream);
 
+/* Mixing along x of the surrogate's decoder blocks, per slab s < S of
+ * [72][64] BF16 (a (sample, time row) of the decoder's NHWC activations),
+ * Xm [72][72] BF16, R() rounding to BF16:
+ *   forward  g1[s] = R(g[s] + R(Xm g[s]))
+ *   VJP      d32[s] += Xm^T d1[s] (FP32, in place),  d16[s] = R(d32[s])
+ * Bitwise equal to the tiled GEMM with its residual / dual-output epilogues.
+ * g and d1 16-byte aligned (else FWI_EINVAL); g1 must not overlap g, nor d16
+ * d1.  Asynchronous. */
+int fwi_nn_mix_forward(long S, const void* Xm, const void* g, void* g1, void* stream);
+int fwi_nn_mix_vjp(long S, const void* Xm, const void* d1, float* d32, void* d16, void* stream);
+
 /* Fused pointwise MLP of the surrogate's blocks (64 -> 128 GELU -> 64 per row,
  * the 1x1 convolutions of the encoder and decoder blocks), R rows, BF16
  * row-major operands: a, res, h, dg [R][64]; W1 [64][128]; W2 [128][64]; FP32

@@ -42,6 +42,8 @@ EXPORTED = (
     "fwi_batch_status",
     "fwi_error_string",
     "fwi_nn_gemm",
+    "fwi_nn_mix_forward",
+    "fwi_nn_mix_vjp",
     "fwi_nn_mlp_forward",
     "fwi_nn_mlp_vjp",
     "fwi_sur_shape",
@@ -154,6 +156,8 @@ def load():
     cl, cf = ctypes.c_long, ctypes.c_float
     L.fwi_nn_gemm.argtypes = [c_int, c_int, c_int, c_int, P, cl, cl, c_int, P, cl, cl, c_int, P, P, cl, cl, cf, cf, P,
                               c_int, c_int, P, P]
+    L.fwi_nn_mix_forward.argtypes = [cl, P, P, P, P]
+    L.fwi_nn_mix_vjp.argtypes = [cl, P, P, P, P, P]
     L.fwi_nn_mlp_forward.argtypes = [cl, P, P, P, P, P, P, P, P]
     L.fwi_nn_mlp_vjp.argtypes = [cl, P, P, P, P, P, P, P]
     L.fwi_sur_set_fused_mlp.argtypes = [P, c_int]

@@ -175,8 +175,7 @@ int forward_impl(fwi_surrogate* s, int B, const float* v, float* traces, hipStre
     for (int i = 0; i < kNBLK; ++i) {
         // mixing along x: per (sample, t) [X][C] = Xm[X][X] g[X][C]
         // g1 = R(g + R(Xm g))
-        c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 0, s->gin[i], kC, xc, 0, nullptr, s->g1[i], kC, xc, nullptr,
-             0.f, kEpiResid, nullptr, s->gin[i]);
+        if (c.rc == FWI_OK) c.rc = nn::mix_fwd((long)B * kT, W + M.dec_xm[i], s->gin[i], s->g1[i], st);
         nn::dw_fwd(B, kT, kX, s->g1[i], P + L.dec_dw_k[i], P + L.dec_dw_b[i], s->ad[i], st);
         mlp_forward(c, fused, rd, s->ad[i], W + M.dec_w1[i], P + L.dec_b1[i], W + M.dec_w2[i], P + L.dec_b2[i],
                     s->g1[i], s->gin[i + 1], s->pd[i], s->qd[i]);
@@ -259,8 +258,7 @@ int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want
         // dg = dg1 + Xm^T dg1
         // the x-mixing's transpose accumulates into dg32; it reads dg16 (dg1) as its B operand,
         // so its BF16 copy goes to the second buffer, which then becomes dg16
-        c.mm(kX, kC, kX, B * kT, W + M.dec_xm[i], kX, 0, 1, s->dg16, kC, xc, 0, s->dg32, nullptr, kC, xc, nullptr,
-             1.f, kEpiDual, s->dg16b);
+        if (c.rc == FWI_OK) c.rc = nn::mix_vjp((long)B * kT, W + M.dec_xm[i], s->dg16, s->dg32, s->dg16b, st);
         std::swap(s->dg16, s->dg16b);
     }
     if (want_w)  // dT = sum_n dy_n h_n^T

@@ -85,6 +85,10 @@ def test_mlp_and_surrogate_option_validation():
     assert L.fwi_nn_mlp_vjp(0, None, None, None, None, None, None, None) == 0
     assert L.fwi_nn_mlp_vjp(16, x, x, x, x, x, None, None) == -1
     assert L.fwi_sur_set_fused_mlp(None, 1) == -1
+    assert L.fwi_nn_mix_forward(-1, x, x, x, None) == -1
+    assert L.fwi_nn_mix_forward(0, None, None, None, None) == 0
+    assert L.fwi_nn_mix_forward(2, x, ctypes.c_void_p(258), x, None) == -1       # not 16-byte aligned
+    assert L.fwi_nn_mix_vjp(2, x, x, None, x, None) == -1
 
 
 def test_variant_entry_point_validation():

@@ -6,7 +6,9 @@ to BF16 at the same points: the GPU accumulates in FP32 on the matrix cores,
 so a rounded value can land one BF16 step away where the FP64 sum sits near a
 rounding boundary; those isolated one-step differences bound the error at a
 few 1e-3 relative L2.  The surrogate's fused path is then compared with its
-two-GEMM path, which must give the same bits.
+two-GEMM path, which must give the same bits, and the mixing along x
+(fwi_nn_mix_forward / fwi_nn_mix_vjp) with the tiled GEMM plus the same
+roundings, also bit for bit.
 """
 import ctypes
 
@@ -197,3 +199,50 @@ def test_set_fused_mlp_rejects_other_values(dev, sur_case):
     sur = sur_case[3]
     assert L.fwi_sur_set_fused_mlp(sur._h, 2) == -1
     assert L.fwi_sur_set_fused_mlp(None, 1) == -1
+
+
+def _gemm32(L, M, N, K, batch, A, lda, sA, tA, B, ldb, sB, C32, ldc, sC, beta):
+    rc = L.fwi_nn_gemm(M, N, K, batch, _p(A), lda, sA, tA, _p(B), ldb, sB, 0, _p(C32), None, ldc, sC, 1.0, beta,
+                       None, 0, 1, None, _stream())
+    assert rc == 0
+
+
+@pytest.mark.parametrize("S", [1, 3, 37, 4096])
+def test_mix_matches_gemm_path_bitwise(dev, S):
+    """Mixing along x (fwi_nn_mix_forward / fwi_nn_mix_vjp) equals the tiled GEMM
+    (FP32 output) followed by the same roundings, bit for bit."""
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    gen = torch.Generator(device="cpu").manual_seed(S)
+    bf = lambda *s, sc=1.0: (torch.randn(*s, generator=gen) * sc).to(torch.bfloat16).to(dev).contiguous()
+    Xm = bf(72, 72, sc=72 ** -0.5)
+    g = bf(S, 72, 64)
+    d32 = (torch.randn(S, 72, 64, generator=gen)).to(dev)
+    # forward: g1 = R(g + R(Xm g))
+    g1 = torch.full_like(g, 3.0)
+    assert L.fwi_nn_mix_forward(S, _p(Xm), _p(g), _p(g1), _stream()) == 0
+    acc = torch.empty(S, 72, 64, device=dev)
+    _gemm32(L, 72, 64, 72, S, Xm, 72, 0, 0, g, 64, 72 * 64, acc, 64, 72 * 64, 0.0)
+    ref = (g.float() + acc.to(torch.bfloat16).float()).to(torch.bfloat16)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, ref)
+    # VJP: d32 += Xm^T d1, d16 = R(d32)
+    ref32 = d32.clone()
+    _gemm32(L, 72, 64, 72, S, Xm, 72, 0, 1, g, 64, 72 * 64, ref32, 64, 72 * 64, 1.0)
+    d16 = torch.full_like(g, 3.0)
+    assert L.fwi_nn_mix_vjp(S, _p(Xm), _p(g), _p(d32), _p(d16), _stream()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(d32, ref32)
+    assert torch.equal(d16, ref32.to(torch.bfloat16))
+
+
+def test_mix_argument_errors(dev):
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    x = torch.zeros(2, 72, 64, dtype=torch.bfloat16, device=dev)
+    assert L.fwi_nn_mix_forward(-1, _p(x), _p(x), _p(x), _stream()) == -1
+    assert L.fwi_nn_mix_forward(0, None, None, None, _stream()) == 0
+    assert L.fwi_nn_mix_forward(1, _p(x), ctypes.c_void_p(x.data_ptr() + 2), _p(x), _stream()) == -1
+    assert L.fwi_nn_mix_vjp(1, _p(x), _p(x), None, _p(x), _stream()) == -1
