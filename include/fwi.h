@@ -330,9 +330,12 @@ int fwi_sur_get_params(fwi_surrogate* s, float* host_params);
 int fwi_sur_get_grads(fwi_surrogate* s, float* host_grads);
 /* fused = 1 (the default): each block's pointwise MLP runs as one kernel
  * (fwi_nn_mlp_forward / fwi_nn_mlp_vjp) and the forward keeps no 128-wide
- * hidden activations; a backward with want_weight_grads recomputes them.
- * fused = 0: two GEMMs per MLP, hidden activations kept.  Both give identical
- * results; the setting applies from the next forward.  FWI_EINVAL unless 0 or 1. */
+ * hidden activations (a backward with want_weight_grads recomputes them); an
+ * input-only backward also runs each decoder block's depthwise-convolution
+ * and mixing VJP as one kernel.  fused = 0: two GEMMs per MLP, hidden
+ * activations kept, separate depthwise and mixing kernels.  Both give
+ * identical results; the setting applies from the next forward.  FWI_EINVAL
+ * unless 0 or 1. */
 int fwi_sur_set_fused_mlp(fwi_surrogate* s, int fused);
 /* traces = S(v) for B <= max_batch samples (asynchronous).  Keeps the
  * activations for fwi_sur_backward. */

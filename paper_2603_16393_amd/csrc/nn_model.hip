@@ -31,9 +31,10 @@ struct BfMap {  // offsets of the BF16 copies
 
 struct fwi_surrogate {
     int device = 0, max_batch = 0, step = 0;
-    // fused: each pointwise MLP runs as one kernel (forward and input VJP); the
-    // forward then keeps no hidden activations (pq_valid false) and a weight
-    // gradient recomputes them
+    // fused: each pointwise MLP runs as one kernel (forward and input VJP), and
+    // an input VJP also takes a decoder block's depthwise convolution and mixing
+    // along x in one pass; the forward then keeps no hidden activations
+    // (pq_valid false) and a weight gradient recomputes them
     bool fused = true, pq_valid = false;
     fwi::SurLayout L;
     fwi::BfMap M;
@@ -250,6 +251,12 @@ int backward_impl(fwi_surrogate* s, int B, const float* dtr, float* dv, int want
         mlp_backward(c, want_w, rd, s->ad[i], s->pd[i], s->qd[i], W + M.dec_w1[i], P + L.dec_b1[i], W + M.dec_w2[i],
                      G + L.dec_w1[i], G + L.dec_b1[i], G + L.dec_w2[i], G + L.dec_b2[i], s->dg32);
         if (c.rc != FWI_OK) return c.rc;
+        if (!want_w && s->fused) {
+            // dg1 = dg + dw^T(da) and dg = dg1 + Xm^T R(dg1) in one pass (dg1 stays on the chip)
+            c.rc = nn::dwmix_vjp(B, W + M.dec_xm[i], P + L.dec_dw_k[i], s->da32, s->dg32, s->dg16b, st);
+            std::swap(s->dg16, s->dg16b);
+            continue;
+        }
         // dg1 = dg + dw^T(da)   (in place in dg32)
         nn::dw_bwd(B, kT, kX, s->g1[i], s->da32, P + L.dec_dw_k[i], s->dg32, s->dg16,
                    want_w ? G + L.dec_dw_k[i] : nullptr, G + L.dec_dw_b[i], s->part, st);

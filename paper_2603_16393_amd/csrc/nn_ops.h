@@ -86,6 +86,9 @@ void out_fwd(int B, const float* out, const float* scale, float* tr, hipStream_t
 // mixing along x, per slab s < S of [72][64]: g1 = R(g + R(Xm g)); VJP d32 += Xm^T d1, d16 = R(d32)
 int mix_fwd(long S, const bf16_t* Xm, const bf16_t* g, bf16_t* g1, hipStream_t st);
 int mix_vjp(long S, const bf16_t* Xm, const bf16_t* d1, float* d32, bf16_t* d16, hipStream_t st);
+// decoder block input VJP of the depthwise convolution and the mixing along x in one pass, B samples of
+// [kT][72][64]: d1 = d32 + dw^T(da); d32 = d1 + Xm^T R(d1); d16 = R(d32)
+int dwmix_vjp(int B, const bf16_t* Xm, const float* dwk, const float* da, float* d32, bf16_t* d16, hipStream_t st);
 int mlp_prepare(hipStream_t st);
 int mlp_fwd(long R, const bf16_t* a, const bf16_t* W1, const float* b1, const bf16_t* W2, const float* b2,
             const bf16_t* res, bf16_t* h, hipStream_t st);
