@@ -396,6 +396,12 @@ def bench_uneven(args):
         "per_size": per_size,
         "gradient": gradient,
         "hbm_frac_alg": round(16.0 * gpts / HBM_PEAK_GBS, 4),
+        # algorithmic bytes: 16 B per point-update (read u^n, u^{n-1}, K; write u^{n+1}) over the persistent
+        # launch's measured duration; the LDS-resident fields move far less through HBM
+        "roofline": {"bound": "hbm", "kernel": "k_batch_forward (one persistent launch)",
+                     "achieved": round(16.0 * gpts, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(16.0 * gpts / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": 16.0 * upd, "launch_ms": round(ms, 3)},
         "tiles": [{"padded": [t[0], t[1]], "kind": "lds" if t[2] == 0 else "hbm", "tile": [t[3], t[4]]} for t in tiles],
         "create_s": round(t_create, 3),
     }
