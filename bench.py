@@ -458,7 +458,12 @@ def bench_surrogate(args):
            "steps": max(3, args.steps), "warmup": 1, "ms_per_step": res["B64"]["forward_ms"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
            "config": {"workload": "trace surrogate, batches of 16 and 64, trained parameters"},
-           "flop_per_sample_forward": SUR_FWD_FLOP, "batches": res}
+           "flop_per_sample_forward": SUR_FWD_FLOP, "batches": res,
+           # whole forward at B = 64 against the dense BF16 matrix-core peak; its layers are thin (K = 64 or 128)
+           # and sit below the ridge point, so the per-kernel HBM figures in the profile are the binding ones
+           "roofline": {"bound": "mfma", "kernel": "surrogate forward (all layers, B = 64)",
+                        "achieved": res["B64"]["forward_tflops"], "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": res["B64"]["forward_mfma_frac"], "traffic": None}}
     sur.close()
     print(json.dumps(out))
 
