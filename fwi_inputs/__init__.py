@@ -64,6 +64,7 @@ class Acquisition:
     rec_iz: np.ndarray
     rec_ix: np.ndarray
     f_peak: float = 15.0
+    pml: bool = False  # the nb-cell absorbing layer is a PML instead of the damping sponge
 
     @property
     def ns(self) -> int:

@@ -8,8 +8,10 @@ The arithmetic lives in ``fwi_oracle.c`` (plain C, double precision, OpenMP
 across independent (sample, shot) units only); this module marshals numpy
 arrays through ctypes.  Functions and the passages they follow:
 
-* :func:`forward`      -- forward operator F(v) (Sec. 2.1 Eq. solving, Sec. 6.1)
-* :func:`gradient`     -- reverse-mode dJ/dv of the discrete objective
+* :func:`forward`      -- forward operator F(v) (Sec. 2.1 Eq. solving, Sec. 6.1); with
+                          ``acq.pml`` the absorbing layer is a PML (Sec. 2.1, Sec. 6.1)
+                          instead of the damping sponge
+* :func:`gradient`     -- reverse-mode dJ/dv of the discrete objective (either layer)
 * :func:`w2_prepare`   -- omega, c', Q_obs, S_obs (Sec. 5.1 (I)-(III), Sec. 6.2)
 * :func:`w2_misfit`    -- J (Eq. final_objective) and dJ/dd_syn
 * :func:`guidance`     -- TV, rho, kappa and the update (Sec. 5.2, Algorithm 2)
@@ -58,6 +60,8 @@ def lib():
         geo = [i, i, d, d, d, i, i, i, d, i, _ip, _ip, i, _ip, _ip]
         L.orc_forward.argtypes = geo + [i, _dp, _dp, _dp]
         L.orc_gradient.argtypes = geo + [i, _dp, _dp, _dp, _dp, _dp]
+        L.orc_forward_pml.argtypes = geo + [i, _dp, _dp, _dp]
+        L.orc_gradient_pml.argtypes = geo + [i, _dp, _dp, _dp, _dp]
         L.orc_w2_prepare.argtypes = [i, i, d, _dp, d, d, i, d, i, _dp, _dp, _dp, _dp]
         L.orc_w2_misfit.argtypes = [i, i, i, d, _dp, _dp, _dp, _dp, d, d, i, i, i, _dp, _dp, _dp]
         L.orc_quantiles.argtypes = [i, d, _dp, d, i, _dp, _dp]
@@ -118,7 +122,10 @@ def forward(acq, v: np.ndarray, wavelet: np.ndarray) -> np.ndarray:
     w = _d(wavelet)
     out = np.zeros((B, acq.ns, acq.nr, acq.nt))
     args, keep = _geo_args(acq)
-    _chk(lib().orc_forward(*args, B, _p(v), _p(w), _p(out)), "orc_forward")
+    if getattr(acq, "pml", False):
+        _chk(lib().orc_forward_pml(*args, B, _p(v), _p(w), _p(out)), "orc_forward_pml")
+    else:
+        _chk(lib().orc_forward(*args, B, _p(v), _p(w), _p(out)), "orc_forward")
     return out[0] if single else out
 
 
@@ -136,8 +143,13 @@ def gradient(acq, v: np.ndarray, wavelet: np.ndarray, adj: np.ndarray, want_wave
     g = np.zeros((B, acq.nz, acq.nx))
     gw = np.zeros((B, acq.ns, acq.nt)) if want_wavelet_grad else None
     args, keep = _geo_args(acq)
-    _chk(lib().orc_gradient(*args, B, _p(v), _p(_d(wavelet)), _p(a), _p(g), _p(gw) if gw is not None else None),
-         "orc_gradient")
+    if getattr(acq, "pml", False):
+        if want_wavelet_grad:
+            raise ValueError("the wavelet gradient is not provided with the PML")
+        _chk(lib().orc_gradient_pml(*args, B, _p(v), _p(_d(wavelet)), _p(a), _p(g)), "orc_gradient_pml")
+    else:
+        _chk(lib().orc_gradient(*args, B, _p(v), _p(_d(wavelet)), _p(a), _p(g),
+                                _p(gw) if gw is not None else None), "orc_gradient")
     if single:
         g = g[0]
         gw = gw[0] if gw is not None else None

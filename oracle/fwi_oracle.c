@@ -22,7 +22,8 @@
  *   - 8th-order central weights for the second derivative; mirror (even)
  *     ghosts above row 0 implement the reflecting top boundary d_n u = 0;
  *   - a damping sponge (separable velocity-damping factor with the quadratic
- *     textbook profile) replaces the paper's PML;
+ *     textbook profile) is the default absorbing layer; the PML section at the
+ *     end of the file gives the paper's layer type in an unsplit form;
  *   - the point source f(t) delta(x - xi) is injected as f(t_n)/(dx dz) at the
  *     source node; sample n of a trace is u^n at the receiver node, t_n = n dt;
  *   - quantile = first crossing of the linearly interpolated trapezoid CDF,
@@ -838,4 +839,390 @@ int orc_wavefield(int nz, int nx, double dz, double dx, double dt, int nt, int n
     free(u2);
     coefs_free(&cf);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Perfectly matched layer (Sec. 2.1 absorbing boundary; Sec. 6.1: PML of 6
+ * grid points on the left, right and bottom).  The paper does not state its
+ * PML equations; this is the unsplit second-order PML of Grote and Sim
+ * ("Efficient PML for the wave equation", 2010) in the form obtained from the
+ * complex coordinate stretch s_x = 1 + zeta_x/(i w), s_z = 1 + zeta_z/(i w):
+ *
+ *   u_tt + (zeta_x + zeta_z) u_t + zeta_x zeta_z u = v^2 (Lap u + d_x psi_x + d_z psi_z + s)
+ *   psi_x,t = -zeta_x psi_x + (zeta_z - zeta_x) d_x u
+ *   psi_z,t = -zeta_z psi_z + (zeta_x - zeta_z) d_z u
+ *
+ * with v^2 outside the divergence (exact here because the padded velocity is
+ * constant along the normal of each layer).  zeta uses the quadratic profile
+ * of the sponge with the same strength formula; it does not depend on v.
+ * Discretisation (8th-order central first derivatives d_k = 4/5, -1/5, 4/105,
+ * -1/280; psi at half steps, advanced by the trapezoid rule):
+ *
+ *   g_x = Dx u^n, g_z = Dz u^n                         (u even across a reflecting top)
+ *   Q   = c (psi^{n-1/2} + h g),  c = 1/(1 + zeta dt/2), h_x = dt/2 (zeta_z - zeta_x),
+ *                                  h_z = dt/2 (zeta_x - zeta_z)   (Q = psi at step n)
+ *   psi^{n+1/2} = 2 Q - psi^{n-1/2}
+ *   D   = L u^n + Dx Q_x + Dz Q_z + s^n                (Q_z odd across a reflecting top)
+ *   u^{n+1} = p u^n - q u^{n-1} + r D,  E = 1/(1 + alpha dt/2), alpha = zeta_x + zeta_z,
+ *             p = (2 - dt^2 zeta_x zeta_z) E, q = (1 - alpha dt/2) E, r = dt^2 v^2 E.
+ *
+ * In the model region zeta = 0, so p = 2, q = 1, r = dt^2 v^2 and Q = 0: the
+ * interior update is the leapfrog of the sponge scheme, operation for
+ * operation.  Outside the padded grid every field is zero. */
+
+static const double D8[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+static const double PML_R = 1e-3;
+
+static double pml_zeta(int delta, int nb, double h, double vmax) {
+    if (nb <= 0 || delta <= 0) return 0.0;
+    double r = (double)delta / nb;
+    return 3.0 * vmax * log(1.0 / PML_R) / (2.0 * nb * h) * r * r;
+}
+
+typedef struct {
+    double *vp, *p, *q, *r, *E, *cx, *cz, *hx, *hz;
+} PmlCoefs;
+
+static void pml_free(PmlCoefs* c) {
+    free(c->vp);
+    free(c->p);
+    free(c->q);
+    free(c->r);
+    free(c->E);
+    free(c->cx);
+    free(c->cz);
+    free(c->hx);
+    free(c->hz);
+}
+
+static int pml_make(const Grid* g, const double* v, double vmax, PmlCoefs* c) {
+    int np = g->nzp * g->nxp;
+    double** arr[9] = {&c->vp, &c->p, &c->q, &c->r, &c->E, &c->cx, &c->cz, &c->hx, &c->hz};
+    int bad = 0;
+    for (int i = 0; i < 9; ++i) {
+        *arr[i] = (double*)malloc(sizeof(double) * np);
+        if (!*arr[i]) bad = 1;
+    }
+    if (bad) return ORC_ENOMEM;
+    pad_velocity(g, v, c->vp);
+    double dt = g->dt;
+    for (int iz = 0; iz < g->nzp; ++iz)
+        for (int ix = 0; ix < g->nxp; ++ix) {
+            int dzc = 0, dxc = 0;
+            if (iz >= g->ztop + g->nz) dzc = iz - (g->ztop + g->nz - 1);
+            if (!g->fs && iz < g->ztop) dzc = g->ztop - iz;
+            if (ix < g->nb) dxc = g->nb - ix;
+            if (ix >= g->nb + g->nx) dxc = ix - (g->nb + g->nx - 1);
+            double zx = pml_zeta(dxc, g->nb, g->dx, vmax), zz = pml_zeta(dzc, g->nb, g->dz, vmax);
+            int p = iz * g->nxp + ix;
+            double alpha = zx + zz;
+            c->E[p] = 1.0 / (1.0 + alpha * dt / 2.0);
+            c->p[p] = (2.0 - dt * dt * zx * zz) * c->E[p];
+            c->q[p] = (1.0 - alpha * dt / 2.0) * c->E[p];
+            c->r[p] = dt * dt * c->vp[p] * c->vp[p] * c->E[p];
+            c->cx[p] = 1.0 / (1.0 + zx * dt / 2.0);
+            c->cz[p] = 1.0 / (1.0 + zz * dt / 2.0);
+            c->hx[p] = dt / 2.0 * (zz - zx);
+            c->hz[p] = dt / 2.0 * (zx - zz);
+        }
+    return ORC_OK;
+}
+
+/* Q_z with the odd extension across a reflecting top. */
+static double qz_at(const Grid* g, const double* q, int iz, int ix) {
+    double sgn = 1.0;
+    if (g->fs && iz < 0) {
+        iz = -iz;
+        sgn = -1.0;
+    }
+    if (iz < 0 || iz >= g->nzp || ix < 0 || ix >= g->nxp) return 0.0;
+    return sgn * q[iz * g->nxp + ix];
+}
+
+static double dx_at(const Grid* g, const double* f, int iz, int ix) {
+    double s = 0.0;
+    for (int k = 1; k <= 4; ++k) s += D8[k] * (uat(g, f, iz, ix + k) - uat(g, f, iz, ix - k));
+    return s / g->dx;
+}
+
+static double dz_even_at(const Grid* g, const double* f, int iz, int ix) {
+    double s = 0.0;
+    for (int k = 1; k <= 4; ++k) s += D8[k] * (uat(g, f, iz + k, ix) - uat(g, f, iz - k, ix));
+    return s / g->dz;
+}
+
+static double dz_odd_at(const Grid* g, const double* f, int iz, int ix) {
+    double s = 0.0;
+    for (int k = 1; k <= 4; ++k) s += D8[k] * (qz_at(g, f, iz + k, ix) - qz_at(g, f, iz - k, ix));
+    return s / g->dz;
+}
+
+/* State of one unit between steps: u^n, u^{n-1}, psi_x^{n-1/2}, psi_z^{n-1/2}. */
+typedef struct {
+    double *u, *um, *px, *pz;
+} PmlState;
+
+/* One step.  Q_x, Q_z and D of the step are returned in the work arrays;
+ * the state advances in place (un receives u^{n+1}). */
+static void pml_step(const Grid* g, const PmlCoefs* c, const double* u, const double* um, double* px, double* pz,
+                     double* un, int src_p, double src_amp, double* Qx, double* Qz, double* D) {
+    for (int iz = 0; iz < g->nzp; ++iz)
+        for (int ix = 0; ix < g->nxp; ++ix) {
+            int p = iz * g->nxp + ix;
+            Qx[p] = c->cx[p] * (px[p] + c->hx[p] * dx_at(g, u, iz, ix));
+            Qz[p] = c->cz[p] * (pz[p] + c->hz[p] * dz_even_at(g, u, iz, ix));
+        }
+    for (int p = 0; p < g->nzp * g->nxp; ++p) {
+        px[p] = 2.0 * Qx[p] - px[p];
+        pz[p] = 2.0 * Qz[p] - pz[p];
+    }
+    for (int iz = 0; iz < g->nzp; ++iz)
+        for (int ix = 0; ix < g->nxp; ++ix) {
+            int p = iz * g->nxp + ix;
+            double d = lap_at(g, u, iz, ix) + dx_at(g, Qx, iz, ix) + dz_odd_at(g, Qz, iz, ix);
+            if (p == src_p) d += src_amp / (g->dx * g->dz);
+            D[p] = d;
+            un[p] = c->p[p] * u[p] - c->q[p] * um[p] + c->r[p] * d;
+        }
+}
+
+/* Forward of one unit; if ck != NULL the state before step n is saved for
+ * every n that is a multiple of K, as 4 planes (u^n, u^{n-1}, psi_x, psi_z). */
+static int pml_forward_unit(const Grid* g, const PmlCoefs* c, const double* wavelet, int src_p, int nr,
+                            const int* rec_p, double* trace, double* ck, int K) {
+    size_t np = (size_t)g->nzp * g->nxp;
+    double* buf = (double*)calloc(8 * np, sizeof(double));
+    if (!buf) return ORC_ENOMEM;
+    double *u = buf, *um = buf + np, *un = buf + 2 * np, *px = buf + 3 * np, *pz = buf + 4 * np;
+    double *Qx = buf + 5 * np, *Qz = buf + 6 * np, *D = buf + 7 * np;
+    for (int r = 0; r < nr; ++r) trace[(size_t)r * g->nt] = u[rec_p[r]];
+    for (int n = 0; n + 1 < g->nt; ++n) {
+        if (ck && n % K == 0) {
+            double* dst = ck + (size_t)(n / K) * 4 * np;
+            memcpy(dst, u, sizeof(double) * np);
+            memcpy(dst + np, um, sizeof(double) * np);
+            memcpy(dst + 2 * np, px, sizeof(double) * np);
+            memcpy(dst + 3 * np, pz, sizeof(double) * np);
+        }
+        pml_step(g, c, u, um, px, pz, un, src_p, wavelet[n], Qx, Qz, D);
+        for (int r = 0; r < nr; ++r) trace[(size_t)r * g->nt + n + 1] = un[rec_p[r]];
+        double* t = um;
+        um = u;
+        u = un;
+        un = t;
+    }
+    free(buf);
+    return ORC_OK;
+}
+
+/* Scatter transposes of the first-derivative gathers (each term of dx_at,
+ * dz_even_at and dz_odd_at sent back to the node it read). */
+static void dx_transpose_add(const Grid* g, const double* y, double* out) {
+    for (int iz = 0; iz < g->nzp; ++iz)
+        for (int ix = 0; ix < g->nxp; ++ix) {
+            double val = y[iz * g->nxp + ix] / g->dx;
+            if (val == 0.0) continue;
+            for (int k = 1; k <= 4; ++k) {
+                if (ix + k < g->nxp) out[iz * g->nxp + ix + k] += D8[k] * val;
+                if (ix - k >= 0) out[iz * g->nxp + ix - k] -= D8[k] * val;
+            }
+        }
+}
+
+static void dz_even_transpose_add(const Grid* g, const double* y, double* out) {
+    for (int iz = 0; iz < g->nzp; ++iz)
+        for (int ix = 0; ix < g->nxp; ++ix) {
+            double val = y[iz * g->nxp + ix] / g->dz;
+            if (val == 0.0) continue;
+            for (int k = 1; k <= 4; ++k) {
+                if (iz + k < g->nzp) out[(iz + k) * g->nxp + ix] += D8[k] * val;
+                int t = iz - k;
+                if (g->fs && t < 0) t = -t;
+                if (t >= 0 && t < g->nzp) out[t * g->nxp + ix] -= D8[k] * val;
+            }
+        }
+}
+
+static void dz_odd_transpose_add(const Grid* g, const double* y, double* out) {
+    for (int iz = 0; iz < g->nzp; ++iz)
+        for (int ix = 0; ix < g->nxp; ++ix) {
+            double val = y[iz * g->nxp + ix] / g->dz;
+            if (val == 0.0) continue;
+            for (int k = 1; k <= 4; ++k) {
+                if (iz + k < g->nzp) out[(iz + k) * g->nxp + ix] += D8[k] * val;
+                int t = iz - k;
+                if (t >= 0)
+                    out[t * g->nxp + ix] -= D8[k] * val;
+                else if (g->fs && -t < g->nzp)
+                    out[(-t) * g->nxp + ix] += D8[k] * val; /* the read was -Q_z(-t) */
+            }
+        }
+}
+
+/* Reverse mode of pml_forward_unit: gC[p] = dJ/d(dt^2 v_p^2) given a^n = dJ/d(trace sample n).
+ * Per step n (reverse order), with ub1 = dJ/du^{n+1} complete, ub2 = dJ/du^{n+2}
+ * and (bx, bz) = dJ/d psi^{n+1/2}:
+ *   dJ/dC += ub1 E D;  Db = r ub1;
+ *   Qb = D^T-gather of Db (x: Dx^T, z: odd-extension transpose) + 2 (bx, bz);
+ *   (bx, bz) <- c Qb - (bx, bz);  gb = c h Qb;
+ *   ub^n = R^T a^n + p ub1 - q ub2 + L^T Db + Dx^T gb_x + Dz^T gb_z (even-extension transpose). */
+static int pml_reverse_unit(const Grid* g, const PmlCoefs* c, const double* wavelet, int src_p, int nr,
+                            const int* rec_p, const double* adj, double* gC) {
+    size_t np = (size_t)g->nzp * g->nxp;
+    int N = g->nt;
+    int K = (int)ceil(sqrt((double)N));
+    if (K < 1) K = 1;
+    int nseg = (N - 1 + K - 1) / K;
+    double* ck = (double*)malloc(sizeof(double) * (size_t)nseg * 4 * np);
+    double* seg = (double*)malloc(sizeof(double) * (size_t)(K + 1) * 4 * np); /* state before each step */
+    double* trace = (double*)malloc(sizeof(double) * (size_t)nr * N);
+    double* w = (double*)calloc(12 * np, sizeof(double));
+    int st = ORC_OK;
+    if (!ck || !seg || !trace || !w) {
+        st = ORC_ENOMEM;
+        goto done;
+    }
+    {
+        double *ub0 = w, *ub1 = w + np, *ub2 = w + 2 * np, *bx = w + 3 * np, *bz = w + 4 * np;
+        double *Db = w + 5 * np, *Qbx = w + 6 * np, *Qbz = w + 7 * np, *Qx = w + 8 * np, *Qz = w + 9 * np;
+        double *D = w + 10 * np, *un = w + 11 * np;
+        st = pml_forward_unit(g, c, wavelet, src_p, nr, rec_p, trace, ck, K);
+        if (st) goto done;
+        memset(gC, 0, sizeof(double) * np);
+        for (int r = 0; r < nr; ++r) ub1[rec_p[r]] += adj[(size_t)r * N + (N - 1)];
+        for (int s = nseg - 1; s >= 0; --s) {
+            int a = s * K, e = a + K;
+            if (e > N - 1) e = N - 1;
+            /* seg[i] = state before step a + i (4 planes each) */
+            memcpy(seg, ck + (size_t)s * 4 * np, sizeof(double) * 4 * np);
+            for (int n = a; n + 1 < e; ++n) {
+                double* cur = seg + (size_t)(n - a) * 4 * np;
+                double* nxt = cur + 4 * np;
+                memcpy(nxt + 2 * np, cur + 2 * np, sizeof(double) * 2 * np);
+                pml_step(g, c, cur, cur + np, nxt + 2 * np, nxt + 3 * np, nxt, src_p, wavelet[n], Qx, Qz, D);
+                memcpy(nxt + np, cur, sizeof(double) * np);
+            }
+            for (int n = e - 1; n >= a; --n) {
+                double* cur = seg + (size_t)(n - a) * 4 * np;
+                /* recompute Q and D of step n from the state before it */
+                memcpy(Qbx, cur + 2 * np, sizeof(double) * np); /* scratch copies of psi */
+                memcpy(Qbz, cur + 3 * np, sizeof(double) * np);
+                pml_step(g, c, cur, cur + np, Qbx, Qbz, un, src_p, wavelet[n], Qx, Qz, D);
+                for (size_t p = 0; p < np; ++p) {
+                    gC[p] += ub1[p] * c->E[p] * D[p];
+                    Db[p] = c->r[p] * ub1[p];
+                    Qbx[p] = 2.0 * bx[p];
+                    Qbz[p] = 2.0 * bz[p];
+                }
+                dx_transpose_add(g, Db, Qbx);
+                dz_odd_transpose_add(g, Db, Qbz);
+                lap_transpose(g, Db, ub0); /* overwrites ub0 */
+                for (size_t p = 0; p < np; ++p) {
+                    bx[p] = c->cx[p] * Qbx[p] - bx[p];
+                    bz[p] = c->cz[p] * Qbz[p] - bz[p];
+                    ub0[p] += c->p[p] * ub1[p] - c->q[p] * ub2[p];
+                    Qbx[p] *= c->cx[p] * c->hx[p]; /* gb_x */
+                    Qbz[p] *= c->cz[p] * c->hz[p]; /* gb_z */
+                }
+                dx_transpose_add(g, Qbx, ub0);
+                dz_even_transpose_add(g, Qbz, ub0);
+                for (int r = 0; r < nr; ++r) ub0[rec_p[r]] += adj[(size_t)r * N + n];
+                double* t = ub2;
+                ub2 = ub1;
+                ub1 = ub0;
+                ub0 = t;
+            }
+        }
+    }
+done:
+    free(ck);
+    free(seg);
+    free(trace);
+    free(w);
+    return st;
+}
+
+/* Forward modelling with the PML as the absorbing layer (nb cells); arguments as orc_forward. */
+int orc_forward_pml(int nz, int nx, double dz, double dx, double dt, int nt, int nb, int fs, double vmax_decl,
+                    int ns, const int* src_iz, const int* src_ix, int nr, const int* rec_iz, const int* rec_ix,
+                    int B, const double* v, const double* wavelet, double* d) {
+    Grid g;
+    int st = grid_init(&g, nz, nx, dz, dx, dt, nt, nb, fs);
+    if (st) return st;
+    st = check_inputs(&g, B, v, vmax_decl, ns, src_iz, src_ix, nr, rec_iz, rec_ix);
+    if (st) return st;
+    int* rec_p = (int*)malloc(sizeof(int) * (nr > 0 ? nr : 1));
+    for (int r = 0; r < nr; ++r) rec_p[r] = padded_index(&g, rec_iz[r], rec_ix[r]);
+    int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int u = 0; u < B * ns; ++u) {
+        int b = u / ns, s = u % ns;
+        PmlCoefs c;
+        memset(&c, 0, sizeof(c));
+        int e = pml_make(&g, v + (size_t)b * nz * nx, vmax_decl, &c);
+        if (!e)
+            e = pml_forward_unit(&g, &c, wavelet, padded_index(&g, src_iz[s], src_ix[s]), nr, rec_p,
+                                 d + (size_t)u * nr * nt, NULL, 1);
+        pml_free(&c);
+        if (e) {
+#pragma omp critical
+            err = e;
+        }
+    }
+    free(rec_p);
+    return err;
+}
+
+/* Reverse-mode gradient dJ/dv with the PML (summed over shots); arguments as orc_gradient
+ * without the wavelet gradient. */
+int orc_gradient_pml(int nz, int nx, double dz, double dx, double dt, int nt, int nb, int fs, double vmax_decl,
+                     int ns, const int* src_iz, const int* src_ix, int nr, const int* rec_iz, const int* rec_ix,
+                     int B, const double* v, const double* wavelet, const double* adj, double* grad) {
+    Grid g;
+    int st = grid_init(&g, nz, nx, dz, dx, dt, nt, nb, fs);
+    if (st) return st;
+    st = check_inputs(&g, B, v, vmax_decl, ns, src_iz, src_ix, nr, rec_iz, rec_ix);
+    if (st) return st;
+    int np = g.nzp * g.nxp;
+    int* rec_p = (int*)malloc(sizeof(int) * (nr > 0 ? nr : 1));
+    for (int r = 0; r < nr; ++r) rec_p[r] = padded_index(&g, rec_iz[r], rec_ix[r]);
+    double* gvp = (double*)calloc((size_t)B * ns * np, sizeof(double));
+    if (!gvp) {
+        free(rec_p);
+        return ORC_ENOMEM;
+    }
+    int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int u = 0; u < B * ns; ++u) {
+        int b = u / ns, s = u % ns;
+        PmlCoefs c;
+        memset(&c, 0, sizeof(c));
+        double* gC = (double*)malloc(sizeof(double) * np);
+        int e = gC ? pml_make(&g, v + (size_t)b * nz * nx, vmax_decl, &c) : ORC_ENOMEM;
+        if (!e)
+            e = pml_reverse_unit(&g, &c, wavelet, padded_index(&g, src_iz[s], src_ix[s]), nr, rec_p,
+                                 adj + (size_t)u * nr * nt, gC);
+        if (!e) /* C = dt^2 vp^2  =>  dC/dvp = 2 dt^2 vp */
+            for (int p = 0; p < np; ++p) gvp[(size_t)u * np + p] = gC[p] * 2.0 * dt * dt * c.vp[p];
+        pml_free(&c);
+        free(gC);
+        if (e) {
+#pragma omp critical
+            err = e;
+        }
+    }
+    if (!err) {
+        memset(grad, 0, sizeof(double) * (size_t)B * nz * nx);
+        for (int b = 0; b < B; ++b)
+            for (int s = 0; s < ns; ++s)
+                for (int iz = 0; iz < g.nzp; ++iz)
+                    for (int ix = 0; ix < g.nxp; ++ix) {
+                        int mz = clampi(iz - g.ztop, 0, nz - 1);
+                        int mx = clampi(ix - g.nb, 0, nx - 1);
+                        grad[(size_t)b * nz * nx + mz * nx + mx] += gvp[((size_t)b * ns + s) * np + iz * g.nxp + ix];
+                    }
+    }
+    free(gvp);
+    free(rec_p);
+    return err;
 }
