@@ -60,10 +60,11 @@ typedef struct {
     double dz, dx;         /* grid spacings (m) */
     double dt;             /* time step (s); trace sample n is the field at t_n = n dt */
     int nt;                /* samples per trace (>= 2); nt - 1 time steps are taken */
-    int nb;                /* damping-sponge width in cells on the left, right and bottom
-                              (and the top when free_surface == 0) */
+    int nb;                /* absorbing-layer width in cells on the left, right and bottom
+                              (and the top when free_surface == 0); the layer is the damping
+                              sponge unless `pml` is set */
     int free_surface;      /* 1: reflecting top, d_n u = 0 by even mirroring (Eq. solving) */
-    double v_max;          /* declared upper bound of v: sets the sponge strength and is
+    double v_max;          /* declared upper bound of v: sets the layer strength and is
                               checked against the CFL limit at plan creation */
     int ns;                /* shots */
     const int* src_iz;     /* HOST [ns] source rows */
@@ -71,6 +72,13 @@ typedef struct {
     int nr;                /* receivers, one spread shared by all shots */
     const int* rec_iz;     /* HOST [nr] receiver rows */
     const int* rec_ix;     /* HOST [nr] receiver columns */
+    int pml;               /* 0: the nb-cell layer is the damping sponge; 1: it is a perfectly matched layer
+                              (Sec. 2.1 absorbing boundary, Sec. 6.1: 6 cells on the left, right and bottom),
+                              the unsplit second-order form of a complex coordinate stretch with the sponge's
+                              quadratic profile and strength.  Plans only (fwi_batch_create rejects it); the
+                              padded field must fit one workgroup's LDS (about 7,000 padded cells, e.g. a
+                              70 x 70 model with 6 cells), with the full forward history (FWI_EINVAL /
+                              FWI_ENOMEM otherwise). */
 } fwi_geometry;
 
 /* Misfit settings (Sec. 5.1 and Sec. 6.2).  Paper values: k = 100,
@@ -115,7 +123,9 @@ typedef struct {
     int nzp, nxp;              /* padded grid */
     int path;                  /* 0: field resident in LDS (one workgroup per (sample, shot), or lds_split
                                   workgroups per field each holding a band of rows);
-                                  1: tiled sweep from HBM, two time steps per launch */
+                                  1: tiled sweep from HBM, two time steps per launch;
+                                  2: PML sweep, field and auxiliary fields resident in LDS, one workgroup
+                                  per (sample, shot) */
     int store_mode;            /* 0: full history of D = L u + s kept for the adjoint;
                                   1: checkpoints every `ckpt_every` steps plus recomputation */
     int ckpt_every;

@@ -66,7 +66,7 @@ class Geometry(ctypes.Structure):
     _fields_ = [
         ("nz", c_int), ("nx", c_int), ("dz", c_double), ("dx", c_double), ("dt", c_double), ("nt", c_int),
         ("nb", c_int), ("free_surface", c_int), ("v_max", c_double), ("ns", c_int), ("src_iz", c_int_p),
-        ("src_ix", c_int_p), ("nr", c_int), ("rec_iz", c_int_p), ("rec_ix", c_int_p),
+        ("src_ix", c_int_p), ("nr", c_int), ("rec_iz", c_int_p), ("rec_ix", c_int_p), ("pml", c_int),
     ]
 
 

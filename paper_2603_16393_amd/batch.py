@@ -34,7 +34,7 @@ class FwiBatch:
             ip = [x.ctypes.data_as(_lib.c_int_p) for x in idx]
             geoms[i] = _lib.Geometry(int(a.nz), int(a.nx), float(a.dz), float(a.dx), float(a.dt), int(a.nt), int(a.nb),
                                      int(bool(a.free_surface)), float(a.v_max), len(idx[0]), ip[0], ip[1], len(idx[2]),
-                                     ip[2], ip[3])
+                                     ip[2], ip[3], int(bool(getattr(a, "pml", False))))
         h = ctypes.c_void_p()
         opts = _lib.BatchOptions(int(bool(autotune)), int(bool(gradients)))
         with torch.cuda.device(self.device):

@@ -842,6 +842,7 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
     for (int r = 0; r < nreq; ++r) {
         const int st = validate_geometry(&geoms[r], 1);
         if (st) return st;
+        if (geoms[r].pml) return FWI_EINVAL;  // the persistent kernels implement the sponge only
     }
     // the persistent kernels may use all of the LDS their static variables
     // leave; set here so that the launches make no other runtime calls

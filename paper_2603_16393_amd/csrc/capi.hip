@@ -58,6 +58,7 @@ int validate_geometry(const fwi_geometry* g, int max_batch) {
     if (!std::isfinite(g->dz) || !std::isfinite(g->dx) || !std::isfinite(g->dt) || !std::isfinite(g->v_max))
         return FWI_EINVAL;
     if (!g->src_iz || !g->src_ix || !g->rec_iz || !g->rec_ix) return FWI_EINVAL;
+    if (g->pml != 0 && g->pml != 1) return FWI_EINVAL;
     for (int s = 0; s < g->ns; ++s)
         if (g->src_iz[s] < 0 || g->src_iz[s] >= g->nz || g->src_ix[s] < 0 || g->src_ix[s] >= g->nx) return FWI_EINVAL;
     std::set<std::pair<int, int>> seen;
@@ -71,6 +72,31 @@ int validate_geometry(const fwi_geometry* g, int max_batch) {
     const long nxp = (long)g->nx + 2L * g->nb;
     if (nzp * nxp > (1L << 30)) return FWI_EINVAL;
     return FWI_OK;
+}
+
+// PML damping per axis, as t = zeta dt / 2: the same quadratic profile and
+// strength as the sponge, zeta = 3 v_max ln(1/R)/(2 nb h) (delta/nb)^2, R = 1e-3.
+void pml_profiles(const fwi_geometry& g, int nzp, int nxp, int ztop, std::vector<float>& tx, std::vector<float>& tz) {
+    tx.assign(nxp, 0.f);
+    tz.assign(nzp, 0.f);
+    if (g.nb <= 0) return;
+    const double base = 3.0 * g.v_max * std::log(1e3) / (2.0 * g.nb);
+    auto t = [&](int d, double h) {
+        const double r = (double)d / g.nb;
+        return (float)(base * r * r / h * g.dt / 2.0);
+    };
+    for (int ix = 0; ix < nxp; ++ix) {
+        int d = 0;
+        if (ix < g.nb) d = g.nb - ix;
+        if (ix >= g.nb + g.nx) d = ix - (g.nb + g.nx - 1);
+        tx[ix] = d > 0 ? t(d, g.dx) : 0.f;
+    }
+    for (int iz = 0; iz < nzp; ++iz) {
+        int d = 0;
+        if (iz >= ztop + g.nz) d = iz - (ztop + g.nz - 1);
+        if (!g.free_surface && iz < ztop) d = ztop - iz;
+        tz[iz] = d > 0 ? t(d, g.dz) : 0.f;
+    }
 }
 
 void build_host_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, HostTables& t) {
@@ -167,17 +193,40 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // spread of Sec. 2.1, or one buried row)
     bool one_row = true;
     for (int r = 1; r < nr; ++r) one_row = one_row && (p.rec_iz[r] == p.rec_iz[0]);
-    bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, o.lds_tile_x, o.lds_tile_z, &p.lds_X, &p.lds_P,
-                                               &p.lds_ncg, &p.lds_nstrip);
-    if ((o.lds_tile_x > 0 || o.lds_tile_z > 0) && !lds_ok) {
-        delete pp;
-        return FWI_EINVAL;
+    std::vector<int> pml_rec;
+    if (p.g.pml) {
+        // the PML sweep keeps the whole field in one workgroup's LDS and the full history of D
+        if (o.force_path != -1 || o.ckpt_every > 0 || o.lds_tile_x > 0 || o.lds_tile_z > 0 || o.split > 0 ||
+            !pml_fits(p.nzp, p.nxp)) {
+            delete pp;
+            return FWI_EINVAL;
+        }
+        p.path = 2;
+        // the sweep gives each thread one receiver: model slots (row-major) of
+        // two receivers must differ modulo the thread count
+        pml_rec.assign(kPmlThreads, -1);
+        for (int r = 0; r < nr; ++r) {
+            const int j = p.rec_iz[r] * p.g.nx + p.rec_ix[r];
+            int& slot = pml_rec[j % kPmlThreads];
+            if (slot >= 0 || nr >= (1 << 16)) {
+                delete pp;
+                return FWI_EINVAL;
+            }
+            slot = ((j / kPmlThreads) << 16) | r;
+        }
+    } else {
+        bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, o.lds_tile_x, o.lds_tile_z, &p.lds_X, &p.lds_P,
+                                                   &p.lds_ncg, &p.lds_nstrip);
+        if ((o.lds_tile_x > 0 || o.lds_tile_z > 0) && !lds_ok) {
+            delete pp;
+            return FWI_EINVAL;
+        }
+        if (o.force_path == 0 && (!lds_ok || o.ckpt_every > 0)) {
+            delete pp;
+            return FWI_EINVAL;
+        }
+        p.path = (o.force_path == 1 || !lds_ok || o.ckpt_every > 0) ? 1 : 0;
     }
-    if (o.force_path == 0 && (!lds_ok || o.ckpt_every > 0)) {
-        delete pp;
-        return FWI_EINVAL;
-    }
-    p.path = (o.force_path == 1 || !lds_ok || o.ckpt_every > 0) ? 1 : 0;
     p.timing = o.timing;
     if (p.timing)
         for (auto* ring : {&p.ev_fwd, &p.ev_adj}) {
@@ -210,6 +259,10 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     } else if (fixed + full_store <= avail) {
         p.store_mode = 0;
         p.ckpt_every = 0;
+    } else if (p.path == 2) {
+        free_all(p);
+        delete pp;
+        return FWI_ENOMEM;
     } else {
         if (p.path == 0) p.path = 1;  // checkpointing runs on the tiled sweep
         p.store_mode = 1;
@@ -297,6 +350,10 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
+    } else if (p.path == 2) {
+        st = st ? st : alloc_n(p, &p.pml_rec, (size_t)kPmlThreads);
+        st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
+        st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
     } else {
         st = st ? st : alloc_n(p, &p.rec_of_col, (size_t)p.nxp);
         if (p.split_G > 1)
@@ -315,9 +372,17 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : hip_ok(hipMemcpy(p.src_pt, src_pt.data(), ns * sizeof(int), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.rec_pt, rec_pt.data(), nr * sizeof(int), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.rec_invw, rec_invw.data(), nr * sizeof(float), hipMemcpyHostToDevice));
+        if (p.path == 2) {
+            std::vector<float> tx, tz;
+            pml_profiles(p.g, p.nzp, p.nxp, p.ztop, tx, tz);
+            st = st ? st : hip_ok(hipMemcpy(p.pml_tx, tx.data(), tx.size() * sizeof(float), hipMemcpyHostToDevice));
+            st = st ? st : hip_ok(hipMemcpy(p.pml_tz, tz.data(), tz.size() * sizeof(float), hipMemcpyHostToDevice));
+            st = st ? st : hip_ok(hipMemcpy(p.pml_rec, pml_rec.data(), pml_rec.size() * sizeof(int),
+                                            hipMemcpyHostToDevice));
+        }
         if (p.path == 1)
             st = st ? st : hip_ok(hipMemcpy(p.rec_map, rec_map.data(), npts * sizeof(int), hipMemcpyHostToDevice));
-        else
+        else if (p.path == 0)
             st = st ? st
                     : hip_ok(hipMemcpy(p.rec_of_col, rec_of_col.data(), p.nxp * sizeof(int), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemset(p.flags, 0, sizeof(int)));
@@ -423,6 +488,8 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
     if (p.timing && hipEventRecord(p.ev_fwd[2 * slot_f], st) != hipSuccess) return FWI_EHIP;
     if (p.path == 0)
         rc = launch_lds_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
+    else if (p.path == 2)
+        rc = launch_pml_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     else
         rc = tiled_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     if (rc) return rc;
@@ -458,6 +525,8 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
     if (p.timing && hipEventRecord(p.ev_adj[2 * slot_a], st) != hipSuccess) return FWI_EHIP;
     if (p.path == 0)
         rc = launch_lds_adjoint(p, B, adj_src, p.wav, st);
+    else if (p.path == 2)
+        rc = launch_pml_adjoint(p, B, adj_src, st);
     else
         rc = tiled_adjoint(p, B, adj_src, p.wav, nullptr, st);
     if (rc) return rc;

@@ -37,6 +37,10 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr int kLdsThreads = 512;
 constexpr int kLdsMaxP = 48;   // rows per thread of the LDS-resident sweep (multiple of 4)
 
+// PML sweep: threads of its workgroup and the most cells one thread owns.
+constexpr int kPmlThreads = 1024;
+constexpr int kPmlMaxCells = 7;
+
 // Device flag bits.
 constexpr int kFlagBadVelocity = 1;
 
@@ -121,7 +125,7 @@ struct Plan {
     int max_batch;
     size_t budget;
     int device;
-    int path;                            // 0 LDS-resident, 1 tiled
+    int path;                            // 0 LDS-resident, 1 tiled, 2 PML (LDS-resident, one workgroup per field)
     int store_mode;                      // 0 full, 1 checkpointed
     int ckpt_every;
     int nseg;
@@ -134,6 +138,9 @@ struct Plan {
 
     // device buffers
     float* K = nullptr;          // [max_batch][npts]
+    float* pml_tx = nullptr;     // PML: [nxp] zeta_x dt / 2 per padded column
+    float* pml_tz = nullptr;     // PML: [nzp] zeta_z dt / 2 per padded row
+    int* pml_rec = nullptr;      // PML: [kPmlThreads] (slot k << 16 | receiver) owned by each thread, or -1
     float* ax = nullptr;         // [nxp] sponge damping factor per padded column
     float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]
@@ -201,6 +208,8 @@ struct HostTables {
     bool one_row = true;
 };
 void build_host_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, HostTables& t);
+// PML damping tables t = zeta dt / 2 per padded column (tx) and row (tz).
+void pml_profiles(const fwi_geometry& g, int nzp, int nxp, int ztop, std::vector<float>& tx, std::vector<float>& tz);
 
 // Register-tile layout of the LDS-resident sweep for an nzp x nxp padded
 // field (false if the field does not fit in LDS).
@@ -224,6 +233,11 @@ int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wave
 int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st);
 int tiled_adjoint(Plan& p, int B, const float* adj, const float* wavelet, float* traces_scratch, hipStream_t st);
 int launch_fold_gradient(const Plan& p, int B, const float* scale, float* grad, hipStream_t st);
+// PML sweeps (path 2): the field of an nzp x nxp padded grid in one workgroup's LDS.
+size_t pml_lds_bytes(int nzp, int nxp);
+bool pml_fits(int nzp, int nxp);
+int launch_pml_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
+int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
 int launch_w2_obs(Plan& p, const float* d_obs, hipStream_t st);
 int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st);

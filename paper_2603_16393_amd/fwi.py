@@ -66,7 +66,7 @@ class FwiPlan:
         ip = [a.ctypes.data_as(_lib.c_int_p) for a in self._idx]
         self._geom = _lib.Geometry(self.nz, self.nx, float(acq.dz), float(acq.dx), float(acq.dt), self.nt,
                                    int(acq.nb), int(bool(acq.free_surface)), float(acq.v_max), self.ns, ip[0], ip[1],
-                                   self.nr, ip[2], ip[3])
+                                   self.nr, ip[2], ip[3], int(bool(getattr(acq, "pml", False))))
         self.max_batch = int(max_batch)
         opts = _lib.PlanOptions(int(force_path), int(ckpt_every), int(lds_tile[0]), int(lds_tile[1]), int(bool(timing)),
                                 int(split))

@@ -114,3 +114,44 @@ def test_product_has_no_oracle_or_cpu_path():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "fwi_oracle" not in src, f
+
+
+def _pml_geom(nz, nx, recs, pml=1, nb=6):
+    from paper_2603_16393_amd import _lib
+
+    keep = [np.array([0], np.int32), np.array([nx // 2], np.int32),
+            np.array([r[0] for r in recs], np.int32), np.array([r[1] for r in recs], np.int32)]
+    p = [k.ctypes.data_as(_lib.c_int_p) for k in keep]
+    g = _lib.Geometry(nz, nx, 10.0, 10.0, 1e-3, 100, nb, 1, 4500.0, 1, p[0], p[1], len(recs), p[2], p[3], pml)
+    return g, keep
+
+
+@pytest.mark.parametrize("case", ["flag", "tiled", "checkpoint", "split", "too_big", "receiver_threads", "batch"])
+def test_pml_plan_validation(case):
+    """The PML layer (Sec. 6.1) runs on its own LDS-resident sweep: every
+    request it cannot serve is refused on the host with FWI_EINVAL."""
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    recs = tuple((0, i) for i in range(8))
+    if case == "flag":
+        g, keep = _pml_geom(20, 20, recs, pml=2)
+        assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
+    elif case in ("tiled", "checkpoint", "split"):
+        g, keep = _pml_geom(20, 20, recs)
+        opts = _lib.PlanOptions(1 if case == "tiled" else -1, 10 if case == "checkpoint" else 0, 0, 0, 0,
+                                1 if case == "split" else 0)
+        assert L.fwi_plan_create_ex(ctypes.byref(g), 1, 0, ctypes.byref(opts), ctypes.byref(h)) == -1
+    elif case == "too_big":
+        g, keep = _pml_geom(120, 120, recs)  # 126 x 132 padded cells: more than one workgroup's LDS
+        assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
+    elif case == "receiver_threads":
+        # model cells 0 and 1024 (row-major, nx = 64) fall on the same thread of the sweep
+        g, keep = _pml_geom(30, 64, ((0, 0), (16, 0)))
+        assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
+    else:
+        g, keep = _pml_geom(20, 20, recs)
+        geoms = (_lib.Geometry * 1)(g)
+        assert L.fwi_batch_create(1, geoms, None, ctypes.byref(h)) == -1
+    assert not h.value
