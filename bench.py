@@ -303,6 +303,69 @@ def perturbed_operators(v0hat, v_true, x0, steps=5, warmup=1):
     return res
 
 
+def pml_guidance(acq, v0hat, v_true, x0, w, steps=10, warmup=2):
+    """The plain guidance step on the same batch and shots with the paper's absorbing layer: a 6-cell PML on
+    the left, right and bottom (Sec. 6.1) in place of the 40-cell sponge, i.e. a 76 x 82 padded grid; the
+    observations are that operator's own traces of v_true.  Reports grads/s, the per-sweep times of the
+    LDS-resident PML kernels (HIP events on the plan's stream) and the adjoint sweep's roofline on
+    algorithmic bytes: per field and step 16 B per padded point (u^n, u^{n-1}, (v dt)^2 in, u^{n+1} out),
+    16 B per layer point (the two auxiliary fields in and out) and 4 B per padded point of the D history."""
+    import dataclasses
+
+    import torch
+
+    from paper_2603_16393_amd import FwiPlan, guidance_step
+
+    dev = torch.device("cuda:0")
+    pacq = dataclasses.replace(acq, nb=6, pml=True)
+    plan = FwiPlan(pacq, max_batch=B, device=dev, timing=True)
+    wt = torch.tensor(w, dtype=torch.float32, device=dev)
+    dobs = plan.forward(torch.tensor(v_true[None], dtype=torch.float32, device=dev), wt, keep_for_adjoint=False)
+    plan.set_obs(dobs[0].contiguous())
+    v = torch.tensor(v0hat, dtype=torch.float32, device=dev)
+    d = torch.empty((B, pacq.ns, pacq.nr, pacq.nt), dtype=torch.float32, device=dev)
+    J = torch.empty(B, dtype=torch.float64, device=dev)
+    adj = torch.empty_like(d)
+    g = torch.empty_like(v)
+    xn = torch.empty_like(v)
+
+    def step():
+        plan.forward(v, wt, keep_for_adjoint=True, out=d)
+        plan.w2_misfit(d, want_adjoint=True, J_out=J, adj_out=adj)
+        plan.adjoint_gradient(v, adj, out=g)
+        guidance_step(x0, g, g, x0, unit_scale=1500.0, out=xn)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.sweep_ms()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fwd_ms, adj_ms = plan.sweep_ms()
+    ok = plan.status() == 0
+    info = dict(plan.info)
+    plan.close()
+    nzp, nxp = info["nzp"], info["nxp"]
+    npts, nlayer = nzp * nxp, nzp * nxp - pacq.nz * pacq.nx
+    alg = float(B * pacq.ns * (pacq.nt - 1) * (16 * npts + 16 * nlayer + 4 * npts))
+    achieved = alg / (adj_ms / 1e3) / 1e9
+    print(f"PML6: {ms:.2f} ms per batch of {B} (forward sweep {fwd_ms:.2f} ms, adjoint {adj_ms:.2f} ms)",
+          file=sys.stderr, flush=True)
+    return {"grads_per_s": round(B / (ms / 1e3), 2) if ok else None, "ms_per_step": round(ms, 3),
+            "padded": [nzp, nxp], "path": info["path"],
+            "sweep_ms": {"forward": round(fwd_ms, 3), "adjoint": round(adj_ms, 3)},
+            "roofline": {"bound": "hbm", "kernel": "k_wave_pml<7, adjoint>", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": None, "alg_bytes_per_launch": alg, "launch_ms": round(adj_ms, 3)},
+            "protocol": f"same {B} models, shots and observations source as the plain line; 6-cell PML, W2 misfit "
+                        f"(k = 100); {steps} timed steps after {warmup} warm-up"}
+
+
 def bench_uneven(args):
     """64 requests (seeds 2000 + r): 70x70 / 140x140 / 256x256 grids with a 40-cell sponge, 1000 / 1500 / 2500
     samples at dt = 1 ms, 5-10 surface shots, faulted or layered models in 1500-4500 m/s; forward modelling of
@@ -703,6 +766,7 @@ def main():
     if not args.no_variants:
         out["variants"] = comparison_variants(plan, acq, wt, dobs[0].contiguous(), v, x0)
         out["operators"] = perturbed_operators(v0hat, v_true, x0)
+        out["pml"] = pml_guidance(acq, v0hat, v_true, x0, w)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_guidance(plan, wt, v_true)
     if not args.no_cpu_baseline:
