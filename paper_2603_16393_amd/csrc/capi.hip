@@ -202,18 +202,10 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
             return FWI_EINVAL;
         }
         p.path = 2;
-        // the sweep gives each thread one receiver: model slots (row-major) of
-        // two receivers must differ modulo the thread count
-        pml_rec.assign(kPmlThreads, -1);
-        for (int r = 0; r < nr; ++r) {
-            const int j = p.rec_iz[r] * p.g.nx + p.rec_ix[r];
-            int& slot = pml_rec[j % kPmlThreads];
-            if (slot >= 0 || nr >= (1 << 16)) {
-                delete pp;
-                return FWI_EINVAL;
-            }
-            slot = ((j / kPmlThreads) << 16) | r;
-        }
+        // receiver of each slot of the sweep's cell order
+        pml_rec.assign(npts, -1);
+        const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
+        for (int r = 0; r < nr; ++r) pml_rec[ord.model_slot(p.rec_iz[r], p.rec_ix[r])] = r;
     } else {
         bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, o.lds_tile_x, o.lds_tile_z, &p.lds_X, &p.lds_P,
                                                    &p.lds_ncg, &p.lds_nstrip);
@@ -351,7 +343,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
     } else if (p.path == 2) {
-        st = st ? st : alloc_n(p, &p.pml_rec, (size_t)kPmlThreads);
+        st = st ? st : alloc_n(p, &p.pml_rec, npts);
         st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
         st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
     } else {

@@ -41,6 +41,79 @@ constexpr int kLdsMaxP = 48;   // rows per thread of the LDS-resident sweep (mul
 constexpr int kPmlThreads = 1024;
 constexpr int kPmlMaxCells = 7;
 
+// Cell order of the PML sweep.  Slots list (1) the model cells at least 4
+// cells from the layer, whose stencils never see the auxiliary fields,
+// row-major; (2) the other model cells (the 4-cell ring next to the layer),
+// row-major; (3) the layer cells: side strips row by row, then the full rows
+// above (no reflecting top) and below the model.  A wavefront of consecutive
+// slots then does the same work throughout.
+struct PmlOrder {
+    int nz, nx, nb, ztop, nxp;
+    int zlo, zhi, dw;  // deep rows [zlo, zhi) and columns [4, 4 + dw) of the model
+    int ndeep, nint;
+    __host__ __device__ PmlOrder(int nz_, int nx_, int nb_, int fs) : nz(nz_), nx(nx_), nb(nb_) {
+        ztop = fs ? 0 : nb;
+        nxp = nx + 2 * nb;
+        zlo = fs ? 0 : 4;
+        zhi = nz - 4 > zlo ? nz - 4 : zlo;
+        dw = (nx > 8 && zhi > zlo) ? nx - 8 : 0;
+        if (dw == 0) zhi = zlo;
+        ndeep = dw * (zhi - zlo);
+        nint = nz * nx;
+    }
+    // slot of model cell (zm, xm)
+    __host__ __device__ int model_slot(int zm, int xm) const {
+        if (zm >= zlo && zm < zhi && xm >= 4 && xm < 4 + dw) return (zm - zlo) * dw + (xm - 4);
+        const int rw = nx - dw;  // ring cells of a deep row
+        int e;
+        if (zm < zlo)
+            e = zm * nx + xm;
+        else if (zm < zhi)
+            e = zlo * nx + (zm - zlo) * rw + (xm < 4 ? xm : xm - dw);
+        else
+            e = zlo * nx + (zhi - zlo) * rw + (zm - zhi) * nx + xm;
+        return ndeep + e;
+    }
+    // padded cell (iz, ix) of slot j
+    __host__ __device__ void cell(int j, int& iz, int& ix) const {
+        int zm, xm;
+        if (j < ndeep) {
+            zm = zlo + j / dw;
+            xm = 4 + j % dw;
+        } else if (j < nint) {
+            int e = j - ndeep;
+            const int rw = nx - dw, top = zlo * nx, mid = (zhi - zlo) * rw;
+            if (e < top) {
+                zm = e / nx;
+                xm = e % nx;
+            } else if (e - top < mid) {
+                e -= top;
+                zm = zlo + e / rw;
+                const int c = e % rw;
+                xm = c < 4 ? c : c + dw;
+            } else {
+                e -= top + mid;
+                zm = zhi + e / nx;
+                xm = e % nx;
+            }
+        } else {
+            const int e = j - nint, w2 = 2 * nb, nside = nz * w2;
+            if (e < nside) {
+                const int c = e % w2;
+                iz = ztop + e / w2;
+                ix = c < nb ? c : nx + c;
+                return;
+            }
+            const int e2 = e - nside, row = e2 / nxp;
+            ix = e2 - row * nxp;
+            iz = row < ztop ? row : row + nz;
+            return;
+        }
+        iz = ztop + zm;
+        ix = nb + xm;
+    }
+};
+
 // Device flag bits.
 constexpr int kFlagBadVelocity = 1;
 
@@ -140,7 +213,7 @@ struct Plan {
     float* K = nullptr;          // [max_batch][npts]
     float* pml_tx = nullptr;     // PML: [nxp] zeta_x dt / 2 per padded column
     float* pml_tz = nullptr;     // PML: [nzp] zeta_z dt / 2 per padded row
-    int* pml_rec = nullptr;      // PML: [kPmlThreads] (slot k << 16 | receiver) owned by each thread, or -1
+    int* pml_rec = nullptr;      // PML: [npts] receiver index of each slot of the sweep's cell order, or -1
     float* ax = nullptr;         // [nxp] sponge damping factor per padded column
     float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]

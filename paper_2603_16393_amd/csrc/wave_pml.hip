@@ -39,9 +39,10 @@
 // One workgroup of kPmlThreads threads holds a whole (sample, shot) field in
 // LDS: three gather planes (u or y, Q_x or G_x, Q_z or G_z) of (nzp + 8) x
 // (nxp + 8) floats with 4-cell zero halos (mirror rows above a reflecting
-// top), and r and E per cell.  Thread t owns the slots t + k kPmlThreads of an
-// ordering that lists the model cells first and the layer cells after them,
-// so a wavefront either skips the auxiliary fields or carries them.  The
+// top), and r and E per cell.  Thread t owns the slots t + k kPmlThreads of
+// the order PmlOrder defines (model cells away from the layer, the model ring
+// next to it, the layer), so a wavefront of the first group skips the
+// divergence of Q and one of the first two skips the auxiliary fields.  The
 // history of D is kept in slot order (coalesced); the imaging sum leaves in
 // padded order.  Two barriers per step separate the gradient phase (writes
 // Q) from the divergence phase (writes u^{n+1}).
@@ -82,7 +83,7 @@ struct PmlArgs {
     const float* tz;         // [nzp] zeta_z dt / 2
     const float* wavelet;
     const int* src_pt;       // [ns] padded index
-    const int* rec_thread;   // [kPmlThreads] (slot k << 16 | receiver) of the thread's receiver, or -1
+    const int* rec_slot;     // [npts] receiver index of each slot, or -1
     const float* rec_invw;   // [nr]
     float* traces;           // forward out [B][ns][nr][nt]
     const float* adj;        // adjoint in [B][ns][nr][nt]
@@ -90,28 +91,6 @@ struct PmlArgs {
     float* gpad;             // adjoint out [B*ns][npts], padded order
     int store;
 };
-
-// Padded cell of slot j: the model cells first (row-major), then the layer
-// cells (side strips row by row, then the full rows above and below the
-// model), so that a wavefront is either all model or all layer.
-__device__ __forceinline__ void pml_slot_cell(const PmlArgs& a, int j, int& iz, int& ix) {
-    const int nint = a.nz * a.nx;
-    if (j < nint) {
-        iz = a.ztop + j / a.nx;
-        ix = a.nb + j % a.nx;
-        return;
-    }
-    const int e = j - nint, w2 = 2 * a.nb, nside = a.nz * w2;
-    if (e < nside) {
-        const int c = e % w2;
-        iz = a.ztop + e / w2;
-        ix = c < a.nb ? c : a.nx + c;
-        return;
-    }
-    const int e2 = e - nside, row = e2 / a.nxp;
-    ix = e2 - row * a.nxp;
-    iz = row < a.ztop ? row : row + a.nz;
-}
 
 template <int KC, bool ADJ>
 __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
@@ -131,7 +110,8 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
     const int b = field / a.ns, s = field - (field / a.ns) * a.ns;
     const int tid = threadIdx.x;
     const int nsteps = a.nt - 1;
-    const int nint = a.nz * a.nx;
+    const PmlOrder ord(a.nz, a.nx, a.nb, a.fs);
+    const int nint = ord.nint, ndeep = ord.ndeep;
 
     for (int i = tid; i < 3 * plane; i += kPmlThreads) lds[i] = 0.f;
     for (int i = tid; i < nxp; i += kPmlThreads) {
@@ -143,14 +123,17 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
         tcz[i] = 1.f / (1.f + a.tz[i]);
     }
     int pos[KC];  // iz << 16 | ix of each slot, -1 past the grid
+    int rec[KC];  // receiver of each slot, or -1
     const float* Kb = a.K + (size_t)b * npts;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int j = tid + k * kPmlThreads;
         pos[k] = -1;
+        rec[k] = -1;
         if (j < npts) {
+            rec[k] = a.rec_slot[j];
             int iz, ix;
-            pml_slot_cell(a, j, iz, ix);
+            ord.cell(j, iz, ix);
             pos[k] = (iz << 16) | ix;
             const float E = 1.f / (1.f + a.tx[ix] + a.tz[iz]);
             rs[j] = Kb[iz * nxp + ix] * E;
@@ -159,16 +142,10 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
     }
     // source slot (a model cell) and this thread's receiver
     const int sp = a.src_pt[s];
-    const int sj = (sp / nxp - a.ztop) * a.nx + (sp % nxp - a.nb);
+    const int sj = ord.model_slot(sp / nxp - a.ztop, sp % nxp - a.nb);
     const bool own_src = (sj % kPmlThreads) == tid;
     const int ksrc = sj / kPmlThreads;
-    const int rt = a.rec_thread[tid];
-    const int krec = rt >= 0 ? rt >> 16 : -1;
-    const int rid = rt >= 0 ? rt & 0xffff : 0;
-    const float rinvw = rt >= 0 ? a.rec_invw[rid] : 0.f;
     const size_t trfield = (size_t)field * a.nr * a.nt;
-    const float* adjrec = ADJ ? a.adj + trfield + (size_t)rid * a.nt : nullptr;
-    float* trrec = ADJ ? nullptr : a.traces + trfield + (size_t)rid * a.nt;
     float* Dfield = a.Dstore + (size_t)field * nsteps * npts;
 
     float w[KC], px[KC], pz[KC], acc[KC], mu[KC], dnext[KC];
@@ -184,13 +161,15 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
     __syncthreads();
 
     if (!ADJ) {
-        if (krec >= 0) trrec[0] = 0.f;
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (rec[k] >= 0) a.traces[trfield + (size_t)rec[k] * a.nt] = 0.f;
     } else {
         // mu^{N-1} = a^{N-1} / w at the receivers, mu^N = 0, nu^{N-1} = mu^{N-1}
 #pragma unroll
         for (int k = 0; k < KC; ++k)
-            if (k == krec) {
-                mu[k] = adjrec[nsteps] * rinvw;
+            if (rec[k] >= 0) {
+                mu[k] = a.adj[trfield + (size_t)rec[k] * a.nt + nsteps] * a.rec_invw[rec[k]];
                 w[k] = mu[k];
                 const float y = rs[tid + k * kPmlThreads] * mu[k];
                 const int iz = pos[k] >> 16, ix = pos[k] & 0xffff;
@@ -251,11 +230,13 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
                 if (a.fs && iz >= 1 && iz <= 4) GZ[o - 2 * iz * S] = -oz;
             }
         }
-        float sv = 0.f, av = 0.f;
+        float sv = 0.f, av[KC];
         if (!ADJ) {
             if (own_src) sv = a.wavelet[n] * a.src_scale;
         } else {
-            if (krec >= 0) av = adjrec[n] * rinvw;
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+                av[k] = rec[k] >= 0 ? a.adj[trfield + (size_t)rec[k] * a.nt + n] * a.rec_invw[rec[k]] : 0.f;
             if (n >= 1) {
 #pragma unroll
                 for (int k = 0; k < KC; ++k)
@@ -272,7 +253,8 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
             const int pk = opaque(pos[k]);
             const int iz = pk >> 16, ix = pk & 0xffff;
             const int o = (iz + 4) * S + ix + 4;
-            const float div = fmaf(a.idx, dfirst(GX + o, 1), a.idz * dfirst(GZ + o, S));
+            // Q is zero within 4 cells of a deep cell
+            const float div = j < ndeep ? 0.f : fmaf(a.idx, dfirst(GX + o, 1), a.idz * dfirst(GZ + o, S));
             const float r = rs[j];
             float q = 1.f, bq = 0.f;
             if (j >= nint) {
@@ -288,10 +270,9 @@ __global__ void __launch_bounds__(kPmlThreads) k_wave_pml(const PmlArgs a) {
                 w[k] = fmaf(r, D, fmaf(q, w[k], -bq * u0));
                 out = u0 + w[k];
                 if (a.store) Dfield[(size_t)n * npts + j] = D;
-                if (k == krec) trrec[n + 1] = out;
+                if (rec[k] >= 0) a.traces[trfield + (size_t)rec[k] * a.nt + n + 1] = out;
             } else {
-                float Fv = lap[k] - div;
-                if (k == krec) Fv += av;
+                const float Fv = (lap[k] - div) + av[k];
                 w[k] = fmaf(q, w[k], fmaf(-bq, mu[k], Fv));
                 mu[k] += w[k];
                 out = r * mu[k];
@@ -331,7 +312,7 @@ PmlArgs make_pml_args(const Plan& p) {
     a.nx = p.g.nx;
     a.nb = p.g.nb;
     a.ztop = p.ztop;
-    a.rec_thread = p.pml_rec;
+    a.rec_slot = p.pml_rec;
     a.rec_invw = p.rec_invw;
     a.Dstore = p.Dstore;
     a.gpad = p.gpad;

@@ -126,7 +126,7 @@ def _pml_geom(nz, nx, recs, pml=1, nb=6):
     return g, keep
 
 
-@pytest.mark.parametrize("case", ["flag", "tiled", "checkpoint", "split", "too_big", "receiver_threads", "batch"])
+@pytest.mark.parametrize("case", ["flag", "tiled", "checkpoint", "split", "too_big", "batch"])
 def test_pml_plan_validation(case):
     """The PML layer (Sec. 6.1) runs on its own LDS-resident sweep: every
     request it cannot serve is refused on the host with FWI_EINVAL."""
@@ -145,10 +145,6 @@ def test_pml_plan_validation(case):
         assert L.fwi_plan_create_ex(ctypes.byref(g), 1, 0, ctypes.byref(opts), ctypes.byref(h)) == -1
     elif case == "too_big":
         g, keep = _pml_geom(120, 120, recs)  # 126 x 132 padded cells: more than one workgroup's LDS
-        assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
-    elif case == "receiver_threads":
-        # model cells 0 and 1024 (row-major, nx = 64) fall on the same thread of the sweep
-        g, keep = _pml_geom(30, 64, ((0, 0), (16, 0)))
         assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
     else:
         g, keep = _pml_geom(20, 20, recs)

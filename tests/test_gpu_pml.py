@@ -40,20 +40,26 @@ def dev():
     return d
 
 
-def _small_acq(nz, nx, fs, nt, ns):
+def _small_acq(nz, nx, fs, nt, ns, two_rows=False):
+    rec_iz = np.full(nx, 0 if fs else 1, np.int32)
+    rec_ix = np.arange(nx, dtype=np.int32)
+    if two_rows:  # a surface spread and a buried one: several receivers share a thread of the sweep
+        rec_iz = np.concatenate([rec_iz, np.full(nx, nz // 2 + 1, np.int32)])
+        rec_ix = np.concatenate([rec_ix, rec_ix])
     return fi.Acquisition(nz=nz, nx=nx, dz=10.0, dx=12.0, dt=0.001, nt=nt, nb=6, free_surface=fs, v_max=4000.0,
                           src_iz=np.full(ns, 1, np.int32), src_ix=np.linspace(1, nx - 2, ns).astype(np.int32),
-                          rec_iz=np.full(nx, 0 if fs else 1, np.int32), rec_ix=np.arange(nx, dtype=np.int32),
-                          f_peak=25.0, pml=True)
+                          rec_iz=rec_iz, rec_ix=rec_ix, f_peak=25.0, pml=True)
 
 
-@pytest.mark.parametrize("nz,nx,fs,nt", [(9, 11, True, 160), (9, 11, False, 160), (40, 50, True, 400),
-                                         (37, 53, False, 300), (62, 70, True, 500)])
-def test_pml_traces_and_gradient(dev, nz, nx, fs, nt):
+@pytest.mark.parametrize("nz,nx,fs,nt,two_rows", [(9, 11, True, 160, False), (9, 11, False, 160, False),
+                                                  (40, 50, True, 400, False), (37, 53, False, 300, False),
+                                                  (62, 70, True, 500, False), (62, 70, True, 300, True),
+                                                  (40, 50, False, 300, True)])
+def test_pml_traces_and_gradient(dev, nz, nx, fs, nt, two_rows):
     import oracle
     from paper_2603_16393_amd import FwiPlan
 
-    acq = _small_acq(nz, nx, fs, nt, 3)
+    acq = _small_acq(nz, nx, fs, nt, 3, two_rows)
     rng = np.random.default_rng(nz * 1000 + nx + int(fs))
     v = (2000.0 + 1500.0 * rng.random((2, nz, nx))).astype(np.float32)
     w = fi.ricker(nt, acq.dt, acq.f_peak).astype(np.float32)
@@ -71,7 +77,7 @@ def test_pml_traces_and_gradient(dev, nz, nx, fs, nt):
     d, g = d.cpu().numpy(), g.cpu().numpy()
     plan.close()
     ed, eg = _rel(d, do), _rel(g, go)
-    print(f"PML {nz}x{nx} fs={fs} nt={nt} padded {info['nzp']}x{info['nxp']} path={info['path']}: "
+    print(f"PML {nz}x{nx} fs={fs} nt={nt} receivers={acq.nr} padded {info['nzp']}x{info['nxp']} path={info['path']}: "
           f"traces {ed:.2e}, gradient {eg:.2e}", flush=True)
     assert info["path"] == 2
     assert ed <= 1e-4 and eg <= 1e-4
