@@ -72,8 +72,8 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
 TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
                    "paper_2603_16393_amd/csrc/wave_split_body.h", "paper_2603_16393_amd/csrc/fwi_internal.h",
                    "paper_2603_16393_amd/csrc/capi.hip")
-TRAFFIC_SHA1 = "c95be2ae0aebb210e7ceebc38a43e4eef5cec4e9"
-TRAFFIC_BYTES = {"forward": 8991429507.0, "adjoint": 8532635784.0}
+TRAFFIC_SHA1 = "a221f038cdb875f32bcffa01ed9c8ff52823408c"
+TRAFFIC_BYTES = {"forward": 8995790672.0, "adjoint": 8533055833.0}
 
 
 def kernel_sources_sha1():
@@ -88,6 +88,23 @@ def measured_traffic(kind):
     if TRAFFIC_SHA1 is None or TRAFFIC_BYTES.get(kind) is None or kernel_sources_sha1() != TRAFFIC_SHA1:
         return None
     return TRAFFIC_BYTES[kind]
+
+
+# The same for the PML sweeps (profiles/k_wave_pml_b16_70x70_hbm_traffic.md).
+PML_TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_pml.hip", "paper_2603_16393_amd/csrc/fwi_internal.h",
+                       "paper_2603_16393_amd/csrc/capi.hip")
+PML_TRAFFIC_SHA1 = "281d592c4ea6aa3096a7d324b1a0e9ccbae8d2aa"
+PML_TRAFFIC_BYTES = {"forward": 2017378301.0, "adjoint": 2021754320.0}
+
+
+def pml_measured_traffic(kind):
+    h = hashlib.sha1()
+    for f in PML_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if PML_TRAFFIC_SHA1 is None or PML_TRAFFIC_BYTES.get(kind) is None or h.hexdigest() != PML_TRAFFIC_SHA1:
+        return None
+    return PML_TRAFFIC_BYTES[kind]
 
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surrogate_70x70.npy")
@@ -361,9 +378,51 @@ def pml_guidance(acq, v0hat, v_true, x0, w, steps=10, warmup=2):
             "sweep_ms": {"forward": round(fwd_ms, 3), "adjoint": round(adj_ms, 3)},
             "roofline": {"bound": "hbm", "kernel": "k_wave_pml<7, adjoint>", "achieved": round(achieved, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": None, "alg_bytes_per_launch": alg, "launch_ms": round(adj_ms, 3)},
+                         "traffic": pml_measured_traffic("adjoint"), "alg_bytes_per_launch": alg,
+                         "launch_ms": round(adj_ms, 3)},
             "protocol": f"same {B} models, shots and observations source as the plain line; 6-cell PML, W2 misfit "
                         f"(k = 100); {steps} timed steps after {warmup} warm-up"}
+
+
+def copy_calibration(dev):
+    """Three dispatches of the library's plain copy kernel on 512 MiB, whose counter readings scale
+    FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+
+    from paper_2603_16393_amd import _lib
+
+    nbytes = 512 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        _lib.check(_lib.load().fwi_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "fwi_copy")
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    del src, dst
+    print(f"copy calibration: 3 x {nbytes} bytes", file=sys.stderr)
+
+
+def bench_pml(args):
+    """The plain guidance step of the default batch with the 6-cell PML alone (the `pml` field of the default
+    run), as its own JSON line; with --copy-calibration the copy kernel runs first (counter passes)."""
+    import torch
+
+    import fwi_inputs as fi
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    acq, v0hat, v_true, w = make_inputs()
+    x0 = torch.tensor(fi.to_normalised(v0hat), dtype=torch.float32, device=dev)
+    if args.copy_calibration:
+        copy_calibration(dev)
+    r = pml_guidance(acq, v0hat, v_true, x0, w, steps=args.steps, warmup=args.warmup)
+    print(json.dumps({
+        "metric": "guidance grads/s (70x70, 5 shots, 1k steps, 6-cell PML)", "value": r["grads_per_s"],
+        "unit": "grads/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain guidance, 16 x 70x70, 5 shots, 1000 steps, 6-cell PML", "global_batch": B},
+        "roofline": r["roofline"], "sweep_ms": r["sweep_ms"]}))
 
 
 def bench_uneven(args):
@@ -606,7 +665,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the library's plain copy kernel on 512 MiB three times "
                          "(the reference dispatch for HBM traffic counters) and exit")
-    ap.add_argument("--workload", choices=["guidance", "checkpointed", "uneven", "surrogate"], default="guidance")
+    ap.add_argument("--workload", choices=["guidance", "checkpointed", "uneven", "surrogate", "pml"],
+                    default="guidance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
@@ -620,6 +680,9 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "pml":
+        bench_pml(args)
         return
 
     import torch
@@ -663,20 +726,8 @@ def main():
             ev[4].record()
 
     if args.copy_calibration:
-        # three dispatches of the library's plain copy kernel on 512 MiB, before any sweep, whose counter
-        # readings scale FETCH_SIZE / WRITE_SIZE to bytes
-        from paper_2603_16393_amd import _lib
-
-        nbytes = 512 << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            _lib.check(_lib.load().fwi_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
-                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "fwi_copy")
-        torch.cuda.synchronize()
-        assert torch.equal(dst, src)
-        del src, dst
-        print(f"copy calibration: 3 x {nbytes} bytes", file=sys.stderr)
+        # before any sweep
+        copy_calibration(dev)
 
     for _ in range(args.warmup):
         step()
