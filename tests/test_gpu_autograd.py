@@ -1,7 +1,9 @@
 """The misfit as a torch.autograd.Function (FwiW2Loss) on the batch-of-16
-acquisition (70 x 70, 5 surface shots, 70 receivers, 1000 samples, 40-cell
-sponge), checked by central finite differences along smooth directions
-supported on a 16 x 16 sub-grid.
+acquisition (70 x 70, 5 surface shots, 70 receivers, 1000 samples), with the
+40-cell sponge and with the paper's 6-cell PML (Sec. 6.1), checked by central
+finite differences along smooth directions supported on a 16 x 16 sub-grid
+(with the PML, every other direction sits on the left edge, whose gradient
+collects the layer's cells).
 
 What the backward pass computes is the adjoint of the forward map applied to
 the misfit's adjoint source a = dJ/dd (held at v), times the upstream
@@ -29,27 +31,32 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=["sponge", "pml"])
+def setup(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    import dataclasses
+
     from paper_2603_16393_amd import FwiPlan
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     acq = fi.surface_acquisition(70, 70, ns=5, nt=1000, nb=40)
+    if request.param == "pml":
+        acq = dataclasses.replace(acq, nb=6, pml=True)
     plan = FwiPlan(acq, max_batch=12, device=dev)
     w = torch.tensor(fi.ricker(acq.nt, acq.dt, acq.f_peak), dtype=torch.float32, device=dev)
     vt = torch.tensor(fi.faulted_model(70, 70, 1000)[None], dtype=torch.float32, device=dev)
     plan.set_obs(plan.forward(vt, w, keep_for_adjoint=False)[0].contiguous())
     v0 = np.stack([fi.faulted_model(70, 70, 0), fi.faulted_model(70, 70, 1)]).astype(np.float32)
-    return dev, plan, w, v0
+    yield dev, plan, w, v0, request.param
+    plan.close()
 
 
 def test_backward_is_the_scaled_adjoint(setup):
     from paper_2603_16393_amd import FwiW2Loss
 
-    dev, plan, w, v0 = setup
+    dev, plan, w, v0, _ = setup
     v = torch.tensor(v0, device=dev, requires_grad=True)
     J = FwiW2Loss.apply(v, plan, w)
     wts = torch.tensor([2.5, -0.75], dtype=torch.float64, device=dev)
@@ -68,7 +75,7 @@ def test_autograd_adjoint_fd_on_16x16_subgrid(setup):
 
     from paper_2603_16393_amd import FwiW2Loss
 
-    dev, plan, w, v0 = setup
+    dev, plan, w, v0, kind = setup
     ndir, h = 6, 10.0
     # the backward pass at v0: the adjoint of F applied to a = dJ/dd(v0)
     v = torch.tensor(v0, device=dev, requires_grad=True)
@@ -83,7 +90,8 @@ def test_autograd_adjoint_fd_on_16x16_subgrid(setup):
     dirs = np.zeros((ndir, 70, 70))
     for i in range(ndir):
         blk = gaussian_filter(rng.standard_normal((16, 16)), 2.0)
-        dirs[i, 4:20, 27:43] = blk / np.abs(blk).max()
+        c0 = 0 if (kind == "pml" and i % 2) else 27
+        dirs[i, 4:20, c0:c0 + 16] = blk / np.abs(blk).max()
     for s in range(2):
         vs = np.concatenate([v0[s] + h * dirs, v0[s] - h * dirs]).astype(np.float32)
         with torch.no_grad():
@@ -92,5 +100,5 @@ def test_autograd_adjoint_fd_on_16x16_subgrid(setup):
         fd = (phi[:ndir] - phi[ndir:]) / (2 * h)
         an = np.einsum("kij,ij->k", dirs, g[s])
         err = np.abs(fd - an) / np.abs(an).max()
-        print(f"sample {s}: directional derivatives {an}, finite differences {fd}, max rel err {err.max():.2e}")
+        print(f"{kind} sample {s}: directional derivatives {an}, finite differences {fd}, max rel err {err.max():.2e}")
         assert err.max() <= 5e-3
