@@ -56,6 +56,8 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
     x0 = fi.to_normalised(v0hat[:n_samples])
     oracle.guidance(x0, g, g, x0, unit_scale=1500.0)
     dt = time.perf_counter() - t0
+    nzp, nxp = acq.padded_shape
+    pts = 2.0 * n_samples * NS * (NT - 1) * nzp * nxp  # forward + adjoint point-updates
     return {
         "value": n_samples / dt,
         "unit": "grads/s",
@@ -63,7 +65,34 @@ def cpu_baseline(acq, v0hat, v_true, w, n_samples=4):
         "kind": "oracle",
         "sample": f"{n_samples} of the {B} samples ({n_samples * NS} shot units), same grid/steps; forward + W2 + "
                   f"reverse-mode gradient + guidance update in FP64, {dt:.1f} s",
+        "gpts_per_s": round(pts / dt / 1e9, 4),
+        "single_core": cpu_baseline_one_core(),
     }
+
+
+def cpu_baseline_one_core():
+    """The oracle on one thread (a child process with OMP_NUM_THREADS=1, no GPU use): forward + W2 + gradient of
+    one shot unit of sample 0, scaled to grads/s (a gradient is NS units)."""
+    import subprocess
+
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import bench, oracle\n"
+        "acq, v0hat, v_true, w = bench.make_inputs()\n"
+        "a1 = acq.subset_shots([0])\n"
+        "obs = oracle.w2_prepare(oracle.forward(a1, v_true, w), a1.dt)\n"
+        "t0 = time.perf_counter()\n"
+        "oracle.objective_and_gradient(a1, v0hat[:1], w, obs)\n"
+        "print(json.dumps(time.perf_counter() - t0))\n" % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return None
+    dt = float(r.stdout.strip().splitlines()[-1])
+    nzp, nxp = NZ + NB, NX + 2 * NB
+    return {"value": round(1.0 / (NS * dt), 4), "unit": "grads/s", "cores": 1,
+            "gpts_per_s": round(2.0 * (NT - 1) * nzp * nxp / dt / 1e9, 4),
+            "sample": f"1 shot unit of sample 0 on one thread, {dt:.2f} s, scaled by {NS} units per gradient"}
 
 
 # HBM bytes per sweep launch of the default workload from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
