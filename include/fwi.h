@@ -15,7 +15,9 @@
  * and S_obs of Sec. 5.1 (I)-(III)).  The comparison variants of Sec. 6 swap
  * single calls: fwi_l2_misfit for fwi_w2_misfit (baseline DPS, Algorithm 1,
  * and the MSE ablations), and fwi_tv_subgradient before fwi_guidance_step
- * (the TV-regularised descent baselines).
+ * (the TV-regularised descent baselines).  The absorbing layer of F is a
+ * damping sponge, or the perfectly matched layer of Sec. 2.1 / Sec. 6.1 when
+ * fwi_geometry.pml is set.
  *
  * Conventions shared by every entry point
  *   - Array arguments are DEVICE pointers unless marked HOST; they are owned by
