@@ -294,6 +294,11 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
             return FWI_EINVAL;
         } else {
             p.split_G = 1;
+            // more fields than CUs: the last partial round may be split (wave_lds.hip)
+            if (coop && force == 0 && (long long)nf > ncu) {
+                p.ncu = ncu;
+                p.tail_W = p.nxp + 8;
+            }
         }
     }
 
@@ -350,6 +355,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.rec_of_col, (size_t)p.nxp);
         if (p.split_G > 1)
             st = st ? st : alloc_n(p, &p.xchg, nf * p.split_G * 2 * 2 * 4 * (size_t)p.split_ncg * p.split_X);
+        if (p.tail_W > 0) st = st ? st : alloc_n(p, &p.tail_xchg, (size_t)p.ncu * 2 * 2 * 4 * p.tail_W);
     }
     if (p.store_mode == 0) {
         st = st ? st : alloc_n(p, &p.Dstore, nf * nsteps * npts);

@@ -163,6 +163,7 @@ struct SplitArgs {
     unsigned long long* xchg;    // [fields][G][2: top, bottom rows][2: slot][4][W], a row as [X][ncg]
                                  // (column x0 + c of column group cg at c * ncg + cg: coalesced)
     int* err;                    // |= 2 when a wait gave up (the sweep's results are then invalid)
+    int field0;                  // first field of this launch; xchg is indexed from it
 };
 constexpr int kSplitSpinMax = 1 << 18;  // polls of one value before a wait gives up
 constexpr int kBufferRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit accesses (gfx9 data format)
@@ -206,6 +207,9 @@ struct Plan {
     int split_G = 1;                     // LDS path: workgroups per field (1: whole field in one workgroup)
     int split_X = 0, split_P = 0, split_ncg = 0, split_nstrip = 0;
     unsigned long long* xchg = nullptr;  // split halo exchange [max_batch*ns][G][2][2][4][ncg*X]
+    int ncu = 0;                         // LDS path: CUs of the device when cooperative launches work, else 0
+    unsigned long long* tail_xchg = nullptr;  // exchange of the split tail launch: [ncu][2][2][4][tail_W]
+    int tail_W = 0;                      // capacity of one exchanged row in tail_xchg
     size_t device_bytes;
     std::vector<void*> allocs;
 

@@ -41,8 +41,8 @@ template <int X, int PI, bool ADJ, bool XEXACT, bool STORE>
 __global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs sp, const float* __restrict__ ax_g,
                                                             const float* __restrict__ az_g) {
     extern __shared__ float lds[];
-    const int field = blockIdx.x / sp.G;
-    split_field<X, PI, ADJ, XEXACT, STORE>(a, sp, field, blockIdx.x - field * sp.G, ax_g, az_g, lds);
+    const int lf = blockIdx.x / sp.G;
+    split_field<X, PI, ADJ, XEXACT, STORE>(a, sp, sp.field0 + lf, blockIdx.x - lf * sp.G, ax_g, az_g, lds);
 }
 
 // Instantiated tiles (X columns, P rows).  (3, 11) tiles the 110 x 150 padded
@@ -232,6 +232,39 @@ static int split_args(const Plan& p, int nfields, LdsArgs& a, SplitArgs& sp, hip
     return launch_fill(reinterpret_cast<float*>(p.xchg), (size_t)nfields * sp.G * 2 * 2 * 4 * sp.W * 2, 0.f, st);
 }
 
+// When the batch has more fields than CUs and is not split as a whole, the
+// whole-field sweep runs in rounds of one field per CU.  The fields of the
+// last, partial round are instead split over the idle CUs (tile and band
+// count from the cost model for that many fields) in a second launch after
+// the full rounds; the results are the same bit for bit.  Returns false
+// when no such split applies.
+static bool tail_split_args(const Plan& p, int nf, const LdsArgs& a, LdsArgs& ta, SplitArgs& sp, int* head,
+                            hipStream_t st, int* rc) {
+    *rc = FWI_OK;
+    if (!p.tail_xchg || p.ncu <= 0 || nf <= p.ncu || capturing(st)) return false;
+    const int h = (nf / p.ncu) * p.ncu, tail = nf - h;
+    if (tail <= 0) return false;
+    int X = 0, P = 0, ncg = 0, nstrip = 0, G = 1;
+    if (!lds_choose_split(p.nzp, p.nxp, tail, p.ncu, p.lds_X, p.lds_P, 0, &X, &P, &ncg, &nstrip, &G) || G < 2 ||
+        ncg * X > p.tail_W || (long long)tail * G > p.ncu)
+        return false;
+    ta = a;
+    ta.X = X;
+    ta.P = P;
+    ta.ncg = ncg;
+    ta.nstrip = nstrip;
+    ta.S = ncg * X + 8;
+    sp = SplitArgs{};
+    sp.G = G;
+    sp.W = ncg * X;
+    sp.xchg = p.tail_xchg;
+    sp.err = p.flags;
+    sp.field0 = h;
+    *head = h;
+    *rc = launch_fill(reinterpret_cast<float*>(p.tail_xchg), (size_t)tail * G * 2 * 2 * 4 * sp.W * 2, 0.f, st);
+    return true;
+}
+
 int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st) {
     LdsArgs a = make_lds_args(p);
     a.traces = traces;
@@ -244,6 +277,19 @@ int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet
         if (rc) return rc;
         if (store) return split_dispatch<false, true>(a, sp, nf, st, p.ax, p.az);
         return split_dispatch<false, false>(a, sp, nf, st, p.ax, p.az);
+    }
+    {
+        LdsArgs ta;
+        SplitArgs sp;
+        int head = 0, rc = FWI_OK;
+        if (tail_split_args(p, nf, a, ta, sp, &head, st, &rc)) {
+            if (!rc) rc = store ? lds_dispatch<false, true>(a, head, st, p.ax, p.az)
+                                : lds_dispatch<false, false>(a, head, st, p.ax, p.az);
+            if (!rc) rc = store ? split_dispatch<false, true>(ta, sp, nf - head, st, p.ax, p.az)
+                                : split_dispatch<false, false>(ta, sp, nf - head, st, p.ax, p.az);
+            return rc;
+        }
+        if (rc) return rc;
     }
     if (store) return lds_dispatch<false, true>(a, nf, st, p.ax, p.az);
     return lds_dispatch<false, false>(a, nf, st, p.ax, p.az);
@@ -259,6 +305,17 @@ int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wave
         const int rc = split_args(p, nf, a, sp, st);
         if (rc) return rc;
         return split_dispatch<true, false>(a, sp, nf, st, p.ax, p.az);
+    }
+    {
+        LdsArgs ta;
+        SplitArgs sp;
+        int head = 0, rc = FWI_OK;
+        if (tail_split_args(p, nf, a, ta, sp, &head, st, &rc)) {
+            if (!rc) rc = lds_dispatch<true, false>(a, head, st, p.ax, p.az);
+            if (!rc) rc = split_dispatch<true, false>(ta, sp, nf - head, st, p.ax, p.az);
+            return rc;
+        }
+        if (rc) return rc;
     }
     return lds_dispatch<true, false>(a, nf, st, p.ax, p.az);
 }

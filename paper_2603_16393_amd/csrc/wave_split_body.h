@@ -299,7 +299,7 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
     // halo row this thread receives: row < 4 -> top halo row `row` from band g - 1's
     // last rows, 4..7 -> bottom halo row `row - 4` from band g + 1's first rows
     const bool recv = has_b && (row < 4 ? g > 0 : g < sp.G - 1);
-    const size_t fb = (size_t)field * sp.G;
+    const size_t fb = (size_t)(field - sp.field0) * sp.G;
     const unsigned long long* src0 = sp.xchg;
     if (recv) {
         const size_t nbr = row < 4 ? ((fb + g - 1) * 2 + 1) : ((fb + g + 1) * 2 + 0);

@@ -91,6 +91,32 @@ def test_split_equals_whole_field_sweep(dev, case):
     pw.close()
 
 
+@pytest.mark.parametrize("ns,nt", [(17, 1000), (20, 500)])
+def test_tail_split_equals_whole_field_sweep(dev, ns, nt):
+    """More fields than CUs (16 samples x 17 or 20 shots): full rounds of the
+    whole-field sweep, then the partial last round split over the idle CUs in
+    a second launch; bit for bit the whole-field sweep's results, on three
+    calls and for a smaller batch that has no partial round."""
+    from paper_2603_16393_amd import FwiPlan
+
+    acq = fi.surface_acquisition(70, 70, ns=ns, nt=nt, nb=40)
+    B = 16
+    ps = FwiPlan(acq, max_batch=B, device=dev)
+    pw = FwiPlan(acq, max_batch=B, device=dev, split=-1)
+    _say(f"{ns} shots: {B * ns} fields, plan {ps.info}")
+    assert ps.info["lds_split"] == 1 and pw.info["lds_split"] == 1
+    v = torch.tensor(np.stack([fi.faulted_model(70, 70, 80 + b) for b in range(B)]).astype(np.float32), device=dev)
+    w = torch.tensor(fi.ricker(acq.nt, acq.dt, acq.f_peak), dtype=torch.float32, device=dev)
+    adj = torch.tensor(_adjoint_sources((B, acq.ns, acq.nr, acq.nt), 5), device=dev)
+    for nb_ in (B, 4):
+        ref = _run(pw, v[:nb_], w, adj[:nb_], 1)[0]
+        for i, (d, g) in enumerate(_run(ps, v[:nb_], w, adj[:nb_], 3 if nb_ == B else 1)):
+            assert torch.equal(d, ref[0]), f"B={nb_} call {i}: traces differ"
+            assert torch.equal(g, ref[1]), f"B={nb_} call {i}: gradients differ"
+    ps.close()
+    pw.close()
+
+
 def test_sources_and_receivers_on_band_boundaries(dev):
     """Receiver row and source on the published rows of a middle band (their
     corrections must precede the publication); split vs whole field bitwise,
