@@ -18,6 +18,7 @@ arrays through ctypes.  Functions and the passages they follow:
 * :func:`l2_misfit`    -- least-squares potential Phi_l2 of baseline DPS (Sec. 4,
                           Algorithm 1) and its weighted / normalised ablation form
 * :func:`tv_subgradient` -- g + alpha dTV (Eq. tv) for the TV-regularised baselines (Sec. 6)
+* :func:`ddpm_step`    -- clean estimator and DDPM posterior mean + noise of Algorithm 2 (numpy)
 
 Every function is pinned by the CPU tests in ``tests/test_oracle_*.py``.
 """
@@ -315,3 +316,20 @@ def wavefield(acq, v, wavelet, shot: int = 0, nsteps: int | None = None, check_c
 def cfl_number(v_max: float, dt: float, dz: float, dx: float) -> float:
     """Courant ratio; the scheme is stable iff it is below 1."""
     return float(lib().orc_cfl_number(v_max, dt, dz, dx))
+
+
+def ddpm_step(v, beta, abar, abar_prev, score=None, v0hat=None, z=None, sigma=0.0):
+    """One reverse DDPM step of Algorithm 2 without the guidance term (Sec. 5.3): the clean estimator
+    Eq. v0hat, v0hat = (v + (1 - abar_i) s) / sqrt(abar_i), when a score s is given (else the caller's
+    v0hat), and the posterior mean plus noise
+    v' = sqrt(alpha_i) (1 - abar_{i-1}) / (1 - abar_i) v + sqrt(abar_{i-1}) beta_i / (1 - abar_i) v0hat + sigma z,
+    alpha_i = 1 - beta_i.  FP64.  Returns (v0hat, v')."""
+    v = np.asarray(v, np.float64)
+    if score is not None:
+        v0hat = (v + (1.0 - abar) * np.asarray(score, np.float64)) / np.sqrt(abar)
+    v0hat = np.asarray(v0hat, np.float64)
+    alpha = 1.0 - beta
+    vp = np.sqrt(alpha) * (1.0 - abar_prev) / (1.0 - abar) * v + np.sqrt(abar_prev) * beta / (1.0 - abar) * v0hat
+    if z is not None:
+        vp = vp + sigma * np.asarray(z, np.float64)
+    return v0hat, vp
