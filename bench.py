@@ -438,6 +438,23 @@ def copy_rate_gbps(dev, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / (float(np.median(ms)) / 1e3) / 1e9
 
 
+def ddpm_step_us(dev, v, reps=200):
+    """Mean device time of fwi_ddpm_step over the batch (score and noise given), HIP events over `reps` calls."""
+    import torch
+
+    from paper_2603_16393_amd import ddpm_step
+
+    s, z, x0, out = torch.randn_like(v), torch.randn_like(v), torch.empty_like(v), torch.empty_like(v)
+    ddpm_step(v, 0.01, 0.5, 0.505, score=s, v0hat=x0, z=z, sigma=0.1, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ddpm_step(v, 0.01, 0.5, 0.505, score=s, v0hat=x0, z=z, sigma=0.1, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    return round(1e3 * e0.elapsed_time(e1) / reps, 2)
+
+
 def copy_calibration(dev):
     """Three dispatches of the library's plain copy kernel on 512 MiB, whose counter readings scale
     FETCH_SIZE / WRITE_SIZE to bytes."""
@@ -827,6 +844,7 @@ def main():
     traffic = measured_traffic("adjoint" if adj_dominant else "forward")
     # after the timed region; not in counter runs, whose calibration dispatches are the only copies
     copy_gbps = None if args.copy_calibration else copy_rate_gbps(dev)
+    ddpm_us = None if args.copy_calibration else ddpm_step_us(dev, v)
     out = {
         "metric": "guidance grads/s (70x70, 5 shots, 1k steps) plain vs surrogate @cos>=0.95",
         "value": round(value, 2),
@@ -868,6 +886,8 @@ def main():
             "frac_of_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
         },
         "sweep_ms": {"forward": round(fwd_sweep_ms, 4), "adjoint": round(adj_sweep_ms, 4)},
+        # reverse DDPM step of Algorithm 2 (clean estimator from a score, posterior mean + noise) on the batch
+        "ddpm_step_us": ddpm_us,
         "variants": None,
         "operators": None,
         "surrogate": None,

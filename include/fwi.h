@@ -15,7 +15,9 @@
  * and S_obs of Sec. 5.1 (I)-(III)).  The comparison variants of Sec. 6 swap
  * single calls: fwi_l2_misfit for fwi_w2_misfit (baseline DPS, Algorithm 1,
  * and the MSE ablations), and fwi_tv_subgradient before fwi_guidance_step
- * (the TV-regularised descent baselines).  The absorbing layer of F is a
+ * (the TV-regularised descent baselines).  fwi_ddpm_step gives the other
+ * lines of a reverse step of Algorithm 2 (clean estimator, posterior mean
+ * plus noise) around the score network.  The absorbing layer of F is a
  * damping sponge, or the perfectly matched layer of Sec. 2.1 / Sec. 6.1 when
  * fwi_geometry.pml is set.
  *
@@ -245,6 +247,17 @@ int fwi_guidance_step(int B, int nz, int nx, const float* v_prop, const float* h
  * W2+TV is gamma = 0 and tau above any TV (rho = rho0), OT-WE+TV uses the
  * preconditioner evaluated at v (v_prop = v0hat = v). */
 int fwi_tv_subgradient(int B, int nz, int nx, const float* v, const float* g, double alpha, float* out, void* stream);
+
+/* One reverse DDPM step of Algorithm 2 without its guidance term (VP schedule in DDPM indexing, Sec. 5.3):
+ *   v0hat = (v + (1 - abar_i) s) / sqrt(abar_i)                                   (Eq. v0hat)
+ *   v_prop = sqrt(alpha_i)(1 - abar_{i-1})/(1 - abar_i) v + sqrt(abar_{i-1}) beta_i/(1 - abar_i) v0hat + sigma z
+ * with alpha_i = 1 - beta_i, over n elements (any layout; all arrays [n] f32, 16-byte aligned).  `score` = s
+ * (the score network's output at (v, i)), or NULL: then v0hat is an INPUT (a clean estimate from elsewhere, e.g.
+ * a denoiser).  `z` = standard normal draws (passed in; NULL = no noise).  The guidance update that completes
+ * the step is fwi_guidance_step with v_prop.  FWI_EINVAL unless 0 < beta < 1, 0 < abar < abar_prev <= 1,
+ * sigma >= 0, pointers non-NULL (except score, z) and aligned. */
+int fwi_ddpm_step(long n, const float* v, const float* score, const float* z, double beta, double abar,
+                  double abar_prev, double sigma, float* v0hat, float* v_prop, void* stream);
 
 /* ------------------------------------------------------------------------
  * Building blocks of the learned surrogate (BF16 storage, FP32 accumulation).

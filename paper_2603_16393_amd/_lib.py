@@ -30,6 +30,7 @@ EXPORTED = (
     "fwi_guidance_step",
     "fwi_l2_misfit",
     "fwi_tv_subgradient",
+    "fwi_ddpm_step",
     "fwi_status",
     "fwi_plan_sweep_ms",
     "fwi_copy",
@@ -140,6 +141,7 @@ def load():
     L.fwi_adjoint_gradient.argtypes = [P, c_int, P, P, P, P, P]
     L.fwi_l2_misfit.argtypes = [P, c_int, P, P, ctypes.POINTER(L2Params), P, P, P]
     L.fwi_tv_subgradient.argtypes = [c_int, c_int, c_int, P, P, c_double, P, P]
+    L.fwi_ddpm_step.argtypes = [ctypes.c_long, P, P, P, c_double, c_double, c_double, c_double, P, P, P]
     L.fwi_guidance_step.argtypes = [c_int, c_int, c_int, P, P, P, P, ctypes.POINTER(GuidanceParams), P, P, P]
     L.fwi_status.argtypes = [P]
     L.fwi_plan_sweep_ms.argtypes = [P, P, P]

@@ -222,3 +222,28 @@ def tv_subgradient(v: torch.Tensor, g: Optional[torch.Tensor] = None, alpha: flo
     check(_lib.load().fwi_tv_subgradient(B, nz, nx, _ptr(v), _ptr(g), float(alpha), _ptr(out), _stream()),
           "fwi_tv_subgradient")
     return out
+
+
+def ddpm_step(v: torch.Tensor, beta: float, abar: float, abar_prev: float, score: Optional[torch.Tensor] = None,
+              v0hat: Optional[torch.Tensor] = None, z: Optional[torch.Tensor] = None, sigma: float = 0.0,
+              out: Optional[torch.Tensor] = None):
+    """Reverse DDPM step of Algorithm 2 before its guidance term: returns (v0hat, v_prop) with
+    v0hat = (v + (1 - abar) score) / sqrt(abar) when `score` is given (else the given v0hat) and
+    v_prop = sqrt(1 - beta)(1 - abar_prev)/(1 - abar) v + sqrt(abar_prev) beta/(1 - abar) v0hat + sigma z."""
+    shape = tuple(v.shape)
+    _need(v, "v", shape, device=v.device)
+    if score is not None:
+        _need(score, "score", shape, device=v.device)
+        v0hat = torch.empty_like(v) if v0hat is None else v0hat
+    elif v0hat is None:
+        raise ValueError("ddpm_step needs a score or a clean estimate v0hat")
+    _need(v0hat, "v0hat", shape, device=v.device)
+    if z is not None:
+        _need(z, "z", shape, device=v.device)
+    if out is None:
+        out = torch.empty_like(v)
+    _need(out, "out", shape, device=v.device)
+    check(_lib.load().fwi_ddpm_step(v.numel(), _ptr(v), _ptr(score), _ptr(z), float(beta), float(abar),
+                                    float(abar_prev), float(sigma), _ptr(v0hat), _ptr(out), _stream()),
+          "fwi_ddpm_step")
+    return v0hat, out

@@ -151,3 +151,15 @@ def test_pml_plan_validation(case):
         geoms = (_lib.Geometry * 1)(g)
         assert L.fwi_batch_create(1, geoms, None, ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("beta,abar,abar_prev,sigma", [(0.0, 0.5, 0.6, 0.0), (0.1, 0.7, 0.6, 0.0),
+                                                      (0.1, 0.5, 1.5, 0.0), (0.1, 0.5, 0.6, -1.0)])
+def test_ddpm_step_validation(beta, abar, abar_prev, sigma):
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    x = ctypes.c_void_p(256)
+    assert L.fwi_ddpm_step(8, x, None, None, beta, abar, abar_prev, sigma, x, x, None) == -1
+    ok = L.fwi_ddpm_step(0, None, None, None, 0.1, 0.5, 0.6, 0.0, None, None, None)
+    assert ok == 0
