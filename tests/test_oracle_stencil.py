@@ -92,31 +92,6 @@ def test_laplacian_transpose_and_weighted_symmetry(orc, fs):
         assert abs(np.sum(La * b) - np.sum(a * Lb)) > 1e-6 * np.sum(np.abs(La * b))
 
 
-def test_sponge_profile(orc):
-    """Damping factor 1 in the model, quadratic-profile damping into the layer,
-    separable (product of the axis factors) in the corners, none on a
-    reflecting top."""
-    acq = fi.surface_acquisition(20, 24, ns=1, nb=10, dx=10.0, dz=5.0, nt=10, dt=1e-3)
-    a = orc.sponge(acq)
-    assert a.shape == (30, 44)
-    assert np.all(a[0:20, 10:34] == 1.0)
-    base = 3 * acq.v_max * math.log(1e3) / (2 * acq.nb)
-
-    def fac(delta, h):
-        e = base * (delta / 10) ** 2 / h * acq.dt / 2
-        return (1 - e) / (1 + e)
-
-    for ix in range(10):  # left layer, row 5: delta_x = 10 - ix
-        assert a[5, ix] == pytest.approx(fac(10 - ix, acq.dx), rel=1e-14)
-    for iz in range(20, 30):  # bottom layer, column 20: delta_z = iz - 19
-        assert a[iz, 20] == pytest.approx(fac(iz - 19, acq.dz), rel=1e-14)
-    assert a[29, 0] == pytest.approx(fac(10, acq.dz) * fac(10, acq.dx), rel=1e-14)
-    assert np.all(np.diff(a[5, :10]) > 0) and np.all(a > 0) and np.all(a <= 1)
-    acq2 = fi.surface_acquisition(20, 24, ns=1, nb=10, free_surface=False, nt=10)
-    a2 = orc.sponge(acq2)
-    assert a2.shape == (40, 44) and a2[0, 20] < 1 and a2[10, 20] == 1
-
-
 def test_sponge_absorbs(orc):
     """With the sponge the field energy left after the wave has crossed the
     model is a small fraction of that without it (reflecting edges)."""
