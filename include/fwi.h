@@ -224,6 +224,21 @@ int fwi_l2_misfit(fwi_plan* plan, int B, const float* d_syn, const float* d_obs,
 int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj_src, const float* scale,
                          float* grad, void* stream);
 
+/* Number of the forward call whose state the plan keeps for the adjoint:
+ * every fwi_forward call takes the next number (1, 2, ...), and the number is
+ * kept while the call's history is (keep_for_adjoint = 1); 0 when no history
+ * is kept.  Host-side, no device work. */
+int fwi_plan_history(const fwi_plan* plan, unsigned long long* history);
+
+/* fwi_adjoint_gradient for the forward call numbered `history` (from
+ * fwi_plan_history right after that call): FWI_ESTATE, with nothing
+ * enqueued, when a later fwi_forward has replaced that call's history.  For
+ * callers that keep several forward results alive at once (an autograd
+ * graph with two misfit evaluations on one plan before one backward pass),
+ * where the plain call would correlate with the newer history. */
+int fwi_adjoint_gradient_of(fwi_plan* plan, unsigned long long history, int B, const float* v,
+                            const float* adj_src, const float* scale, float* grad, void* stream);
+
 /* Preconditioned guidance update (Eqs. tv, rho, kappa, precond_step), per sample b:
  *   TV   = (1/(nz nx)) sum of |forward differences| of v0hat in x and z (those that exist)
  *   rho  = rho0 exp(-max(TV - tau, 0) / c)

@@ -27,6 +27,8 @@ EXPORTED = (
     "fwi_forward",
     "fwi_w2_misfit",
     "fwi_adjoint_gradient",
+    "fwi_plan_history",
+    "fwi_adjoint_gradient_of",
     "fwi_guidance_step",
     "fwi_l2_misfit",
     "fwi_tv_subgradient",
@@ -139,6 +141,8 @@ def load():
     L.fwi_forward.argtypes = [P, c_int, P, P, P, c_int, P]
     L.fwi_w2_misfit.argtypes = [P, c_int, P, P, P, P]
     L.fwi_adjoint_gradient.argtypes = [P, c_int, P, P, P, P, P]
+    L.fwi_plan_history.argtypes = [P, ctypes.POINTER(ctypes.c_ulonglong)]
+    L.fwi_adjoint_gradient_of.argtypes = [P, ctypes.c_ulonglong, c_int, P, P, P, P, P]
     L.fwi_l2_misfit.argtypes = [P, c_int, P, P, ctypes.POINTER(L2Params), P, P, P]
     L.fwi_tv_subgradient.argtypes = [c_int, c_int, c_int, P, P, c_double, P, P]
     L.fwi_ddpm_step.argtypes = [ctypes.c_long, P, P, P, c_double, c_double, c_double, c_double, P, P, P]

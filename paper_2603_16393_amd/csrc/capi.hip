@@ -478,6 +478,8 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
     int rc = launch_prep_velocity(p, B, v, st);
     if (rc) return rc;
     p.stored_B = 0;
+    p.history = 0;
+    const unsigned long long call = ++p.n_forward;
     if (keep_for_adjoint) {
         rc = launch_copy(p.wav, wavelet, (size_t)p.g.nt, st);
         if (rc) return rc;
@@ -496,6 +498,7 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
         ++p.n_fwd_rec;
     }
     p.stored_B = keep_for_adjoint ? B : 0;
+    p.history = keep_for_adjoint ? call : 0;
     return FWI_OK;
 }
 
@@ -533,6 +536,19 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
         ++p.n_adj_rec;
     }
     return launch_fold_gradient(p, B, scale, grad, st);
+}
+
+int fwi_plan_history(const fwi_plan* plan, unsigned long long* history) {
+    if (!plan || !history) return FWI_EINVAL;
+    *history = plan->history;
+    return FWI_OK;
+}
+
+int fwi_adjoint_gradient_of(fwi_plan* plan, unsigned long long history, int B, const float* v, const float* adj_src,
+                            const float* scale, float* grad, void* stream) {
+    if (!plan) return FWI_EINVAL;
+    if (history == 0 || plan->history != history) return FWI_ESTATE;
+    return fwi_adjoint_gradient(plan, B, v, adj_src, scale, grad, stream);
 }
 
 int fwi_l2_misfit(fwi_plan* plan, int B, const float* d_syn, const float* d_obs, const fwi_l2_params* params,

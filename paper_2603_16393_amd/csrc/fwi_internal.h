@@ -251,6 +251,8 @@ struct Plan {
     int qobs_cap = 0;            // n_xi capacity of qobs
 
     int stored_B = 0;            // batch of the forward state kept for the adjoint (0 = none)
+    unsigned long long n_forward = 0;  // forward calls so far (each gets the next number)
+    unsigned long long history = 0;    // number of the forward call whose state is kept (0 = none)
 
     // tiled path: sweeps captured as graphs on a private stream, replayed on the caller's
     hipStream_t cap = nullptr;

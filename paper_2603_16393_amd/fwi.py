@@ -141,8 +141,16 @@ class FwiPlan:
                                         _stream()), "fwi_l2_misfit")
         return J, adj
 
+    def history(self) -> int:
+        """Number of the forward call whose history the plan keeps (0 = none)."""
+        h = ctypes.c_ulonglong()
+        check(_lib.load().fwi_plan_history(self._h, ctypes.byref(h)), "fwi_plan_history")
+        return h.value
+
     def adjoint_gradient(self, v: torch.Tensor, adj: torch.Tensor, scale: Optional[torch.Tensor] = None,
-                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                         out: Optional[torch.Tensor] = None, history: Optional[int] = None) -> torch.Tensor:
+        """dJ/dv for the kept forward history; with `history` (from history() after that forward call) the call
+        fails with FWI_ESTATE if a later forward call has replaced it."""
         B = v.shape[0]
         _need(v, "v", (B, self.nz, self.nx), device=self.device)
         _need(adj, "adj", (B, self.ns, self.nr, self.nt), device=self.device)
@@ -151,8 +159,12 @@ class FwiPlan:
         if out is None:
             out = torch.empty((B, self.nz, self.nx), dtype=torch.float32, device=self.device)
         _need(out, "out", (B, self.nz, self.nx), device=self.device)
-        check(_lib.load().fwi_adjoint_gradient(self._h, B, _ptr(v), _ptr(adj), _ptr(scale), _ptr(out), _stream()),
-              "fwi_adjoint_gradient")
+        if history is None:
+            check(_lib.load().fwi_adjoint_gradient(self._h, B, _ptr(v), _ptr(adj), _ptr(scale), _ptr(out),
+                                                   _stream()), "fwi_adjoint_gradient")
+        else:
+            check(_lib.load().fwi_adjoint_gradient_of(self._h, int(history), B, _ptr(v), _ptr(adj), _ptr(scale),
+                                                      _ptr(out), _stream()), "fwi_adjoint_gradient_of")
         return out
 
     def sweep_ms(self):
@@ -178,6 +190,7 @@ class FwiW2Loss(torch.autograd.Function):
         d = plan.forward(v, wavelet, keep_for_adjoint=True)
         J, adj = plan.w2_misfit(d, want_adjoint=True)
         ctx.plan = plan
+        ctx.history = plan.history()
         ctx.save_for_backward(v, adj)
         return J
 
@@ -185,7 +198,8 @@ class FwiW2Loss(torch.autograd.Function):
     def backward(ctx, gJ):
         v, adj = ctx.saved_tensors
         scale = gJ.detach().to(torch.float32).contiguous()
-        g = ctx.plan.adjoint_gradient(v, adj, scale=scale)
+        # raises FwiError (FWI_ESTATE) if another forward call on the plan replaced this one's history
+        g = ctx.plan.adjoint_gradient(v, adj, scale=scale, history=ctx.history)
         return g, None, None
 
 

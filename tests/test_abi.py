@@ -163,3 +163,13 @@ def test_ddpm_step_validation(beta, abar, abar_prev, sigma):
     assert L.fwi_ddpm_step(8, x, None, None, beta, abar, abar_prev, sigma, x, x, None) == -1
     ok = L.fwi_ddpm_step(0, None, None, None, 0.1, 0.5, 0.6, 0.0, None, None, None)
     assert ok == 0
+
+
+def test_history_entry_points_validate_on_the_host():
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    h = ctypes.c_ulonglong(7)
+    assert L.fwi_plan_history(None, ctypes.byref(h)) == _lib.FWI_EINVAL
+    assert L.fwi_adjoint_gradient_of(None, 1, 1, None, None, None, None, None) == _lib.FWI_EINVAL
+

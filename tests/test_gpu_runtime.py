@@ -67,3 +67,43 @@ def test_sweep_timing(dev):
     assert e.value.code == _lib.FWI_ESTATE
     plan.close()
     plain.close()
+
+
+def test_adjoint_refuses_a_replaced_forward_history(dev):
+    """Two misfit evaluations on one plan before one backward pass: the first one's history has been replaced,
+    so its backward raises FWI_ESTATE instead of correlating with the second model's wavefields; in order
+    (forward, backward, forward, backward) both gradients equal the plain calls'."""
+    import fwi_inputs as fi
+    from paper_2603_16393_amd import FwiPlan, FwiW2Loss, _lib
+
+    acq = fi.surface_acquisition(40, 48, ns=2, nt=300, nb=12)
+    w = torch.tensor(fi.ricker(acq.nt, acq.dt, acq.f_peak), dtype=torch.float32, device=dev)
+    plan = FwiPlan(acq, max_batch=2, device=dev)
+    vt = torch.tensor(fi.faulted_model(40, 48, 1000)[None], dtype=torch.float32, device=dev)
+    plan.set_obs(plan.forward(vt, w, keep_for_adjoint=False)[0].contiguous())
+    assert plan.history() == 0
+    v1 = torch.tensor(np.stack([fi.faulted_model(40, 48, s) for s in (1, 2)]), dtype=torch.float32, device=dev)
+    v2 = (v1 * 1.03).contiguous()
+    a = v1.clone().requires_grad_(True)
+    b = v2.clone().requires_grad_(True)
+    J1 = FwiW2Loss.apply(a, plan, w)
+    h1 = plan.history()
+    J2 = FwiW2Loss.apply(b, plan, w)
+    assert plan.history() == h1 + 1
+    with pytest.raises(_lib.FwiError) as e:
+        (J1.sum() + J2.sum()).backward()
+    assert e.value.code == _lib.FWI_ESTATE
+    # in order: each backward right after its forward
+    ga = []
+    for v in (v1, v2):
+        x = v.clone().requires_grad_(True)
+        FwiW2Loss.apply(x, plan, w).sum().backward()
+        ga.append(x.grad.clone())
+    for v, g in zip((v1, v2), ga):
+        d = plan.forward(v, w)
+        _, adj = plan.w2_misfit(d)
+        assert torch.equal(plan.adjoint_gradient(v, adj), g)
+    plan.forward(v1, w, keep_for_adjoint=False)
+    assert plan.history() == 0
+    torch.cuda.synchronize()
+    plan.close()
