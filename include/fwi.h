@@ -201,6 +201,24 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
  *   adj_src  [B][ns][nr][nt] output dJ/dd_syn, or NULL to skip the adjoint. */
 int fwi_w2_misfit(fwi_plan* plan, int B, const float* d_syn, double* J, float* adj_src, void* stream);
 
+/* Largest B * ns * nr that fwi_w2_misfit_noalloc accepts (2 MiB of FP64
+ * per-pair terms per GPU). */
+#define FWI_W2_SCRATCH_PAIRS 262144
+
+/* fwi_w2_misfit that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results
+ * (bit for bit) as fwi_w2_misfit; the per-pair W2 terms go to a fixed
+ * device array of FWI_W2_SCRATCH_PAIRS doubles that the library holds once
+ * per GPU until the process ends, instead of the plan's workspace.  The
+ * array's address is looked up on the first call on each device; no call
+ * allocates or frees memory.  Every call on a GPU reuses that GPU's array
+ * (each term is written before it is read, so nothing carries over), so
+ * calls that overlap on one GPU, e.g. on two streams, race and must be
+ * ordered by the caller.  FWI_ENOMEM when B * ns * nr > FWI_W2_SCRATCH_PAIRS;
+ * otherwise the errors of fwi_w2_misfit. */
+int fwi_w2_misfit_noalloc(fwi_plan* plan, int B, const float* d_syn, double* J, float* adj_src, void* stream);
+
 /* Least-squares misfit and its adjoint source (fwi_l2_params), per sample b:
  *   J[b]        = (1/2) sum (w (d_syn[b] - d_obs))^2 / S
  *   adj_src[b]  = dJ[b]/dd_syn[b] = w^2 (d_syn[b] - d_obs) / S

@@ -16,6 +16,7 @@ c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_si
 c_int_p = ctypes.POINTER(ctypes.c_int)
 
 FWI_OK, FWI_EINVAL, FWI_ECFL, FWI_ENOMEM, FWI_EHIP, FWI_ESTATE, FWI_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+FWI_W2_SCRATCH_PAIRS = 262144  # include/fwi.h
 
 # Every symbol include/fwi.h declares.
 EXPORTED = (
@@ -26,6 +27,7 @@ EXPORTED = (
     "fwi_set_obs",
     "fwi_forward",
     "fwi_w2_misfit",
+    "fwi_w2_misfit_noalloc",
     "fwi_adjoint_gradient",
     "fwi_plan_history",
     "fwi_adjoint_gradient_of",
@@ -140,6 +142,7 @@ def load():
     L.fwi_set_obs.argtypes = [P, P, ctypes.POINTER(W2Params), P]
     L.fwi_forward.argtypes = [P, c_int, P, P, P, c_int, P]
     L.fwi_w2_misfit.argtypes = [P, c_int, P, P, P, P]
+    L.fwi_w2_misfit_noalloc.argtypes = [P, c_int, P, P, P, P]
     L.fwi_adjoint_gradient.argtypes = [P, c_int, P, P, P, P, P]
     L.fwi_plan_history.argtypes = [P, ctypes.POINTER(ctypes.c_ulonglong)]
     L.fwi_adjoint_gradient_of.argtypes = [P, ctypes.c_ulonglong, c_int, P, P, P, P, P]

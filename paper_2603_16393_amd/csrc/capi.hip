@@ -511,6 +511,16 @@ int fwi_w2_misfit(fwi_plan* plan, int B, const float* d_syn, double* J, float* a
     return launch_w2_misfit(*plan, B, d_syn, J, adj_src, as_stream(stream));
 }
 
+int fwi_w2_misfit_noalloc(fwi_plan* plan, int B, const float* d_syn, double* J, float* adj_src, void* stream) {
+    if (!plan || B < 0 || B > plan->max_batch) return FWI_EINVAL;
+    if (B == 0) return FWI_OK;
+    if (!d_syn || !J) return FWI_EINVAL;
+    if ((long long)B * plan->g.ns * plan->g.nr > FWI_W2_SCRATCH_PAIRS) return FWI_ENOMEM;
+    if (!plan->have_obs) return FWI_ESTATE;
+    (void)hipSetDevice(plan->device);
+    return launch_w2_misfit_noalloc(*plan, B, d_syn, J, adj_src, as_stream(stream));
+}
+
 int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj_src, const float* scale, float* grad,
                          void* stream) {
     if (!plan || B < 0 || B > plan->max_batch) return FWI_EINVAL;
@@ -639,7 +649,7 @@ const char* fwi_error_string(int code) {
         case FWI_OK: return "ok";
         case FWI_EINVAL: return "invalid argument";
         case FWI_ECFL: return "CFL condition violated for the declared v_max";
-        case FWI_ENOMEM: return "out of device memory or memory budget";
+        case FWI_ENOMEM: return "out of device memory, memory budget or fixed scratch capacity";
         case FWI_EHIP: return "HIP runtime error";
         case FWI_ESTATE: return "call out of order (observations or forward state missing)";
         case FWI_EDEVICE: return "device-side check failed (velocity not finite, <= 0 or > v_max)";

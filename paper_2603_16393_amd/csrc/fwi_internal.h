@@ -320,6 +320,7 @@ int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
 int launch_w2_obs(Plan& p, const float* d_obs, hipStream_t st);
 int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st);
+int launch_w2_misfit_noalloc(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st);
 int launch_l2_misfit(const Plan& p, int B, const float* d_syn, const float* d_obs, const fwi_l2_params& lp, double* J,
                      float* adj, hipStream_t st);
 int launch_tv_subgradient(int B, int nz, int nx, const float* v, const float* g, double alpha, float* out,

@@ -19,6 +19,7 @@
 // reproducible run to run.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "fwi_internal.h"
 
@@ -347,16 +348,63 @@ __global__ __launch_bounds__(W2T) void k_sum_pairs(const double* __restrict__ jp
     if (threadIdx.x == 0) J[b] = s;
 }
 
-int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st) {
+static int launch_w2_misfit_into(const Plan& p, int B, const float* d_syn, double* J, float* adj, double* pairs,
+                                 hipStream_t st) {
     const int ntr = p.g.ns * p.g.nr;
     const int nt = p.g.nt;
     const int nxi = p.w2p.n_xi;
     const size_t bytes = w2_lds_bytes(nt, nxi);
     hipFuncSetAttribute((const void*)k_w2_misfit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL(k_w2_misfit, dim3(B * ntr), dim3(W2T), bytes, st, ntr, nt, nxi, p.g.dt, d_syn, p.omega,
-                       p.cprime, p.qobs, p.sobs, p.w2p.eps_prime, p.w2p.squared, p.w2p.reduction, p.w2pair, adj);
-    hipLaunchKernelGGL(k_sum_pairs, dim3(B), dim3(W2T), 0, st, p.w2pair, ntr, J);
+                       p.cprime, p.qobs, p.sobs, p.w2p.eps_prime, p.w2p.squared, p.w2p.reduction, pairs, adj);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(B), dim3(W2T), 0, st, pairs, ntr, J);
     return hip_ok(hipGetLastError());
+}
+
+int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st) {
+    return launch_w2_misfit_into(p, B, d_syn, J, adj, p.w2pair, st);
+}
+
+// Per-pair terms of the allocation-free entry point (fwi_w2_misfit_noalloc):
+// a fixed array in device memory instead of the plan's workspace.  Every GPU
+// the library runs on holds its own copy until the process ends, and every
+// call on that GPU reuses it.  k_w2_misfit writes each pair's term before
+// k_sum_pairs reads it, so nothing has to be cleared between calls; two calls
+// that overlap on one GPU (different streams) race on it.
+static __device__ __align__(256) double w2_scratch[FWI_W2_SCRATCH_PAIRS];
+
+// Device address of w2_scratch on each device, looked up once per device with
+// that device current (the array's host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+static int scratch_address(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return FWI_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return FWI_EHIP;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return FWI_EHIP;
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(w2_scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return FWI_EHIP;
+        }
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return FWI_OK;
+}
+
+int launch_w2_misfit_noalloc(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st) {
+    if ((long long)B * p.g.ns * p.g.nr > FWI_W2_SCRATCH_PAIRS) return FWI_ENOMEM;
+    double* pairs = nullptr;
+    const int rc = scratch_address(p.device, &pairs);
+    if (rc) return rc;
+    return launch_w2_misfit_into(p, B, d_syn, J, adj, pairs, st);
 }
 
 size_t w2_lds_requirement(int nt, int nxi) { return w2_lds_bytes(nt, nxi); }

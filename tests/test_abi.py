@@ -173,3 +173,12 @@ def test_history_entry_points_validate_on_the_host():
     assert L.fwi_plan_history(None, ctypes.byref(h)) == _lib.FWI_EINVAL
     assert L.fwi_adjoint_gradient_of(None, 1, 1, None, None, None, None, None) == _lib.FWI_EINVAL
 
+
+def test_noalloc_capacity_matches_the_header():
+    from paper_2603_16393_amd import _lib
+
+    txt = open(os.path.join(ROOT, "include", "fwi.h")).read()
+    m = re.search(r"#define FWI_W2_SCRATCH_PAIRS (\d+)", txt)
+    assert m and int(m.group(1)) == _lib.FWI_W2_SCRATCH_PAIRS
+    L = _lib.load()
+    assert L.fwi_w2_misfit_noalloc(None, 1, None, None, None, None) == _lib.FWI_EINVAL
