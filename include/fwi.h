@@ -432,6 +432,77 @@ int fwi_mf_predict(int B, int n, const float* g_anchor, const float* s_now, cons
                    const double* J_anchor, const double* Js_now, const double* Js_anchor, double* J_out,
                    void* stream);
 
+/* ---- score network of the reverse-diffusion loop (Algorithm 2) ----------
+ *
+ * A noise-prediction network eps_theta(x, t) for the 70 x 70 diffusion state
+ * (the score model of Sec. 3 in the form s = -eps / sqrt(1 - abar_i),
+ * trained by denoising score matching, Eq. L2_rewrite with the weight
+ * 1 - abar), its vector-Jacobian product and an Adam step, on the BF16
+ * matrix cores (FP32 accumulation):
+ *   time embedding (FP32): e = [sin(1000 t f_k), cos(1000 t f_k)],
+ *     f_k = 10000^(-k/16), k < 16; tb = W_t2^T gelu(W_t1^T e + b_t1) + b_t2
+ *     (320 per-channel biases of the five blocks, in their order);
+ *   lift: 32 channels on a 72 x 72 grid holding x in rows/columns 1..70 (zero
+ *     ring): h = W_l^T [x, (i - 35.5)/36, (j - 35.5)/36] + b_l;
+ *   block(C): p = conv3(h; W1) + b1 + tb, q = gelu(p),
+ *     h' = h + conv3(q; W2) + b2 (3 x 3, zero padding; W [9 C][C], row
+ *     (3 dy + dx) C + c_in holds the tap at offset (dy - 1, dx - 1));
+ *   U-Net: block b0a (C 32, 72^2); 2 x 2 mean, 1 x 1 32 -> 64; b1a (64, 36^2);
+ *     mean, 1 x 1 64 -> 128; b2 (128, 18^2); 1 x 1 128 -> 64, nearest x 2,
+ *     + b1a output; b1b (64); 1 x 1 64 -> 32, nearest x 2, + b0a output;
+ *     b0b (32); head eps = w_h . h + b_h on rows/columns 1..70;
+ *   output map: out = skip_b x + scale_b eps per sample (skip, scale NULL:
+ *     0 and 1).  skip = 0, scale = -1/sqrt(1 - abar) gives the score;
+ *     skip = 1/sqrt(abar), scale = -sqrt(1 - abar)/sqrt(abar) gives the
+ *     clean estimate v0hat of Eq. v0hat.
+ * Activations and GEMM weights are BF16, FP32 elsewhere.  Parameters are one
+ * FP32 vector of fwi_score_param_count() entries: temb_w1 [32][128], temb_b1,
+ * temb_w2 [128][320], temb_b2, lift_w [3][32], lift_b, then per block
+ * W1, b1, W2, b2 with the 1 x 1 maps between them (b0a, down0 [32][64] + b,
+ * b1a, down1 [64][128] + b, b2, up1 [128][64] + b, b1b, up0 [64][32] + b,
+ * b0b), head_w [32], head_b [1]. */
+typedef struct fwi_score_net fwi_score_net;
+
+typedef struct {
+    float lr, beta1, beta2, eps; /* Adam */
+} fwi_score_train_params;
+
+long fwi_score_param_count(void);
+/* max_batch in [1, 256]; parameters start at zero (set them before use). */
+int fwi_score_create(int max_batch, fwi_score_net** net);
+int fwi_score_destroy(fwi_score_net* net);
+/* Synchronous host <-> device copies of the FP32 parameter vector; set also
+ * refreshes the BF16 copies and resets the Adam state (moments and step). */
+int fwi_score_set_params(fwi_score_net* net, const float* host_params);
+int fwi_score_get_params(fwi_score_net* net, float* host_params);
+/* Parameter gradient of the last fwi_score_backward(want_weight_grads = 1)
+ * or training step (synchronous). */
+int fwi_score_get_grads(fwi_score_net* net, float* host_grads);
+/* Adam moments and step count (synchronous): with the parameters, the state
+ * a resumed training run needs. */
+int fwi_score_get_adam(fwi_score_net* net, float* host_m, float* host_v, int* step);
+int fwi_score_set_adam(fwi_score_net* net, const float* host_m, const float* host_v, int step);
+/* out = skip_b x + scale_b eps_theta(x, t_b) for B <= max_batch states
+ * x [B][70][70] at conditioning times tcond [B] (t = i / N for step i of N);
+ * skip, scale [B] or NULL.  Keeps the activations for fwi_score_backward
+ * (asynchronous). */
+int fwi_score_forward(fwi_score_net* net, int B, const float* x, const float* tcond, const float* skip,
+                      const float* scale, float* out, void* stream);
+/* Vector-Jacobian product of the last fwi_score_forward (same B, else
+ * FWI_ESTATE): dx = (d out / d x)^T dout (dx may be NULL), and with
+ * want_weight_grads the parameter gradient.  For the clean estimate this is
+ * the chain rule of Eq. chain_rule, h = (d v0hat / d x_i)^T g (asynchronous). */
+int fwi_score_backward(fwi_score_net* net, int B, const float* dout, float* dx, int want_weight_grads,
+                       void* stream);
+/* One denoising score-matching step: x_t = sqrt_abar_b x0 + sqrt_1m_abar_b noise,
+ * L = mean over samples and nodes of (eps_theta(x_t, tcond_b) - noise)^2, its
+ * parameter gradient and one Adam update.  x0, noise [B][70][70]; tcond,
+ * sqrt_abar, sqrt_1m_abar [B]; loss_out (device float, may be NULL) receives
+ * L before the update (asynchronous). */
+int fwi_score_train_step(fwi_score_net* net, int B, const float* x0, const float* noise, const float* tcond,
+                         const float* sqrt_abar, const float* sqrt_1m_abar, const fwi_score_train_params* params,
+                         float* loss_out, void* stream);
+
 /* Mean device time, in ms, of the forward sweeps (the nt - 1 time steps of
  * fwi_forward, without the velocity preparation) and of the adjoint sweeps
  * (of fwi_adjoint_gradient, without the gradient fold) enqueued since the

@@ -64,6 +64,17 @@ EXPORTED = (
     "fwi_sur_train_step",
     "fwi_judge",
     "fwi_mf_predict",
+    "fwi_score_param_count",
+    "fwi_score_create",
+    "fwi_score_destroy",
+    "fwi_score_set_params",
+    "fwi_score_get_params",
+    "fwi_score_get_grads",
+    "fwi_score_get_adam",
+    "fwi_score_set_adam",
+    "fwi_score_forward",
+    "fwi_score_backward",
+    "fwi_score_train_step",
 )
 
 
@@ -113,6 +124,10 @@ class BatchRequestInfo(ctypes.Structure):
 class SurTrainParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("loss_k", ctypes.c_float), ("pair_weight", ctypes.c_float)]
+
+
+class ScoreTrainParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class FwiError(RuntimeError):
@@ -182,10 +197,22 @@ def load():
     L.fwi_sur_train_step.argtypes = [P, c_int, P, P, ctypes.POINTER(SurTrainParams), P, P]
     L.fwi_judge.argtypes = [c_int, c_int, P, P, P, P, P, P, P]
     L.fwi_mf_predict.argtypes = [c_int, c_int, P, P, P, P, P, P, P, P, P]
+    L.fwi_score_param_count.argtypes = []
+    L.fwi_score_create.argtypes = [c_int, ctypes.POINTER(P)]
+    L.fwi_score_destroy.argtypes = [P]
+    L.fwi_score_set_params.argtypes = [P, P]
+    L.fwi_score_get_params.argtypes = [P, P]
+    L.fwi_score_get_grads.argtypes = [P, P]
+    L.fwi_score_get_adam.argtypes = [P, P, P, ctypes.POINTER(c_int)]
+    L.fwi_score_set_adam.argtypes = [P, P, P, c_int]
+    L.fwi_score_forward.argtypes = [P, c_int, P, P, P, P, P, P]
+    L.fwi_score_backward.argtypes = [P, c_int, P, P, c_int, P]
+    L.fwi_score_train_step.argtypes = [P, c_int, P, P, P, P, P, ctypes.POINTER(ScoreTrainParams), P, P]
     for name in EXPORTED:
         if name != "fwi_error_string":
             getattr(L, name).restype = c_int
     L.fwi_sur_param_count.restype = cl
+    L.fwi_score_param_count.restype = cl
     _lib = L
     return _lib
 
