@@ -31,6 +31,7 @@ __all__ = [
     "large_lens_model",
     "smooth_noise",
     "to_normalised",
+    "prior_model",
     "from_normalised",
     "V_LO",
     "V_HI",
@@ -250,6 +251,15 @@ def stand_in_zeta(nz: int, nx: int, sample: int) -> np.ndarray:
     """Per-sample smooth perturbation of the stand-in estimates: white noise
     smoothed by a 3-cell Gaussian, std 600 m/s (seed 7000 + sample)."""
     return smooth_noise(nz, nx, 7000 + sample, sigma_cells=3.0, std=600.0)
+
+
+def prior_model(seed: int, nz: int = 70, nx: int = 70) -> np.ndarray:
+    """One draw from the stand-in prior the score network learns: a faulted
+    model of dipping layers (even seeds) or flat layers with 2-5 layers and
+    interfaces in rows 5..64 (odd seeds), 1500-4500 m/s increasing with depth."""
+    if seed % 2 == 0:
+        return faulted_model(nz, nx, seed)
+    return layered_model(nz, nx, seed, n_layers=2 + (seed // 2) % 4, depth_range=(5, min(64, nz - 1)))
 
 
 def surrogate_training_pair(seed: int, nz: int = 70, nx: int = 70):

@@ -386,6 +386,10 @@ int fwi_sur_get_params(fwi_surrogate* s, float* host_params);
 /* Weight gradients of the last fwi_sur_backward(want_weight_grads = 1) or
  * training step (synchronous). */
 int fwi_sur_get_grads(fwi_surrogate* s, float* host_grads);
+/* Adam moments and step count (synchronous): with the parameters, the state
+ * a resumed training run needs. */
+int fwi_sur_get_adam(fwi_surrogate* s, float* host_m, float* host_v, int* step);
+int fwi_sur_set_adam(fwi_surrogate* s, const float* host_m, const float* host_v, int step);
 /* fused = 1 (the default): each block's pointwise MLP runs as one kernel
  * (fwi_nn_mlp_forward / fwi_nn_mlp_vjp) and the forward keeps no 128-wide
  * hidden activations (a backward with want_weight_grads recomputes them); an

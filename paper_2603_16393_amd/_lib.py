@@ -58,6 +58,8 @@ EXPORTED = (
     "fwi_sur_set_params",
     "fwi_sur_get_params",
     "fwi_sur_get_grads",
+    "fwi_sur_get_adam",
+    "fwi_sur_set_adam",
     "fwi_sur_set_fused_mlp",
     "fwi_sur_forward",
     "fwi_sur_backward",
@@ -192,6 +194,8 @@ def load():
     L.fwi_sur_set_params.argtypes = [P, P]
     L.fwi_sur_get_params.argtypes = [P, P]
     L.fwi_sur_get_grads.argtypes = [P, P]
+    L.fwi_sur_get_adam.argtypes = [P, P, P, ctypes.POINTER(c_int)]
+    L.fwi_sur_set_adam.argtypes = [P, P, P, c_int]
     L.fwi_sur_forward.argtypes = [P, c_int, P, P, P]
     L.fwi_sur_backward.argtypes = [P, c_int, P, P, c_int, P]
     L.fwi_sur_train_step.argtypes = [P, c_int, P, P, ctypes.POINTER(SurTrainParams), P, P]

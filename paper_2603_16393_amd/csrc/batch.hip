@@ -738,17 +738,35 @@ void bfree(fwi_batch* b) {
     b->allocs.clear();
 }
 
+static bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// The persistent kernels run one workgroup per CU at most (grid <= CUs, and
+// their LDS allows one per CU).  Row parts of a field wait for each other at
+// a per-step barrier, which needs every workgroup resident: outside graph
+// capture the launch is cooperative, which guarantees that; a cooperative
+// launch cannot be captured, so under capture it is a plain launch, and a
+// wait that outlasts its bounded spin raises the batch flag instead of hanging.
 int launch_units(BatchUnit* d_units, int nunits, int* counter, int grid, size_t lds, float* traces,
                  const float* wavelets, hipStream_t st, const float* adj = nullptr, bool gradient = false) {
     hipLaunchKernelGGL(k_batch_bind, dim3((nunits + 255) / 256), dim3(256), 0, st, d_units, nunits, traces, wavelets,
                        adj);
-    if (gradient) {
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-        hipLaunchKernelGGL(k_batch_gradient, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
-        return hip_ok(hipGetLastError());
-    }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-    hipLaunchKernelGGL(k_batch_forward, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
+    const void* kern = gradient ? (const void*)k_batch_gradient : (const void*)k_batch_forward;
+    if (!stream_capturing(st)) {
+        void* args[] = {(void*)&d_units, (void*)&nunits, (void*)&counter};
+        return hip_ok(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kLdsThreads), args, (unsigned)lds, st));
+    }
+    if (gradient)
+        hipLaunchKernelGGL(k_batch_gradient, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
+    else
+        hipLaunchKernelGGL(k_batch_forward, dim3(grid), dim3(kLdsThreads), lds, st, d_units, nunits, counter);
     return hip_ok(hipGetLastError());
 }
 

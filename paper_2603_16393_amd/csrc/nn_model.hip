@@ -411,6 +411,25 @@ static int copy_out(fwi_surrogate* s, const float* src, float* host) {
 int fwi_sur_get_params(fwi_surrogate* s, float* host) { return copy_out(s, s ? s->P : nullptr, host); }
 int fwi_sur_get_grads(fwi_surrogate* s, float* host) { return copy_out(s, s ? s->G : nullptr, host); }
 
+int fwi_sur_get_adam(fwi_surrogate* s, float* host_m, float* host_v, int* step) {
+    if (!s || !host_m || !host_v || !step) return FWI_EINVAL;
+    int rc = copy_out(s, s->Am, host_m);
+    if (rc == FWI_OK) rc = copy_out(s, s->Av, host_v);
+    *step = s->step;
+    return rc;
+}
+
+int fwi_sur_set_adam(fwi_surrogate* s, const float* host_m, const float* host_v, int step) {
+    if (!s || !host_m || !host_v || step < 0) return FWI_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess) return FWI_EHIP;
+    const size_t pb = (size_t)s->L.total * sizeof(float);
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(s->Am, host_m, pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->Av, host_v, pb, hipMemcpyHostToDevice) != hipSuccess)
+        return FWI_EHIP;
+    s->step = step;
+    return hipDeviceSynchronize() == hipSuccess ? FWI_OK : FWI_EHIP;
+}
+
 int fwi_sur_set_fused_mlp(fwi_surrogate* s, int fused) {
     if (!s || (fused != 0 && fused != 1)) return FWI_EINVAL;
     s->fused = fused == 1;

@@ -141,6 +141,23 @@ class Surrogate:
         check(_lib.load().fwi_sur_get_grads(self._h, out.ctypes.data_as(ctypes.c_void_p)), "fwi_sur_get_grads")
         return out
 
+    def get_adam(self):
+        """(m, v, step) of the Adam optimiser."""
+        m = np.empty(self.n_params, np.float32)
+        v = np.empty(self.n_params, np.float32)
+        step = ctypes.c_int()
+        check(_lib.load().fwi_sur_get_adam(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                           v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(step)), "fwi_sur_get_adam")
+        return m, v, step.value
+
+    def set_adam(self, m: np.ndarray, v: np.ndarray, step: int) -> None:
+        m = np.ascontiguousarray(m, np.float32)
+        v = np.ascontiguousarray(v, np.float32)
+        if m.shape != (self.n_params,) or v.shape != (self.n_params,):
+            raise ValueError("Adam moments of the wrong size")
+        check(_lib.load().fwi_sur_set_adam(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                           v.ctypes.data_as(ctypes.c_void_p), int(step)), "fwi_sur_set_adam")
+
     # compute ------------------------------------------------------------
     def forward(self, v: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         B = v.shape[0]

@@ -1,6 +1,7 @@
 """Train the trace surrogate on pairs the wave solver generates.
 
-    python -m paper_2603_16393_amd.train_surrogate --pairs 32768 --epochs 8 --out weights.npy
+    python -m paper_2603_16393_amd.train_surrogate --pairs 50000 --epochs 8 --out weights.npy \\
+        [--ckpt ckpt.npz [--resume]]
 
 Inputs are seeded synthetic models (fwi_inputs.surrogate_training_pair):
 each pair is a model v and a smooth perturbation v + delta.  The solver
@@ -17,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import math
+import os
 import sys
 import time
 
@@ -29,7 +31,7 @@ def log(*a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--pairs", type=int, default=32768)
+    ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch-pairs", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -38,6 +40,10 @@ def main(argv=None):
     ap.add_argument("--pair-scale", type=float, default=1.0, help="pair weight relative to (rms d / rms delta d)^2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--ckpt", default=None, help="checkpoint written after every epoch (parameters, Adam state, "
+                                                 "step, epoch, the batch-order generator's state)")
+    ap.add_argument("--resume", action="store_true", help="continue from --ckpt")
+    ap.add_argument("--stop-after-epoch", type=int, default=None)
     args = ap.parse_args(argv)
 
     import torch
@@ -87,8 +93,16 @@ def main(argv=None):
     gen.manual_seed(args.seed)
     loss = torch.zeros(1, device=dev)
     step = 0
+    ep0 = 0
+    if args.resume and args.ckpt and os.path.exists(args.ckpt):
+        ck = np.load(args.ckpt)
+        sur.set_params(ck["params"])
+        sur.set_adam(ck["adam_m"], ck["adam_v"], int(ck["adam_step"]))
+        step, ep0 = int(ck["step"]), int(ck["epoch"])
+        gen.set_state(torch.from_numpy(ck["gen_state"]))
+        log(f"resumed after epoch {ep0} (step {step})")
     t0 = time.time()
-    for ep in range(args.epochs):
+    for ep in range(ep0, args.epochs):
         perm = torch.randperm(n_tr, device=dev, generator=gen)
         acc = torch.zeros(1, device=dev)
         for j in range(steps_per_epoch):
@@ -102,6 +116,15 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"epoch {ep + 1}/{args.epochs}: loss / rms^2 {acc.item() / steps_per_epoch / rms ** 2:.4f} "
             f"({time.time() - t0:.0f} s)")
+        if args.ckpt:
+            m, v, astep = sur.get_adam()
+            tmp = args.ckpt + ".tmp.npz"
+            np.savez(tmp, params=sur.get_params(), adam_m=m, adam_v=v, adam_step=np.int64(astep),
+                     step=np.int64(step), epoch=np.int64(ep + 1), gen_state=gen.get_state().numpy())
+            os.replace(tmp, args.ckpt)
+        if args.stop_after_epoch is not None and ep + 1 >= args.stop_after_epoch:
+            log(f"stopped after epoch {ep + 1}")
+            return 0
     # held-out pairs: trace error and finite-difference error
     te, de = [], []
     for i in range(n_tr, n, bp):

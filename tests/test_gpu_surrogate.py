@@ -212,3 +212,33 @@ def test_argument_errors(dev, case):
     rc = L.fwi_sur_train_step(sur._h, 2, ctypes.c_void_p(vt.data_ptr()), ctypes.c_void_p(tgt.data_ptr()),
                               ctypes.byref(tp), None, None)
     assert rc == _lib.FWI_EINVAL
+
+
+def test_resumed_training_equals_uninterrupted(dev):
+    """Parameters plus Adam moments and step (fwi_sur_get_adam / fwi_sur_set_adam) are the whole optimiser state:
+    a run continued from them equals the uninterrupted run bit for bit."""
+    import fwi_inputs as fi
+    from paper_2603_16393_amd.surrogate import Surrogate, init_params
+
+    rng = np.random.default_rng(41)
+    p0 = init_params(5, out_scale=0.05)
+    batches = [(torch.tensor(np.stack([fi.faulted_model(70, 70, 200 + 2 * k + s) for s in range(2)]),
+                             dtype=torch.float32, device=dev),
+                torch.tensor(rng.standard_normal((2, 5, 70, 1000)).astype(np.float32) * 1e-3, device=dev))
+               for k in range(4)]
+    a = Surrogate(max_batch=2, device=dev)
+    a.set_params(p0)
+    for v, t in batches[:2]:
+        a.train_step(v, t, lr=1e-3, loss_k=20.0)
+    saved = (a.get_params(), *a.get_adam())
+    for v, t in batches[2:]:
+        a.train_step(v, t, lr=1e-3, loss_k=20.0)
+    b = Surrogate(max_batch=2, device=dev)
+    b.set_params(saved[0])
+    b.set_adam(saved[1], saved[2], saved[3])
+    assert saved[3] == 2
+    for v, t in batches[2:]:
+        b.train_step(v, t, lr=1e-3, loss_k=20.0)
+    assert np.array_equal(a.get_params(), b.get_params())
+    a.close()
+    b.close()
