@@ -228,7 +228,7 @@ SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surro
 GUIDED_STEPS = 200
 
 
-def guided_run(plan, wt, v_true, sur, predictor, steps=GUIDED_STEPS, record=False):
+def guided_run(plan, wt, v_true, sur, predictor, steps=GUIDED_STEPS, record=False, cos_min=0.95):
     """16 samples x `steps` reverse steps, t from 1 down to 0.005; the clean
     estimates come from the stand-in denoiser v0hat = clip(v_true + t zeta_b).
     Each step: guidance gradient (solver, or judged prediction above t = 0.5)
@@ -244,7 +244,7 @@ def guided_run(plan, wt, v_true, sur, predictor, steps=GUIDED_STEPS, record=Fals
     zeta = torch.tensor(np.stack([fi.stand_in_zeta(NZ, NX, b) for b in range(B)]), dtype=torch.float32, device=dev)
     vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
     ts = np.linspace(1.0, 0.005, steps)
-    src = GuidanceGradients(plan, wt, B, surrogate=sur, predictor=predictor)
+    src = GuidanceGradients(plan, wt, B, surrogate=sur, predictor=predictor, cos_min=cos_min)
     v = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
     x0 = torch.empty_like(v)
     vn = torch.empty_like(v)
@@ -286,9 +286,11 @@ def surrogate_guidance(plan, wt, v_true):
     vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
     ts = np.linspace(1.0, 0.005, GUIDED_STEPS)
     g_ex = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
-    for name, pred, net in (("surrogate", "surrogate", sur), ("anchor_only", "anchor", None)):
-        t_run, st, _ = guided_run(plan, wt, v_true, net, pred)
-        _, _, served = guided_run(plan, wt, v_true, net, pred, record=True)   # same schedule, kept for checking
+    for name, pred, net, cmin in (("surrogate", "surrogate", sur, 0.95), ("anchor_only", "anchor", None, 0.95),
+                                  ("surrogate_judge097", "surrogate", sur, 0.97),
+                                  ("anchor_only_judge097", "anchor", None, 0.97)):
+        t_run, st, _ = guided_run(plan, wt, v_true, net, pred, cos_min=cmin)
+        _, _, served = guided_run(plan, wt, v_true, net, pred, record=True, cos_min=cmin)   # same schedule, checked
         cos_all = []
         for i, g in served:
             v = torch.clamp(vt + float(ts[i]) * zeta, fi.V_LO, fi.V_HI)
@@ -305,8 +307,10 @@ def surrogate_guidance(plan, wt, v_true):
             "predicted_steps": st.served_predicted,
             "judged": st.judged,
             "judge_passed": st.passed,
-            "served_cos": {"min": round(float(c.min()), 4), "p5": round(float(np.percentile(c, 5)), 4),
-                           "median": round(float(np.median(c)), 4), "frac_ge_0.95": round(float(np.mean(c >= 0.95)), 4)},
+            "served_cos": {"min": round(float(c.min()), 4), "p1": round(float(np.percentile(c, 1)), 4),
+                           "p5": round(float(np.percentile(c, 5)), 4), "median": round(float(np.median(c)), 4),
+                           "frac_ge_0.95": round(float(np.mean(c >= 0.95)), 4), "n": int(c.size)},
+            "judged_misfit_error_median": round(float(np.median(st.judge_jerr)), 4) if st.judge_jerr else None,
         }
     res["protocol"] = (f"{B} samples x {GUIDED_STEPS} steps, t = 1 -> 0.005; stand-in denoiser clip(v_true + t zeta_b); "
                        "t > 0.5: anchor + surrogate change, solver judge (cos >= 0.95, misfit error <= 5%) with an "
@@ -317,6 +321,9 @@ def surrogate_guidance(plan, wt, v_true):
 
 SCORE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "score_70x70.npy")
 REVERSE_STEPS = 100
+# the paper's rho0 = 1.15 (Table 'parameter', CurveVel-A) per step of a 1000-step chain, times the 10 chain steps
+# that each of the 100 respaced steps stands for
+REVERSE_RHO0 = 11.5
 
 
 def reverse_loop(plan, wt, v_true):
@@ -340,7 +347,7 @@ def reverse_loop(plan, wt, v_true):
     vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
     res = {}
     for name, pl in (("guided", plan), ("unguided", None)):
-        loop = ReverseLoop(net, B, REVERSE_STEPS, plan=pl, wavelet=wt)
+        loop = ReverseLoop(net, B, REVERSE_STEPS, plan=pl, wavelet=wt, guidance=dict(rho0=REVERSE_RHO0))
         z = loop.step_noise(12)
         loop.run(x, noise=z[:, :, :, :])            # warm-up
         torch.cuda.synchronize()
@@ -372,7 +379,8 @@ def reverse_loop(plan, wt, v_true):
     res["network_ms_per_batch"] = {"forward": round(fw / 20, 4), "vjp": round(bw / 20, 4)}
     res["protocol"] = (f"{B} samples x {REVERSE_STEPS} respaced DDPM steps of the VP schedule (N = 1000), seeded "
                        "noise; trained score network (weights/score_70x70.npy); guidance: W2 misfit of the "
-                       "5-shot workload's observations of the true model, preconditioner rho0 = 1.15, gamma = 0.55")
+                       "5-shot workload's observations of the true model, preconditioner rho0 = 11.5 (1.15 per step "
+                       "of the 1000-step chain), gamma = 0.55")
     net.close()
     return res
 

@@ -97,7 +97,7 @@ def main(argv=None):
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--stop-after", type=int, default=None, help="stop (after a checkpoint) at this step")
     ap.add_argument("--ema", type=float, default=0.999, help="decay per step of the parameter average kept on "
-                                                            "the host (updated every 10 steps); 0 = off")
+                                                            "the host (updated every 50 steps); 0 = off")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -130,7 +130,7 @@ def main(argv=None):
         net.set_params(init_params(args.seed))
     if args.ema > 0 and ema is None:
         ema = net.get_params().astype(np.float64)
-    ema_decay = args.ema ** 10
+    ema_decay = args.ema ** 50
     loss_t = torch.zeros(1, dtype=torch.float32, device=dev)
     B = args.batch
     t0 = time.time()
@@ -138,14 +138,14 @@ def main(argv=None):
     while step < args.steps:
         idx = rng.integers(0, args.pool, B)
         ti = rng.integers(1, N + 1, B)
-        z = rng.standard_normal((B, 70, 70)).astype(np.float32)
+        z = rng.standard_normal((B, 70, 70), dtype=np.float32)
         ab = abar[ti - 1]
         x0 = pool[torch.tensor(idx, device=dev)].contiguous()
         f = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)  # noqa: E731
         net.train_step(x0, f(z), f(ti / N), f(np.sqrt(ab)), f(np.sqrt(1 - ab)),
                        lr=lr_at(step, args.steps, args.lr, args.lr_min, args.warmup), loss_out=loss_t)
         step += 1
-        if ema is not None and step % 10 == 0:
+        if ema is not None and step % 50 == 0:
             ema = ema_decay * ema + (1.0 - ema_decay) * net.get_params()
         if step % 50 == 0:
             lv = float(loss_t.item())
