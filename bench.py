@@ -226,6 +226,9 @@ def pml_measured_traffic(kind):
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surrogate_70x70.npy")
 GUIDED_STEPS = 200
+# the judge's cosine threshold: it sees only the farthest prediction of an interval, so it judges with a margin
+# over the 0.95 the served gradients are held to
+JUDGE_COS = 0.97
 
 
 def guided_run(plan, wt, v_true, sur, predictor, steps=GUIDED_STEPS, record=False, cos_min=0.95):
@@ -286,9 +289,9 @@ def surrogate_guidance(plan, wt, v_true):
     vt = torch.tensor(v_true, dtype=torch.float32, device=dev)
     ts = np.linspace(1.0, 0.005, GUIDED_STEPS)
     g_ex = torch.empty((B, NZ, NX), dtype=torch.float32, device=dev)
-    for name, pred, net, cmin in (("surrogate", "surrogate", sur, 0.95), ("anchor_only", "anchor", None, 0.95),
-                                  ("surrogate_judge097", "surrogate", sur, 0.97),
-                                  ("anchor_only_judge097", "anchor", None, 0.97)):
+    for name, pred, net, cmin in (("surrogate", "surrogate", sur, JUDGE_COS), ("anchor_only", "anchor", None, JUDGE_COS),
+                                  ("surrogate_judge095", "surrogate", sur, 0.95),
+                                  ("anchor_only_judge095", "anchor", None, 0.95)):
         t_run, st, _ = guided_run(plan, wt, v_true, net, pred, cos_min=cmin)
         _, _, served = guided_run(plan, wt, v_true, net, pred, record=True, cos_min=cmin)   # same schedule, checked
         cos_all = []
@@ -313,8 +316,11 @@ def surrogate_guidance(plan, wt, v_true):
             "judged_misfit_error_median": round(float(np.median(st.judge_jerr)), 4) if st.judge_jerr else None,
         }
     res["protocol"] = (f"{B} samples x {GUIDED_STEPS} steps, t = 1 -> 0.005; stand-in denoiser clip(v_true + t zeta_b); "
-                       "t > 0.5: anchor + surrogate change, solver judge (cos >= 0.95, misfit error <= 5%) with an "
-                       "adaptive interval (4, x2 on pass up to 32, /2 on fail); t <= 0.5: solver")
+                       f"t > 0.5: anchor + surrogate change, solver judge (cos >= {JUDGE_COS}, misfit error <= 5%) "
+                       "with an adaptive interval (4, x2 on pass up to 32, /2 on fail); t <= 0.5: solver; served "
+                       "gradients checked against the solver afterwards at cos >= 0.95 (the judge's margin keeps the "
+                       "served steps inside an interval, which lie closer to the anchor than the judged one, above "
+                       "0.95); the *_judge095 entries judge at 0.95")
     sur.close()
     return res
 
