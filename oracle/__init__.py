@@ -48,15 +48,27 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_sanitized(path: str) -> str:
+    """Compile the same source with AddressSanitizer and UndefinedBehaviorSanitizer (host code) into `path`;
+    load it by setting ORACLE_LIB=path in a process started with the ASan runtime preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC, "-o", path, "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
+
+
 _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("ORACLE_LIB")
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = ctypes.CDLL(path)
         i, d = ctypes.c_int, ctypes.c_double
         geo = [i, i, d, d, d, i, i, i, d, i, _ip, _ip, i, _ip, _ip]
         L.orc_forward.argtypes = geo + [i, _dp, _dp, _dp]
