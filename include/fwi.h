@@ -543,11 +543,13 @@ typedef struct {
 typedef struct {
     size_t v_offset, wavelet_offset, trace_offset;
     int nzp, nxp;           /* padded grid */
-    int kind;               /* 0: LDS-resident, 1: swept from HBM */
-    int tile_x, tile_z;     /* kind 0: register tile (columns, rows); kind 1: sweep tile */
-    int tuned;              /* 1 if the tile was picked by timing */
-    int parts;              /* HBM-swept fields: row parts per field, each swept by its own workgroup in lockstep
-                               with the others (1: one workgroup per field) */
+    int kind;               /* 0: LDS-resident, 1: swept from HBM, 2: LDS-resident row bands on several
+                               workgroups (forward-only batches, fields too large for one workgroup's LDS whose
+                               receivers share a row) */
+    int tile_x, tile_z;     /* kinds 0 and 2: register tile (columns, rows); kind 1: sweep tile */
+    int tuned;              /* 1 if the tile was picked by timing (kind 2: by the cost model, 0) */
+    int parts;              /* workgroups per field: kind 1 row parts swept in lockstep, kind 2 row bands
+                               exchanging halos (1: one workgroup per field) */
 } fwi_batch_request_info;
 
 /* Validates every geometry (FWI_EINVAL / FWI_ECFL as fwi_plan_create), builds

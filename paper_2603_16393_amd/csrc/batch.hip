@@ -10,7 +10,14 @@
 //    time loop (wave_lds_body.h) with this request's tile;
 //  * larger fields keep (u^n, u^{n+1}, w) in HBM (the unit's own arrays, hot in
 //    L2 / MALL) and stream them column panel by column panel each step
-//    (glb_field_forward).
+//    (glb_field_forward);
+//  * in a forward-only batch, larger fields whose receivers share a row are
+//    instead cut into G row bands that stay in LDS for the whole time loop,
+//    one unit per band, exchanging 4-row halos every step through tagged
+//    64-bit words (the split sweep body of wave_split_body.h, bitwise equal to
+//    the other sweeps).  The bands of a field are queued next to each other
+//    and the launch is cooperative, so they all become resident; a band that
+//    starts early waits, with a bounded spin, for its neighbours' first rows.
 // The tile of each size class (LDS register tile or HBM prefetch depth) comes from
 // the autotuner below, which times the candidates on a short sweep of the
 // class's first unit replicated over every compute unit.
@@ -23,6 +30,7 @@
 
 #include "fwi_internal.h"
 #include "wave_lds_body.h"
+#include "wave_split_body.h"
 
 namespace fwi {
 
@@ -33,13 +41,18 @@ constexpr int kBatchLdsVariants = 6;
 //   HBM sweeps (RB rows loaded ahead per block, SMUL x the minimal row segments per column group)
 #define FWI_BATCH_GLB(M) M(0, 2, 1) M(1, 4, 1) M(2, 8, 1) M(3, 4, 2) M(4, 8, 2)
 constexpr int kBatchGlbVariants = 5;
+//   LDS-resident row bands (X columns, PI interior rows per tile, exact column cover); wider tiles
+//   than the plan's split sweep, since 8 boundary rows of ncg = nxp / X column groups must fit 512 threads
+#define FWI_BATCH_SPLIT(M) \
+    M(0, 4, 3, true) M(1, 4, 3, false) M(2, 4, 4, true) M(3, 4, 4, false) M(4, 6, 3, true) M(5, 6, 3, false)
 
 struct BatchUnit {
-    int kind;       // 0: LDS-resident, 1: HBM sweep
+    int kind;       // 0: LDS-resident, 1: HBM sweep, 2: LDS-resident row band of a split field
     int variant;    // index into the list of its kind
     int nsteps;     // time steps to take (nt - 1, or fewer when tuning)
     long long tr_off, w_off;  // offsets of this unit's traces and wavelet in the call's packed buffers
-    LdsArgs la;     // kind 0: pointers already offset to this unit (field index 0)
+    LdsArgs la;     // kinds 0 and 2: pointers already offset to this unit (field index 0)
+    SplitArgs sp;   // kind 2: bands of the field, its exchange rows (field0 = 0); the band is `part`
     // kind 1
     int nzp, nxp, fs, nt, nr, src_pt, rec_z0, rec_z1;
     float idz2, idx2, src_scale;
@@ -550,8 +563,24 @@ __device__ __noinline__ void unit_glb_forward(const BatchUnit* __restrict__ U, f
     glb_field_forward<RB, SM>(*U, lds);
 }
 
+template <int X, int PI, bool EX>
+__device__ __noinline__ void unit_split_forward(const BatchUnit* __restrict__ U, float* lds) {
+    const LdsArgs a = U->la;
+    split_field<X, PI, false, EX, false>(a, U->sp, 0, U->part, U->ax, U->az, lds);
+}
+
 __device__ void run_unit_forward(const BatchUnit* U, float* lds) {
     const int kind = U->kind, variant = U->variant;
+    if (kind == 2) {
+#define FWI_SPLIT_CASE(ID, XX, PP, EX)               \
+    if (variant == ID) {                             \
+        unit_split_forward<XX, PP, EX>(U, lds);      \
+        return;                                      \
+    }
+        FWI_BATCH_SPLIT(FWI_SPLIT_CASE)
+#undef FWI_SPLIT_CASE
+        return;
+    }
     if (kind == 0) {
 #define FWI_LDS_CASE(ID, XX, PP, EX)                 \
     if (variant == ID) {                             \
@@ -595,7 +624,7 @@ __global__ void k_batch_bind(BatchUnit* __restrict__ units, int nunits, float* _
     BatchUnit& U = units[u];
     U.adj = adj ? adj + U.tr_off : nullptr;
     if (U.kind == 1 && U.nparts > 1 && U.part == 0) *U.bar = 0;
-    if (U.kind == 0) {
+    if (U.kind == 0 || U.kind == 2) {
         U.la.traces = traces + U.tr_off;
         U.la.wavelet = wavelets + U.w_off;
         U.la.adj = U.adj;
@@ -659,6 +688,10 @@ struct fwi_batch {
     std::vector<int> unit_req;                   // request of each queued unit
     std::vector<int> unit_shot;                  // shot of each queued unit
     int* bars = nullptr;                         // barrier counters of the fields cut into parts
+    // kind 2 (row bands in LDS): per request the split layout, and the bands' exchange rows
+    std::vector<int> sp_X, sp_P, sp_ncg, sp_nstrip, sp_G;
+    unsigned long long* xchg = nullptr;
+    size_t xchg_words = 0;
     BatchUnit* d_units = nullptr;
     PrepReq* d_prep = nullptr;
     int* counter = nullptr;
@@ -722,6 +755,45 @@ bool lds_var_fits(int v, int nzp, int nxp, int* ncg, int* nstrip) {
     const bool exact = *ncg * L.X == nxp && *nstrip * L.P == nzp;
     if (L.exact != exact) return false;
     return *ncg * *nstrip <= kLdsThreads && lds_bytes(L.X, L.P, *ncg, *nstrip) <= (size_t)kBatchDynLds;
+}
+
+// Row-band layout of a field held in LDS by G workgroups (kind 2): X columns
+// per thread (4 or 6) so that the 8 boundary rows of ncg column groups fit
+// 512 threads, PI interior rows per tile, as many strips as threads allow.
+// Among the layouts whose band fits the LDS, the one with the fewest cycles
+// per step summed over its bands (VALU and LDS work per point as the split
+// sweep's cost model, plus the exchange latency per band).
+bool batch_split_layout(int nzp, int nxp, int* Xo, int* Po, int* ncgo, int* nstripo, int* Go, int* vo) {
+    double best = 1e300;
+    bool found = false;
+#define FWI_TRY_SPLIT(ID, XX, PP, EX)                                                                  \
+    {                                                                                                \
+        const int ncg = (nxp + XX - 1) / XX;                                                         \
+        const int smax = kLdsThreads / ncg;                                                          \
+        if (smax >= 8 && (ncg * XX == nxp) == EX) {                                                  \
+            const int G = (nzp + 8 + smax * PP - 1) / (8 + smax * PP);                               \
+            const int nstrip = std::max(1, ((nzp + G - 1) / G - 8 + PP - 1) / PP);                   \
+            const int H = 8 + nstrip * PP;                                                           \
+            if (G >= 2 && nstrip <= smax && (long long)G * H >= nzp &&                               \
+                split_lds_bytes(XX, PP, ncg, nstrip) <= (size_t)kBatchDynLds) {                      \
+                const double pts = (double)ncg * XX * H;                                             \
+                const double c = G * (pts * (33.0 / 64.0 + ((PP + 8.0) / PP + 8.0 / XX + 1.0) / 32.0) + 1500.0); \
+                if (c < best) {                                                                      \
+                    best = c;                                                                        \
+                    *Xo = XX;                                                                        \
+                    *Po = PP;                                                                        \
+                    *ncgo = ncg;                                                                     \
+                    *nstripo = nstrip;                                                               \
+                    *Go = G;                                                                         \
+                    *vo = ID;                                                                        \
+                    found = true;                                                                    \
+                }                                                                                    \
+            }                                                                                        \
+        }                                                                                            \
+    }
+    FWI_BATCH_SPLIT(FWI_TRY_SPLIT)
+#undef FWI_TRY_SPLIT
+    return found;
 }
 
 template <class T>
@@ -794,16 +866,23 @@ BatchUnit make_unit(const fwi_batch* b, int r, int s, int kind, int variant, con
     U.ax = rd.ax;
     U.az = rd.az;
     const int nzp = b->nzp[r], nxp = b->nxp[r];
-    if (kind == 0) {
-        const LdsVar& V = kLdsVar[variant];
+    if (kind == 0 || kind == 2) {
         LdsArgs& a = U.la;
         a.nzp = nzp;
         a.nxp = nxp;
         a.npts = nzp * nxp;
-        a.X = V.X;
-        a.P = V.P;
-        a.ncg = (nxp + V.X - 1) / V.X;
-        a.nstrip = (nzp + V.P - 1) / V.P;
+        if (kind == 0) {
+            const LdsVar& V = kLdsVar[variant];
+            a.X = V.X;
+            a.P = V.P;
+            a.ncg = (nxp + V.X - 1) / V.X;
+            a.nstrip = (nzp + V.P - 1) / V.P;
+        } else {
+            a.X = b->sp_X[r];
+            a.P = b->sp_P[r];
+            a.ncg = b->sp_ncg[r];
+            a.nstrip = b->sp_nstrip[r];
+        }
         a.S = a.ncg * a.X + 8;
         a.fs = g.free_surface ? 1 : 0;
         a.nt = nsteps + 1;
@@ -945,11 +1024,32 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             for (int v = 0; v < kBatchLdsVariants; ++v)
                 if (lds_var_fits(v, b->nzp[r], b->nxp[r], &ncg, &nstrip)) b->kind[r] = 0;
     }
+    // forward-only batches: fields too large for one workgroup's LDS run as row
+    // bands held in LDS (layout from the split sweep's cost model), when their
+    // receivers share a row
+    b->sp_X.assign(nreq, 0);
+    b->sp_P.assign(nreq, 0);
+    b->sp_ncg.assign(nreq, 0);
+    b->sp_nstrip.assign(nreq, 0);
+    b->sp_G.assign(nreq, 0);
+    for (int r = 0; r < nreq && st == FWI_OK && !o.gradients; ++r) {
+        if (b->kind[r] != 1 || !rd[r].ht.one_row) continue;
+        int X = 0, P = 0, ncg = 0, nstrip = 0, G = 0, v = -1;
+        if (!batch_split_layout(b->nzp[r], b->nxp[r], &X, &P, &ncg, &nstrip, &G, &v) || G > b->n_cu) continue;
+        b->kind[r] = 2;
+        b->variant[r] = v;
+        b->sp_X[r] = X;
+        b->sp_P[r] = P;
+        b->sp_ncg[r] = ncg;
+        b->sp_nstrip[r] = nstrip;
+        b->sp_G[r] = G;
+    }
 
     // autotuning per size class: every candidate on a 64-step sweep of the
     // class's first request, one copy per compute unit
     const int tune_steps = 64;
     for (int r = 0; r < nreq && st == FWI_OK; ++r) {
+        if (b->kind[r] == 2) continue;  // layout from the split cost model
         const int nzp = b->nzp[r], nxp = b->nxp[r];
         int ncg, nstrip;
         std::vector<int> cands;
@@ -1068,28 +1168,35 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
         };
         double total = 0.0;
         for (int r = 0; r < nreq; ++r)
-            total += (double)b->g[r].ns * b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1) * (b->kind[r] == 0 ? 0.2 : 1.0);
+            total += (double)b->g[r].ns * b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1) * (b->kind[r] != 1 ? 0.2 : 1.0);
         const double share = total / std::max(1, b->n_cu);
         std::vector<Job> jobs;
-        size_t state_elems = 0;
+        size_t state_elems = 0, xchg_words = 0;
         int nsplit = 0;
         for (int r = 0; r < nreq; ++r)
             for (int s = 0; s < b->g[r].ns; ++s) {
-                const double cost = (double)b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1) * (b->kind[r] == 0 ? 0.2 : 1.0);
+                const double cost = (double)b->nzp[r] * b->nxp[r] * (b->g[r].nt - 1) * (b->kind[r] != 1 ? 0.2 : 1.0);
                 int np = 1;
                 if (b->kind[r] == 1 && cost > 1.25 * share)
                     np = std::max(1, std::min({kMaxParts, (int)std::ceil(cost / share), b->nzp[r] / kMinPartRows}));
+                if (b->kind[r] == 2) np = b->sp_G[r];
                 for (int q = 0; q < np; ++q) jobs.push_back({cost / np, r, s, q, np});
-                if (np > 1) ++nsplit;
+                if (np > 1 && b->kind[r] == 1) ++nsplit;
+                if (b->kind[r] == 2) xchg_words += (size_t)np * 2 * 2 * 4 * b->sp_ncg[r] * b->sp_X[r];
                 if (b->kind[r] == 1) state_elems += 3 * (size_t)b->nzp[r] * b->nxp[r];
             }
         std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& c) { return a.cost > c.cost; });
         float* state = nullptr;
         st = balloc(b, &state, state_elems);
         st = st ? st : balloc(b, &b->bars, (size_t)std::max(nsplit, 1));
-        size_t so = 0;
+        if (xchg_words) {
+            st = st ? st : balloc(b, &b->xchg, xchg_words);
+            b->xchg_words = xchg_words;
+        }
+        size_t so = 0, xo = 0;
         int nb = 0;
         std::map<std::pair<int, int>, std::pair<float*, int*>> field;  // (r, s) -> state, barrier
+        std::map<std::pair<int, int>, unsigned long long*> fxchg;     // (r, s) -> exchange rows of its bands
         for (const Job& j : jobs) {
             if (st) break;
             const int r = j.r;
@@ -1110,7 +1217,24 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             }
             BatchUnit U = make_unit(b, r, j.s, b->kind[r], b->variant[r], rd[r], b->K + b->pt_off[r], b->w_off[r],
                                     tr_off, sp, b->g[r].nt - 1);
-            if (j.nparts > 1) {
+            if (b->kind[r] == 2) {
+                auto it = fxchg.find({r, j.s});
+                unsigned long long* xb;
+                if (it == fxchg.end()) {
+                    xb = b->xchg + xo;
+                    xo += (size_t)j.nparts * 2 * 2 * 4 * b->sp_ncg[r] * b->sp_X[r];
+                    fxchg[{r, j.s}] = xb;
+                } else {
+                    xb = it->second;
+                }
+                U.sp.G = j.nparts;
+                U.sp.W = b->sp_ncg[r] * b->sp_X[r];
+                U.sp.xchg = xb;
+                U.sp.err = b->flags;
+                U.sp.field0 = 0;
+                U.part = j.part;
+                U.nparts = j.nparts;
+            } else if (j.nparts > 1) {
                 // rows split evenly; every part takes part of the sweep's panels
                 const int nzp = b->nzp[r];
                 U.part = j.part;
@@ -1122,7 +1246,9 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             b->units.push_back(U);
             b->unit_req.push_back(r);
             b->unit_shot.push_back(j.s);
-            const size_t lb = b->kind[r] == 0 ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip) : glb_lds(U.variant, U.nzp);
+            const size_t lb = b->kind[r] == 0   ? lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip)
+                              : b->kind[r] == 2 ? split_lds_bytes(U.la.X, U.la.P, U.la.ncg, U.la.nstrip)
+                                                : glb_lds(U.variant, U.nzp);
             b->lds_bytes = std::max(b->lds_bytes, lb);
         }
         if (st == FWI_OK && o.gradients) {
@@ -1227,6 +1353,9 @@ int fwi_batch_get_info(const fwi_batch* b, int r, fwi_batch_request_info* info) 
     if (b->kind[r] == 0) {
         info->tile_x = kLdsVar[b->variant[r]].X;
         info->tile_z = kLdsVar[b->variant[r]].P;
+    } else if (b->kind[r] == 2) {
+        info->tile_x = b->sp_X[r];
+        info->tile_z = b->sp_P[r];
     } else {
         info->tile_x = 64;
         info->tile_z = kGlbVar[b->variant[r]].RB;
@@ -1234,7 +1363,7 @@ int fwi_batch_get_info(const fwi_batch* b, int r, fwi_batch_request_info* info) 
     info->tuned = b->tuned[r];
     info->parts = 1;
     for (size_t i = 0; i < b->units.size(); ++i)
-        if (b->unit_req[i] == r && b->units[i].kind == 1) info->parts = std::max(info->parts, b->units[i].nparts);
+        if (b->unit_req[i] == r && b->units[i].kind != 0) info->parts = std::max(info->parts, b->units[i].nparts);
     return FWI_OK;
 }
 
@@ -1254,6 +1383,10 @@ int fwi_batch_forward(fwi_batch* b, const float* v, const float* wavelets, float
     const int blocks = (int)std::min<long long>((total + 255) / 256, 65535);
     hipLaunchKernelGGL(k_batch_prep, dim3(blocks), dim3(256), 0, st, b->d_prep, b->nreq, total, v, b->K, b->flags);
     if (hipGetLastError() != hipSuccess) return FWI_EHIP;
+    if (b->xchg) {  // the bands' exchange rows start at time level 0
+        const int rc = launch_fill(reinterpret_cast<float*>(b->xchg), 2 * b->xchg_words, 0.f, st);
+        if (rc) return rc;
+    }
     const int grid = std::min<int>(b->n_cu, (int)b->units.size());
     return launch_units(b->d_units, (int)b->units.size(), b->counter, grid, b->lds_bytes, traces, wavelets, st);
 }
