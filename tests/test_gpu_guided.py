@@ -107,8 +107,11 @@ def test_judge_adapts_interval_and_falls_back(setup):
 def test_trained_surrogate_improves_on_anchor_reuse(setup):
     """Same fixed schedule (judge every 8 steps over t in (1, 0.5]) with and
     without the trained network: the network's predictions of the misfit are
-    closer to the solver's (measured: median error 0.025 vs 0.042), and its
-    gradients are no worse (judged cosine medians 0.989 vs 0.989)."""
+    closer to the solver's (measured with the 50,000-pair weights: median
+    error 0.022 vs 0.042), and its gradients are no worse (judged cosine
+    medians 0.988 vs 0.989).  The network does not improve the gradient
+    itself, so on throughput it does not beat anchor reuse; this test holds it
+    to the gain it does make."""
     from paper_2603_16393_amd.guided import GuidanceGradients
     from paper_2603_16393_amd.surrogate import Surrogate
 
@@ -128,5 +131,5 @@ def test_trained_surrogate_improves_on_anchor_reuse(setup):
     ca, ja = res["anchor"]
     print("judged cos median net / anchor", np.median(cn), np.median(ca), "misfit err median", np.median(jn),
           np.median(ja))
-    assert np.median(jn) < 0.8 * np.median(ja)
+    assert np.median(jn) < 0.7 * np.median(ja)
     assert np.median(cn) >= np.median(ca) - 0.01
