@@ -567,9 +567,12 @@ def pml_guidance(acq, v0hat, v_true, x0, w, steps=10, warmup=2):
     print(f"PML6: {ms:.2f} ms per batch of {B} (forward sweep {fwd_ms:.2f} ms, adjoint {adj_ms:.2f} ms)",
           file=sys.stderr, flush=True)
     return {"grads_per_s": round(B / (ms / 1e3), 2) if ok else None, "ms_per_step": round(ms, 3),
-            "padded": [nzp, nxp], "path": info["path"],
+            "padded": [nzp, nxp], "path": info["path"], "bands": info["lds_split"],
             "sweep_ms": {"forward": round(fwd_ms, 3), "adjoint": round(adj_ms, 3)},
-            "roofline": {"bound": "hbm", "kernel": "k_wave_pml<7, adjoint>", "achieved": round(achieved, 1),
+            "roofline": {"bound": "hbm",
+                         "kernel": ("k_wave_pml_band<adjoint> (row bands)" if info["lds_split"] > 1
+                                    else "k_wave_pml<7, adjoint>"),
+                         "achieved": round(achieved, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                          "traffic": pml_measured_traffic("adjoint"), "alg_bytes_per_launch": alg,
                          "launch_ms": round(adj_ms, 3)},
@@ -657,7 +660,7 @@ def bench_pml(args):
         "unit": "grads/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "plain guidance, 16 x 70x70, 5 shots, 1000 steps, 6-cell PML", "global_batch": B},
-        "roofline": r["roofline"], "sweep_ms": r["sweep_ms"]}))
+        "roofline": r["roofline"], "sweep_ms": r["sweep_ms"], "bands": r["bands"]}))
 
 
 # work-unit kinds of the uneven batch: whole field in one workgroup's LDS, HBM-swept field (gradient batches),

@@ -79,10 +79,14 @@ typedef struct {
     int pml;               /* 0: the nb-cell layer is the damping sponge; 1: it is a perfectly matched layer
                               (Sec. 2.1 absorbing boundary, Sec. 6.1: 6 cells on the left, right and bottom),
                               the unsplit second-order form of a complex coordinate stretch with the sponge's
-                              quadratic profile and strength.  Plans only (fwi_batch_create rejects it); the
-                              padded field must fit one workgroup's LDS (about 7,000 padded cells, e.g. a
-                              70 x 70 model with 6 cells), with the full forward history (FWI_EINVAL /
-                              FWI_ENOMEM otherwise). */
+                              quadratic profile and strength.  Plans only (fwi_batch_create rejects it), with
+                              the full forward history (FWI_ENOMEM otherwise).  When max_batch * ns fields
+                              leave CUs idle, each field is split into row bands held by several workgroups
+                              (launched cooperatively; see `split` of fwi_plan_options); otherwise, and while
+                              the caller's stream is capturing a graph, the padded field must fit one
+                              workgroup's LDS (about 7,000 padded cells, e.g. a 70 x 70 model with 6 cells):
+                              FWI_EINVAL at plan creation if neither applies, at the call if only the bands
+                              apply and the stream is capturing. */
 } fwi_geometry;
 
 /* Misfit settings (Sec. 5.1 and Sec. 6.2).  Paper values: k = 100,
@@ -129,15 +133,16 @@ typedef struct {
                                   workgroups per field each holding a band of rows);
                                   1: tiled sweep from HBM, two time steps per launch;
                                   2: PML sweep, field and auxiliary fields resident in LDS, one workgroup
-                                  per (sample, shot) */
+                                  per (sample, shot), or lds_split workgroups per field each holding a band
+                                  of rows */
     int store_mode;            /* 0: full history of D = L u + s kept for the adjoint;
                                   1: checkpoints every `ckpt_every` steps plus recomputation */
     int ckpt_every;
     int max_batch;
     size_t device_bytes;       /* device memory held by the plan */
     int lds_tile_x, lds_tile_z;  /* register tile of the LDS-resident path (0 on the tiled path) */
-    int lds_split;             /* LDS-resident path: workgroups sharing one field (1: one per field; 0 on the
-                                  tiled path) */
+    int lds_split;             /* LDS-resident and PML paths: workgroups sharing one field (1: one per field;
+                                  0 on the tiled path) */
 } fwi_plan_info;
 
 /* Creates a plan for up to `max_batch` velocity samples on the current device.
@@ -158,11 +163,12 @@ typedef struct {
     int lds_tile_z;     /* 0, 0 = the built-in cost model's choice; FWI_EINVAL if not available */
     int timing;         /* 1: record HIP events around each forward and adjoint sweep on the caller's
                            stream (read with fwi_plan_sweep_ms); 0: off */
-    int split;          /* LDS-resident path, when max_batch * ns fields leave CUs idle: 0 = split each field
-                           over several workgroups (row bands exchanging 4-row halos every step, launched
-                           cooperatively) if the cost model prefers it, and never with an explicit lds tile;
-                           1 = split whenever feasible (FWI_EINVAL if not); -1 = never.  While the caller's
-                           stream is capturing a graph the unsplit kernels run (same results bit for bit). */
+    int split;          /* LDS-resident and PML paths, when max_batch * ns fields leave CUs idle: 0 = split
+                           each field over several workgroups (row bands exchanging halos every step, launched
+                           cooperatively) if the cost model prefers it (PML: whenever feasible), and never with
+                           an explicit lds tile; 1 = split whenever feasible (FWI_EINVAL if not); -1 = never.
+                           While the caller's stream is capturing a graph the unsplit kernels run (same
+                           results bit for bit). */
 } fwi_plan_options;
 
 /* fwi_plan_create with explicit execution options (NULL = automatic). */

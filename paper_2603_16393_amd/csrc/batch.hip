@@ -810,15 +810,6 @@ void bfree(fwi_batch* b) {
     b->allocs.clear();
 }
 
-static bool stream_capturing(hipStream_t st) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return cs != hipStreamCaptureStatusNone;
-}
-
 // The persistent kernels run one workgroup per CU at most (grid <= CUs, and
 // their LDS allows one per CU).  Row parts of a field wait for each other at
 // a per-step barrier, which needs every workgroup resident: outside graph

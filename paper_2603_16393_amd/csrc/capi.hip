@@ -195,9 +195,9 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     for (int r = 1; r < nr; ++r) one_row = one_row && (p.rec_iz[r] == p.rec_iz[0]);
     std::vector<int> pml_rec;
     if (p.g.pml) {
-        // the PML sweep keeps the whole field in one workgroup's LDS and the full history of D
-        if (o.force_path != -1 || o.ckpt_every > 0 || o.lds_tile_x > 0 || o.lds_tile_z > 0 || o.split > 0 ||
-            !pml_fits(p.nzp, p.nxp)) {
+        // the PML sweep keeps the field in LDS (one workgroup, or row bands over several) and the full
+        // history of D
+        if (o.force_path != -1 || o.ckpt_every > 0 || o.lds_tile_x > 0 || o.lds_tile_z > 0) {
             delete pp;
             return FWI_EINVAL;
         }
@@ -219,6 +219,31 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         }
         p.path = (o.force_path == 1 || !lds_ok || o.ckpt_every > 0) ? 1 : 0;
     }
+    // PML path: row bands when the batch leaves CUs idle (cooperative launches); the whole-field sweep needs
+    // the field in one workgroup's LDS
+    std::vector<int> band_cells, band_qcells, band_npub;
+    if (p.path == 2) {
+        int ncu = 0, coop = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device) != hipSuccess ||
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p.device) != hipSuccess) {
+            (void)hipGetLastError();
+            ncu = coop = 0;
+        }
+        int G = 1, H = 0, KC = 0, NW = 0;
+        const bool bands = coop && pml_choose_bands(p.g, p.nzp, p.nxp, p.ztop, (int)nf, ncu, o.split, &G, &H, &KC, &NW);
+        if ((o.split > 0 && !bands) || (!bands && !pml_fits(p.nzp, p.nxp))) {
+            delete pp;
+            return FWI_EINVAL;
+        }
+        if (bands) {
+            p.pml_G = G;
+            p.pml_H = H;
+            p.pml_KC = KC;
+            p.pml_NW = NW;
+            pml_band_tables(p.g, p.nzp, p.nxp, p.ztop, G, H, KC, band_cells, band_qcells, band_npub);
+        }
+    }
+
     p.timing = o.timing;
     if (p.timing)
         for (auto* ring : {&p.ev_fwd, &p.ev_adj}) {
@@ -273,7 +298,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     }
 
     // LDS-resident path: several workgroups per field when the batch leaves CUs idle
-    if (o.split > 0 && p.path != 0) {
+    if (o.split > 0 && p.path == 1) {
         free_all(p);
         delete pp;
         return FWI_EINVAL;
@@ -351,6 +376,12 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.pml_rec, npts);
         st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
         st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
+        if (p.pml_G > 1) {
+            st = st ? st : alloc_n(p, &p.pml_cells, band_cells.size());
+            st = st ? st : alloc_n(p, &p.pml_qcells, band_qcells.size());
+            st = st ? st : alloc_n(p, &p.pml_npub, band_npub.size());
+            st = st ? st : alloc_n(p, &p.pml_xchg, nf * p.pml_G * 4 * (size_t)p.pml_NW);
+        }
     } else {
         st = st ? st : alloc_n(p, &p.rec_of_col, (size_t)p.nxp);
         if (p.split_G > 1)
@@ -377,6 +408,14 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
             st = st ? st : hip_ok(hipMemcpy(p.pml_tz, tz.data(), tz.size() * sizeof(float), hipMemcpyHostToDevice));
             st = st ? st : hip_ok(hipMemcpy(p.pml_rec, pml_rec.data(), pml_rec.size() * sizeof(int),
                                             hipMemcpyHostToDevice));
+            if (p.pml_G > 1) {
+                st = st ? st : hip_ok(hipMemcpy(p.pml_cells, band_cells.data(), band_cells.size() * sizeof(int),
+                                                hipMemcpyHostToDevice));
+                st = st ? st : hip_ok(hipMemcpy(p.pml_qcells, band_qcells.data(), band_qcells.size() * sizeof(int),
+                                                hipMemcpyHostToDevice));
+                st = st ? st : hip_ok(hipMemcpy(p.pml_npub, band_npub.data(), band_npub.size() * sizeof(int),
+                                                hipMemcpyHostToDevice));
+            }
         }
         if (p.path == 1)
             st = st ? st : hip_ok(hipMemcpy(p.rec_map, rec_map.data(), npts * sizeof(int), hipMemcpyHostToDevice));
@@ -434,7 +473,7 @@ int fwi_plan_get_info(const fwi_plan* plan, fwi_plan_info* info) {
     const bool split = plan->path == 0 && plan->split_G > 1;
     info->lds_tile_x = plan->path == 0 ? (split ? plan->split_X : plan->lds_X) : 0;
     info->lds_tile_z = plan->path == 0 ? (split ? plan->split_P : plan->lds_P) : 0;
-    info->lds_split = plan->path == 0 ? plan->split_G : 0;
+    info->lds_split = plan->path == 0 ? plan->split_G : (plan->path == 2 ? plan->pml_G : 0);
     return FWI_OK;
 }
 

@@ -40,6 +40,12 @@ constexpr int kLdsMaxP = 48;   // rows per thread of the LDS-resident sweep (mul
 // PML sweep: threads of its workgroup and the most cells one thread owns.
 constexpr int kPmlThreads = 1024;
 constexpr int kPmlMaxCells = 7;
+// PML row bands: threads per band, most cells per thread, auxiliary-update
+// cells and received halo words per thread.
+constexpr int kPmlBandThreads = 512;
+constexpr int kPmlBandMaxKC = 8;
+constexpr int kPmlBandKQ = 2;
+constexpr int kPmlBandKH = 2;
 
 // Cell order of the PML sweep.  Slots list (1) the model cells at least 4
 // cells from the layer, whose stencils never see the auxiliary fields,
@@ -73,6 +79,15 @@ struct PmlOrder {
         else
             e = zlo * nx + (zhi - zlo) * rw + (zm - zhi) * nx + xm;
         return ndeep + e;
+    }
+    // slot of padded cell (iz, ix): the inverse of cell()
+    __host__ __device__ int slot_of(int iz, int ix) const {
+        const int zm = iz - ztop, xm = ix - nb;
+        if (zm >= 0 && zm < nz && xm >= 0 && xm < nx) return model_slot(zm, xm);
+        const int w2 = 2 * nb;
+        if (zm >= 0 && zm < nz) return nint + zm * w2 + (ix < nb ? ix : ix - nx);
+        const int row = iz < ztop ? iz : iz - nz;
+        return nint + nz * w2 + row * nxp + ix;
     }
     // padded cell (iz, ix) of slot j
     __host__ __device__ void cell(int j, int& iz, int& ix) const {
@@ -218,6 +233,13 @@ struct Plan {
     float* pml_tx = nullptr;     // PML: [nxp] zeta_x dt / 2 per padded column
     float* pml_tz = nullptr;     // PML: [nzp] zeta_z dt / 2 per padded row
     int* pml_rec = nullptr;      // PML: [npts] receiver index of each slot of the sweep's cell order, or -1
+    // PML row bands (several workgroups per field, section of wave_pml.hip): bands, rows per band, cells per
+    // thread, words per exchanged edge; per band the cell lists and the published-cell counts
+    int pml_G = 1, pml_H = 0, pml_KC = 0, pml_NW = 0;
+    int* pml_cells = nullptr;    // [G][KC * kPmlBandThreads] own cells, iz << 16 | ix (published first), or -1
+    int* pml_qcells = nullptr;   // [G][kPmlBandKQ * kPmlBandThreads] cells of the auxiliary update, or -1
+    int* pml_npub = nullptr;     // [G]
+    unsigned long long* pml_xchg = nullptr;  // [max_batch*ns][G][2 edges][2 parity][NW]
     float* ax = nullptr;         // [nxp] sponge damping factor per padded column
     float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]
@@ -317,6 +339,15 @@ size_t pml_lds_bytes(int nzp, int nxp);
 bool pml_fits(int nzp, int nxp);
 int launch_pml_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
 int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st);
+// PML row bands for `nfields` fields on `ncu` CUs: bands G and rows per band H
+// (false when no split into 2 or more bands applies; force > 0: the largest
+// feasible G, force < 0: never).  Host tables for the chosen split.
+bool pml_choose_bands(const fwi_geometry& g, int nzp, int nxp, int ztop, int nfields, int ncu, int force, int* G,
+                      int* H, int* KC, int* NW);
+void pml_band_tables(const fwi_geometry& g, int nzp, int nxp, int ztop, int G, int H, int KC, std::vector<int>& cells,
+                     std::vector<int>& qcells, std::vector<int>& npub);
+// true while the stream is capturing a graph (cooperative launches cannot be captured)
+bool stream_capturing(hipStream_t st);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
 int launch_w2_obs(Plan& p, const float* d_obs, hipStream_t st);
 int launch_w2_misfit(const Plan& p, int B, const float* d_syn, double* J, float* adj, hipStream_t st);

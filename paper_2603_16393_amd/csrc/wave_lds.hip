@@ -208,7 +208,7 @@ static LdsArgs make_lds_args(const Plan& p) {
 // A cooperative launch cannot be recorded into a graph: while the caller's
 // stream is capturing, the whole-field kernels run instead (same results, bit
 // for bit).
-static bool capturing(hipStream_t st) {
+bool stream_capturing(hipStream_t st) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
         (void)hipGetLastError();
@@ -241,7 +241,7 @@ static int split_args(const Plan& p, int nfields, LdsArgs& a, SplitArgs& sp, hip
 static bool tail_split_args(const Plan& p, int nf, const LdsArgs& a, LdsArgs& ta, SplitArgs& sp, int* head,
                             hipStream_t st, int* rc) {
     *rc = FWI_OK;
-    if (!p.tail_xchg || p.ncu <= 0 || nf <= p.ncu || capturing(st)) return false;
+    if (!p.tail_xchg || p.ncu <= 0 || nf <= p.ncu || stream_capturing(st)) return false;
     const int h = (nf / p.ncu) * p.ncu, tail = nf - h;
     if (tail <= 0) return false;
     int X = 0, P = 0, ncg = 0, nstrip = 0, G = 1;
@@ -271,7 +271,7 @@ int launch_lds_forward(const Plan& p, int B, float* traces, const float* wavelet
     a.wavelet = wavelet;
     a.store = store;
     const int nf = B * p.g.ns;
-    if (p.split_G > 1 && !capturing(st)) {
+    if (p.split_G > 1 && !stream_capturing(st)) {
         SplitArgs sp{};
         const int rc = split_args(p, nf, a, sp, st);
         if (rc) return rc;
@@ -300,7 +300,7 @@ int launch_lds_adjoint(const Plan& p, int B, const float* adj, const float* wave
     a.adj = adj;
     a.wavelet = wavelet;
     const int nf = B * p.g.ns;
-    if (p.split_G > 1 && !capturing(st)) {
+    if (p.split_G > 1 && !stream_capturing(st)) {
         SplitArgs sp{};
         const int rc = split_args(p, nf, a, sp, st);
         if (rc) return rc;
