@@ -42,9 +42,9 @@ constexpr int kPmlThreads = 1024;
 constexpr int kPmlMaxCells = 7;
 // PML row bands: threads per band, most cells per thread, auxiliary-update
 // cells and received halo words per thread.
-constexpr int kPmlBandThreads = 512;
-constexpr int kPmlBandMaxKC = 8;
-constexpr int kPmlBandKQ = 2;
+constexpr int kPmlBandThreads = 1024;
+constexpr int kPmlBandMaxKC = 4;
+constexpr int kPmlBandKQ = 1;
 constexpr int kPmlBandKH = 2;
 
 // Cell order of the PML sweep.  Slots list (1) the model cells at least 4

@@ -70,6 +70,12 @@
 #include <algorithm>
 #include <utility>
 
+// No implicit fusing of a multiply and an add: the whole-field and the band
+// sweeps must round every operation alike (the compiler otherwise fuses,
+// say, the source term's product into the following sum in one kernel and
+// not in the other).  Fused multiply-adds are written out with fmaf.
+#pragma clang fp contract(off)
+
 namespace fwi {
 
 namespace {
@@ -93,7 +99,7 @@ __device__ __forceinline__ int opaque(int x) {
 }
 
 // Cells per thread of the compiled band kernels.
-#define FWI_PML_BAND_CASES(X) X(2) X(3) X(4) X(5) X(6) X(8)
+#define FWI_PML_BAND_CASES(X) X(1) X(2) X(3) X(4)
 
 struct PmlArgs {
     int nzp, nxp, npts;
@@ -715,7 +721,7 @@ bool pml_choose_bands(const fwi_geometry& g, int nzp, int nxp, int ztop, int nfi
         if (!ok) continue;
         int KC = 0;
         const int need = (H * nxp + T - 1) / T;
-        for (int c : {2, 3, 4, 5, 6, 8})
+        for (int c : {1, 2, 3, 4})
             if (c >= need) {
                 KC = c;
                 break;
