@@ -68,15 +68,39 @@ int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st) {
 // 64 x 16 tile); the tile of u^n plus a 4-cell halo is staged in LDS.
 constexpr int TX = 64, TZ = 16, TSTRIP = 4, TROWS = TZ / TSTRIP;
 
+// Tile of a block, XCD-aware.  Workgroups are dealt to the 8 XCDs in turn
+// (hardware block b runs on XCD b mod 8), each with its own L2; the tiles are
+// therefore renumbered so that every XCD sweeps one contiguous run of them in
+// row-major order (columns, then rows, then fields), and the halo rows and
+// columns a tile shares with its neighbours are read from that XCD's L2.
+// A bijection of the grid, so every tile is still computed exactly once.
+struct TileIdx {
+    int tx, tz, field;
+};
+__device__ __forceinline__ TileIdx tile_of_block() {
+    constexpr int kXcd = 8;
+    const int nbx = gridDim.x, nby = gridDim.y;
+    const int n = nbx * nby * gridDim.z;
+    const int b = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const int xcd = b % kXcd, q = n / kXcd, r = n - q * kXcd;
+    const int t = xcd * q + min(xcd, r) + b / kXcd;
+    TileIdx ti;
+    ti.tx = t % nbx;
+    ti.tz = (t / nbx) % nby;
+    ti.field = t / (nbx * nby);
+    return ti;
+}
+
 template <bool ADJ>
 __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const float* __restrict__ ax_g,
                                                    const float* __restrict__ az_g) {
     constexpr int SS = TX + 8;
     __shared__ float tile[(TZ + 8) * SS];
-    const int field = blockIdx.z;
+    const TileIdx ti = tile_of_block();
+    const int field = ti.field;
     const int b = field / a.ns;
     const int s = field - b * a.ns;
-    const int x0 = blockIdx.x * TX, zt = blockIdx.y * TZ;
+    const int x0 = ti.tx * TX, zt = ti.tz * TZ;
     const int tx = threadIdx.x % TX, ts = threadIdx.x / TX;
     const int nxp = a.nxp, nzp = a.nzp;
     const float* uc = a.ucur + (size_t)field * a.npts;
@@ -151,63 +175,106 @@ template <bool ADJ>
 __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const float* __restrict__ ax_g,
                                                     const float* __restrict__ az_g, float* __restrict__ wout,
                                                     float* __restrict__ Dout2, const float* __restrict__ Din2) {
+    // Each phase first issues all of a thread's global loads (clamped addresses, so no
+    // load sits in a divergent branch) and only then uses them: the loads of one
+    // thread overlap instead of waiting one by one.
+    constexpr int NA = (AZ * AX + 255) / 256;  // u^n values staged per thread
+    constexpr int NE = (EZ * EX + 255) / 256;  // step-1 points per thread
     __shared__ float A[AZ * AX];   // u^n
     __shared__ float Bt[EZ * EX];  // u^{n+1}
     __shared__ float W1[TZ * TX];  // w^{n+1} of the tile
-    const int field = blockIdx.z;
+    const TileIdx ti = tile_of_block();
+    const int field = ti.field;
     const int b = field / a.ns;
     const int s = field - b * a.ns;
-    const int x0 = blockIdx.x * TX, zt = blockIdx.y * TZ;
+    const int x0 = ti.tx * TX, zt = ti.tz * TZ;
     const int nxp = a.nxp, nzp = a.nzp;
     const float* uc = a.ucur + (size_t)field * a.npts;
     const float* wg = a.wst + (size_t)field * a.npts;
     const float* Kb = a.K + (size_t)b * a.npts;
     const int sp = a.src_pt[s];
     const size_t trf = (size_t)field * a.nr;
+    const int tid = threadIdx.x;
 
-    for (int i = threadIdx.x; i < AZ * AX; i += 256) {
-        const int r = i / AX, c = i - (i / AX) * AX;
-        int gz = zt + r - 8;
-        const int gx = x0 + c - 8;
-        if (a.fs && gz < 0) gz = -gz;
-        A[i] = (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) ? uc[gz * nxp + gx] : 0.f;
+    {
+        float va[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int i = tid + k * 256;
+            const int r = i / AX, c = i - (i / AX) * AX;
+            int gz = zt + r - 8;
+            const int gx = x0 + c - 8;
+            if (a.fs && gz < 0) gz = -gz;
+            const float t = uc[min(max(gz, 0), nzp - 1) * nxp + min(max(gx, 0), nxp - 1)];
+            va[k] = (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) ? t : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k)
+            if (tid + k * 256 < AZ * AX) A[tid + k * 256] = va[k];
     }
     __syncthreads();
 
     // step 1 on the tile and its ring
     const bool rec1 = (zt + TZ + 4 > a.rec_z0) && (zt - 4 <= a.rec_z1);
-    for (int i = threadIdx.x; i < EZ * EX; i += 256) {
-        const int r = i / EX, c = i - (i / EX) * EX;
-        const int gz = zt + r - 4, gx = x0 + c - 4;
-        float un = 0.f;
-        if (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) {
+    {
+        float kv[NE], wv[NE], dv[NE], av[NE], iv[NE];
+        int rv[NE];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int i = tid + k * 256;
+            const int r = i / EX, c = i - (i / EX) * EX;
+            const int gz = min(max(zt + r - 4, 0), nzp - 1), gx = min(max(x0 + c - 4, 0), nxp - 1);
             const int p = gz * nxp + gx;
-            const int li = (r + 4) * AX + c + 4;
-            const float cc = A[li];
-            const float lzs = FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX], A[li + AX],
-                                       A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
-            const float lxs = FWI_LAPD(cc, A[li - 4], A[li - 3], A[li - 2], A[li - 1], A[li + 1], A[li + 2], A[li + 3],
-                                       A[li + 4]);
-            float D = fmaf(lzs, a.idz2, lxs * a.idx2);
-            const int rr = rec1 ? a.rec_map[p] : -1;
-            if (!ADJ && p == sp) D = fmaf(a.wavelet[m], a.src_scale, D);
-            if (ADJ && rr >= 0) D = fmaf(a.rec_invw[rr], a.adj[(trf + rr) * a.nt + (a.nt - 1 - m)], D);
-            const float wn = fmaf(Kb[p], D, (ax_g[gx] * az_g[gz]) * wg[p]);
-            un = cc + wn;
-            const bool own = r >= 4 && r < 4 + TZ && c >= 4 && c < 4 + TX;
-            if (own) {
-                W1[(r - 4) * TX + c - 4] = wn;
-                if (!ADJ) {
-                    if (a.Dout) a.Dout[(size_t)field * a.dstride + p] = D;
-                    if (rr >= 0 && a.traces) a.traces[(trf + rr) * a.nt + m + 1] = un;
+            kv[k] = Kb[p];
+            wv[k] = wg[p];
+            dv[k] = ax_g[gx] * az_g[gz];
+            rv[k] = -1;
+            av[k] = iv[k] = 0.f;
+            if (rec1) {
+                rv[k] = a.rec_map[p];
+                if (ADJ) {
+                    const int q = max(rv[k], 0);
+                    av[k] = a.adj[(trf + q) * a.nt + (a.nt - 1 - m)];
+                    iv[k] = a.rec_invw[q];
                 }
             }
         }
-        Bt[i] = un;
+        const float src = ADJ ? 0.f : a.wavelet[m];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int i = tid + k * 256;
+            const int r = i / EX, c = i - (i / EX) * EX;
+            const int gz = zt + r - 4, gx = x0 + c - 4;
+            float un = 0.f;
+            if (i < EZ * EX && gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) {
+                const int p = gz * nxp + gx;
+                const int li = (r + 4) * AX + c + 4;
+                const float cc = A[li];
+                const float lzs = FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX],
+                                           A[li + AX], A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
+                const float lxs = FWI_LAPD(cc, A[li - 4], A[li - 3], A[li - 2], A[li - 1], A[li + 1], A[li + 2],
+                                           A[li + 3], A[li + 4]);
+                float D = fmaf(lzs, a.idz2, lxs * a.idx2);
+                const int rr = rv[k];
+                if (!ADJ && p == sp) D = fmaf(src, a.src_scale, D);
+                if (ADJ && rr >= 0) D = fmaf(iv[k], av[k], D);
+                const float wn = fmaf(kv[k], D, dv[k] * wv[k]);
+                un = cc + wn;
+                const bool own = r >= 4 && r < 4 + TZ && c >= 4 && c < 4 + TX;
+                if (own) {
+                    W1[(r - 4) * TX + c - 4] = wn;
+                    if (!ADJ) {
+                        if (a.Dout) a.Dout[(size_t)field * a.dstride + p] = D;
+                        if (rr >= 0 && a.traces) a.traces[(trf + rr) * a.nt + m + 1] = un;
+                    }
+                }
+            }
+            if (i < EZ * EX) Bt[i] = un;
+        }
     }
     __syncthreads();
     if (a.fs && zt == 0) {  // rows above a reflecting top mirror rows 1..4 of u^{n+1}
-        for (int i = threadIdx.x; i < 4 * EX; i += 256) {
+        for (int i = tid; i < 4 * EX; i += 256) {
             const int r = i / EX, c = i - (i / EX) * EX;
             Bt[i] = Bt[(8 - r) * EX + c];
         }
@@ -215,13 +282,38 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
     }
 
     // step 2 on the tile (the mapping of k_wave_tile)
-    const int tx = threadIdx.x % TX, ts = threadIdx.x / TX;
+    const int tx = tid % TX, ts = tid / TX;
     const int gx = x0 + tx;
     if (gx >= nxp) return;
     const float axv = ax_g[gx];
     const bool rec2 = (zt + TZ > a.rec_z0) && (zt <= a.rec_z1);
     float* un_g = a.unxt + (size_t)field * a.npts;
     float* wo = wout + (size_t)field * a.npts;
+    float kv[TROWS], zv[TROWS], av[TROWS], iv[TROWS], d1[TROWS], d2[TROWS], sv[TROWS];
+    int rv[TROWS];
+#pragma unroll
+    for (int j = 0; j < TROWS; ++j) {
+        const int gz = min(zt + ts * TROWS + j, nzp - 1);
+        const int p = gz * nxp + gx;
+        kv[j] = Kb[p];
+        zv[j] = az_g[gz];
+        rv[j] = -1;
+        av[j] = iv[j] = d1[j] = d2[j] = sv[j] = 0.f;
+        if (rec2) {
+            rv[j] = a.rec_map[p];
+            if (ADJ) {
+                const int q = max(rv[j], 0);
+                av[j] = a.adj[(trf + q) * a.nt + (a.nt - 2 - m)];
+                iv[j] = a.rec_invw[q];
+            }
+        }
+        if (ADJ && a.Din) {
+            d1[j] = a.Din[(size_t)field * a.dstride + p];
+            d2[j] = Din2[(size_t)field * a.dstride + p];
+            sv[j] = a.acc[(size_t)field * a.npts + p];
+        }
+    }
+    const float src = ADJ ? 0.f : a.wavelet[m + 1];
 #pragma unroll
     for (int j = 0; j < TROWS; ++j) {
         const int lz = ts * TROWS + j;
@@ -235,18 +327,17 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
         const float lxs = FWI_LAPD(cc, Bt[li - 4], Bt[li - 3], Bt[li - 2], Bt[li - 1], Bt[li + 1], Bt[li + 2],
                                    Bt[li + 3], Bt[li + 4]);
         float D = fmaf(lzs, a.idz2, lxs * a.idx2);
-        const int rr = rec2 ? a.rec_map[p] : -1;
-        if (!ADJ && p == sp) D = fmaf(a.wavelet[m + 1], a.src_scale, D);
-        if (ADJ && rr >= 0) D = fmaf(a.rec_invw[rr], a.adj[(trf + rr) * a.nt + (a.nt - 2 - m)], D);
-        const float wn = fmaf(Kb[p], D, (axv * az_g[gz]) * W1[lz * TX + tx]);
+        const int rr = rv[j];
+        if (!ADJ && p == sp) D = fmaf(src, a.src_scale, D);
+        if (ADJ && rr >= 0) D = fmaf(iv[j], av[j], D);
+        const float wn = fmaf(kv[j], D, (axv * zv[j]) * W1[lz * TX + tx]);
         const float un = cc + wn;
         wo[p] = wn;
         un_g[p] = un;
         if (ADJ) {
             if (a.Din) {
-                float* acc = a.acc + (size_t)field * a.npts + p;
-                const float s1 = fmaf(cc, a.Din[(size_t)field * a.dstride + p], *acc);
-                *acc = fmaf(un, Din2[(size_t)field * a.dstride + p], s1);
+                const float s1 = fmaf(cc, d1[j], sv[j]);
+                a.acc[(size_t)field * a.npts + p] = fmaf(un, d2[j], s1);
             }
         } else {
             if (Dout2) Dout2[(size_t)field * a.dstride + p] = D;
