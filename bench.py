@@ -183,45 +183,36 @@ def cpu_baseline_one_core():
             "sample": f"1 shot unit of sample 0 on one thread, {dt:.2f} s, scaled by {NS} units per gradient"}
 
 
-# HBM bytes per sweep launch of the default workload from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
-# scaled by the same counters' reading for the library's plain copy kernel (profiles/
-# k_wave_split_b16_70x70_hbm_traffic.md).  Valid only for the kernel sources they were taken on.
-TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_lds.hip", "paper_2603_16393_amd/csrc/wave_lds_body.h",
-                   "paper_2603_16393_amd/csrc/wave_split_body.h", "paper_2603_16393_amd/csrc/fwi_internal.h",
-                   "paper_2603_16393_amd/csrc/capi.hip")
-TRAFFIC_SHA1 = "a57887327f76d6070fa8ed3042681b09880e670f"
-TRAFFIC_BYTES = {"forward": 8993384903.0, "adjoint": 8532083148.0}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the same counter reads
+# for the library's plain copy kernel in the same run (profiles/*_hbm_traffic.md).  A figure holds only while the
+# sources of its kernel are the ones the counters were taken on (SHA-1 over the listed files); otherwise None.
+CSRC = "paper_2603_16393_amd/csrc/"
+MEASURED_TRAFFIC = {
+    # split LDS-resident sweep of the default workload (profiles/k_wave_split_b16_70x70_hbm_traffic.md)
+    "split": {"sources": (CSRC + "wave_lds.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
+              "sha1": "299bbb53899791cd234802952f4a601f17afe23f", "bytes": {"forward": 8.9947e9, "adjoint": 8.5322e9}},
+    # PML row bands (profiles/k_wave_pml_b16_70x70_hbm_traffic.md)
+    "pml": {"sources": (CSRC + "wave_pml.hip", CSRC + "wave_split_body.h"), "sha1": "106660c4198f1f4b2299be354e8ae8219440761d",
+            "bytes": {"forward": 4.2929e9, "adjoint": 4.3226e9}},
+    # two-step tiled sweep of the 400 x 800 workload, per launch (profiles/k_wave_tile2_ckpt_400x800_hbm_traffic.md):
+    # forward launch u, w, K read and u, w written; a recomputation launch also writes its two D slices
+    "tile2": {"sources": (CSRC + "wave.hip",), "sha1": "cc9c480f5925e6d77586e193ec94ba5af0d23279",
+              "bytes": {"forward": 9.936e7 + 6.48e7, "recompute": 9.936e7 + 2 * 6.48e7, "adjoint": 2.971e8}},
+    # uneven persistent forward launch of the 64-request mix (profiles/k_batch_uneven64_hbm_traffic.md)
+    "uneven": {"sources": (CSRC + "batch.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
+               "sha1": "3b31d958d4103aaa3ebc4b867139e4623c31c145", "bytes": {"forward": 1.2330e11, "gradient": 2.7489e12}},
+}
 
 
-def kernel_sources_sha1():
+def measured_traffic(name, kind):
+    t = MEASURED_TRAFFIC[name]
+    if t["sha1"] is None or t["bytes"].get(kind) is None:
+        return None
     h = hashlib.sha1()
-    for f in TRAFFIC_SOURCES:
+    for f in t["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return h.hexdigest()
-
-
-def measured_traffic(kind):
-    if TRAFFIC_SHA1 is None or TRAFFIC_BYTES.get(kind) is None or kernel_sources_sha1() != TRAFFIC_SHA1:
-        return None
-    return TRAFFIC_BYTES[kind]
-
-
-# The same for the PML sweeps (profiles/k_wave_pml_b16_70x70_hbm_traffic.md).
-PML_TRAFFIC_SOURCES = ("paper_2603_16393_amd/csrc/wave_pml.hip", "paper_2603_16393_amd/csrc/fwi_internal.h",
-                       "paper_2603_16393_amd/csrc/capi.hip")
-PML_TRAFFIC_SHA1 = "26585e8458d82c08ada843d9007e68199654f34e"
-PML_TRAFFIC_BYTES = {"forward": 2017390302.0, "adjoint": 2021792880.0}
-
-
-def pml_measured_traffic(kind):
-    h = hashlib.sha1()
-    for f in PML_TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if PML_TRAFFIC_SHA1 is None or PML_TRAFFIC_BYTES.get(kind) is None or h.hexdigest() != PML_TRAFFIC_SHA1:
-        return None
-    return PML_TRAFFIC_BYTES[kind]
+    return t["bytes"][kind] if h.hexdigest() == t["sha1"] else None
 
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2603_16393_amd", "weights", "surrogate_70x70.npy")
@@ -574,7 +565,7 @@ def pml_guidance(acq, v0hat, v_true, x0, w, steps=10, warmup=2):
                                     else "k_wave_pml<7, adjoint>"),
                          "achieved": round(achieved, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": pml_measured_traffic("adjoint"), "alg_bytes_per_launch": alg,
+                         "traffic": measured_traffic("pml", "adjoint"), "alg_bytes_per_launch": alg,
                          "launch_ms": round(adj_ms, 3)},
             "protocol": f"same {B} models, shots and observations source as the plain line; 6-cell PML, W2 misfit "
                         f"(k = 100); {steps} timed steps after {warmup} warm-up"}
@@ -668,7 +659,6 @@ def bench_pml(args):
 UNIT_KIND = {0: "lds", 1: "hbm", 2: "bands"}
 # HBM bytes per forward launch of the 64-request mix from FETCH_SIZE and WRITE_SIZE (None until measured for the
 # current batch kernel)
-UNEVEN_TRAFFIC_BYTES = None
 
 
 def bench_uneven(args):
@@ -748,6 +738,9 @@ def bench_uneven(args):
     gradient = {"ms": round(gms, 3), "requests_per_s": round(len(reqs) / (gms / 1e3), 2),
                 "fields_per_s": round(sum(a.ns for a, _, _ in reqs) / (gms / 1e3), 1),
                 "forward_gpts_per_s": round(upd / (gms / 1e3) / 1e9, 1), "cost_vs_forward": round(gms / ms, 3)}
+    gtr = measured_traffic("uneven", "gradient")
+    gradient["traffic"] = gtr  # HBM bytes of the launch (counters), and their rate over the timed launch
+    gradient["measured_traffic_GBps"] = round(gtr / (gms / 1e3) / 1e9, 1) if gtr else None
     out = {
         "metric": "uneven batch forward GPts/s (64 requests, 70/140/256 grids, 1000-2500 steps)",
         "value": round(gpts, 1),
@@ -771,11 +764,11 @@ def bench_uneven(args):
         # LDS-resident row bands), so the rate is effective and the HBM bytes the counters measure are far fewer
         "roofline": {"bound": "hbm", "kernel": "k_batch_forward (one persistent launch)",
                      "achieved": round(16.0 * gpts, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(16.0 * gpts / HBM_PEAK_GBS, 4), "traffic": UNEVEN_TRAFFIC_BYTES,
+                     "frac": round(16.0 * gpts / HBM_PEAK_GBS, 4), "traffic": measured_traffic("uneven", "forward"),
                      "alg_bytes_per_launch": 16.0 * upd, "launch_ms": round(ms, 3),
                      "achieved_kind": "effective (algorithmic bytes / launch time)",
-                     "measured_traffic_GBps": (round(UNEVEN_TRAFFIC_BYTES / (ms / 1e3) / 1e9, 1)
-                                               if UNEVEN_TRAFFIC_BYTES else None),
+                     "measured_traffic_GBps": (round(measured_traffic("uneven", "forward") / (ms / 1e3) / 1e9, 1)
+                                               if measured_traffic("uneven", "forward") else None),
                      "limiter": "VALU issue and per-step workgroup barriers / halo exchange (fields LDS-resident)"},
         "tiles": [{"padded": [t[0], t[1]], "kind": UNIT_KIND[t[2]], "tile": [t[3], t[4]], "parts": t[5]}
                   for t in tiles],
@@ -897,6 +890,9 @@ def bench_checkpointed(args):
     # read back by the adjoint (4 B each)
     alg = per_sweep * (16.0 + 4.0) * 2
     achieved = alg / (adj_ms / 1e3) / 1e9
+    # measured HBM bytes of the same phase: its recomputation and adjoint launches (two steps each)
+    tr, ta = measured_traffic("tile2", "recompute"), measured_traffic("tile2", "adjoint")
+    phase_traffic = (nt // 2) * (tr + ta) if tr and ta else None
     print(json.dumps({
         "metric": f"checkpointed guidance gradient (400x800, 20 shots, {nt} samples)",
         "value": round(1e3 / ms, 4), "unit": "grads/s", "ms_per_gradient": round(ms, 2), "steps": args.steps,
@@ -904,7 +900,9 @@ def bench_checkpointed(args):
         "sweep_ms": {"forward": round(fwd_ms, 2), "recompute_and_adjoint": round(adj_ms, 2)},
         "roofline": {"bound": "hbm", "kernel": "k_wave_tile2 (recomputation + adjoint steps, two steps per launch)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_phase": alg},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": phase_traffic, "alg_bytes_per_phase": alg,
+                     "measured_traffic_GBps": (round(phase_traffic / (adj_ms / 1e3) / 1e9, 1) if phase_traffic
+                                               else None)},
         "plan": {k: plan.info[k] for k in ("path", "store_mode", "ckpt_every", "device_bytes")},
         "memory_budget_bytes": budget, "dtype": "f32", "data": "synthetic",
     }))
@@ -1030,7 +1028,7 @@ def main():
     kname = "k_wave_split" if split else "k_wave_lds"
     dom = f"{kname}<ADJ> (adjoint sweep)" if adj_dominant else f"{kname} (forward sweep)"
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
-    traffic = measured_traffic("adjoint" if adj_dominant else "forward")
+    traffic = measured_traffic("split", "adjoint" if adj_dominant else "forward")
     # after the timed region; not in counter runs, whose calibration dispatches are the only copies
     copy_gbps = None if args.copy_calibration else copy_rate_gbps(dev)
     ddpm_us = None if args.copy_calibration else ddpm_step_us(dev, v)
