@@ -542,16 +542,20 @@ typedef struct fwi_batch fwi_batch;
 typedef struct {
     int autotune;   /* 1: time the candidate tiles per size class at creation; 0: cost model */
     int gradients;  /* 1: also allocate what fwi_batch_gradient needs (per field: the full history of D for
-                       LDS-resident fields; checkpoints every ceil(sqrt(2 (nt - 1))) steps, one segment of D
-                       and the adjoint state for HBM-swept ones) */
+                       LDS-resident fields and row bands; checkpoints every ceil(sqrt(2 (nt - 1))) steps, one
+                       segment of D and the adjoint state for HBM-swept ones) */
+    int bands;      /* 0: fields too large for one workgroup's LDS whose receivers share a row run as
+                       LDS-resident row bands (in a gradient batch only when the full history of D of those
+                       fields takes at most 60 % of the device memory free at creation); -1: never, they are
+                       swept from HBM */
 } fwi_batch_options;
 
 typedef struct {
     size_t v_offset, wavelet_offset, trace_offset;
     int nzp, nxp;           /* padded grid */
     int kind;               /* 0: LDS-resident, 1: swept from HBM, 2: LDS-resident row bands on several
-                               workgroups (forward-only batches, fields too large for one workgroup's LDS whose
-                               receivers share a row) */
+                               workgroups (fields too large for one workgroup's LDS whose receivers share a
+                               row; see fwi_batch_options.bands) */
     int tile_x, tile_z;     /* kinds 0 and 2: register tile (columns, rows); kind 1: sweep tile */
     int tuned;              /* 1 if the tile was picked by timing (kind 2: by the cost model, 0) */
     int parts;              /* workgroups per field: kind 1 row parts swept in lockstep, kind 2 row bands
@@ -576,7 +580,8 @@ int fwi_batch_forward(fwi_batch* batch, const float* v, const float* wavelets, f
  * the linearised forward map, Sec. 4, summed over shots and folded onto the
  * model): grad packed like v.  Each field runs its forward sweep and its
  * adjoint sweep in the same persistent launch (HBM-swept fields recompute
- * each checkpoint segment), then one launch folds the imaging sums.
+ * each checkpoint segment; row bands run both sweeps band by band, exchanging
+ * halos in each), then one launch folds the imaging sums.
  * FWI_ESTATE unless the batch was created with options.gradients = 1.
  * Asynchronous. */
 int fwi_batch_gradient(fwi_batch* batch, const float* v, const float* wavelets, const float* adj, float* grad,

@@ -114,7 +114,7 @@ class PlanOptions(ctypes.Structure):
 
 
 class BatchOptions(ctypes.Structure):
-    _fields_ = [("autotune", c_int), ("gradients", c_int)]
+    _fields_ = [("autotune", c_int), ("gradients", c_int), ("bands", c_int)]
 
 
 class BatchRequestInfo(ctypes.Structure):

@@ -22,7 +22,7 @@ __all__ = ["FwiBatch"]
 
 class FwiBatch:
     def __init__(self, acqs: Sequence, autotune: bool = True, device: Optional[torch.device] = None,
-                 gradients: bool = False):
+                 gradients: bool = False, bands: bool = True):
         L = _lib.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.acqs = list(acqs)
@@ -36,7 +36,7 @@ class FwiBatch:
                                      int(bool(a.free_surface)), float(a.v_max), len(idx[0]), ip[0], ip[1], len(idx[2]),
                                      ip[2], ip[3], int(bool(getattr(a, "pml", False))))
         h = ctypes.c_void_p()
-        opts = _lib.BatchOptions(int(bool(autotune)), int(bool(gradients)))
+        opts = _lib.BatchOptions(int(bool(autotune)), int(bool(gradients)), 0 if bands else -1)
         with torch.cuda.device(self.device):
             check(L.fwi_batch_create(len(self.acqs), geoms, ctypes.byref(opts), ctypes.byref(h)), "fwi_batch_create")
         self._h = h

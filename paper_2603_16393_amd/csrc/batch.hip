@@ -22,6 +22,7 @@
 // the autotuner below, which times the candidates on a short sweep of the
 // class's first unit replicated over every compute unit.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -53,6 +54,7 @@ struct BatchUnit {
     long long tr_off, w_off;  // offsets of this unit's traces and wavelet in the call's packed buffers
     LdsArgs la;     // kinds 0 and 2: pointers already offset to this unit (field index 0)
     SplitArgs sp;   // kind 2: bands of the field, its exchange rows (field0 = 0); the band is `part`
+    unsigned long long* xchg_adj;  // kind 2 in gradient batches: exchange rows of the adjoint sweep
     // kind 1
     int nzp, nxp, fs, nt, nr, src_pt, rec_z0, rec_z1;
     float idz2, idx2, src_scale;
@@ -472,8 +474,45 @@ __device__ void unit_lds_gradient(const BatchUnit* __restrict__ U, float* lds) {
     unit_lds_adjoint<X, P, EX>(U, lds);
 }
 
+// Row band of a split field: its forward sweep keeping the history of D of
+// its rows, then its adjoint sweep with the imaging sum of its rows.  The
+// bands of the field exchange halos in both sweeps (separate exchange rows,
+// so a band that starts its adjoint early never meets forward words).
+template <int X, int PI, bool EX>
+__device__ __noinline__ void unit_split_forward_store(const BatchUnit* __restrict__ U, float* lds) {
+    const LdsArgs a = U->la;
+    split_field<X, PI, false, EX, true>(a, U->sp, 0, U->part, U->ax, U->az, lds);
+}
+
+template <int X, int PI, bool EX>
+__device__ __noinline__ void unit_split_adjoint(const BatchUnit* __restrict__ U, float* lds) {
+    LdsArgs a = U->la;
+    a.adj = U->adj;
+    a.gpad = U->gpad;
+    SplitArgs sp = U->sp;
+    sp.xchg = U->xchg_adj;
+    split_field<X, PI, true, EX, false>(a, sp, 0, U->part, U->ax, U->az, lds);
+}
+
+template <int X, int PI, bool EX>
+__device__ void unit_split_gradient(const BatchUnit* __restrict__ U, float* lds) {
+    unit_split_forward_store<X, PI, EX>(U, lds);
+    __syncthreads();
+    unit_split_adjoint<X, PI, EX>(U, lds);
+}
+
 __device__ void run_unit_gradient(const BatchUnit* U, float* lds) {
     const int kind = U->kind, variant = U->variant;
+    if (kind == 2) {
+#define FWI_SPLIT_CASE(ID, XX, PP, EX)               \
+    if (variant == ID) {                             \
+        unit_split_gradient<XX, PP, EX>(U, lds);     \
+        return;                                      \
+    }
+        FWI_BATCH_SPLIT(FWI_SPLIT_CASE)
+#undef FWI_SPLIT_CASE
+        return;
+    }
     if (kind == 0) {
 #define FWI_LDS_CASE(ID, XX, PP, EX)              \
     if (variant == ID) {                          \
@@ -924,9 +963,10 @@ extern "C" {
 int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_options* opt, fwi_batch** out) {
     if (!out || nreq < 1 || !geoms) return FWI_EINVAL;
     *out = nullptr;
-    fwi_batch_options o{1, 0};
+    fwi_batch_options o{1, 0, 0};
     if (opt) o = *opt;
-    if (o.autotune < 0 || o.autotune > 1 || o.gradients < 0 || o.gradients > 1) return FWI_EINVAL;
+    if (o.autotune < 0 || o.autotune > 1 || o.gradients < 0 || o.gradients > 1 || o.bands < -1 || o.bands > 0)
+        return FWI_EINVAL;
     for (int r = 0; r < nreq; ++r) {
         const int st = validate_geometry(&geoms[r], 1);
         if (st) return st;
@@ -1015,25 +1055,44 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             for (int v = 0; v < kBatchLdsVariants; ++v)
                 if (lds_var_fits(v, b->nzp[r], b->nxp[r], &ncg, &nstrip)) b->kind[r] = 0;
     }
-    // forward-only batches: fields too large for one workgroup's LDS run as row
-    // bands held in LDS (layout from the split sweep's cost model), when their
-    // receivers share a row
+    // fields too large for one workgroup's LDS run as row bands held in LDS
+    // (layout from the split sweep's cost model) when their receivers share a
+    // row; in a gradient batch only when the full history of D of those fields
+    // fits (at most 60 % of the device memory free at creation), else they are
+    // swept from HBM with checkpoints
     b->sp_X.assign(nreq, 0);
     b->sp_P.assign(nreq, 0);
     b->sp_ncg.assign(nreq, 0);
     b->sp_nstrip.assign(nreq, 0);
     b->sp_G.assign(nreq, 0);
-    for (int r = 0; r < nreq && st == FWI_OK && !o.gradients; ++r) {
-        if (b->kind[r] != 1 || !rd[r].ht.one_row) continue;
-        int X = 0, P = 0, ncg = 0, nstrip = 0, G = 0, v = -1;
-        if (!batch_split_layout(b->nzp[r], b->nxp[r], &X, &P, &ncg, &nstrip, &G, &v) || G > b->n_cu) continue;
-        b->kind[r] = 2;
-        b->variant[r] = v;
-        b->sp_X[r] = X;
-        b->sp_P[r] = P;
-        b->sp_ncg[r] = ncg;
-        b->sp_nstrip[r] = nstrip;
-        b->sp_G[r] = G;
+    {
+        std::vector<std::array<int, 7>> cand;  // r, X, P, ncg, nstrip, G, variant
+        size_t dbytes = 0;
+        for (int r = 0; r < nreq && st == FWI_OK && o.bands >= 0; ++r) {
+            if (b->kind[r] != 1 || !rd[r].ht.one_row) continue;
+            int X = 0, P = 0, ncg = 0, nstrip = 0, G = 0, v = -1;
+            if (!batch_split_layout(b->nzp[r], b->nxp[r], &X, &P, &ncg, &nstrip, &G, &v) || G > b->n_cu) continue;
+            cand.push_back({r, X, P, ncg, nstrip, G, v});
+            dbytes += (size_t)b->g[r].ns * b->nzp[r] * b->nxp[r] * (size_t)(b->g[r].nt - 1) * sizeof(float);
+        }
+        if (o.gradients && !cand.empty()) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                (void)hipGetLastError();
+                free_b = 0;
+            }
+            if ((double)dbytes > 0.6 * (double)free_b) cand.clear();
+        }
+        for (const auto& c : cand) {
+            const int r = c[0];
+            b->kind[r] = 2;
+            b->variant[r] = c[6];
+            b->sp_X[r] = c[1];
+            b->sp_P[r] = c[2];
+            b->sp_ncg[r] = c[3];
+            b->sp_nstrip[r] = c[4];
+            b->sp_G[r] = c[5];
+        }
     }
 
     // autotuning per size class: every candidate on a 64-step sweep of the
@@ -1173,7 +1232,9 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                 if (b->kind[r] == 2) np = b->sp_G[r];
                 for (int q = 0; q < np; ++q) jobs.push_back({cost / np, r, s, q, np});
                 if (np > 1 && b->kind[r] == 1) ++nsplit;
-                if (b->kind[r] == 2) xchg_words += (size_t)np * 2 * 2 * 4 * b->sp_ncg[r] * b->sp_X[r];
+                // kind 2: exchange rows of the forward sweep, and of the adjoint sweep in gradient batches
+                if (b->kind[r] == 2)
+                    xchg_words += (o.gradients ? 2 : 1) * (size_t)np * 2 * 2 * 4 * b->sp_ncg[r] * b->sp_X[r];
                 if (b->kind[r] == 1) state_elems += 3 * (size_t)b->nzp[r] * b->nxp[r];
             }
         std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& c) { return a.cost > c.cost; });
@@ -1211,9 +1272,10 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             if (b->kind[r] == 2) {
                 auto it = fxchg.find({r, j.s});
                 unsigned long long* xb;
+                const size_t words = (size_t)j.nparts * 2 * 2 * 4 * b->sp_ncg[r] * b->sp_X[r];
                 if (it == fxchg.end()) {
                     xb = b->xchg + xo;
-                    xo += (size_t)j.nparts * 2 * 2 * 4 * b->sp_ncg[r] * b->sp_X[r];
+                    xo += (o.gradients ? 2 : 1) * words;
                     fxchg[{r, j.s}] = xb;
                 } else {
                     xb = it->second;
@@ -1221,6 +1283,7 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                 U.sp.G = j.nparts;
                 U.sp.W = b->sp_ncg[r] * b->sp_X[r];
                 U.sp.xchg = xb;
+                U.xchg_adj = o.gradients ? xb + words : nullptr;
                 U.sp.err = b->flags;
                 U.sp.field0 = 0;
                 U.part = j.part;
@@ -1243,8 +1306,9 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
             b->lds_bytes = std::max(b->lds_bytes, lb);
         }
         if (st == FWI_OK && o.gradients) {
-            // per unit: LDS-resident -> full history of D; HBM-swept -> adjoint state,
-            // checkpoints every C = ceil(sqrt(2 (nt - 1))) steps and one segment of D
+            // per field: LDS-resident or row bands -> full history of D; HBM-swept ->
+            // adjoint state, checkpoints every C = ceil(sqrt(2 (nt - 1))) steps and one
+            // segment of D
             b->gradients = 1;
             long long gtot = 0;
             for (int r = 0; r < nreq; ++r) {
@@ -1276,7 +1340,7 @@ int fwi_batch_create(int nreq, const fwi_geometry* geoms, const fwi_batch_option
                 const size_t npts = (size_t)b->nzp[r] * b->nxp[r];
                 const int nsteps = b->g[r].nt - 1;
                 U.gpad = b->gpad + b->g_off[r] + (long long)shot * npts;
-                if (U.kind == 0) {
+                if (U.kind == 0 || U.kind == 2) {
                     float* dst = nullptr;
                     st = balloc(b, &dst, (size_t)nsteps * npts);
                     U.la.Dstore = dst;
@@ -1392,6 +1456,10 @@ int fwi_batch_gradient(fwi_batch* b, const float* v, const float* wavelets, cons
     const int blocks = (int)std::min<long long>((total + 255) / 256, 65535);
     hipLaunchKernelGGL(k_batch_prep, dim3(blocks), dim3(256), 0, st, b->d_prep, b->nreq, total, v, b->K, b->flags);
     if (hipGetLastError() != hipSuccess) return FWI_EHIP;
+    if (b->xchg) {  // the bands' exchange rows (both sweeps) start at time level 0
+        const int rc = launch_fill(reinterpret_cast<float*>(b->xchg), 2 * b->xchg_words, 0.f, st);
+        if (rc) return rc;
+    }
     const int grid = std::min<int>(b->n_cu, (int)b->units.size());
     int rc = launch_units(b->d_units, (int)b->units.size(), b->counter, grid, b->lds_bytes, b->tr_scratch, wavelets,
                           st, adj, true);

@@ -110,9 +110,9 @@ def test_small_uneven_batch_vs_oracle_and_plans(dev, autotune):
 
 def test_row_bands_agree_with_the_hbm_sweep(dev):
     """The 140 x 140 and 256 x 256 requests of the uneven workload (one of each, all shots): as LDS-resident row
-    bands (forward-only batch, kind 2) and as HBM-swept fields (a gradient batch keeps kind 1).  The two evaluate
-    the Laplacian in different FMA orders (the LDS family's and the tiled family's), so they agree to FP32
-    rounding, not bit for bit; each is reproducible bit for bit."""
+    bands (kind 2) and as HBM-swept fields (bands switched off: kind 1), forward traces and, in gradient batches,
+    gradients.  The two evaluate the Laplacian in different FMA orders (the LDS family's and the tiled family's),
+    so they agree to FP32 rounding, not bit for bit; each is reproducible bit for bit."""
     from paper_2603_16393_amd.batch import FwiBatch
 
     reqs = fi.uneven_requests()
@@ -120,24 +120,30 @@ def test_row_bands_agree_with_the_hbm_sweep(dev):
     for size in (140, 256):
         pick.append(next(r for r in range(len(reqs)) if reqs[r][0].nz == size))
     sel = [reqs[r] for r in pick]
-    out = {}
-    for grads in (False, True):
-        b = FwiBatch([a for a, _, _ in sel], autotune=False, device=dev, gradients=grads)
+    out, grad = {}, {}
+    for bands in (True, False):
+        b = FwiBatch([a for a, _, _ in sel], autotune=False, device=dev, gradients=True, bands=bands)
         kinds = [i["kind"] for i in b.info]
-        _say(f"gradients={grads}: kinds {kinds} parts {[i['parts'] for i in b.info]} "
+        _say(f"bands={bands}: kinds {kinds} parts {[i['parts'] for i in b.info]} "
              f"tiles {[(i['tile_x'], i['tile_z']) for i in b.info]}")
-        assert kinds == ([1, 1] if grads else [2, 2])
+        assert kinds == ([2, 2] if bands else [1, 1])
         v = b.pack_velocity([m for _, m, _ in sel])
         w = b.pack_wavelets([x for _, _, x in sel])
-        out[grads] = b.forward(v, w).cpu().numpy()
+        adj = b.pack_traces([_adjoint_sources(a, 70 + i) for i, (a, _, _) in enumerate(sel)])
+        out[bands] = b.forward(v, w).cpu().numpy()
         again = b.forward(v, w).cpu().numpy()
+        grad[bands] = b.gradient(v, w, adj).cpu().numpy()
+        grad_again = b.gradient(v, w, adj).cpu().numpy()
         torch.cuda.synchronize()
         assert b.status() == 0
-        assert np.array_equal(out[grads], again)
+        assert np.array_equal(out[bands], again)
+        assert np.array_equal(grad[bands], grad_again)
         b.close()
-    e = _rel(out[False], out[True])
-    _say(f"row bands vs HBM sweep: rel L2 {e:.2e}")
+    e = _rel(out[True], out[False])
+    eg = _rel(grad[True], grad[False])
+    _say(f"row bands vs HBM sweep: traces rel L2 {e:.2e}, gradients rel L2 {eg:.2e}")
     assert e <= 1e-5
+    assert eg <= 1e-5
 
 
 def test_invalid_velocity_flag(dev):
@@ -233,7 +239,12 @@ def test_small_uneven_batch_gradient_vs_oracle_and_plans(dev, autotune):
         ep = _rel(got, gp)
         _say(f"request {r} kind {kinds[r]}: gradient rel L2 vs oracle {err:.2e}, vs plan {ep:.2e}")
         assert err <= 1e-4
-        assert np.array_equal(got, gp), f"request {r}: batch and plan gradients differ"
+        if kinds[r] == 2:
+            # row bands evaluate the Laplacian in the LDS family's order, the plan's tiled sweep in the tiled
+            # family's: FP32 rounding apart
+            assert ep <= 1e-5, f"request {r}: batch and plan gradients differ"
+        else:
+            assert np.array_equal(got, gp), f"request {r}: batch and plan gradients differ"
     b.close()
 
 
