@@ -32,6 +32,18 @@ namespace fwi {
          fmaf(FWI_W2, ((p2) - (c)) - ((c) - (m2)),                                 \
               fmaf(FWI_W3, ((p3) - (c)) - ((c) - (m3)), FWI_W4 * (((p4) - (c)) - ((c) - (m4))))))
 
+// Global-memory view of a generic pointer: accesses through it compile to
+// global instructions rather than flat ones.  A flat access is also counted
+// as an LDS access, so a wave that waits for its LDS reads would wait for
+// every outstanding flat load or store too; this matters where a pointer
+// comes from a descriptor in memory (the persistent batch kernels), whose
+// address space the compiler cannot infer.
+#define FWI_AS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ FWI_AS_GLOBAL T* gmem(T* p) {
+    return (FWI_AS_GLOBAL T*)p;
+}
+
 // Largest LDS allocation of one workgroup on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kLdsThreads = 512;

@@ -60,7 +60,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
     const int nsteps = a.nt - 1;
 
     for (int i = tid; i < 2 * plane; i += blockDim.x) lds[i] = 0.f;
-    for (int i = tid; i < a.nstrip * P; i += blockDim.x) az_s[i] = (i < nzp) ? az_g[i] : 1.f;
+    for (int i = tid; i < a.nstrip * P; i += blockDim.x) az_s[i] = (i < nzp) ? gmem(az_g)[i] : 1.f;
 
     const int cg = tid % a.ncg;
     const int strip = tid / a.ncg;
@@ -80,11 +80,11 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
     int rr[X];
     int src_j = -1, src_c = -1;  // tile position of this field's source, if this thread owns it
     int rec_j = -1;              // tile row of the receiver row, if it crosses this tile
-    const float* Kb = a.K + (size_t)b * npts;
+    const FWI_AS_GLOBAL float* Kb = gmem(a.K) + (size_t)b * npts;
 #pragma unroll
     for (int c = 0; c < X; ++c) {
         const int x = x0 + c;
-        axv[c] = (active && x < nxp) ? ax_g[x] : 1.f;
+        axv[c] = (active && x < nxp) ? gmem(ax_g)[x] : 1.f;
         rr[c] = -1;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -95,7 +95,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
         }
     }
     if (active) {
-        const int sp = a.src_pt[s];
+        const int sp = gmem(a.src_pt)[s];
         const int sz = sp / nxp, sx = sp - (sp / nxp) * nxp;
         if (sx >= x0 && sx < x0 + X && sz >= z0 && sz < z0 + P) {
             src_j = sz - z0;
@@ -104,17 +104,17 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
         if (a.rec_row >= z0 && a.rec_row < z0 + P) {
             rec_j = a.rec_row - z0;
 #pragma unroll
-            for (int c = 0; c < X; ++c) rr[c] = (x0 + c < nxp) ? a.rec_of_col[x0 + c] : -1;
+            for (int c = 0; c < X; ++c) rr[c] = (x0 + c < nxp) ? gmem(a.rec_of_col)[x0 + c] : -1;
         }
     }
     const size_t trfield = (size_t)field * a.nr * a.nt;
     if (!ADJ && rec_j >= 0) {
 #pragma unroll
         for (int c = 0; c < X; ++c)
-            if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt] = 0.f;
+            if (rr[c] >= 0) gmem(a.traces)[trfield + (size_t)rr[c] * a.nt] = 0.f;
     }
-    float* Dfield = a.Dstore + (size_t)field * nsteps * npts;
-    float* Drow0 = Dfield + z0 * nxp + x0;  // this thread's tile corner in one D slice
+    FWI_AS_GLOBAL float* Dfield = gmem(a.Dstore) + (size_t)field * nsteps * npts;
+    FWI_AS_GLOBAL float* Drow0 = Dfield + z0 * nxp + x0;  // this thread's tile corner in one D slice
     __syncthreads();
 
     float* cur = lds;          // u^n
@@ -127,21 +127,21 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
     float dc[P][X];
     float adjv[X];
     if (ADJ && active) {
-        const float* Dr = Drow0 + (size_t)(nsteps - 1) * npts;
+        const FWI_AS_GLOBAL float* Dr = Drow0 + (size_t)(nsteps - 1) * npts;
 #pragma unroll
         for (int j = 0; j < P; ++j)
 #pragma unroll
             for (int c = 0; c < X; ++c) dc[j][c] = (EXACT || (z0 + j < nzp && x0 + c < nxp)) ? Dr[j * nxp + c] : 0.f;
 #pragma unroll
         for (int c = 0; c < X; ++c)
-            adjv[c] = (rec_j >= 0 && rr[c] >= 0) ? a.adj[trfield + (size_t)rr[c] * a.nt + nsteps] : 0.f;
+            adjv[c] = (rec_j >= 0 && rr[c] >= 0) ? gmem(a.adj)[trfield + (size_t)rr[c] * a.nt + nsteps] : 0.f;
     }
     for (int m = 0; m < nsteps; ++m) {
         if (active) {
             const bool more = ADJ && m + 1 < nsteps;
             // next step's slice (the last step re-reads slice 0: harmless, and the
             // reload stays unconditional so old and new values never coexist)
-            const float* Dn = ADJ ? Drow0 + (size_t)max(nsteps - 2 - m, 0) * npts : nullptr;
+            const FWI_AS_GLOBAL float* Dn = ADJ ? Drow0 + (size_t)max(nsteps - 2 - m, 0) * npts : nullptr;
             float drec[X];  // D at this thread's receivers for the current step
             if (ADJ && rec_j >= 0) {
 #pragma unroll
@@ -162,7 +162,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
 #pragma unroll
                 for (int c = 0; c < X; ++c) win[q][c] = rp[c];
             }
-            float* Dw = (!ADJ && STORE) ? Drow0 + (size_t)m * npts : nullptr;
+            FWI_AS_GLOBAL float* Dw = (!ADJ && STORE) ? Drow0 + (size_t)m * npts : nullptr;
             float* nb_ = nxt + (z0 + 4) * S + x0 + 4;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
@@ -224,12 +224,12 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
                 if (more) {
 #pragma unroll
                     for (int c = 0; c < X; ++c)
-                        adjv[c] = rr[c] >= 0 ? a.adj[trfield + (size_t)rr[c] * a.nt + (nsteps - m - 1)] : 0.f;
+                        adjv[c] = rr[c] >= 0 ? gmem(a.adj)[trfield + (size_t)rr[c] * a.nt + (nsteps - m - 1)] : 0.f;
                 }
             }
             if (src_j >= 0) {
                 if (!ADJ) {
-                    const float sv = a.wavelet[m] * a.src_scale;
+                    const float sv = gmem(a.wavelet)[m] * a.src_scale;
 #pragma unroll
                     for (int j = 0; j < P; ++j)
 #pragma unroll
@@ -241,7 +241,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
                             }
                 } else {
                     // the source's share of D^{N-2-m}: acc += psi^{N-1-m} s^{N-2-m}
-                    const float sv = a.wavelet[nsteps - 1 - m] * a.src_scale;
+                    const float sv = gmem(a.wavelet)[nsteps - 1 - m] * a.src_scale;
 #pragma unroll
                     for (int j = 0; j < P; ++j)
 #pragma unroll
@@ -252,7 +252,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
             if (!ADJ && rec_j >= 0) {
 #pragma unroll
                 for (int c = 0; c < X; ++c)
-                    if (rr[c] >= 0) a.traces[trfield + (size_t)rr[c] * a.nt + m + 1] = nb_[rec_j * S + c];
+                    if (rr[c] >= 0) gmem(a.traces)[trfield + (size_t)rr[c] * a.nt + m + 1] = nb_[rec_j * S + c];
             }
         }
         __syncthreads();
@@ -266,7 +266,7 @@ __device__ __forceinline__ void lds_field(const LdsArgs a, const int field, cons
 #pragma unroll
             for (int c = 0; c < X; ++c) {
                 const int z = z0 + j, x = x0 + c;
-                if (z < nzp && x < nxp) a.gpad[(size_t)field * npts + z * nxp + x] = acc[j][c];
+                if (z < nzp && x < nxp) gmem(a.gpad)[(size_t)field * npts + z * nxp + x] = acc[j][c];
             }
     }
 }

@@ -21,12 +21,12 @@
 namespace fwi {
 
 __device__ __forceinline__ void split_put(unsigned long long* p, float v, unsigned level) {
-    __hip_atomic_store(p, ((unsigned long long)level << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+    __hip_atomic_store(gmem(p), ((unsigned long long)level << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ unsigned long long split_get(const unsigned long long* p) {
-    return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One register tile of R rows x X columns: per-point K, w, imaging sum and
@@ -55,21 +55,21 @@ __device__ __forceinline__ void split_tile_init(SplitTile<R, X>& t, const LdsArg
 #pragma unroll
     for (int c = 0; c < X; ++c) {
         const int x = x0 + c;
-        t.ax[c] = (on && x < nxp) ? ax_g[x] : 1.f;
+        t.ax[c] = (on && x < nxp) ? gmem(ax_g)[x] : 1.f;
         t.rr[c] = -1;
         t.adjv[c] = 0.f;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int z = t.z + j;
             const bool in = on && z < nzp && x < nxp;
-            t.K[j][c] = in ? Kb[z * nxp + x] : 0.f;
+            t.K[j][c] = in ? gmem(Kb)[z * nxp + x] : 0.f;
             t.w[j][c] = 0.f;
             t.acc[j][c] = 0.f;
-            t.dc[j][c] = (ADJ && in) ? Dr[j * nxp + c] : 0.f;  // the adjoint's first slice
+            t.dc[j][c] = (ADJ && in) ? gmem(Dr)[j * nxp + c] : 0.f;  // the adjoint's first slice
         }
     }
     if (on) {
-        const int sp = a.src_pt[s];
+        const int sp = gmem(a.src_pt)[s];
         const int sz = sp / nxp, sx = sp - (sp / nxp) * nxp;
         if (sx >= x0 && sx < x0 + X && sz >= t.z && sz < t.z + R) {
             t.src_j = sz - t.z;
@@ -78,16 +78,16 @@ __device__ __forceinline__ void split_tile_init(SplitTile<R, X>& t, const LdsArg
         if (a.rec_row >= t.z && a.rec_row < t.z + R) {
             t.rec_j = a.rec_row - t.z;
 #pragma unroll
-            for (int c = 0; c < X; ++c) t.rr[c] = (x0 + c < nxp) ? a.rec_of_col[x0 + c] : -1;
+            for (int c = 0; c < X; ++c) t.rr[c] = (x0 + c < nxp) ? gmem(a.rec_of_col)[x0 + c] : -1;
             if (!ADJ) {
 #pragma unroll
                 for (int c = 0; c < X; ++c)
-                    if (t.rr[c] >= 0) a.traces[trfield + (size_t)t.rr[c] * a.nt] = 0.f;
+                    if (t.rr[c] >= 0) gmem(a.traces)[trfield + (size_t)t.rr[c] * a.nt] = 0.f;
             } else {
                 const int nsteps = a.nt - 1;
 #pragma unroll
                 for (int c = 0; c < X; ++c)
-                    if (t.rr[c] >= 0) t.adjv[c] = a.adj[trfield + (size_t)t.rr[c] * a.nt + nsteps];
+                    if (t.rr[c] >= 0) t.adjv[c] = gmem(a.adj)[trfield + (size_t)t.rr[c] * a.nt + nsteps];
             }
         }
     }
@@ -111,8 +111,8 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
     const int nsteps = a.nt - 1;
     const float* cb = cur + (t.lz + 4) * S + x0 + 4;
     float* nb = nxt + (t.lz + 4) * S + x0 + 4;
-    const float* Dn = ADJ ? Dt + (size_t)max(nsteps - 2 - m, 0) * npts : nullptr;
-    float* Dw = (!ADJ && STORE) ? Dt + (size_t)m * npts : nullptr;
+    const FWI_AS_GLOBAL float* Dn = ADJ ? gmem(Dt) + (size_t)max(nsteps - 2 - m, 0) * npts : nullptr;
+    FWI_AS_GLOBAL float* Dw = (!ADJ && STORE) ? gmem(Dt) + (size_t)m * npts : nullptr;
     // with exact columns, D goes through buffer accesses bounded by the field's
     // slice: rows past the field (last band) are dropped on store and read as 0,
     // so no per-point guard is needed
@@ -208,12 +208,12 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
         if (m + 1 < nsteps) {
 #pragma unroll
             for (int c = 0; c < X; ++c)
-                t.adjv[c] = t.rr[c] >= 0 ? a.adj[trfield + (size_t)t.rr[c] * a.nt + (nsteps - m - 1)] : 0.f;
+                t.adjv[c] = t.rr[c] >= 0 ? gmem(a.adj)[trfield + (size_t)t.rr[c] * a.nt + (nsteps - m - 1)] : 0.f;
         }
     }
     if (t.src_j >= 0) {
         if (!ADJ) {
-            const float sv = a.wavelet[m] * a.src_scale;
+            const float sv = gmem(a.wavelet)[m] * a.src_scale;
 #pragma unroll
             for (int j = 0; j < R; ++j)
 #pragma unroll
@@ -224,7 +224,7 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
                         nb[j * S + c] += dv;
                     }
         } else {
-            const float sv = a.wavelet[nsteps - 1 - m] * a.src_scale;
+            const float sv = gmem(a.wavelet)[nsteps - 1 - m] * a.src_scale;
 #pragma unroll
             for (int j = 0; j < R; ++j)
 #pragma unroll
@@ -235,7 +235,7 @@ __device__ __forceinline__ void split_tile_step(SplitTile<R, X>& t, const LdsArg
     if (!ADJ && t.rec_j >= 0) {
 #pragma unroll
         for (int c = 0; c < X; ++c)
-            if (t.rr[c] >= 0) a.traces[trfield + (size_t)t.rr[c] * a.nt + m + 1] = nb[t.rec_j * S + c];
+            if (t.rr[c] >= 0) gmem(a.traces)[trfield + (size_t)t.rr[c] * a.nt + m + 1] = nb[t.rec_j * S + c];
     }
 }
 
@@ -246,7 +246,7 @@ __device__ __forceinline__ void split_tile_gpad(const SplitTile<R, X>& t, const 
 #pragma unroll
         for (int c = 0; c < X; ++c) {
             const int z = t.z + j, x = x0 + c;
-            if (t.on && z < a.nzp && x < a.nxp) a.gpad[(size_t)field * a.npts + z * a.nxp + x] = t.acc[j][c];
+            if (t.on && z < a.nzp && x < a.nxp) gmem(a.gpad)[(size_t)field * a.npts + z * a.nxp + x] = t.acc[j][c];
         }
 }
 
@@ -271,7 +271,7 @@ __device__ __forceinline__ void split_field(const LdsArgs a, const SplitArgs sp,
     const int nsteps = a.nt - 1;
 
     for (int i = tid; i < 2 * plane; i += blockDim.x) lds[i] = 0.f;
-    for (int i = tid; i < H; i += blockDim.x) az_s[i] = (zs + i < nzp) ? az_g[zs + i] : 1.f;
+    for (int i = tid; i < H; i += blockDim.x) az_s[i] = (zs + i < nzp) ? gmem(az_g)[zs + i] : 1.f;
 
     const int cg = tid % ncg;
     const int row = tid / ncg;  // boundary row 0..7 / interior strip / halo row
