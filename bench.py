@@ -190,17 +190,17 @@ CSRC = "paper_2603_16393_amd/csrc/"
 MEASURED_TRAFFIC = {
     # split LDS-resident sweep of the default workload (profiles/k_wave_split_b16_70x70_hbm_traffic.md)
     "split": {"sources": (CSRC + "wave_lds.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
-              "sha1": "299bbb53899791cd234802952f4a601f17afe23f", "bytes": {"forward": 8.9947e9, "adjoint": 8.5322e9}},
+              "sha1": "48fba527a13d2bee2b5149d12fb76b8f0d2997f5", "bytes": {"forward": 8.9911e9, "adjoint": 8.5322e9}},
     # PML row bands (profiles/k_wave_pml_b16_70x70_hbm_traffic.md)
-    "pml": {"sources": (CSRC + "wave_pml.hip", CSRC + "wave_split_body.h"), "sha1": "106660c4198f1f4b2299be354e8ae8219440761d",
-            "bytes": {"forward": 4.2929e9, "adjoint": 4.3226e9}},
+    "pml": {"sources": (CSRC + "wave_pml.hip", CSRC + "wave_split_body.h"), "sha1": "7975399530e2a18482fe7d45aafc3036622c3739",
+            "bytes": {"forward": 4.2936e9, "adjoint": 4.3203e9}},
     # two-step tiled sweep of the 400 x 800 workload, per launch (profiles/k_wave_tile2_ckpt_400x800_hbm_traffic.md):
     # forward launch u, w, K read and u, w written; a recomputation launch also writes its two D slices
     "tile2": {"sources": (CSRC + "wave.hip",), "sha1": "cc9c480f5925e6d77586e193ec94ba5af0d23279",
               "bytes": {"forward": 9.936e7 + 6.48e7, "recompute": 9.936e7 + 2 * 6.48e7, "adjoint": 2.971e8}},
     # uneven persistent forward launch of the 64-request mix (profiles/k_batch_uneven64_hbm_traffic.md)
     "uneven": {"sources": (CSRC + "batch.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
-               "sha1": "3b31d958d4103aaa3ebc4b867139e4623c31c145", "bytes": {"forward": 1.2330e11, "gradient": 2.7489e12}},
+               "sha1": "89131c2aebfef7914550cba6f79dd6b123802a90", "bytes": {"forward": 1.2374e11, "gradient": 6.8432e11}},
 }
 
 
