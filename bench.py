@@ -837,10 +837,12 @@ def bench_surrogate(args):
     print(json.dumps(out))
 
 
-def bench_checkpointed(args):
+def bench_checkpointed(args, pml=False):
     """Adjoint with checkpointing: 400 x 800 model (dx = 10 m) with a 50-cell sponge, 20 surface shots x 800
     receivers, 4000 samples at dt = 0.8 ms, 10 Hz Ricker, smooth-plus-layered model with a high-velocity lens
-    (1500-5000 m/s); forward (u, w) checkpointed every 100 steps under a fixed memory budget."""
+    (1500-5000 m/s); forward (u, w) checkpointed every 100 steps under a fixed memory budget.  pml: the same
+    with the paper's 6-cell PML (Sec. 6.1) in place of the sponge, swept from HBM (forward u, w and psi
+    checkpointed)."""
     import torch
 
     import fwi_inputs as fi
@@ -849,8 +851,10 @@ def bench_checkpointed(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     nz, nx, ns, nt = 400, 800, 20, args.nt
-    acq = fi.surface_acquisition(nz, nx, ns=ns, shot_cols=np.arange(ns) * 40, nt=nt, nb=50, dt=8e-4, f_peak=10.0,
-                                 v_max=5000.0)
+    acq = fi.surface_acquisition(nz, nx, ns=ns, shot_cols=np.arange(ns) * 40, nt=nt, nb=6 if pml else 50, dt=8e-4,
+                                 f_peak=10.0, v_max=5000.0)
+    if pml:
+        acq = dataclass_replace(acq, pml=True)
     v = fi.large_lens_model(nz, nx, seed=0)
     vt = fi.large_lens_model(nz, nx, seed=1)
     w = fi.ricker(nt, acq.dt, acq.f_peak)
@@ -871,7 +875,7 @@ def bench_checkpointed(args):
     for i in range(max(1, args.warmup)):
         step()
         torch.cuda.synchronize()
-        print(f"checkpointed: warm-up gradient {i + 1} done", file=sys.stderr, flush=True)
+        print(f"checkpointed{' PML' if pml else ''}: warm-up gradient {i + 1} done", file=sys.stderr, flush=True)
     plan.sweep_ms()  # restart the sweep event averages at the timed region
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -885,20 +889,29 @@ def bench_checkpointed(args):
     nzp, nxp = acq.padded_shape
     per_sweep = ns * (nt - 1) * nzp * nxp
     updates = 3 * per_sweep  # forward, recomputation, adjoint
-    # algorithmic bytes of the adjoint phase (the dominant one): per point-update 16 B (u^n, w^n, K read,
-    # u^{n+1} written) in both the recomputation and the adjoint steps, plus D written by the recomputation and
-    # read back by the adjoint (4 B each)
-    alg = per_sweep * (16.0 + 4.0) * 2
+    if pml:
+        # PML HBM sweep, per point-update: recomputation 24 B (u^n read, w read and written, K read, u^{n+1} and
+        # D written), adjoint 40 B (y^{n+1} read, nu and mu read and written, K and D read, the imaging sum read
+        # and written, y^n written); the layer's auxiliary fields are 1 % of the cells
+        alg = per_sweep * (24.0 + 40.0)
+        kernel = "k_pml_hbm_step (recomputation + adjoint steps, one step per launch)"
+        phase_traffic = None
+    else:
+        # algorithmic bytes of the adjoint phase (the dominant one): per point-update 16 B (u^n, w^n, K read,
+        # u^{n+1} written) in both the recomputation and the adjoint steps, plus D written by the recomputation
+        # and read back by the adjoint (4 B each)
+        alg = per_sweep * (16.0 + 4.0) * 2
+        kernel = "k_wave_tile2 (recomputation + adjoint steps, two steps per launch)"
+        # measured HBM bytes of the same phase: its recomputation and adjoint launches (two steps each)
+        tr, ta = measured_traffic("tile2", "recompute"), measured_traffic("tile2", "adjoint")
+        phase_traffic = (nt // 2) * (tr + ta) if tr and ta else None
     achieved = alg / (adj_ms / 1e3) / 1e9
-    # measured HBM bytes of the same phase: its recomputation and adjoint launches (two steps each)
-    tr, ta = measured_traffic("tile2", "recompute"), measured_traffic("tile2", "adjoint")
-    phase_traffic = (nt // 2) * (tr + ta) if tr and ta else None
     print(json.dumps({
-        "metric": f"checkpointed guidance gradient (400x800, 20 shots, {nt} samples)",
+        "metric": f"checkpointed guidance gradient (400x800, 20 shots, {nt} samples{', 6-cell PML' if pml else ''})",
         "value": round(1e3 / ms, 4), "unit": "grads/s", "ms_per_gradient": round(ms, 2), "steps": args.steps,
         "gpts_per_s": round(updates / (ms / 1e3) / 1e9, 2),
         "sweep_ms": {"forward": round(fwd_ms, 2), "recompute_and_adjoint": round(adj_ms, 2)},
-        "roofline": {"bound": "hbm", "kernel": "k_wave_tile2 (recomputation + adjoint steps, two steps per launch)",
+        "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": phase_traffic, "alg_bytes_per_phase": alg,
                      "measured_traffic_GBps": (round(phase_traffic / (adj_ms / 1e3) / 1e9, 1) if phase_traffic
@@ -920,7 +933,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run the library's plain copy kernel on 512 MiB three times "
                          "(the reference dispatch for HBM traffic counters) and exit")
-    ap.add_argument("--workload", choices=["guidance", "checkpointed", "uneven", "surrogate", "pml"],
+    ap.add_argument("--workload", choices=["guidance", "checkpointed", "checkpointed_pml", "uneven", "surrogate", "pml"],
                     default="guidance")
     ap.add_argument("--nt", type=int, default=4000,
                     help="checkpointed workload: trace samples (the workload has 4000; shorter runs serve the HBM "
@@ -930,8 +943,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload == "checkpointed":
-        bench_checkpointed(args)
+    if args.workload in ("checkpointed", "checkpointed_pml"):
+        bench_checkpointed(args, pml=args.workload == "checkpointed_pml")
         return
     if args.workload == "uneven":
         bench_uneven(args)

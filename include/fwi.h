@@ -79,14 +79,16 @@ typedef struct {
     int pml;               /* 0: the nb-cell layer is the damping sponge; 1: it is a perfectly matched layer
                               (Sec. 2.1 absorbing boundary, Sec. 6.1: 6 cells on the left, right and bottom),
                               the unsplit second-order form of a complex coordinate stretch with the sponge's
-                              quadratic profile and strength.  Plans only (fwi_batch_create rejects it), with
-                              the full forward history (FWI_ENOMEM otherwise).  When max_batch * ns fields
-                              leave CUs idle, each field is split into row bands held by several workgroups
-                              (launched cooperatively; see `split` of fwi_plan_options); otherwise, and while
-                              the caller's stream is capturing a graph, the padded field must fit one
-                              workgroup's LDS (about 7,000 padded cells, e.g. a 70 x 70 model with 6 cells):
-                              FWI_EINVAL at plan creation if neither applies, at the call if only the bands
-                              apply and the stream is capturing. */
+                              quadratic profile and strength.  Plans only (fwi_batch_create rejects it).
+                              The field stays in LDS when it can (plan path 2, full forward history): in one
+                              workgroup (about 7,000 padded cells, e.g. a 70 x 70 model with 6 cells) or, when
+                              max_batch * ns fields leave CUs idle, split into row bands held by several
+                              workgroups (launched cooperatively; see `split` of fwi_plan_options).  Larger
+                              fields, a history that does not fit, ckpt_every > 0 and force_path = 1 take the
+                              HBM sweep (path 3, full history or checkpoints), with the same results bit for
+                              bit where both apply.  While the caller's stream is capturing a graph, path 2
+                              runs its one-workgroup sweep: FWI_EINVAL at the call if the field only fits as
+                              row bands. */
 } fwi_geometry;
 
 /* Misfit settings (Sec. 5.1 and Sec. 6.2).  Paper values: k = 100,
@@ -134,15 +136,17 @@ typedef struct {
                                   1: tiled sweep from HBM, two time steps per launch;
                                   2: PML sweep, field and auxiliary fields resident in LDS, one workgroup
                                   per (sample, shot), or lds_split workgroups per field each holding a band
-                                  of rows */
+                                  of rows;
+                                  3: PML sweep from HBM, one time step per two launches (auxiliary fields
+                                  of the layer, then every cell) */
     int store_mode;            /* 0: full history of D = L u + s kept for the adjoint;
                                   1: checkpoints every `ckpt_every` steps plus recomputation */
     int ckpt_every;
     int max_batch;
     size_t device_bytes;       /* device memory held by the plan */
     int lds_tile_x, lds_tile_z;  /* register tile of the LDS-resident path (0 on the tiled path) */
-    int lds_split;             /* LDS-resident and PML paths: workgroups sharing one field (1: one per field;
-                                  0 on the tiled path) */
+    int lds_split;             /* LDS-resident paths (0, 2): workgroups sharing one field (1: one per field;
+                                  0 on the tiled and PML HBM paths) */
 } fwi_plan_info;
 
 /* Creates a plan for up to `max_batch` velocity samples on the current device.
@@ -156,9 +160,10 @@ int fwi_plan_create(const fwi_geometry* geom, int max_batch, size_t mem_budget_b
 /* Execution options for fwi_plan_create_ex. */
 typedef struct {
     int force_path;     /* -1: automatic; 0: LDS-resident (FWI_EINVAL if the field does not fit);
-                           1: tiled sweep */
+                           1: tiled sweep (PML: its HBM sweep) */
     int ckpt_every;     /* 0: automatic (full history when it fits the budget, else checkpoints);
-                           > 0: checkpoint every ckpt_every steps and recompute (tiled path only) */
+                           > 0: checkpoint every ckpt_every steps and recompute (tiled sweep, or the PML's
+                           HBM sweep; FWI_EINVAL with force_path = 0) */
     int lds_tile_x;     /* LDS-resident path: columns x rows of one thread's register tile;   */
     int lds_tile_z;     /* 0, 0 = the built-in cost model's choice; FWI_EINVAL if not available */
     int timing;         /* 1: record HIP events around each forward and adjoint sweep on the caller's

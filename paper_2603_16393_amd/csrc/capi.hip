@@ -193,19 +193,17 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // spread of Sec. 2.1, or one buried row)
     bool one_row = true;
     for (int r = 1; r < nr; ++r) one_row = one_row && (p.rec_iz[r] == p.rec_iz[0]);
-    std::vector<int> pml_rec;
+    std::vector<int> pml_rec, pml_lcells;
     if (p.g.pml) {
-        // the PML sweep keeps the field in LDS (one workgroup, or row bands over several) and the full
-        // history of D
-        if (o.force_path != -1 || o.ckpt_every > 0 || o.lds_tile_x > 0 || o.lds_tile_z > 0) {
+        // the PML sweep keeps the field in LDS (one workgroup, or row bands over several) with the full
+        // history of D (path 2), or sweeps it from HBM (path 3: fields too large for that, a history that
+        // does not fit, checkpoints, or force_path = 1)
+        if (o.lds_tile_x > 0 || o.lds_tile_z > 0 || (o.force_path == 0 && o.ckpt_every > 0) ||
+            (o.split > 0 && (o.force_path == 1 || o.ckpt_every > 0))) {
             delete pp;
             return FWI_EINVAL;
         }
-        p.path = 2;
-        // receiver of each slot of the sweep's cell order
-        pml_rec.assign(npts, -1);
-        const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
-        for (int r = 0; r < nr; ++r) pml_rec[ord.model_slot(p.rec_iz[r], p.rec_ix[r])] = r;
+        p.path = (o.force_path == 1 || o.ckpt_every > 0) ? 3 : 2;
     } else {
         bool lds_ok = one_row && lds_choose_layout(p.nzp, p.nxp, o.lds_tile_x, o.lds_tile_z, &p.lds_X, &p.lds_P,
                                                    &p.lds_ncg, &p.lds_nstrip);
@@ -231,11 +229,13 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         }
         int G = 1, H = 0, KC = 0, NW = 0;
         const bool bands = coop && pml_choose_bands(p.g, p.nzp, p.nxp, p.ztop, (int)nf, ncu, o.split, &G, &H, &KC, &NW);
-        if ((o.split > 0 && !bands) || (!bands && !pml_fits(p.nzp, p.nxp))) {
+        if ((o.split > 0 && !bands) || (!bands && !pml_fits(p.nzp, p.nxp) && o.force_path == 0)) {
             delete pp;
             return FWI_EINVAL;
         }
-        if (bands) {
+        if (!bands && !pml_fits(p.nzp, p.nxp)) {
+            p.path = 3;
+        } else if (bands) {
             p.pml_G = G;
             p.pml_H = H;
             p.pml_KC = KC;
@@ -259,7 +259,13 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // fixed-size buffers
     size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
                    nf * nr * 8 + (size_t)ns * nr * 1000 * 8;
+    // PML HBM sweep: bordered planes (u, u, y, y, Q or G twice), w, nu, mu, psi, phi, traces, layer table
+    const size_t plane = (size_t)(p.nzp + 8) * (p.nxp + 8);
+    const size_t nl = (size_t)(p.nzp * p.nxp - p.g.nz * p.g.nx);
+    const size_t fixed_hbm_pml = (6 * nf * plane + 3 * nf * npts + 4 * nf * nl + 2 * nf * nr * (size_t)nt + npts + nl) *
+                                 sizeof(float);
     if (p.path == 1) fixed += (8 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
+    if (p.path == 3) fixed += fixed_hbm_pml;
     const size_t full_store = nf * nsteps * npts * sizeof(float);
     size_t avail = budget;
     if (avail == 0) {
@@ -276,20 +282,27 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     } else if (fixed + full_store <= avail) {
         p.store_mode = 0;
         p.ckpt_every = 0;
-    } else if (p.path == 2) {
+    } else if (p.path == 2 && o.force_path == 0) {
         free_all(p);
         delete pp;
         return FWI_ENOMEM;
     } else {
         if (p.path == 0) p.path = 1;  // checkpointing runs on the tiled sweep
+        if (p.path == 2) {            // and, for the PML, on its HBM sweep
+            p.path = 3;
+            p.pml_G = 1;
+            fixed += fixed_hbm_pml;
+        }
         p.store_mode = 1;
         int K = (int)std::ceil(std::sqrt(2.0 * (double)nsteps));
         p.ckpt_every = std::max(1, std::min<int>(K, (int)nsteps));
     }
     if (p.store_mode == 1) {
         p.nseg = (int)((nsteps + p.ckpt_every - 1) / p.ckpt_every);
-        const size_t need = fixed + 8 * nf * npts * sizeof(float) +
-                            nf * ((size_t)p.ckpt_every + 2 * (size_t)p.nseg) * npts * sizeof(float);
+        const size_t need = p.path == 3 ? fixed + nf * ((size_t)p.ckpt_every * npts +
+                                                        (size_t)p.nseg * (plane + npts + 2 * nl)) * sizeof(float)
+                                        : fixed + 8 * nf * npts * sizeof(float) +
+                                              nf * ((size_t)p.ckpt_every + 2 * (size_t)p.nseg) * npts * sizeof(float);
         if (need > avail) {
             free_all(p);
             delete pp;
@@ -298,7 +311,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     }
 
     // LDS-resident path: several workgroups per field when the batch leaves CUs idle
-    if (o.split > 0 && p.path == 1) {
+    if (o.split > 0 && (p.path == 1 || p.path == 3)) {
         free_all(p);
         delete pp;
         return FWI_EINVAL;
@@ -339,7 +352,17 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     p.rec_z0 = ht.rec_z0;
     p.rec_z1 = ht.rec_z1;
     std::vector<int> rec_of_col, rec_map;
-    if (p.path == 1) {
+    if (p.path == 2) {
+        // receiver of each slot of the LDS-resident PML sweep's cell order
+        pml_rec.assign(npts, -1);
+        const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
+        for (int r = 0; r < nr; ++r) pml_rec[ord.model_slot(p.rec_iz[r], p.rec_ix[r])] = r;
+    }
+    if (p.path == 3) {
+        pml_lcells = pml_layer_cells(p.g, p.nzp, p.nxp, p.ztop);
+        p.pml_nl = (int)pml_lcells.size();
+    }
+    if (p.path == 1 || p.path == 3) {
         rec_map = ht.rec_map;
     } else {
         p.rec_row = ht.rec_row;
@@ -372,6 +395,18 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
+    } else if (p.path == 3) {
+        const size_t nl2 = 2 * (size_t)p.pml_nl;
+        st = st ? st : alloc_n(p, &p.rec_map, npts);
+        st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
+        st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
+        st = st ? st : alloc_n(p, &p.pml_lcells, std::max<size_t>(pml_lcells.size(), 1));
+        st = st ? st : alloc_n(p, &p.state, nf * (2 * plane + npts + nl2));
+        st = st ? st : alloc_n(p, &p.astate, nf * (2 * plane + 2 * npts + nl2));
+        st = st ? st : alloc_n(p, &p.pml_gplanes, 2 * nf * plane);
+        st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
+        st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
+        if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
     } else if (p.path == 2) {
         st = st ? st : alloc_n(p, &p.pml_rec, npts);
         st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
@@ -392,7 +427,8 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.Dstore, nf * nsteps * npts);
     } else {
         st = st ? st : alloc_n(p, &p.Dstore, nf * (size_t)p.ckpt_every * npts);
-        st = st ? st : alloc_n(p, &p.ckpt, nf * (size_t)p.nseg * 2 * npts);
+        const size_t per = p.path == 3 ? plane + npts + 2 * (size_t)p.pml_nl : 2 * npts;
+        st = st ? st : alloc_n(p, &p.ckpt, nf * (size_t)p.nseg * per);
     }
     if (!st) {
         st = hip_ok(hipMemcpy(p.ax, axf.data(), axf.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -401,11 +437,16 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : hip_ok(hipMemcpy(p.src_pt, src_pt.data(), ns * sizeof(int), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.rec_pt, rec_pt.data(), nr * sizeof(int), hipMemcpyHostToDevice));
         st = st ? st : hip_ok(hipMemcpy(p.rec_invw, rec_invw.data(), nr * sizeof(float), hipMemcpyHostToDevice));
-        if (p.path == 2) {
+        if (p.path == 2 || p.path == 3) {
             std::vector<float> tx, tz;
             pml_profiles(p.g, p.nzp, p.nxp, p.ztop, tx, tz);
             st = st ? st : hip_ok(hipMemcpy(p.pml_tx, tx.data(), tx.size() * sizeof(float), hipMemcpyHostToDevice));
             st = st ? st : hip_ok(hipMemcpy(p.pml_tz, tz.data(), tz.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
+        if (p.path == 3 && !pml_lcells.empty())
+            st = st ? st : hip_ok(hipMemcpy(p.pml_lcells, pml_lcells.data(), pml_lcells.size() * sizeof(int),
+                                            hipMemcpyHostToDevice));
+        if (p.path == 2) {
             st = st ? st : hip_ok(hipMemcpy(p.pml_rec, pml_rec.data(), pml_rec.size() * sizeof(int),
                                             hipMemcpyHostToDevice));
             if (p.pml_G > 1) {
@@ -417,7 +458,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
                                                 hipMemcpyHostToDevice));
             }
         }
-        if (p.path == 1)
+        if (p.path == 1 || p.path == 3)
             st = st ? st : hip_ok(hipMemcpy(p.rec_map, rec_map.data(), npts * sizeof(int), hipMemcpyHostToDevice));
         else if (p.path == 0)
             st = st ? st
@@ -529,6 +570,8 @@ int fwi_forward(fwi_plan* plan, int B, const float* v, const float* wavelet, flo
         rc = launch_lds_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     else if (p.path == 2)
         rc = launch_pml_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
+    else if (p.path == 3)
+        rc = pml_hbm_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     else
         rc = tiled_forward(p, B, d_syn, wavelet, keep_for_adjoint ? 1 : 0, st);
     if (rc) return rc;
@@ -577,6 +620,8 @@ int fwi_adjoint_gradient(fwi_plan* plan, int B, const float* v, const float* adj
         rc = launch_lds_adjoint(p, B, adj_src, p.wav, st);
     else if (p.path == 2)
         rc = launch_pml_adjoint(p, B, adj_src, st);
+    else if (p.path == 3)
+        rc = pml_hbm_adjoint(p, B, adj_src, st);
     else
         rc = tiled_adjoint(p, B, adj_src, p.wav, nullptr, st);
     if (rc) return rc;

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "fwi.h"
@@ -226,7 +227,7 @@ struct Plan {
     int max_batch;
     size_t budget;
     int device;
-    int path;                            // 0 LDS-resident, 1 tiled, 2 PML (LDS-resident, one workgroup per field)
+    int path;                            // 0 LDS-resident, 1 tiled, 2 PML LDS-resident, 3 PML HBM sweep
     int store_mode;                      // 0 full, 1 checkpointed
     int ckpt_every;
     int nseg;
@@ -252,6 +253,11 @@ struct Plan {
     int* pml_qcells = nullptr;   // [G][kPmlBandKQ * kPmlBandThreads] cells of the auxiliary update, or -1
     int* pml_npub = nullptr;     // [G]
     unsigned long long* pml_xchg = nullptr;  // [max_batch*ns][G][2 edges][2 parity][NW]
+    // PML HBM sweep (path 3): layer cells, the Q / G planes; its u, w, psi and y, nu, mu, phi live in state and
+    // astate, the traces in trace_buf and adj_buf, the checkpoints in ckpt
+    int pml_nl = 0;
+    int* pml_lcells = nullptr;   // [pml_nl] layer cells iz << 16 | ix
+    float* pml_gplanes = nullptr;  // [2][max_batch*ns][(nzp + 8) (nxp + 8)]
     float* ax = nullptr;         // [nxp] sponge damping factor per padded column
     float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]
@@ -262,9 +268,11 @@ struct Plan {
     int rec_row = -1;            // padded row of the receivers when they share one row
     float* rec_invw = nullptr;   // [nr]
     float* Dstore = nullptr;     // full: [max_batch*ns][nt-1][npts]; ckpt: [max_batch*ns][ckpt_every][npts]
-    float* ckpt = nullptr;       // ckpt: [max_batch*ns][nseg][2][npts] (u^n, w^n)
-    float* state = nullptr;      // tiled: [4][max_batch*ns][npts] u and w, each ping-pong
-    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]
+    float* ckpt = nullptr;       // ckpt: [max_batch*ns][nseg][2][npts] (u^n, w^n); PML HBM sweep:
+                                 // [max_batch*ns][nseg][(nzp + 8) (nxp + 8) + npts + 2 pml_nl] (u plane, w, psi)
+    float* state = nullptr;      // tiled: [4][max_batch*ns][npts] u and w, each ping-pong; PML HBM sweep:
+                                 // two bordered u planes, w, psi (offsets by max_batch)
+    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]; PML HBM sweep: two y planes, nu, mu, phi
     float* acc = nullptr;        // tiled adjoint: [max_batch*ns][npts]
     float* gpad = nullptr;       // [max_batch*ns][npts]
     float* fold_tmp = nullptr;   // [max_batch][nzp][nx] column-folded gradient
@@ -351,6 +359,12 @@ size_t pml_lds_bytes(int nzp, int nxp);
 bool pml_fits(int nzp, int nxp);
 int launch_pml_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
 int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st);
+// PML HBM sweep (path 3): the padded cells outside the model, and the sweeps (captured graphs).
+std::vector<int> pml_layer_cells(const fwi_geometry& g, int nzp, int nxp, int ztop);
+int pml_hbm_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st);
+int pml_hbm_adjoint(Plan& p, int B, const float* adj, hipStream_t st);
+// Captures enqueue(p.cap) into an executable graph (replacing *exec).
+int capture_graph(Plan& p, hipGraphExec_t* exec, const std::function<void(hipStream_t)>& enqueue);
 // PML row bands for `nfields` fields on `ncu` CUs: bands G and rows per band H
 // (false when no split into 2 or more bands applies; force > 0: the largest
 // feasible G, force < 0: never).  Host tables for the chosen split.

@@ -583,8 +583,7 @@ static void enqueue_adjoint(Plan& p, int B, hipStream_t st) {
 }
 
 // Captures enqueue(p.cap) into an executable graph.
-template <class F>
-static int capture(Plan& p, hipGraphExec_t* exec, F&& enqueue) {
+int capture_graph(Plan& p, hipGraphExec_t* exec, const std::function<void(hipStream_t)>& enqueue) {
     if (*exec) {
         (void)hipGraphExecDestroy(*exec);
         *exec = nullptr;
@@ -602,7 +601,7 @@ int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep,
     copy(p.wav, wavelet, (size_t)p.g.nt, st);
     const int k = keep ? 1 : 0;
     if (!p.g_fwd[k] || p.g_fwd_B[k] != B) {
-        const int rc = capture(p, &p.g_fwd[k], [&](hipStream_t cs) { enqueue_forward(p, B, keep, cs); });
+        const int rc = capture_graph(p, &p.g_fwd[k], [&](hipStream_t cs) { enqueue_forward(p, B, keep, cs); });
         if (rc) return rc;
         p.g_fwd_B[k] = B;
     }
@@ -614,7 +613,7 @@ int tiled_forward(Plan& p, int B, float* traces, const float* wavelet, int keep,
 int tiled_adjoint(Plan& p, int B, const float* adj, const float* /*wavelet*/, float* /*unused*/, hipStream_t st) {
     copy(p.adj_buf, adj, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
     if (!p.g_adj || p.g_adj_B != B) {
-        const int rc = capture(p, &p.g_adj, [&](hipStream_t cs) { enqueue_adjoint(p, B, cs); });
+        const int rc = capture_graph(p, &p.g_adj, [&](hipStream_t cs) { enqueue_adjoint(p, B, cs); });
         if (rc) return rc;
         p.g_adj_B = B;
     }

@@ -126,10 +126,11 @@ def _pml_geom(nz, nx, recs, pml=1, nb=6):
     return g, keep
 
 
-@pytest.mark.parametrize("case", ["flag", "tiled", "checkpoint", "split", "too_big", "batch"])
+@pytest.mark.parametrize("case", ["flag", "lds_checkpoint", "lds_tile", "split", "split_hbm", "batch"])
 def test_pml_plan_validation(case):
-    """The PML layer (Sec. 6.1) runs on its own LDS-resident sweep: every
-    request it cannot serve is refused on the host with FWI_EINVAL."""
+    """The PML layer (Sec. 6.1) runs on its LDS-resident sweeps or on its HBM
+    sweep: every request neither can serve is refused on the host with
+    FWI_EINVAL."""
     from paper_2603_16393_amd import _lib
 
     L = _lib.load()
@@ -138,19 +139,44 @@ def test_pml_plan_validation(case):
     if case == "flag":
         g, keep = _pml_geom(20, 20, recs, pml=2)
         assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
-    elif case in ("tiled", "checkpoint", "split"):
-        g, keep = _pml_geom(20, 20, recs)
-        opts = _lib.PlanOptions(1 if case == "tiled" else -1, 10 if case == "checkpoint" else 0, 0, 0, 0,
-                                1 if case == "split" else 0)
-        assert L.fwi_plan_create_ex(ctypes.byref(g), 1, 0, ctypes.byref(opts), ctypes.byref(h)) == -1
-    elif case == "too_big":
-        g, keep = _pml_geom(120, 120, recs)  # 126 x 132 padded cells: more than one workgroup's LDS
-        assert L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h)) == -1
-    else:
+    elif case == "batch":
         g, keep = _pml_geom(20, 20, recs)
         geoms = (_lib.Geometry * 1)(g)
         assert L.fwi_batch_create(1, geoms, None, ctypes.byref(h)) == -1
+    else:
+        g, keep = _pml_geom(20, 20, recs)
+        opts = {"lds_checkpoint": (0, 10, 0, 0, 0, 0),  # the LDS-resident PML sweeps keep the full history
+                "lds_tile": (-1, 0, 3, 3, 0, 0),        # register tiles belong to the sponge's LDS sweep
+                "split": (-1, 0, 0, 0, 0, 1),           # 26 padded rows: too few for two row bands
+                "split_hbm": (1, 0, 0, 0, 0, 1)}[case]  # the HBM sweep has no row bands
+        o = _lib.PlanOptions(*opts)
+        assert L.fwi_plan_create_ex(ctypes.byref(g), 1, 0, ctypes.byref(o), ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("case", ["tiled", "checkpoint", "too_big"])
+def test_pml_hbm_requests_pass_host_validation(case):
+    """Requests the LDS-resident PML sweeps cannot serve go to the HBM sweep:
+    the host accepts them (without a GPU the plan then fails on device
+    memory, not on validation)."""
+    from paper_2603_16393_amd import _lib
+
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    recs = tuple((0, i) for i in range(8))
+    if case == "too_big":
+        g, keep = _pml_geom(120, 120, recs)  # 126 x 132 padded cells: more than one workgroup's LDS
+        rc = L.fwi_plan_create(ctypes.byref(g), 1, 0, ctypes.byref(h))
+    else:
+        g, keep = _pml_geom(20, 20, recs)
+        o = _lib.PlanOptions(1 if case == "tiled" else -1, 10 if case == "checkpoint" else 0, 0, 0, 0, 0)
+        rc = L.fwi_plan_create_ex(ctypes.byref(g), 1, 0, ctypes.byref(o), ctypes.byref(h))
+    assert rc != _lib.FWI_EINVAL
+    if rc == 0:
+        info = _lib.PlanInfo()
+        assert L.fwi_plan_get_info(h, ctypes.byref(info)) == 0
+        assert info.path in (2, 3)
+        assert L.fwi_plan_destroy(h) == 0
 
 
 @pytest.mark.parametrize("beta,abar,abar_prev,sigma", [(0.0, 0.5, 0.6, 0.0), (0.1, 0.7, 0.6, 0.0),
