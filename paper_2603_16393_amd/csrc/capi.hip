@@ -193,7 +193,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // spread of Sec. 2.1, or one buried row)
     bool one_row = true;
     for (int r = 1; r < nr; ++r) one_row = one_row && (p.rec_iz[r] == p.rec_iz[0]);
-    std::vector<int> pml_rec, pml_lcells;
+    std::vector<int> pml_rec;
     if (p.g.pml) {
         // the PML sweep keeps the field in LDS (one workgroup, or row bands over several) with the full
         // history of D (path 2), or sweeps it from HBM (path 3: fields too large for that, a history that
@@ -259,10 +259,10 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // fixed-size buffers
     size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
                    nf * nr * 8 + (size_t)ns * nr * 1000 * 8;
-    // PML HBM sweep: bordered planes (u, u, y, y, Q or G twice), w, nu, mu, psi, phi, traces, layer table
+    // PML HBM sweep: bordered planes (u, u, y, y), w, nu, mu, psi and phi (two each), traces, layer table
     const size_t plane = (size_t)(p.nzp + 8) * (p.nxp + 8);
     const size_t nl = (size_t)(p.nzp * p.nxp - p.g.nz * p.g.nx);
-    const size_t fixed_hbm_pml = (6 * nf * plane + 3 * nf * npts + 4 * nf * nl + 2 * nf * nr * (size_t)nt + npts + nl) *
+    const size_t fixed_hbm_pml = (4 * nf * plane + 3 * nf * npts + 8 * nf * nl + 2 * nf * nr * (size_t)nt + npts) *
                                  sizeof(float);
     if (p.path == 1) fixed += (8 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
     if (p.path == 3) fixed += fixed_hbm_pml;
@@ -358,10 +358,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
         for (int r = 0; r < nr; ++r) pml_rec[ord.model_slot(p.rec_iz[r], p.rec_ix[r])] = r;
     }
-    if (p.path == 3) {
-        pml_lcells = pml_layer_cells(p.g, p.nzp, p.nxp, p.ztop);
-        p.pml_nl = (int)pml_lcells.size();
-    }
+    if (p.path == 3) p.pml_nl = (int)nl;
     if (p.path == 1 || p.path == 3) {
         rec_map = ht.rec_map;
     } else {
@@ -400,10 +397,8 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.rec_map, npts);
         st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
         st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
-        st = st ? st : alloc_n(p, &p.pml_lcells, std::max<size_t>(pml_lcells.size(), 1));
-        st = st ? st : alloc_n(p, &p.state, nf * (2 * plane + npts + nl2));
-        st = st ? st : alloc_n(p, &p.astate, nf * (2 * plane + 2 * npts + nl2));
-        st = st ? st : alloc_n(p, &p.pml_gplanes, 2 * nf * plane);
+        st = st ? st : alloc_n(p, &p.state, nf * (2 * plane + npts + 2 * nl2));
+        st = st ? st : alloc_n(p, &p.astate, nf * (2 * plane + 2 * npts + 2 * nl2));
         st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
@@ -443,9 +438,6 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
             st = st ? st : hip_ok(hipMemcpy(p.pml_tx, tx.data(), tx.size() * sizeof(float), hipMemcpyHostToDevice));
             st = st ? st : hip_ok(hipMemcpy(p.pml_tz, tz.data(), tz.size() * sizeof(float), hipMemcpyHostToDevice));
         }
-        if (p.path == 3 && !pml_lcells.empty())
-            st = st ? st : hip_ok(hipMemcpy(p.pml_lcells, pml_lcells.data(), pml_lcells.size() * sizeof(int),
-                                            hipMemcpyHostToDevice));
         if (p.path == 2) {
             st = st ? st : hip_ok(hipMemcpy(p.pml_rec, pml_rec.data(), pml_rec.size() * sizeof(int),
                                             hipMemcpyHostToDevice));

@@ -33,6 +33,29 @@ namespace fwi {
          fmaf(FWI_W2, ((p2) - (c)) - ((c) - (m2)),                                 \
               fmaf(FWI_W3, ((p3) - (c)) - ((c) - (m3)), FWI_W4 * (((p4) - (c)) - ((c) - (m4))))))
 
+// Tile of a block, XCD-aware.  Workgroups are dealt to the 8 XCDs in turn
+// (hardware block b runs on XCD b mod 8), each with its own L2; the tiles are
+// therefore renumbered so that every XCD sweeps one contiguous run of them in
+// row-major order (columns, then rows, then fields), and the halo rows and
+// columns a tile shares with its neighbours are read from that XCD's L2.
+// A bijection of the grid, so every tile is still computed exactly once.
+struct TileIdx {
+    int tx, tz, field;
+};
+__device__ __forceinline__ TileIdx tile_of_block() {
+    constexpr int kXcd = 8;
+    const int nbx = gridDim.x, nby = gridDim.y;
+    const int n = nbx * nby * gridDim.z;
+    const int b = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const int xcd = b % kXcd, q = n / kXcd, r = n - q * kXcd;
+    const int t = xcd * q + min(xcd, r) + b / kXcd;
+    TileIdx ti;
+    ti.tx = t % nbx;
+    ti.tz = (t / nbx) % nby;
+    ti.field = t / (nbx * nby);
+    return ti;
+}
+
 // Global-memory view of a generic pointer: accesses through it compile to
 // global instructions rather than flat ones.  A flat access is also counted
 // as an LDS access, so a wave that waits for its LDS reads would wait for
@@ -253,11 +276,9 @@ struct Plan {
     int* pml_qcells = nullptr;   // [G][kPmlBandKQ * kPmlBandThreads] cells of the auxiliary update, or -1
     int* pml_npub = nullptr;     // [G]
     unsigned long long* pml_xchg = nullptr;  // [max_batch*ns][G][2 edges][2 parity][NW]
-    // PML HBM sweep (path 3): layer cells, the Q / G planes; its u, w, psi and y, nu, mu, phi live in state and
-    // astate, the traces in trace_buf and adj_buf, the checkpoints in ckpt
+    // PML HBM sweep (path 3): padded cells outside the model (each has psi_x, psi_z); its u, w, psi and y, nu,
+    // mu, phi live in state and astate, the traces in trace_buf and adj_buf, the checkpoints in ckpt
     int pml_nl = 0;
-    int* pml_lcells = nullptr;   // [pml_nl] layer cells iz << 16 | ix
-    float* pml_gplanes = nullptr;  // [2][max_batch*ns][(nzp + 8) (nxp + 8)]
     float* ax = nullptr;         // [nxp] sponge damping factor per padded column
     float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]
@@ -271,8 +292,9 @@ struct Plan {
     float* ckpt = nullptr;       // ckpt: [max_batch*ns][nseg][2][npts] (u^n, w^n); PML HBM sweep:
                                  // [max_batch*ns][nseg][(nzp + 8) (nxp + 8) + npts + 2 pml_nl] (u plane, w, psi)
     float* state = nullptr;      // tiled: [4][max_batch*ns][npts] u and w, each ping-pong; PML HBM sweep:
-                                 // two bordered u planes, w, psi (offsets by max_batch)
-    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]; PML HBM sweep: two y planes, nu, mu, phi
+                                 // two bordered u planes, w, two psi buffers (offsets by max_batch)
+    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]; PML HBM sweep: two y planes, nu, mu,
+                                 // two phi buffers
     float* acc = nullptr;        // tiled adjoint: [max_batch*ns][npts]
     float* gpad = nullptr;       // [max_batch*ns][npts]
     float* fold_tmp = nullptr;   // [max_batch][nzp][nx] column-folded gradient
@@ -359,8 +381,7 @@ size_t pml_lds_bytes(int nzp, int nxp);
 bool pml_fits(int nzp, int nxp);
 int launch_pml_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
 int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st);
-// PML HBM sweep (path 3): the padded cells outside the model, and the sweeps (captured graphs).
-std::vector<int> pml_layer_cells(const fwi_geometry& g, int nzp, int nxp, int ztop);
+// PML HBM sweep (path 3), captured graphs.
 int pml_hbm_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st);
 int pml_hbm_adjoint(Plan& p, int B, const float* adj, hipStream_t st);
 // Captures enqueue(p.cap) into an executable graph (replacing *exec).

@@ -68,29 +68,6 @@ int launch_prep_velocity(const Plan& p, int B, const float* v, hipStream_t st) {
 // 64 x 16 tile); the tile of u^n plus a 4-cell halo is staged in LDS.
 constexpr int TX = 64, TZ = 16, TSTRIP = 4, TROWS = TZ / TSTRIP;
 
-// Tile of a block, XCD-aware.  Workgroups are dealt to the 8 XCDs in turn
-// (hardware block b runs on XCD b mod 8), each with its own L2; the tiles are
-// therefore renumbered so that every XCD sweeps one contiguous run of them in
-// row-major order (columns, then rows, then fields), and the halo rows and
-// columns a tile shares with its neighbours are read from that XCD's L2.
-// A bijection of the grid, so every tile is still computed exactly once.
-struct TileIdx {
-    int tx, tz, field;
-};
-__device__ __forceinline__ TileIdx tile_of_block() {
-    constexpr int kXcd = 8;
-    const int nbx = gridDim.x, nby = gridDim.y;
-    const int n = nbx * nby * gridDim.z;
-    const int b = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
-    const int xcd = b % kXcd, q = n / kXcd, r = n - q * kXcd;
-    const int t = xcd * q + min(xcd, r) + b / kXcd;
-    TileIdx ti;
-    ti.tx = t % nbx;
-    ti.tz = (t / nbx) % nby;
-    ti.field = t / (nbx * nby);
-    return ti;
-}
-
 template <bool ADJ>
 __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const float* __restrict__ ax_g,
                                                    const float* __restrict__ az_g) {

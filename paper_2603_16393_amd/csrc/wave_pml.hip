@@ -65,6 +65,7 @@
 // and either may run the adjoint of the other's forward pass.
 
 #include "fwi_internal.h"
+#include "pml_stencil.h"
 #include "wave_split_body.h"
 
 #include <algorithm>
@@ -79,16 +80,6 @@
 namespace fwi {
 
 namespace {
-
-constexpr float kD1 = 4.0f / 5.0f;
-constexpr float kD2 = -1.0f / 5.0f;
-constexpr float kD3 = 4.0f / 105.0f;
-constexpr float kD4 = -1.0f / 280.0f;
-
-// Central first difference sum_k d_k (f(+k s) - f(-k s)) at c (unscaled).
-__device__ __forceinline__ float dfirst(const float* c, int s) {
-    return fmaf(kD1, c[s] - c[-s], fmaf(kD2, c[2 * s] - c[-2 * s], fmaf(kD3, c[3 * s] - c[-3 * s], kD4 * (c[4 * s] - c[-4 * s]))));
-}
 
 // Returns x unchanged, opaque to the optimiser: per-slot addresses derived
 // from it are recomputed in every step instead of being held in registers
@@ -704,355 +695,6 @@ int pml_band_args(const Plan& p, int nf, PmlBandArgs& bd, hipStream_t st) {
     return launch_fill(reinterpret_cast<float*>(p.pml_xchg), (size_t)nf * bd.G * 4 * bd.NW * 2, 0.f, st);
 }
 
-// ---------------------------------------------------------------------------
-// HBM sweep (path 3): the fields stay in device memory, for grids too large
-// for the LDS-resident sweeps and for checkpointed gradients.  Every gathered
-// plane (u or y, Q_x or G_x, Q_z or G_z) is stored with the 4-cell border of
-// the LDS planes, (nzp + 8) x (nxp + 8) per field, so a stencil never leaves
-// its plane: the border holds zeros, or the even (u, y) and odd (Q_z, G_z)
-// mirror rows above a reflecting top, written by the producer of each row.
-// One step is two launches: the auxiliary update over the layer cells
-// (psi, writes the Q or G planes), then the time update over every cell
-// (u^{n+1} into the other gather plane).  Each cell undergoes the operations
-// of the LDS-resident sweep in the same order, so the two give the same bits.
-struct PmlHbmArgs {
-    int nzp, nxp, npts;
-    int S, plane;                 // bordered row stride nxp + 8 and plane size (nzp + 8) S
-    int nz, nx, nb, ztop, fs;
-    int zlo, zhi, dw;             // deep model cells (no Q within 4 cells): rows [zlo, zhi), columns [4, 4 + dw)
-    int nt, ns, nr, nl;           // nl: layer cells
-    float idz, idx, idz2, idx2, src_scale;
-    const float* K;               // [B][npts] (v dt)^2
-    const float* tx;              // [nxp]
-    const float* tz;              // [nzp]
-    const int* lcells;            // [nl] layer cells iz << 16 | ix
-    const float* wavelet;         // [nt]
-    const int* src_pt;            // [ns] padded index
-    const int* rec_map;           // [npts] receiver of each padded cell, or -1
-    int rec_z0, rec_z1;           // padded rows holding receivers (inclusive): rec_map is read only there
-    const int* rec_pt;            // [nr]
-    const float* rec_invw;        // [nr]
-    float* traces;                // forward: [nf][nr][nt], or null (recomputation)
-    const float* adj;             // adjoint: [nf][nr][nt]
-    float* gpad;                  // adjoint: [nf][npts] imaging sums, padded order
-};
-
-// Auxiliary update of the layer cells (grid: layer cells x fields).
-// PS = [nf][2][nl]: psi_x (phi_x) then psi_z (phi_z) of each layer cell.
-template <bool ADJ>
-__global__ void __launch_bounds__(256) k_pml_hbm_aux(const PmlHbmArgs a, const float* __restrict__ F,
-                                                     float* __restrict__ GX, float* __restrict__ GZ,
-                                                     float* __restrict__ PS) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.nl) return;
-    const int f = blockIdx.y;
-    const int cell = a.lcells[i];
-    const int iz = cell >> 16, ix = cell & 0xffff;
-    const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
-    const float* c = F + o;
-    const float gx = a.idx * dfirst(c, 1);
-    const float gz = a.idz * dfirst(c, a.S);
-    const float txv = a.tx[ix], tzv = a.tz[iz];
-    const float cxv = 1.f / (1.f + txv), czv = 1.f / (1.f + tzv);
-    float* px = PS + (size_t)f * 2 * a.nl + i;
-    float* pz = px + a.nl;
-    const float pxv = *px, pzv = *pz;
-    float ox, oz;
-    if (!ADJ) {
-        const float Qx = cxv * fmaf(tzv - txv, gx, pxv);
-        const float Qz = czv * fmaf(txv - tzv, gz, pzv);
-        *px = 2.f * Qx - pxv;
-        *pz = 2.f * Qz - pzv;
-        ox = Qx;
-        oz = Qz;
-    } else {
-        const float Qx = 2.f * pxv - gx;
-        const float Qz = 2.f * pzv - gz;
-        *px = cxv * Qx - pxv;
-        *pz = czv * Qz - pzv;
-        ox = cxv * (tzv - txv) * Qx;
-        oz = czv * (txv - tzv) * Qz;
-    }
-    GX[o] = ox;
-    GZ[o] = oz;
-    if (a.fs && iz >= 1 && iz <= 4) GZ[o - 2 * iz * a.S] = -oz;
-}
-
-// Time update of every cell (block: 64 columns x 4 rows; grid: column and row
-// blocks x fields).  Forward: F = u^n, Fn = u^{n+1}, W = w, Dst = D^n slice
-// (or null).  Adjoint: F = y^{n+1}, Fn = y^n, W = nu, MU = mu, Dst = D^n.
-template <bool ADJ>
-__global__ void __launch_bounds__(256) k_pml_hbm_step(const PmlHbmArgs a, int n, const float* __restrict__ F,
-                                                      float* __restrict__ Fn, const float* __restrict__ GX,
-                                                      const float* __restrict__ GZ, float* __restrict__ W,
-                                                      float* __restrict__ MU, float* __restrict__ Dst,
-                                                      size_t dstride) {
-    const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int iz = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (ix >= a.nxp || iz >= a.nzp) return;
-    const int f = blockIdx.z;
-    const int b = f / a.ns, s = f - (f / a.ns) * a.ns;
-    const int S = a.S;
-    const int p = iz * a.nxp + ix;
-    const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * S + ix + 4;
-    const float* c = F + o;
-    const float c0 = c[0];
-    const float lz = FWI_LAPD(c0, c[-4 * S], c[-3 * S], c[-2 * S], c[-S], c[S], c[2 * S], c[3 * S], c[4 * S]);
-    const float lx = FWI_LAPD(c0, c[-4], c[-3], c[-2], c[-1], c[1], c[2], c[3], c[4]);
-    const float lap = fmaf(a.idx2, lx, a.idz2 * lz);
-    const int zm = iz - a.ztop, xm = ix - a.nb;
-    const bool model = zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx;
-    const bool deep = zm >= a.zlo && zm < a.zhi && xm >= 4 && xm < 4 + a.dw;
-    const float div = deep ? 0.f : fmaf(a.idx, dfirst(GX + o, 1), a.idz * dfirst(GZ + o, S));
-    const float txv = a.tx[ix], tzv = a.tz[iz];
-    const float E = 1.f / (1.f + txv + tzv);
-    const float r = a.K[(size_t)b * a.npts + p] * E;
-    float q = 1.f, bq = 0.f;
-    if (!model) {
-        q = (1.f - txv - tzv) * E;
-        bq = 4.f * txv * tzv * E;
-    }
-    const size_t fp = (size_t)f * a.npts + p;
-    const int rec = (iz >= a.rec_z0 && iz <= a.rec_z1) ? a.rec_map[p] : -1;
-    const size_t tr = ((size_t)f * a.nr + (rec >= 0 ? rec : 0)) * a.nt;
-    float out;
-    if (!ADJ) {
-        float D = lap + div;
-        if (p == a.src_pt[s]) D += a.wavelet[n] * a.src_scale;
-        const float w = fmaf(r, D, fmaf(q, W[fp], -bq * c0));
-        W[fp] = w;
-        out = c0 + w;
-        if (Dst) Dst[(size_t)f * dstride + p] = D;
-        if (rec >= 0 && a.traces) a.traces[tr + n + 1] = out;
-    } else {
-        const float dn = Dst[(size_t)f * dstride + p];
-        a.gpad[fp] = fmaf(c0, dn, a.gpad[fp]);  // imaging: y^{n+1} D^n
-        const float av = rec >= 0 ? a.adj[tr + n] * a.rec_invw[rec] : 0.f;
-        const float Fv = (lap - div) + av;
-        const float mu0 = MU[fp];
-        const float w = fmaf(q, W[fp], fmaf(-bq, mu0, Fv));
-        const float mu = mu0 + w;
-        W[fp] = w;
-        MU[fp] = mu;
-        out = r * mu;
-    }
-    Fn[o] = out;
-    if (a.fs && iz >= 1 && iz <= 4) Fn[o - 2 * iz * S] = out;
-}
-
-// Receivers at the start of a sweep (grid: receivers x fields).  Forward:
-// sample 0 of every trace is u^0 = 0.  Adjoint: mu^{N-1} = a^{N-1} / w at the
-// receivers, nu^{N-1} = mu^{N-1} and y = r mu (the other cells are zero).
-template <bool ADJ>
-__global__ void k_pml_hbm_start(const PmlHbmArgs a, float* __restrict__ Y, float* __restrict__ W,
-                                float* __restrict__ MU) {
-    const int rcv = blockIdx.x * 256 + threadIdx.x;
-    if (rcv >= a.nr) return;
-    const int f = blockIdx.y;
-    const size_t tr = ((size_t)f * a.nr + rcv) * a.nt;
-    if (!ADJ) {
-        a.traces[tr] = 0.f;
-        return;
-    }
-    const int p = a.rec_pt[rcv];
-    const int iz = p / a.nxp, ix = p - (p / a.nxp) * a.nxp;
-    const int b = f / a.ns;
-    const float mu = a.adj[tr + a.nt - 1] * a.rec_invw[rcv];
-    const size_t fp = (size_t)f * a.npts + p;
-    W[fp] = mu;
-    MU[fp] = mu;
-    const float E = 1.f / (1.f + a.tx[ix] + a.tz[iz]);
-    const float y = (a.K[(size_t)b * a.npts + p] * E) * mu;
-    const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
-    Y[o] = y;
-    if (a.fs && iz >= 1 && iz <= 4) Y[o - 2 * iz * a.S] = y;
-}
-
-// Saves (SAVE) or restores the forward state of every field at checkpoint
-// `seg`: the bordered u plane, w, and the layer's psi.
-// ckpt = [max fields][nseg][plane + npts + 2 nl].
-template <bool SAVE>
-__global__ void k_pml_hbm_ckpt(float* __restrict__ ckpt, float* __restrict__ F, float* __restrict__ W,
-                               float* __restrict__ PS, int nf, int nseg, int seg, int plane, int npts, int nl) {
-    const size_t per = (size_t)plane + npts + 2 * (size_t)nl;
-    const size_t total = (size_t)nf * per;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t f = i / per, e = i - (i / per) * per;
-        float* x = e < (size_t)plane ? F + f * plane + e
-                   : e < (size_t)plane + npts ? W + f * npts + (e - plane)
-                                              : PS + f * 2 * nl + (e - plane - npts);
-        float* c = ckpt + (f * nseg + seg) * per + e;
-        if (SAVE)
-            *c = *x;
-        else
-            *x = *c;
-    }
-}
-
-PmlHbmArgs make_pml_hbm_args(const Plan& p) {
-    PmlHbmArgs a{};
-    a.nzp = p.nzp;
-    a.nxp = p.nxp;
-    a.npts = p.npts;
-    a.S = p.nxp + 8;
-    a.plane = (p.nzp + 8) * a.S;
-    a.nz = p.g.nz;
-    a.nx = p.g.nx;
-    a.nb = p.g.nb;
-    a.ztop = p.ztop;
-    a.fs = p.g.free_surface;
-    const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
-    a.zlo = ord.zlo;
-    a.zhi = ord.zhi;
-    a.dw = ord.dw;
-    a.nt = p.g.nt;
-    a.ns = p.g.ns;
-    a.nr = p.g.nr;
-    a.nl = p.pml_nl;
-    a.idz = (float)(1.0 / p.g.dz);
-    a.idx = (float)(1.0 / p.g.dx);
-    a.idz2 = (float)(1.0 / (p.g.dz * p.g.dz));
-    a.idx2 = (float)(1.0 / (p.g.dx * p.g.dx));
-    a.src_scale = (float)(1.0 / (p.g.dx * p.g.dz));
-    a.K = p.K;
-    a.tx = p.pml_tx;
-    a.tz = p.pml_tz;
-    a.lcells = p.pml_lcells;
-    a.wavelet = p.wav;
-    a.src_pt = p.src_pt;
-    a.rec_map = p.rec_map;
-    a.rec_z0 = p.rec_z0;
-    a.rec_z1 = p.rec_z1;
-    a.rec_pt = p.rec_pt;
-    a.rec_invw = p.rec_invw;
-    a.gpad = p.gpad;
-    return a;
-}
-
-// State buffers of the HBM sweep, offsets fixed by max_batch.
-struct PmlHbmState {
-    float *F0, *F1, *W, *PS;      // forward: u planes (ping-pong), w, psi
-    float *Y0, *Y1, *NU, *MU, *PH;  // adjoint: y planes, nu, mu, phi
-    float *GX, *GZ;               // Q or G planes
-};
-
-PmlHbmState pml_hbm_state(const Plan& p) {
-    const size_t mf = (size_t)p.max_batch * p.g.ns;
-    const size_t plane = (size_t)(p.nzp + 8) * (p.nxp + 8), npts = (size_t)p.npts;
-    PmlHbmState s{};
-    s.F0 = p.state;
-    s.F1 = s.F0 + mf * plane;
-    s.W = s.F1 + mf * plane;
-    s.PS = s.W + mf * npts;
-    s.Y0 = p.astate;
-    s.Y1 = s.Y0 + mf * plane;
-    s.NU = s.Y1 + mf * plane;
-    s.MU = s.NU + mf * npts;
-    s.PH = s.MU + mf * npts;
-    s.GX = p.pml_gplanes;
-    s.GZ = s.GX + mf * plane;
-    return s;
-}
-
-int hbm_grid(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
-
-// One forward step n from F to Fn.
-void pml_hbm_forward_step(const PmlHbmArgs& a, int nf, int n, const float* F, float* Fn, float* W, float* PS,
-                          float* GX, float* GZ, float* Dst, size_t dstride, hipStream_t st) {
-    if (a.nl > 0)
-        hipLaunchKernelGGL(k_pml_hbm_aux<false>, dim3((a.nl + 255) / 256, nf), dim3(256), 0, st, a, F, GX, GZ, PS);
-    hipLaunchKernelGGL(k_pml_hbm_step<false>, dim3((a.nxp + 63) / 64, (a.nzp + 3) / 4, nf), dim3(256), 0, st, a,
-                       n, F, Fn, GX, GZ, W, nullptr, Dst, dstride);
-}
-
-void pml_hbm_adjoint_step(const PmlHbmArgs& a, int nf, int n, const float* Y, float* Yn, float* NU, float* MU,
-                          float* PH, float* GX, float* GZ, float* Dsrc, size_t dstride, hipStream_t st) {
-    if (a.nl > 0)
-        hipLaunchKernelGGL(k_pml_hbm_aux<true>, dim3((a.nl + 255) / 256, nf), dim3(256), 0, st, a, Y, GX, GZ, PH);
-    hipLaunchKernelGGL(k_pml_hbm_step<true>, dim3((a.nxp + 63) / 64, (a.nzp + 3) / 4, nf), dim3(256), 0, st, a, n,
-                       Y, Yn, GX, GZ, NU, MU, Dsrc, dstride);
-}
-
-// Enqueues the whole forward sweep of B samples on st (reads p.wav, writes p.trace_buf; keeps the history of D
-// or the checkpoints when keep is set).
-void pml_hbm_enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
-    const int nf = B * p.g.ns;
-    PmlHbmArgs a = make_pml_hbm_args(p);
-    a.traces = p.trace_buf;
-    PmlHbmState s = pml_hbm_state(p);
-    const size_t plane = (size_t)a.plane, npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
-    launch_fill(s.F0, nf * plane, 0.f, st);
-    launch_fill(s.F1, nf * plane, 0.f, st);
-    launch_fill(s.W, nf * npts, 0.f, st);
-    launch_fill(s.PS, nf * nl2, 0.f, st);
-    launch_fill(s.GX, nf * plane, 0.f, st);
-    launch_fill(s.GZ, nf * plane, 0.f, st);
-    hipLaunchKernelGGL(k_pml_hbm_start<false>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, nullptr,
-                       nullptr, nullptr);
-    const int nsteps = p.g.nt - 1;
-    const bool full = keep && p.store_mode == 0, ck = keep && p.store_mode == 1;
-    const size_t dstride = (size_t)nsteps * npts;
-    float *F0 = s.F0, *F1 = s.F1;
-    for (int n = 0; n < nsteps; ++n) {
-        if (ck && n % p.ckpt_every == 0)
-            hipLaunchKernelGGL(k_pml_hbm_ckpt<true>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
-                               p.ckpt, F0, s.W, s.PS, nf, p.nseg, n / p.ckpt_every, (int)plane, (int)npts, p.pml_nl);
-        pml_hbm_forward_step(a, nf, n, F0, F1, s.W, s.PS, s.GX, s.GZ, full ? p.Dstore + (size_t)n * npts : nullptr,
-                             dstride, st);
-        std::swap(F0, F1);
-    }
-}
-
-// Enqueues the whole adjoint sweep (reads p.adj_buf, p.wav; writes p.gpad).
-void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
-    const int nf = B * p.g.ns;
-    PmlHbmArgs a = make_pml_hbm_args(p);
-    a.adj = p.adj_buf;
-    PmlHbmState s = pml_hbm_state(p);
-    const size_t plane = (size_t)a.plane, npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
-    const int nsteps = p.g.nt - 1;
-    launch_fill(s.Y0, nf * plane, 0.f, st);
-    launch_fill(s.Y1, nf * plane, 0.f, st);
-    launch_fill(s.NU, nf * npts, 0.f, st);
-    launch_fill(s.MU, nf * npts, 0.f, st);
-    launch_fill(s.PH, nf * nl2, 0.f, st);
-    launch_fill(s.GX, nf * plane, 0.f, st);
-    launch_fill(s.GZ, nf * plane, 0.f, st);
-    launch_fill(p.gpad, nf * npts, 0.f, st);
-    hipLaunchKernelGGL(k_pml_hbm_start<true>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, s.Y0, s.NU, s.MU);
-    float *Y0 = s.Y0, *Y1 = s.Y1;
-    if (p.store_mode == 0) {
-        const size_t dstride = (size_t)nsteps * npts;
-        for (int n = nsteps - 1; n >= 0; --n) {
-            pml_hbm_adjoint_step(a, nf, n, Y0, Y1, s.NU, s.MU, s.PH, s.GX, s.GZ, p.Dstore + (size_t)n * npts, dstride,
-                                 st);
-            std::swap(Y0, Y1);
-        }
-        return;
-    }
-    // checkpointed: recompute each segment's D from its checkpoint, then step the adjoint through it
-    PmlHbmArgs fa = make_pml_hbm_args(p);
-    fa.traces = nullptr;
-    const int K = p.ckpt_every;
-    const size_t dstride = (size_t)K * npts;
-    for (int c = p.nseg - 1; c >= 0; --c) {
-        const int n0 = c * K, n1 = std::min(n0 + K, nsteps);
-        float *F0 = s.F0, *F1 = s.F1;
-        hipLaunchKernelGGL(k_pml_hbm_ckpt<false>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
-                           p.ckpt, F0, s.W, s.PS, nf, p.nseg, c, (int)plane, (int)npts, p.pml_nl);
-        for (int n = n0; n < n1; ++n) {
-            pml_hbm_forward_step(fa, nf, n, F0, F1, s.W, s.PS, s.GX, s.GZ, p.Dstore + (size_t)(n - n0) * npts, dstride,
-                                 st);
-            std::swap(F0, F1);
-        }
-        for (int n = n1 - 1; n >= n0; --n) {
-            pml_hbm_adjoint_step(a, nf, n, Y0, Y1, s.NU, s.MU, s.PH, s.GX, s.GZ, p.Dstore + (size_t)(n - n0) * npts,
-                                 dstride, st);
-            std::swap(Y0, Y1);
-        }
-    }
-}
-
 }  // namespace
 
 bool pml_choose_bands(const fwi_geometry& g, int nzp, int nxp, int ztop, int nfields, int ncu, int force, int* Go,
@@ -1174,43 +816,6 @@ int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st) {
     }
     if (!pml_fits(p.nzp, p.nxp)) return FWI_EINVAL;
     return pml_dispatch<true>(a, nf, st);
-}
-
-std::vector<int> pml_layer_cells(const fwi_geometry& g, int nzp, int nxp, int ztop) {
-    std::vector<int> cells;
-    for (int iz = 0; iz < nzp; ++iz)
-        for (int ix = 0; ix < nxp; ++ix) {
-            const int zm = iz - ztop, xm = ix - g.nb;
-            if (!(zm >= 0 && zm < g.nz && xm >= 0 && xm < g.nx)) cells.push_back((iz << 16) | ix);
-        }
-    return cells;
-}
-
-// The sweeps are captured as graphs on the plan's private stream and replayed on the caller's, as the tiled
-// sponge sweeps are.
-int pml_hbm_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st) {
-    int rc = launch_copy(p.wav, wavelet, (size_t)p.g.nt, st);
-    if (rc) return rc;
-    const int k = keep ? 1 : 0;
-    if (!p.g_fwd[k] || p.g_fwd_B[k] != B) {
-        rc = capture_graph(p, &p.g_fwd[k], [&](hipStream_t cs) { pml_hbm_enqueue_forward(p, B, keep, cs); });
-        if (rc) return rc;
-        p.g_fwd_B[k] = B;
-    }
-    if (hipGraphLaunch(p.g_fwd[k], st) != hipSuccess) return FWI_EHIP;
-    return launch_copy(traces, p.trace_buf, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
-}
-
-int pml_hbm_adjoint(Plan& p, int B, const float* adj, hipStream_t st) {
-    int rc = launch_copy(p.adj_buf, adj, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
-    if (rc) return rc;
-    if (!p.g_adj || p.g_adj_B != B) {
-        rc = capture_graph(p, &p.g_adj, [&](hipStream_t cs) { pml_hbm_enqueue_adjoint(p, B, cs); });
-        if (rc) return rc;
-        p.g_adj_B = B;
-    }
-    if (hipGraphLaunch(p.g_adj, st) != hipSuccess) return FWI_EHIP;
-    return hip_ok(hipGetLastError());
 }
 
 }  // namespace fwi

@@ -1,0 +1,449 @@
+// Sweeps of the PML (Sec. 2.1 absorbing boundary realised by a PML; Sec. 6.1:
+// 6 grid points on the left, right and bottom, reflecting top) over fields
+// kept in device memory: plan path 3, for grids too large for the
+// LDS-resident PML sweeps of wave_pml.hip, histories that do not fit, and
+// checkpointed gradients.  The scheme and its exact adjoint are those stated
+// in wave_pml.hip (unsplit second-order form of a complex coordinate stretch,
+// Grote and Sim 2010).
+
+#include "fwi_internal.h"
+#include "pml_stencil.h"
+
+#include <algorithm>
+#include <utility>
+
+// No implicit fusing of a multiply and an add: this sweep must round every
+// operation as the LDS-resident sweeps do.
+#pragma clang fp contract(off)
+
+namespace fwi {
+namespace {
+
+// HBM sweep (path 3): the fields stay in device memory, for grids too large
+// for the LDS-resident sweeps and for checkpointed gradients.  The gathered
+// field (u or y) is stored with the 4-cell border of the LDS planes,
+// (nzp + 8) x (nxp + 8) per field, so a stencil never leaves its plane: the
+// border holds zeros, or the even mirror rows above a reflecting top, written
+// by the producer of each row.  The auxiliary fields of the layer cells are
+// kept compact.  One launch per step: each tile evaluates Q (G) of the layer
+// cells in it and in its 4-cell ring in LDS, then the time update of its
+// cells.  Each cell undergoes the operations of the LDS-resident sweep in the
+// same order, so the two give the same bits.
+struct PmlHbmArgs {
+    int nzp, nxp, npts;
+    int S, plane;                 // bordered row stride nxp + 8 and plane size (nzp + 8) S
+    int nz, nx, nb, ztop, fs;
+    int zlo, zhi, dw;             // deep model cells (no Q within 4 cells): rows [zlo, zhi), columns [4, 4 + dw)
+    int nt, ns, nr, nl;           // nl: layer cells
+    float idz, idx, idz2, idx2, src_scale;
+    const float* K;               // [B][npts] (v dt)^2
+    const float* tx;              // [nxp]
+    const float* tz;              // [nzp]
+    const float* wavelet;         // [nt]
+    const int* src_pt;            // [ns] padded index
+    const int* rec_map;           // [npts] receiver of each padded cell, or -1
+    int rec_z0, rec_z1;           // padded rows holding receivers (inclusive): rec_map is read only there
+    const int* rec_pt;            // [nr]
+    const float* rec_invw;        // [nr]
+    float* traces;                // forward: [nf][nr][nt], or null (recomputation)
+    const float* adj;             // adjoint: [nf][nr][nt]
+    float* gpad;                  // adjoint: [nf][npts] imaging sums, padded order
+};
+
+// Index of layer cell (iz, ix) in the compact order of the auxiliary fields:
+// row-major over the padded cells outside the model.
+__device__ __forceinline__ int pml_layer_index(const PmlHbmArgs& a, int iz, int ix) {
+    const int top = a.ztop * a.nxp, side = 2 * a.nb;
+    if (iz < a.ztop) return iz * a.nxp + ix;
+    if (iz < a.ztop + a.nz) return top + (iz - a.ztop) * side + (ix < a.nb ? ix : ix - a.nx);
+    return top + a.nz * side + (iz - a.ztop - a.nz) * a.nxp + ix;
+}
+
+// One time step on a 64 x 16 tile of one field (block: 64 columns x 4 strips
+// of 4 rows; grid: column and row tiles x fields, XCD-aware order).
+// Forward: F = u^n, Fn = u^{n+1}, W = w, Dst = D^n slice (or null).
+// Adjoint: F = y^{n+1}, Fn = y^n, W = nu, MU = mu, Dst = D^n.
+// Pin / Pout: auxiliary fields before / after the step, [nf][2][nl] each
+// (psi or phi, x then z); two buffers, because a tile also evaluates the Q
+// (G) values of the layer cells in its 4-cell ring, from their values before
+// the step, while the owning tile replaces them.  A tile whose ring holds no
+// layer cell stages u with a 4-cell ring and skips Q; the others stage an
+// 8-cell ring and keep Q (G) of the tile and its ring in LDS, zero outside the
+// layer and the grid, odd across a reflecting top.
+constexpr int kPtX = 64, kPtZ = 16;                  // tile
+constexpr int kPqX = kPtX + 8, kPqZ = kPtZ + 8;      // Q region: the tile and a 4-cell ring
+constexpr int kPfX = kPtX + 16, kPfZ = kPtZ + 16;    // staged u window: the tile and an 8-cell ring
+
+template <int HW>
+__device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __restrict__ Ff, float* fw, int zt,
+                                          int x0) {
+    constexpr int WX = kPtX + 2 * HW, WZ = kPtZ + 2 * HW;
+    for (int i = threadIdx.x; i < WZ * WX; i += 256) {
+        const int r = i / WX, c = i - (i / WX) * WX;
+        const int iz = zt - HW + r, ix = x0 - HW + c;
+        float v = 0.f;
+        if (iz >= -4 && iz < a.nzp + 4 && ix >= -4 && ix < a.nxp + 4) v = Ff[(size_t)(iz + 4) * a.S + ix + 4];
+        fw[(r + 8 - HW) * kPfX + c + 8 - HW] = v;
+    }
+}
+
+template <bool ADJ>
+__global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n, const float* __restrict__ F,
+                                                      float* __restrict__ Fn, const float* __restrict__ Pin,
+                                                      float* __restrict__ Pout, float* __restrict__ W,
+                                                      float* __restrict__ MU, float* __restrict__ Dst,
+                                                      size_t dstride) {
+    __shared__ float fw[kPfZ * kPfX];
+    __shared__ float gxs[kPqZ * kPqX];
+    __shared__ float gzs[kPqZ * kPqX];
+    const TileIdx ti = tile_of_block();
+    const int f = ti.field, x0 = ti.tx * kPtX, zt = ti.tz * kPtZ;
+    const float* Ff = F + (size_t)f * a.plane;
+    // does the tile or its 4-cell ring hold a layer cell (or lie past the grid)?
+    const bool layer = !(zt - 4 >= a.ztop && zt + kPtZ + 4 <= a.ztop + a.nz && x0 - 4 >= a.nb &&
+                         x0 + kPtX + 4 <= a.nb + a.nx);
+    if (layer)
+        pml_stage<8>(a, Ff, fw, zt, x0);
+    else
+        pml_stage<4>(a, Ff, fw, zt, x0);
+    __syncthreads();
+    if (layer) {
+        const size_t pf = (size_t)f * 2 * a.nl;
+        for (int i = threadIdx.x; i < kPqZ * kPqX; i += 256) {
+            const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
+            const int iz = zt - 4 + r, ix = x0 - 4 + c;
+            // rows above a reflecting top hold the odd mirror of Q_z (G_z) of the layer cells below
+            const bool mirror = a.fs && iz < 0;
+            const int cz = mirror ? -iz : iz;
+            float ox = 0.f, oz = 0.f;
+            const int zm = cz - a.ztop, xm = ix - a.nb;
+            if (cz >= 0 && cz < a.nzp && ix >= 0 && ix < a.nxp && !(zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx)) {
+                const float* c0 = fw + (cz - zt + 8) * kPfX + (ix - x0 + 8);
+                const float gx = a.idx * dfirst(c0, 1);
+                const float gz = a.idz * dfirst(c0, kPfX);
+                const float txv = a.tx[ix], tzv = a.tz[cz];
+                const float cxv = 1.f / (1.f + txv), czv = 1.f / (1.f + tzv);
+                const int li = pml_layer_index(a, cz, ix);
+                const float pxv = Pin[pf + li], pzv = Pin[pf + a.nl + li];
+                const bool own = !mirror && r >= 4 && r < 4 + kPtZ && c >= 4 && c < 4 + kPtX;
+                if (!ADJ) {
+                    const float Qx = cxv * fmaf(tzv - txv, gx, pxv);
+                    const float Qz = czv * fmaf(txv - tzv, gz, pzv);
+                    if (own) {
+                        Pout[pf + li] = 2.f * Qx - pxv;
+                        Pout[pf + a.nl + li] = 2.f * Qz - pzv;
+                    }
+                    ox = Qx;
+                    oz = Qz;
+                } else {
+                    const float Qx = 2.f * pxv - gx;
+                    const float Qz = 2.f * pzv - gz;
+                    if (own) {
+                        Pout[pf + li] = cxv * Qx - pxv;
+                        Pout[pf + a.nl + li] = czv * Qz - pzv;
+                    }
+                    ox = cxv * (tzv - txv) * Qx;
+                    oz = czv * (txv - tzv) * Qz;
+                }
+                if (mirror) {
+                    ox = 0.f;
+                    oz = -oz;
+                }
+            }
+            gxs[i] = ox;
+            gzs[i] = oz;
+        }
+        __syncthreads();
+    }
+    const int tx = threadIdx.x & 63, ts = threadIdx.x >> 6;
+    const int ix = x0 + tx;
+    if (ix >= a.nxp) return;
+    const int b = f / a.ns, s = f - (f / a.ns) * a.ns;
+    const int sp = a.src_pt[s];
+    const float txv = a.tx[ix];
+    const int xm = ix - a.nb;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int lz = ts * 4 + j;
+        const int iz = zt + lz;
+        if (iz >= a.nzp) break;
+        const int p = iz * a.nxp + ix;
+        const float* c = fw + (lz + 8) * kPfX + tx + 8;
+        const float c0 = c[0];
+        const float lzs = FWI_LAPD(c0, c[-4 * kPfX], c[-3 * kPfX], c[-2 * kPfX], c[-kPfX], c[kPfX], c[2 * kPfX],
+                                   c[3 * kPfX], c[4 * kPfX]);
+        const float lxs = FWI_LAPD(c0, c[-4], c[-3], c[-2], c[-1], c[1], c[2], c[3], c[4]);
+        const float lap = fmaf(a.idx2, lxs, a.idz2 * lzs);
+        const int zm = iz - a.ztop;
+        const bool model = zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx;
+        const bool deep = zm >= a.zlo && zm < a.zhi && xm >= 4 && xm < 4 + a.dw;
+        float div = 0.f;  // Q (G) is zero within 4 cells of a deep cell, and in a tile whose ring has no layer
+        if (layer && !deep) {
+            const int q = (lz + 4) * kPqX + tx + 4;
+            div = fmaf(a.idx, dfirst(gxs + q, 1), a.idz * dfirst(gzs + q, kPqX));
+        }
+        const float tzv = a.tz[iz];
+        const float E = 1.f / (1.f + txv + tzv);
+        const float r = a.K[(size_t)b * a.npts + p] * E;
+        float qd = 1.f, bq = 0.f;
+        if (!model) {
+            qd = (1.f - txv - tzv) * E;
+            bq = 4.f * txv * tzv * E;
+        }
+        const size_t fp = (size_t)f * a.npts + p;
+        const int rec = (iz >= a.rec_z0 && iz <= a.rec_z1) ? a.rec_map[p] : -1;
+        const size_t tr = ((size_t)f * a.nr + (rec >= 0 ? rec : 0)) * a.nt;
+        float out;
+        if (!ADJ) {
+            float D = lap + div;
+            if (p == sp) D += a.wavelet[n] * a.src_scale;
+            const float w = fmaf(r, D, fmaf(qd, W[fp], -bq * c0));
+            W[fp] = w;
+            out = c0 + w;
+            if (Dst) Dst[(size_t)f * dstride + p] = D;
+            if (rec >= 0 && a.traces) a.traces[tr + n + 1] = out;
+        } else {
+            const float dn = Dst[(size_t)f * dstride + p];
+            a.gpad[fp] = fmaf(c0, dn, a.gpad[fp]);  // imaging: y^{n+1} D^n
+            const float av = rec >= 0 ? a.adj[tr + n] * a.rec_invw[rec] : 0.f;
+            const float Fv = (lap - div) + av;
+            const float mu0 = MU[fp];
+            const float w = fmaf(qd, W[fp], fmaf(-bq, mu0, Fv));
+            const float mu = mu0 + w;
+            W[fp] = w;
+            MU[fp] = mu;
+            out = r * mu;
+        }
+        const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
+        Fn[o] = out;
+        if (a.fs && iz >= 1 && iz <= 4) Fn[o - 2 * iz * a.S] = out;
+    }
+}
+
+// Receivers at the start of a sweep (grid: receivers x fields).  Forward:
+// sample 0 of every trace is u^0 = 0.  Adjoint: mu^{N-1} = a^{N-1} / w at the
+// receivers, nu^{N-1} = mu^{N-1} and y = r mu (the other cells are zero).
+template <bool ADJ>
+__global__ void k_pml_hbm_start(const PmlHbmArgs a, float* __restrict__ Y, float* __restrict__ W,
+                                float* __restrict__ MU) {
+    const int rcv = blockIdx.x * 256 + threadIdx.x;
+    if (rcv >= a.nr) return;
+    const int f = blockIdx.y;
+    const size_t tr = ((size_t)f * a.nr + rcv) * a.nt;
+    if (!ADJ) {
+        a.traces[tr] = 0.f;
+        return;
+    }
+    const int p = a.rec_pt[rcv];
+    const int iz = p / a.nxp, ix = p - (p / a.nxp) * a.nxp;
+    const int b = f / a.ns;
+    const float mu = a.adj[tr + a.nt - 1] * a.rec_invw[rcv];
+    const size_t fp = (size_t)f * a.npts + p;
+    W[fp] = mu;
+    MU[fp] = mu;
+    const float E = 1.f / (1.f + a.tx[ix] + a.tz[iz]);
+    const float y = (a.K[(size_t)b * a.npts + p] * E) * mu;
+    const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
+    Y[o] = y;
+    if (a.fs && iz >= 1 && iz <= 4) Y[o - 2 * iz * a.S] = y;
+}
+
+// Saves (SAVE) or restores the forward state of every field at checkpoint
+// `seg`: the bordered u plane, w, and the layer's psi.
+// ckpt = [max fields][nseg][plane + npts + 2 nl].
+template <bool SAVE>
+__global__ void k_pml_hbm_ckpt(float* __restrict__ ckpt, float* __restrict__ F, float* __restrict__ W,
+                               float* __restrict__ PS, int nf, int nseg, int seg, int plane, int npts, int nl) {
+    const size_t per = (size_t)plane + npts + 2 * (size_t)nl;
+    const size_t total = (size_t)nf * per;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t f = i / per, e = i - (i / per) * per;
+        float* x = e < (size_t)plane ? F + f * plane + e
+                   : e < (size_t)plane + npts ? W + f * npts + (e - plane)
+                                              : PS + f * 2 * nl + (e - plane - npts);
+        float* c = ckpt + (f * nseg + seg) * per + e;
+        if (SAVE)
+            *c = *x;
+        else
+            *x = *c;
+    }
+}
+
+PmlHbmArgs make_pml_hbm_args(const Plan& p) {
+    PmlHbmArgs a{};
+    a.nzp = p.nzp;
+    a.nxp = p.nxp;
+    a.npts = p.npts;
+    a.S = p.nxp + 8;
+    a.plane = (p.nzp + 8) * a.S;
+    a.nz = p.g.nz;
+    a.nx = p.g.nx;
+    a.nb = p.g.nb;
+    a.ztop = p.ztop;
+    a.fs = p.g.free_surface;
+    const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
+    a.zlo = ord.zlo;
+    a.zhi = ord.zhi;
+    a.dw = ord.dw;
+    a.nt = p.g.nt;
+    a.ns = p.g.ns;
+    a.nr = p.g.nr;
+    a.nl = p.pml_nl;
+    a.idz = (float)(1.0 / p.g.dz);
+    a.idx = (float)(1.0 / p.g.dx);
+    a.idz2 = (float)(1.0 / (p.g.dz * p.g.dz));
+    a.idx2 = (float)(1.0 / (p.g.dx * p.g.dx));
+    a.src_scale = (float)(1.0 / (p.g.dx * p.g.dz));
+    a.K = p.K;
+    a.tx = p.pml_tx;
+    a.tz = p.pml_tz;
+    a.wavelet = p.wav;
+    a.src_pt = p.src_pt;
+    a.rec_map = p.rec_map;
+    a.rec_z0 = p.rec_z0;
+    a.rec_z1 = p.rec_z1;
+    a.rec_pt = p.rec_pt;
+    a.rec_invw = p.rec_invw;
+    a.gpad = p.gpad;
+    return a;
+}
+
+// State buffers of the HBM sweep, offsets fixed by max_batch.
+struct PmlHbmState {
+    float *F0, *F1, *W, *P0, *P1;      // forward: u planes (ping-pong), w, psi (ping-pong)
+    float *Y0, *Y1, *NU, *MU, *H0, *H1;  // adjoint: y planes, nu, mu, phi
+};
+
+PmlHbmState pml_hbm_state(const Plan& p) {
+    const size_t mf = (size_t)p.max_batch * p.g.ns;
+    const size_t plane = (size_t)(p.nzp + 8) * (p.nxp + 8), npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
+    PmlHbmState s{};
+    s.F0 = p.state;
+    s.F1 = s.F0 + mf * plane;
+    s.W = s.F1 + mf * plane;
+    s.P0 = s.W + mf * npts;
+    s.P1 = s.P0 + mf * nl2;
+    s.Y0 = p.astate;
+    s.Y1 = s.Y0 + mf * plane;
+    s.NU = s.Y1 + mf * plane;
+    s.MU = s.NU + mf * npts;
+    s.H0 = s.MU + mf * npts;
+    s.H1 = s.H0 + mf * nl2;
+    return s;
+}
+
+int hbm_grid(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
+
+dim3 pml_tile_grid(const PmlHbmArgs& a, int nf) {
+    return dim3((a.nxp + kPtX - 1) / kPtX, (a.nzp + kPtZ - 1) / kPtZ, nf);
+}
+
+// Enqueues the whole forward sweep of B samples on st (reads p.wav, writes p.trace_buf; keeps the history of D
+// or the checkpoints when keep is set).
+void pml_hbm_enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
+    const int nf = B * p.g.ns;
+    PmlHbmArgs a = make_pml_hbm_args(p);
+    a.traces = p.trace_buf;
+    PmlHbmState s = pml_hbm_state(p);
+    const size_t plane = (size_t)a.plane, npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
+    launch_fill(s.F0, nf * plane, 0.f, st);
+    launch_fill(s.F1, nf * plane, 0.f, st);
+    launch_fill(s.W, nf * npts, 0.f, st);
+    launch_fill(s.P0, nf * nl2, 0.f, st);
+    launch_fill(s.P1, nf * nl2, 0.f, st);
+    hipLaunchKernelGGL(k_pml_hbm_start<false>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, nullptr,
+                       nullptr, nullptr);
+    const int nsteps = p.g.nt - 1;
+    const bool full = keep && p.store_mode == 0, ck = keep && p.store_mode == 1;
+    const size_t dstride = (size_t)nsteps * npts;
+    const dim3 grid = pml_tile_grid(a, nf);
+    float *F0 = s.F0, *F1 = s.F1, *P0 = s.P0, *P1 = s.P1;
+    for (int n = 0; n < nsteps; ++n) {
+        if (ck && n % p.ckpt_every == 0)
+            hipLaunchKernelGGL(k_pml_hbm_ckpt<true>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
+                               p.ckpt, F0, s.W, P0, nf, p.nseg, n / p.ckpt_every, (int)plane, (int)npts, p.pml_nl);
+        hipLaunchKernelGGL(k_pml_hbm_tile<false>, grid, dim3(256), 0, st, a, n, F0, F1, P0, P1, s.W, nullptr,
+                           full ? p.Dstore + (size_t)n * npts : nullptr, dstride);
+        std::swap(F0, F1);
+        std::swap(P0, P1);
+    }
+}
+
+// Enqueues the whole adjoint sweep (reads p.adj_buf, p.wav; writes p.gpad).
+void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
+    const int nf = B * p.g.ns;
+    PmlHbmArgs a = make_pml_hbm_args(p);
+    a.adj = p.adj_buf;
+    PmlHbmState s = pml_hbm_state(p);
+    const size_t plane = (size_t)a.plane, npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
+    const int nsteps = p.g.nt - 1;
+    const dim3 grid = pml_tile_grid(a, nf);
+    launch_fill(s.Y0, nf * plane, 0.f, st);
+    launch_fill(s.Y1, nf * plane, 0.f, st);
+    launch_fill(s.NU, nf * npts, 0.f, st);
+    launch_fill(s.MU, nf * npts, 0.f, st);
+    launch_fill(s.H0, nf * nl2, 0.f, st);
+    launch_fill(s.H1, nf * nl2, 0.f, st);
+    launch_fill(p.gpad, nf * npts, 0.f, st);
+    hipLaunchKernelGGL(k_pml_hbm_start<true>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, s.Y0, s.NU, s.MU);
+    float *Y0 = s.Y0, *Y1 = s.Y1, *H0 = s.H0, *H1 = s.H1;
+    auto adjoint_step = [&](int n, float* Dn, size_t dstride) {
+        hipLaunchKernelGGL(k_pml_hbm_tile<true>, grid, dim3(256), 0, st, a, n, Y0, Y1, H0, H1, s.NU, s.MU, Dn,
+                           dstride);
+        std::swap(Y0, Y1);
+        std::swap(H0, H1);
+    };
+    if (p.store_mode == 0) {
+        for (int n = nsteps - 1; n >= 0; --n) adjoint_step(n, p.Dstore + (size_t)n * npts, (size_t)nsteps * npts);
+        return;
+    }
+    // checkpointed: recompute each segment's D from its checkpoint, then step the adjoint through it
+    PmlHbmArgs fa = make_pml_hbm_args(p);
+    fa.traces = nullptr;
+    const int K = p.ckpt_every;
+    const size_t dstride = (size_t)K * npts;
+    for (int c = p.nseg - 1; c >= 0; --c) {
+        const int n0 = c * K, n1 = std::min(n0 + K, nsteps);
+        float *F0 = s.F0, *F1 = s.F1, *P0 = s.P0, *P1 = s.P1;
+        hipLaunchKernelGGL(k_pml_hbm_ckpt<false>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
+                           p.ckpt, F0, s.W, P0, nf, p.nseg, c, (int)plane, (int)npts, p.pml_nl);
+        for (int n = n0; n < n1; ++n) {
+            hipLaunchKernelGGL(k_pml_hbm_tile<false>, grid, dim3(256), 0, st, fa, n, F0, F1, P0, P1, s.W, nullptr,
+                               p.Dstore + (size_t)(n - n0) * npts, dstride);
+            std::swap(F0, F1);
+            std::swap(P0, P1);
+        }
+        for (int n = n1 - 1; n >= n0; --n) adjoint_step(n, p.Dstore + (size_t)(n - n0) * npts, dstride);
+    }
+}
+
+}  // namespace
+
+// The sweeps are captured as graphs on the plan's private stream and replayed on the caller's, as the tiled
+// sponge sweeps are.
+int pml_hbm_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st) {
+    int rc = launch_copy(p.wav, wavelet, (size_t)p.g.nt, st);
+    if (rc) return rc;
+    const int k = keep ? 1 : 0;
+    if (!p.g_fwd[k] || p.g_fwd_B[k] != B) {
+        rc = capture_graph(p, &p.g_fwd[k], [&](hipStream_t cs) { pml_hbm_enqueue_forward(p, B, keep, cs); });
+        if (rc) return rc;
+        p.g_fwd_B[k] = B;
+    }
+    if (hipGraphLaunch(p.g_fwd[k], st) != hipSuccess) return FWI_EHIP;
+    return launch_copy(traces, p.trace_buf, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
+}
+
+int pml_hbm_adjoint(Plan& p, int B, const float* adj, hipStream_t st) {
+    int rc = launch_copy(p.adj_buf, adj, (size_t)B * p.g.ns * p.g.nr * p.g.nt, st);
+    if (rc) return rc;
+    if (!p.g_adj || p.g_adj_B != B) {
+        rc = capture_graph(p, &p.g_adj, [&](hipStream_t cs) { pml_hbm_enqueue_adjoint(p, B, cs); });
+        if (rc) return rc;
+        p.g_adj_B = B;
+    }
+    if (hipGraphLaunch(p.g_adj, st) != hipSuccess) return FWI_EHIP;
+    return hip_ok(hipGetLastError());
+}
+
+}  // namespace fwi
