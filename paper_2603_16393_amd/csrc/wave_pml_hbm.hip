@@ -59,6 +59,107 @@ __device__ __forceinline__ int pml_layer_index(const PmlHbmArgs& a, int iz, int 
     return top + a.nz * side + (iz - a.ztop - a.nz) * a.nxp + ix;
 }
 
+// Per-cell pieces, each written with the LDS-resident sweep's expressions in
+// its order.  Global values come in as arguments: a kernel first issues all
+// loads of a phase, then computes (a load inside the compute loop would be
+// waited for in every iteration).
+
+// Q (forward) or G (adjoint) of a layer cell from the gathered field around it
+// (gp at the cell, row stride gs), its damping (txv, tzv) and its auxiliary
+// values before the step (pxv, pzv); px1, pz1 receive them after the step.
+template <bool ADJ>
+__device__ __forceinline__ void pml_aux(const PmlHbmArgs& a, const float* gp, int gs, float txv, float tzv, float pxv,
+                                        float pzv, float& ox, float& oz, float& px1, float& pz1) {
+    const float gx = a.idx * dfirst(gp, 1);
+    const float gz = a.idz * dfirst(gp, gs);
+    const float cxv = 1.f / (1.f + txv), czv = 1.f / (1.f + tzv);
+    if (!ADJ) {
+        const float Qx = cxv * fmaf(tzv - txv, gx, pxv);
+        const float Qz = czv * fmaf(txv - tzv, gz, pzv);
+        px1 = 2.f * Qx - pxv;
+        pz1 = 2.f * Qz - pzv;
+        ox = Qx;
+        oz = Qz;
+    } else {
+        const float Qx = 2.f * pxv - gx;
+        const float Qz = 2.f * pzv - gz;
+        px1 = cxv * Qx - pxv;
+        pz1 = czv * Qz - pzv;
+        ox = cxv * (tzv - txv) * Qx;
+        oz = czv * (txv - tzv) * Qz;
+    }
+}
+
+// Coefficients of cell (iz, ix) with (v dt)^2 = kv: r = kv E, and q, bq of the
+// layer's update (1 and 0 in the model).
+struct PmlCoef {
+    float r, q, bq;
+    bool deep;
+};
+__device__ __forceinline__ PmlCoef pml_coef(const PmlHbmArgs& a, float kv, float txv, float tzv, int iz, int ix) {
+    PmlCoef c;
+    const int zm = iz - a.ztop, xm = ix - a.nb;
+    const bool model = zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx;
+    c.deep = zm >= a.zlo && zm < a.zhi && xm >= 4 && xm < 4 + a.dw;
+    const float E = 1.f / (1.f + txv + tzv);
+    c.r = kv * E;
+    c.q = 1.f;
+    c.bq = 0.f;
+    if (!model) {
+        c.q = (1.f - txv - tzv) * E;
+        c.bq = 4.f * txv * tzv * E;
+    }
+    return c;
+}
+
+__device__ __forceinline__ float pml_lap(const PmlHbmArgs& a, const float* c, int s) {
+    const float c0 = c[0];
+    const float lz = FWI_LAPD(c0, c[-4 * s], c[-3 * s], c[-2 * s], c[-s], c[s], c[2 * s], c[3 * s], c[4 * s]);
+    const float lx = FWI_LAPD(c0, c[-4], c[-3], c[-2], c[-1], c[1], c[2], c[3], c[4]);
+    return fmaf(a.idx2, lx, a.idz2 * lz);
+}
+
+__device__ __forceinline__ float pml_div(const PmlHbmArgs& a, const float* gx, const float* gz, int s) {
+    return fmaf(a.idx, dfirst(gx, 1), a.idz * dfirst(gz, s));
+}
+
+__device__ __forceinline__ bool pml_in_layer(const PmlHbmArgs& a, int iz, int ix) {
+    const int zm = iz - a.ztop, xm = ix - a.nb;
+    return iz >= 0 && iz < a.nzp && ix >= 0 && ix < a.nxp && !(zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx);
+}
+
+__device__ __forceinline__ int pml_rec_of(const PmlHbmArgs& a, int iz, int p) {
+    return (iz >= a.rec_z0 && iz <= a.rec_z1) ? a.rec_map[p] : -1;
+}
+
+constexpr int kPtX = 64, kPtZ = 16;                  // tile
+constexpr int kPqX = kPtX + 8, kPqZ = kPtZ + 8;      // Q region: the tile and a 4-cell ring
+
+// Stages the gathered field of the tile and an HW-cell ring into fw (row
+// stride WX, offset off rows and columns), from the bordered plane (zero past
+// its border), and the damping of those columns and rows into txs, tzs (zero
+// past the grid).
+template <int HW, int WX>
+__device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __restrict__ Ff, float* fw, float* txs,
+                                          float* tzs, int zt, int x0, int off) {
+    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW;
+    for (int i = threadIdx.x; i < GZ * GX; i += 256) {
+        const int r = i / GX, c = i - (i / GX) * GX;
+        const int iz = zt - HW + r, ix = x0 - HW + c;
+        float v = 0.f;
+        if (iz >= -4 && iz < a.nzp + 4 && ix >= -4 && ix < a.nxp + 4) v = Ff[(size_t)(iz + 4) * a.S + ix + 4];
+        fw[(r + off) * WX + c + off] = v;
+    }
+    for (int i = threadIdx.x; i < GX; i += 256) {
+        const int ix = x0 - HW + i;
+        txs[i] = ix >= 0 && ix < a.nxp ? a.tx[ix] : 0.f;
+    }
+    for (int i = threadIdx.x; i < GZ; i += 256) {
+        const int iz = zt - HW + i;
+        tzs[i] = iz >= 0 && iz < a.nzp ? a.tz[iz] : 0.f;
+    }
+}
+
 // One time step on a 64 x 16 tile of one field (block: 64 columns x 4 strips
 // of 4 rows; grid: column and row tiles x fields, XCD-aware order).
 // Forward: F = u^n, Fn = u^{n+1}, W = w, Dst = D^n slice (or null).
@@ -70,22 +171,7 @@ __device__ __forceinline__ int pml_layer_index(const PmlHbmArgs& a, int iz, int 
 // layer cell stages u with a 4-cell ring and skips Q; the others stage an
 // 8-cell ring and keep Q (G) of the tile and its ring in LDS, zero outside the
 // layer and the grid, odd across a reflecting top.
-constexpr int kPtX = 64, kPtZ = 16;                  // tile
-constexpr int kPqX = kPtX + 8, kPqZ = kPtZ + 8;      // Q region: the tile and a 4-cell ring
 constexpr int kPfX = kPtX + 16, kPfZ = kPtZ + 16;    // staged u window: the tile and an 8-cell ring
-
-template <int HW>
-__device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __restrict__ Ff, float* fw, int zt,
-                                          int x0) {
-    constexpr int WX = kPtX + 2 * HW, WZ = kPtZ + 2 * HW;
-    for (int i = threadIdx.x; i < WZ * WX; i += 256) {
-        const int r = i / WX, c = i - (i / WX) * WX;
-        const int iz = zt - HW + r, ix = x0 - HW + c;
-        float v = 0.f;
-        if (iz >= -4 && iz < a.nzp + 4 && ix >= -4 && ix < a.nxp + 4) v = Ff[(size_t)(iz + 4) * a.S + ix + 4];
-        fw[(r + 8 - HW) * kPfX + c + 8 - HW] = v;
-    }
-}
 
 template <bool ADJ>
 __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n, const float* __restrict__ F,
@@ -96,6 +182,7 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n,
     __shared__ float fw[kPfZ * kPfX];
     __shared__ float gxs[kPqZ * kPqX];
     __shared__ float gzs[kPqZ * kPqX];
+    __shared__ float txs[kPfX], tzs[kPfZ];
     const TileIdx ti = tile_of_block();
     const int f = ti.field, x0 = ti.tx * kPtX, zt = ti.tz * kPtZ;
     const float* Ff = F + (size_t)f * a.plane;
@@ -103,47 +190,46 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n,
     const bool layer = !(zt - 4 >= a.ztop && zt + kPtZ + 4 <= a.ztop + a.nz && x0 - 4 >= a.nb &&
                          x0 + kPtX + 4 <= a.nb + a.nx);
     if (layer)
-        pml_stage<8>(a, Ff, fw, zt, x0);
+        pml_stage<8, kPfX>(a, Ff, fw, txs, tzs, zt, x0, 0);
     else
-        pml_stage<4>(a, Ff, fw, zt, x0);
+        pml_stage<4, kPfX>(a, Ff, fw, txs + 4, tzs + 4, zt, x0, 4);
     __syncthreads();
     if (layer) {
+        constexpr int NQ = (kPqZ * kPqX + 255) / 256;
         const size_t pf = (size_t)f * 2 * a.nl;
-        for (int i = threadIdx.x; i < kPqZ * kPqX; i += 256) {
+        int li[NQ];
+        float pxv[NQ], pzv[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int i = threadIdx.x + k * 256;
+            const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
+            const int iz = zt - 4 + r, ix = x0 - 4 + c;
+            const int cz = a.fs && iz < 0 ? -iz : iz;
+            li[k] = i < kPqZ * kPqX && pml_in_layer(a, cz, ix) ? pml_layer_index(a, cz, ix) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int l = li[k] >= 0 ? li[k] : 0;
+            pxv[k] = Pin[pf + l];
+            pzv[k] = Pin[pf + a.nl + l];
+        }
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int i = threadIdx.x + k * 256;
+            if (i >= kPqZ * kPqX) break;
             const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
             const int iz = zt - 4 + r, ix = x0 - 4 + c;
             // rows above a reflecting top hold the odd mirror of Q_z (G_z) of the layer cells below
             const bool mirror = a.fs && iz < 0;
             const int cz = mirror ? -iz : iz;
             float ox = 0.f, oz = 0.f;
-            const int zm = cz - a.ztop, xm = ix - a.nb;
-            if (cz >= 0 && cz < a.nzp && ix >= 0 && ix < a.nxp && !(zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx)) {
-                const float* c0 = fw + (cz - zt + 8) * kPfX + (ix - x0 + 8);
-                const float gx = a.idx * dfirst(c0, 1);
-                const float gz = a.idz * dfirst(c0, kPfX);
-                const float txv = a.tx[ix], tzv = a.tz[cz];
-                const float cxv = 1.f / (1.f + txv), czv = 1.f / (1.f + tzv);
-                const int li = pml_layer_index(a, cz, ix);
-                const float pxv = Pin[pf + li], pzv = Pin[pf + a.nl + li];
-                const bool own = !mirror && r >= 4 && r < 4 + kPtZ && c >= 4 && c < 4 + kPtX;
-                if (!ADJ) {
-                    const float Qx = cxv * fmaf(tzv - txv, gx, pxv);
-                    const float Qz = czv * fmaf(txv - tzv, gz, pzv);
-                    if (own) {
-                        Pout[pf + li] = 2.f * Qx - pxv;
-                        Pout[pf + a.nl + li] = 2.f * Qz - pzv;
-                    }
-                    ox = Qx;
-                    oz = Qz;
-                } else {
-                    const float Qx = 2.f * pxv - gx;
-                    const float Qz = 2.f * pzv - gz;
-                    if (own) {
-                        Pout[pf + li] = cxv * Qx - pxv;
-                        Pout[pf + a.nl + li] = czv * Qz - pzv;
-                    }
-                    ox = cxv * (tzv - txv) * Qx;
-                    oz = czv * (txv - tzv) * Qz;
+            if (li[k] >= 0) {
+                float px1, pz1;
+                pml_aux<ADJ>(a, fw + (cz - zt + 8) * kPfX + (ix - x0 + 8), kPfX, txs[ix - x0 + 8], tzs[cz - zt + 8],
+                             pxv[k], pzv[k], ox, oz, px1, pz1);
+                if (!mirror && r >= 4 && r < 4 + kPtZ && c >= 4 && c < 4 + kPtX) {
+                    Pout[pf + li[k]] = px1;
+                    Pout[pf + a.nl + li[k]] = pz1;
                 }
                 if (mirror) {
                     ox = 0.f;
@@ -160,8 +246,20 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n,
     if (ix >= a.nxp) return;
     const int b = f / a.ns, s = f - (f / a.ns) * a.ns;
     const int sp = a.src_pt[s];
-    const float txv = a.tx[ix];
-    const int xm = ix - a.nb;
+    float kv[4], wv[4], mv[4], gv[4], dv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int iz = min(zt + ts * 4 + j, a.nzp - 1);
+        const int p = iz * a.nxp + ix;
+        const size_t fp = (size_t)f * a.npts + p;
+        kv[j] = a.K[(size_t)b * a.npts + p];
+        wv[j] = W[fp];
+        if (ADJ) {
+            mv[j] = MU[fp];
+            gv[j] = a.gpad[fp];
+            dv[j] = Dst[(size_t)f * dstride + p];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int lz = ts * 4 + j;
@@ -170,49 +268,34 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n,
         const int p = iz * a.nxp + ix;
         const float* c = fw + (lz + 8) * kPfX + tx + 8;
         const float c0 = c[0];
-        const float lzs = FWI_LAPD(c0, c[-4 * kPfX], c[-3 * kPfX], c[-2 * kPfX], c[-kPfX], c[kPfX], c[2 * kPfX],
-                                   c[3 * kPfX], c[4 * kPfX]);
-        const float lxs = FWI_LAPD(c0, c[-4], c[-3], c[-2], c[-1], c[1], c[2], c[3], c[4]);
-        const float lap = fmaf(a.idx2, lxs, a.idz2 * lzs);
-        const int zm = iz - a.ztop;
-        const bool model = zm >= 0 && zm < a.nz && xm >= 0 && xm < a.nx;
-        const bool deep = zm >= a.zlo && zm < a.zhi && xm >= 4 && xm < 4 + a.dw;
+        const float lap = pml_lap(a, c, kPfX);
+        const PmlCoef pc = pml_coef(a, kv[j], txs[tx + 8], tzs[lz + 8], iz, ix);
         float div = 0.f;  // Q (G) is zero within 4 cells of a deep cell, and in a tile whose ring has no layer
-        if (layer && !deep) {
+        if (layer && !pc.deep) {
             const int q = (lz + 4) * kPqX + tx + 4;
-            div = fmaf(a.idx, dfirst(gxs + q, 1), a.idz * dfirst(gzs + q, kPqX));
-        }
-        const float tzv = a.tz[iz];
-        const float E = 1.f / (1.f + txv + tzv);
-        const float r = a.K[(size_t)b * a.npts + p] * E;
-        float qd = 1.f, bq = 0.f;
-        if (!model) {
-            qd = (1.f - txv - tzv) * E;
-            bq = 4.f * txv * tzv * E;
+            div = pml_div(a, gxs + q, gzs + q, kPqX);
         }
         const size_t fp = (size_t)f * a.npts + p;
-        const int rec = (iz >= a.rec_z0 && iz <= a.rec_z1) ? a.rec_map[p] : -1;
+        const int rec = pml_rec_of(a, iz, p);
         const size_t tr = ((size_t)f * a.nr + (rec >= 0 ? rec : 0)) * a.nt;
         float out;
         if (!ADJ) {
             float D = lap + div;
             if (p == sp) D += a.wavelet[n] * a.src_scale;
-            const float w = fmaf(r, D, fmaf(qd, W[fp], -bq * c0));
+            const float w = fmaf(pc.r, D, fmaf(pc.q, wv[j], -pc.bq * c0));
             W[fp] = w;
             out = c0 + w;
             if (Dst) Dst[(size_t)f * dstride + p] = D;
             if (rec >= 0 && a.traces) a.traces[tr + n + 1] = out;
         } else {
-            const float dn = Dst[(size_t)f * dstride + p];
-            a.gpad[fp] = fmaf(c0, dn, a.gpad[fp]);  // imaging: y^{n+1} D^n
+            a.gpad[fp] = fmaf(c0, dv[j], gv[j]);  // imaging: y^{n+1} D^n
             const float av = rec >= 0 ? a.adj[tr + n] * a.rec_invw[rec] : 0.f;
             const float Fv = (lap - div) + av;
-            const float mu0 = MU[fp];
-            const float w = fmaf(qd, W[fp], fmaf(-bq, mu0, Fv));
-            const float mu = mu0 + w;
+            const float w = fmaf(pc.q, wv[j], fmaf(-pc.bq, mv[j], Fv));
+            const float mu = mv[j] + w;
             W[fp] = w;
             MU[fp] = mu;
-            out = r * mu;
+            out = pc.r * mu;
         }
         const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
         Fn[o] = out;
