@@ -193,16 +193,16 @@ MEASURED_TRAFFIC = {
               "sha1": "48fba527a13d2bee2b5149d12fb76b8f0d2997f5", "bytes": {"forward": 8.9911e9, "adjoint": 8.5322e9}},
     # PML row bands (profiles/k_wave_pml_b16_70x70_hbm_traffic.md)
     "pml": {"sources": (CSRC + "wave_pml.hip", CSRC + "pml_stencil.h", CSRC + "wave_split_body.h"),
-            "sha1": "7975399530e2a18482fe7d45aafc3036622c3739",
-            "bytes": {"forward": 4.2936e9, "adjoint": 4.3203e9}},
+            "sha1": "b81ad6386bd6265bd3c4f2f4f6a6209533ab3a71",
+            "bytes": {"forward": 4.2920e9, "adjoint": 4.3224e9}},
     # two-step tiled sweep of the 400 x 800 workload, per launch (profiles/k_wave_tile2_ckpt_400x800_hbm_traffic.md):
     # forward launch u, w, K read and u, w written; a recomputation launch also writes its two D slices
     "tile2": {"sources": (CSRC + "wave.hip",), "sha1": "cc9c480f5925e6d77586e193ec94ba5af0d23279",
               "bytes": {"forward": 9.936e7 + 6.48e7, "recompute": 9.936e7 + 2 * 6.48e7, "adjoint": 2.971e8}},
     # HBM-swept PML, per launch of the 400 x 800 checkpointed workload
     # (profiles/k_pml_hbm_tile_ckpt_400x800_hbm_traffic.md): recomputation (D written) and adjoint
-    "pml_hbm": {"sources": (CSRC + "wave_pml_hbm.hip", CSRC + "pml_stencil.h"), "sha1": "b54deb513a37d403ab7515094d5a4265a206d4cb",
-                "bytes": {"recompute": 1.647e8, "adjoint": 2.755e8}},
+    "pml_hbm": {"sources": (CSRC + "wave_pml_hbm.hip", CSRC + "pml_stencil.h"), "sha1": "0e774311cf46f086c3b7cb1f964d298f765fd844",
+                "bytes": {"recompute": 1.644e8, "adjoint": 2.752e8}},
     # uneven persistent forward launch of the 64-request mix (profiles/k_batch_uneven64_hbm_traffic.md)
     "uneven": {"sources": (CSRC + "batch.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
                "sha1": "89131c2aebfef7914550cba6f79dd6b123802a90", "bytes": {"forward": 1.2374e11, "gradient": 6.8432e11}},
