@@ -135,8 +135,9 @@ __global__ __launch_bounds__(256) void k_wave_tile(TileArgs a, int m, const floa
 
 // Two time steps per launch (temporal blocking): the block computes step 1
 // on its 64 x 16 tile plus a 4-cell ring (72 x 24 points, from u^n staged with
-// an 8-cell ring), keeps u^{n+1} of that region in LDS and w^{n+1} of the tile,
-// then computes step 2 on the tile.  Every point is updated with the same
+// an 8-cell ring), keeps u^{n+1} of that region in LDS and w^{n+1} of the tile
+// in the registers of the thread that updates the point again in step 2, then
+// computes step 2 on the tile.  Every point is updated with the same
 // operations as in k_wave_tile (the ring points again by each block that
 // needs them), so two launches of k_wave_tile and one of this kernel agree
 // bitwise; u, w and K pass through HBM once per two steps and, in the adjoint,
@@ -152,14 +153,13 @@ template <bool ADJ>
 __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const float* __restrict__ ax_g,
                                                     const float* __restrict__ az_g, float* __restrict__ wout,
                                                     float* __restrict__ Dout2, const float* __restrict__ Din2) {
-    // Each phase first issues all of a thread's global loads (clamped addresses, so no
-    // load sits in a divergent branch) and only then uses them: the loads of one
-    // thread overlap instead of waiting one by one.
+    // Each phase first issues a thread's global loads (clamped addresses, so no load sits
+    // in a divergent branch; in step 1 four points at a time, which keeps the kernel within
+    // 64 VGPRs) and only then uses them: the loads of one thread overlap instead of waiting
+    // one by one.  17 KB of LDS and at most 64 VGPRs: 8 waves per SIMD.
     constexpr int NA = (AZ * AX + 255) / 256;  // u^n values staged per thread
-    constexpr int NE = (EZ * EX + 255) / 256;  // step-1 points per thread
     __shared__ float A[AZ * AX];   // u^n
     __shared__ float Bt[EZ * EX];  // u^{n+1}
-    __shared__ float W1[TZ * TX];  // w^{n+1} of the tile
     const TileIdx ti = tile_of_block();
     const int field = ti.field;
     const int b = field / a.ns;
@@ -191,62 +191,95 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
     }
     __syncthreads();
 
-    // step 1 on the tile and its ring
+    // step 1 on the tile and its ring: each thread first takes the 4 tile points it updates again in step 2
+    // (w^{n+1} stays in its registers), then up to 3 of the 704 ring points
     const bool rec1 = (zt + TZ + 4 > a.rec_z0) && (zt - 4 <= a.rec_z1);
+    const int tx = tid % TX, ts = tid / TX;
+    float w1[TROWS];
     {
-        float kv[NE], wv[NE], dv[NE], av[NE], iv[NE];
-        int rv[NE];
+        constexpr int NRING = EZ * EX - TZ * TX;  // 704
+        constexpr int NP = TROWS + (NRING + 255) / 256;
+        const float src = ADJ ? 0.f : a.wavelet[m];
+        // region coordinates (r, c) of this thread's points: the tile points, then the ring points
+        auto point = [&](int k, int& r, int& c) -> bool {
+            if (k < TROWS) {
+                r = 4 + ts * TROWS + k;
+                c = 4 + tx;
+                return true;
+            }
+            const int q = tid + (k - TROWS) * 256;
+            if (q >= NRING) return false;
+            if (q < 4 * EX) {
+                r = q / EX;
+                c = q - r * EX;
+            } else if (q < 8 * EX) {
+                r = TZ + 4 + (q - 4 * EX) / EX;
+                c = (q - 4 * EX) - (r - TZ - 4) * EX;
+            } else {
+                const int e = q - 8 * EX;  // rows 4 .. TZ + 3, the 4 columns at each side
+                r = 4 + e / 8;
+                const int c8 = e - (e / 8) * 8;
+                c = c8 < 4 ? c8 : TX + c8;
+            }
+            return true;
+        };
+        constexpr int CH = 4;  // points whose loads are in flight together
 #pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            const int i = tid + k * 256;
-            const int r = i / EX, c = i - (i / EX) * EX;
-            const int gz = min(max(zt + r - 4, 0), nzp - 1), gx = min(max(x0 + c - 4, 0), nxp - 1);
-            const int p = gz * nxp + gx;
-            kv[k] = Kb[p];
-            wv[k] = wg[p];
-            dv[k] = ax_g[gx] * az_g[gz];
-            rv[k] = -1;
-            av[k] = iv[k] = 0.f;
-            if (rec1) {
-                rv[k] = a.rec_map[p];
-                if (ADJ) {
-                    const int q = max(rv[k], 0);
-                    av[k] = a.adj[(trf + q) * a.nt + (a.nt - 1 - m)];
-                    iv[k] = a.rec_invw[q];
+        for (int k0 = 0; k0 < NP; k0 += CH) {
+            float kv[CH], wv[CH], dv[CH], av[CH], iv[CH];
+            int rv[CH];
+#pragma unroll
+            for (int kk = 0; kk < CH; ++kk) {
+                const int k = k0 + kk;
+                if (k >= NP) break;
+                int r = 0, c = 0;
+                point(k, r, c);
+                const int gz = min(max(zt + r - 4, 0), nzp - 1), gx = min(max(x0 + c - 4, 0), nxp - 1);
+                const int p = gz * nxp + gx;
+                kv[kk] = Kb[p];
+                wv[kk] = wg[p];
+                dv[kk] = ax_g[gx] * az_g[gz];
+                rv[kk] = -1;
+                av[kk] = iv[kk] = 0.f;
+                if (rec1) {
+                    rv[kk] = a.rec_map[p];
+                    if (ADJ) {
+                        const int q = max(rv[kk], 0);
+                        av[kk] = a.adj[(trf + q) * a.nt + (a.nt - 1 - m)];
+                        iv[kk] = a.rec_invw[q];
+                    }
                 }
             }
-        }
-        const float src = ADJ ? 0.f : a.wavelet[m];
 #pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            const int i = tid + k * 256;
-            const int r = i / EX, c = i - (i / EX) * EX;
-            const int gz = zt + r - 4, gx = x0 + c - 4;
-            float un = 0.f;
-            if (i < EZ * EX && gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) {
-                const int p = gz * nxp + gx;
-                const int li = (r + 4) * AX + c + 4;
-                const float cc = A[li];
-                const float lzs = FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX],
-                                           A[li + AX], A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
-                const float lxs = FWI_LAPD(cc, A[li - 4], A[li - 3], A[li - 2], A[li - 1], A[li + 1], A[li + 2],
-                                           A[li + 3], A[li + 4]);
-                float D = fmaf(lzs, a.idz2, lxs * a.idx2);
-                const int rr = rv[k];
-                if (!ADJ && p == sp) D = fmaf(src, a.src_scale, D);
-                if (ADJ && rr >= 0) D = fmaf(iv[k], av[k], D);
-                const float wn = fmaf(kv[k], D, dv[k] * wv[k]);
-                un = cc + wn;
-                const bool own = r >= 4 && r < 4 + TZ && c >= 4 && c < 4 + TX;
-                if (own) {
-                    W1[(r - 4) * TX + c - 4] = wn;
-                    if (!ADJ) {
+            for (int kk = 0; kk < CH; ++kk) {
+                const int k = k0 + kk;
+                if (k >= NP) break;
+                int r = 0, c = 0;
+                if (!point(k, r, c)) continue;
+                const int gz = zt + r - 4, gx = x0 + c - 4;
+                float un = 0.f, wn = 0.f;
+                if (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) {
+                    const int p = gz * nxp + gx;
+                    const int li = (r + 4) * AX + c + 4;
+                    const float cc = A[li];
+                    const float lzs = FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX],
+                                               A[li + AX], A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
+                    const float lxs = FWI_LAPD(cc, A[li - 4], A[li - 3], A[li - 2], A[li - 1], A[li + 1], A[li + 2],
+                                               A[li + 3], A[li + 4]);
+                    float D = fmaf(lzs, a.idz2, lxs * a.idx2);
+                    const int rr = rv[kk];
+                    if (!ADJ && p == sp) D = fmaf(src, a.src_scale, D);
+                    if (ADJ && rr >= 0) D = fmaf(iv[kk], av[kk], D);
+                    wn = fmaf(kv[kk], D, dv[kk] * wv[kk]);
+                    un = cc + wn;
+                    if (k < TROWS && !ADJ) {
                         if (a.Dout) a.Dout[(size_t)field * a.dstride + p] = D;
                         if (rr >= 0 && a.traces) a.traces[(trf + rr) * a.nt + m + 1] = un;
                     }
                 }
+                if (k < TROWS) w1[k] = wn;
+                Bt[r * EX + c] = un;
             }
-            if (i < EZ * EX) Bt[i] = un;
         }
     }
     __syncthreads();
@@ -259,7 +292,6 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
     }
 
     // step 2 on the tile (the mapping of k_wave_tile)
-    const int tx = tid % TX, ts = tid / TX;
     const int gx = x0 + tx;
     if (gx >= nxp) return;
     const float axv = ax_g[gx];
@@ -307,7 +339,7 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
         const int rr = rv[j];
         if (!ADJ && p == sp) D = fmaf(src, a.src_scale, D);
         if (ADJ && rr >= 0) D = fmaf(iv[j], av[j], D);
-        const float wn = fmaf(kv[j], D, (axv * zv[j]) * W1[lz * TX + tx]);
+        const float wn = fmaf(kv[j], D, (axv * zv[j]) * w1[j]);
         const float un = cc + wn;
         wo[p] = wn;
         un_g[p] = un;
