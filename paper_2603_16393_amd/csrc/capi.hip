@@ -262,8 +262,9 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // PML HBM sweep: bordered planes (u, u, y, y), w, nu, mu, psi and phi (two each), traces, layer table
     const size_t plane = (size_t)(p.nzp + 8) * (p.nxp + 8);
     const size_t nl = (size_t)(p.nzp * p.nxp - p.g.nz * p.g.nx);
-    const size_t fixed_hbm_pml = (4 * nf * plane + 3 * nf * npts + 8 * nf * nl + 2 * nf * nr * (size_t)nt + npts) *
-                                 sizeof(float);
+    const size_t ntiles = (size_t)((p.nzp + 15) / 16) * ((p.nxp + 63) / 64);
+    const size_t fixed_hbm_pml =
+        (4 * nf * plane + 3 * nf * npts + 8 * nf * nl + 2 * nf * nr * (size_t)nt + npts + ntiles) * sizeof(float);
     if (p.path == 1) fixed += (8 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
     if (p.path == 3) fixed += fixed_hbm_pml;
     const size_t full_store = nf * nsteps * npts * sizeof(float);
@@ -358,7 +359,14 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         const PmlOrder ord(p.g.nz, p.g.nx, p.g.nb, p.g.free_surface);
         for (int r = 0; r < nr; ++r) pml_rec[ord.model_slot(p.rec_iz[r], p.rec_ix[r])] = r;
     }
-    if (p.path == 3) p.pml_nl = (int)nl;
+    std::vector<int> tiles_plain, tiles_layer;
+    if (p.path == 3) {
+        p.pml_nl = (int)nl;
+        pml_tile_classes(p.g, p.nzp, p.nxp, p.ztop, tiles_plain, tiles_layer);
+        p.pml_ntp = (int)tiles_plain.size();
+        p.pml_ntl = (int)tiles_layer.size();
+        tiles_plain.insert(tiles_plain.end(), tiles_layer.begin(), tiles_layer.end());
+    }
     if (p.path == 1 || p.path == 3) {
         rec_map = ht.rec_map;
     } else {
@@ -399,6 +407,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
         st = st ? st : alloc_n(p, &p.state, nf * (2 * plane + npts + 2 * nl2));
         st = st ? st : alloc_n(p, &p.astate, nf * (2 * plane + 2 * npts + 2 * nl2));
+        st = st ? st : alloc_n(p, &p.pml_tiles, tiles_plain.size());
         st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);
         if (!st && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) st = FWI_EHIP;
@@ -438,6 +447,9 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
             st = st ? st : hip_ok(hipMemcpy(p.pml_tx, tx.data(), tx.size() * sizeof(float), hipMemcpyHostToDevice));
             st = st ? st : hip_ok(hipMemcpy(p.pml_tz, tz.data(), tz.size() * sizeof(float), hipMemcpyHostToDevice));
         }
+        if (p.path == 3)
+            st = st ? st : hip_ok(hipMemcpy(p.pml_tiles, tiles_plain.data(), tiles_plain.size() * sizeof(int),
+                                            hipMemcpyHostToDevice));
         if (p.path == 2) {
             st = st ? st : hip_ok(hipMemcpy(p.pml_rec, pml_rec.data(), pml_rec.size() * sizeof(int),
                                             hipMemcpyHostToDevice));

@@ -279,6 +279,8 @@ struct Plan {
     // PML HBM sweep (path 3): padded cells outside the model (each has psi_x, psi_z); its u, w, psi and y, nu,
     // mu, phi live in state and astate, the traces in trace_buf and adj_buf, the checkpoints in ckpt
     int pml_nl = 0;
+    int* pml_tiles = nullptr;    // tiles (tz << 16 | tx): the pml_ntp plain ones, then the pml_ntl with layer cells
+    int pml_ntp = 0, pml_ntl = 0;  // within 4 cells
     float* ax = nullptr;         // [nxp] sponge damping factor per padded column
     float* az = nullptr;         // [nzp] sponge damping factor per padded row
     float* wgt_row = nullptr;    // [nzp]
@@ -381,7 +383,10 @@ size_t pml_lds_bytes(int nzp, int nxp);
 bool pml_fits(int nzp, int nxp);
 int launch_pml_forward(const Plan& p, int B, float* traces, const float* wavelet, int store, hipStream_t st);
 int launch_pml_adjoint(const Plan& p, int B, const float* adj, hipStream_t st);
-// PML HBM sweep (path 3), captured graphs.
+// PML HBM sweep (path 3): tile classes (no layer cell within 4 cells, and the others) and the sweeps (captured
+// graphs).
+void pml_tile_classes(const fwi_geometry& g, int nzp, int nxp, int ztop, std::vector<int>& plain,
+                      std::vector<int>& layer);
 int pml_hbm_forward(Plan& p, int B, float* traces, const float* wavelet, int keep, hipStream_t st);
 int pml_hbm_adjoint(Plan& p, int B, const float* adj, hipStream_t st);
 // Captures enqueue(p.cap) into an executable graph (replacing *exec).

@@ -161,40 +161,39 @@ __device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __re
 }
 
 // One time step on a 64 x 16 tile of one field (block: 64 columns x 4 strips
-// of 4 rows; grid: column and row tiles x fields, XCD-aware order).
+// of 4 rows; grid: the tiles of one class from a host list x fields, XCD-aware
+// order).
 // Forward: F = u^n, Fn = u^{n+1}, W = w, Dst = D^n slice (or null).
 // Adjoint: F = y^{n+1}, Fn = y^n, W = nu, MU = mu, Dst = D^n.
 // Pin / Pout: auxiliary fields before / after the step, [nf][2][nl] each
 // (psi or phi, x then z); two buffers, because a tile also evaluates the Q
 // (G) values of the layer cells in its 4-cell ring, from their values before
-// the step, while the owning tile replaces them.  A tile whose ring holds no
-// layer cell stages u with a 4-cell ring and skips Q; the others stage an
-// 8-cell ring and keep Q (G) of the tile and its ring in LDS, zero outside the
-// layer and the grid, odd across a reflecting top.
-constexpr int kPfX = kPtX + 16, kPfZ = kPtZ + 16;    // staged u window: the tile and an 8-cell ring
-
-template <bool ADJ>
-__global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n, const float* __restrict__ F,
-                                                      float* __restrict__ Fn, const float* __restrict__ Pin,
-                                                      float* __restrict__ Pout, float* __restrict__ W,
-                                                      float* __restrict__ MU, float* __restrict__ Dst,
-                                                      size_t dstride) {
-    __shared__ float fw[kPfZ * kPfX];
-    __shared__ float gxs[kPqZ * kPqX];
-    __shared__ float gzs[kPqZ * kPqX];
-    __shared__ float txs[kPfX], tzs[kPfZ];
+// the step, while the owning tile replaces them.  Plain tiles (LAYER false:
+// no layer cell within 4 cells, rows past a reflecting top being mirror
+// images of model rows) stage u with a 4-cell ring and run the leapfrog; layer
+// tiles stage an 8-cell ring and keep Q (G) of the tile and its ring in LDS,
+// zero outside the layer and the grid, odd across a reflecting top.  The two
+// classes are separate launches so that the plain tiles, most of the grid,
+// hold only their 7 KB of LDS.
+template <bool ADJ, bool LAYER>
+__global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const int* __restrict__ tiles, int n,
+                                                      const float* __restrict__ F, float* __restrict__ Fn,
+                                                      const float* __restrict__ Pin, float* __restrict__ Pout,
+                                                      float* __restrict__ W, float* __restrict__ MU,
+                                                      float* __restrict__ Dst, size_t dstride) {
+    constexpr int HW = LAYER ? 8 : 4;  // staged ring
+    constexpr int FX = kPtX + 2 * HW, FZ = kPtZ + 2 * HW;
+    __shared__ float fw[FZ * FX];
+    __shared__ float gxs[LAYER ? kPqZ * kPqX : 1];
+    __shared__ float gzs[LAYER ? kPqZ * kPqX : 1];
+    __shared__ float txs[FX], tzs[FZ];
     const TileIdx ti = tile_of_block();
-    const int f = ti.field, x0 = ti.tx * kPtX, zt = ti.tz * kPtZ;
+    const int code = tiles[ti.tx];
+    const int f = ti.field, x0 = (code & 0xffff) * kPtX, zt = (code >> 16) * kPtZ;
     const float* Ff = F + (size_t)f * a.plane;
-    // does the tile or its 4-cell ring hold a layer cell (or lie past the grid)?
-    const bool layer = !(zt - 4 >= a.ztop && zt + kPtZ + 4 <= a.ztop + a.nz && x0 - 4 >= a.nb &&
-                         x0 + kPtX + 4 <= a.nb + a.nx);
-    if (layer)
-        pml_stage<8, kPfX>(a, Ff, fw, txs, tzs, zt, x0, 0);
-    else
-        pml_stage<4, kPfX>(a, Ff, fw, txs + 4, tzs + 4, zt, x0, 4);
+    pml_stage<HW, FX>(a, Ff, fw, txs, tzs, zt, x0, 0);
     __syncthreads();
-    if (layer) {
+    if (LAYER) {
         constexpr int NQ = (kPqZ * kPqX + 255) / 256;
         const size_t pf = (size_t)f * 2 * a.nl;
         int li[NQ];
@@ -225,7 +224,7 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n,
             float ox = 0.f, oz = 0.f;
             if (li[k] >= 0) {
                 float px1, pz1;
-                pml_aux<ADJ>(a, fw + (cz - zt + 8) * kPfX + (ix - x0 + 8), kPfX, txs[ix - x0 + 8], tzs[cz - zt + 8],
+                pml_aux<ADJ>(a, fw + (cz - zt + HW) * FX + (ix - x0 + HW), FX, txs[ix - x0 + HW], tzs[cz - zt + HW],
                              pxv[k], pzv[k], ox, oz, px1, pz1);
                 if (!mirror && r >= 4 && r < 4 + kPtZ && c >= 4 && c < 4 + kPtX) {
                     Pout[pf + li[k]] = px1;
@@ -266,12 +265,12 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, int n,
         const int iz = zt + lz;
         if (iz >= a.nzp) break;
         const int p = iz * a.nxp + ix;
-        const float* c = fw + (lz + 8) * kPfX + tx + 8;
+        const float* c = fw + (lz + HW) * FX + tx + HW;
         const float c0 = c[0];
-        const float lap = pml_lap(a, c, kPfX);
-        const PmlCoef pc = pml_coef(a, kv[j], txs[tx + 8], tzs[lz + 8], iz, ix);
+        const float lap = pml_lap(a, c, FX);
+        const PmlCoef pc = pml_coef(a, kv[j], txs[tx + HW], tzs[lz + HW], iz, ix);
         float div = 0.f;  // Q (G) is zero within 4 cells of a deep cell, and in a tile whose ring has no layer
-        if (layer && !pc.deep) {
+        if (LAYER && !pc.deep) {
             const int q = (lz + 4) * kPqX + tx + 4;
             div = pml_div(a, gxs + q, gzs + q, kPqX);
         }
@@ -417,8 +416,16 @@ PmlHbmState pml_hbm_state(const Plan& p) {
 
 int hbm_grid(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
 
-dim3 pml_tile_grid(const PmlHbmArgs& a, int nf) {
-    return dim3((a.nxp + kPtX - 1) / kPtX, (a.nzp + kPtZ - 1) / kPtZ, nf);
+// One step over all tiles: the plain tiles, then the layer tiles (independent launches within a step).
+template <bool ADJ>
+void pml_hbm_step(const Plan& p, const PmlHbmArgs& a, int nf, int n, const float* F, float* Fn, const float* Pin,
+                  float* Pout, float* W, float* MU, float* D, size_t dstride, hipStream_t st) {
+    if (p.pml_ntp > 0)
+        hipLaunchKernelGGL((k_pml_hbm_tile<ADJ, false>), dim3(p.pml_ntp, 1, nf), dim3(256), 0, st, a, p.pml_tiles, n,
+                           F, Fn, Pin, Pout, W, MU, D, dstride);
+    if (p.pml_ntl > 0)
+        hipLaunchKernelGGL((k_pml_hbm_tile<ADJ, true>), dim3(p.pml_ntl, 1, nf), dim3(256), 0, st, a,
+                           p.pml_tiles + p.pml_ntp, n, F, Fn, Pin, Pout, W, MU, D, dstride);
 }
 
 // Enqueues the whole forward sweep of B samples on st (reads p.wav, writes p.trace_buf; keeps the history of D
@@ -439,14 +446,13 @@ void pml_hbm_enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
     const int nsteps = p.g.nt - 1;
     const bool full = keep && p.store_mode == 0, ck = keep && p.store_mode == 1;
     const size_t dstride = (size_t)nsteps * npts;
-    const dim3 grid = pml_tile_grid(a, nf);
     float *F0 = s.F0, *F1 = s.F1, *P0 = s.P0, *P1 = s.P1;
     for (int n = 0; n < nsteps; ++n) {
         if (ck && n % p.ckpt_every == 0)
             hipLaunchKernelGGL(k_pml_hbm_ckpt<true>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
                                p.ckpt, F0, s.W, P0, nf, p.nseg, n / p.ckpt_every, (int)plane, (int)npts, p.pml_nl);
-        hipLaunchKernelGGL(k_pml_hbm_tile<false>, grid, dim3(256), 0, st, a, n, F0, F1, P0, P1, s.W, nullptr,
-                           full ? p.Dstore + (size_t)n * npts : nullptr, dstride);
+        pml_hbm_step<false>(p, a, nf, n, F0, F1, P0, P1, s.W, nullptr, full ? p.Dstore + (size_t)n * npts : nullptr,
+                            dstride, st);
         std::swap(F0, F1);
         std::swap(P0, P1);
     }
@@ -460,7 +466,6 @@ void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
     PmlHbmState s = pml_hbm_state(p);
     const size_t plane = (size_t)a.plane, npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
     const int nsteps = p.g.nt - 1;
-    const dim3 grid = pml_tile_grid(a, nf);
     launch_fill(s.Y0, nf * plane, 0.f, st);
     launch_fill(s.Y1, nf * plane, 0.f, st);
     launch_fill(s.NU, nf * npts, 0.f, st);
@@ -471,8 +476,7 @@ void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
     hipLaunchKernelGGL(k_pml_hbm_start<true>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, s.Y0, s.NU, s.MU);
     float *Y0 = s.Y0, *Y1 = s.Y1, *H0 = s.H0, *H1 = s.H1;
     auto adjoint_step = [&](int n, float* Dn, size_t dstride) {
-        hipLaunchKernelGGL(k_pml_hbm_tile<true>, grid, dim3(256), 0, st, a, n, Y0, Y1, H0, H1, s.NU, s.MU, Dn,
-                           dstride);
+        pml_hbm_step<true>(p, a, nf, n, Y0, Y1, H0, H1, s.NU, s.MU, Dn, dstride, st);
         std::swap(Y0, Y1);
         std::swap(H0, H1);
     };
@@ -491,8 +495,8 @@ void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
         hipLaunchKernelGGL(k_pml_hbm_ckpt<false>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
                            p.ckpt, F0, s.W, P0, nf, p.nseg, c, (int)plane, (int)npts, p.pml_nl);
         for (int n = n0; n < n1; ++n) {
-            hipLaunchKernelGGL(k_pml_hbm_tile<false>, grid, dim3(256), 0, st, fa, n, F0, F1, P0, P1, s.W, nullptr,
-                               p.Dstore + (size_t)(n - n0) * npts, dstride);
+            pml_hbm_step<false>(p, fa, nf, n, F0, F1, P0, P1, s.W, nullptr, p.Dstore + (size_t)(n - n0) * npts,
+                                dstride, st);
             std::swap(F0, F1);
             std::swap(P0, P1);
         }
@@ -501,6 +505,20 @@ void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
 }
 
 }  // namespace
+
+void pml_tile_classes(const fwi_geometry& g, int nzp, int nxp, int ztop, std::vector<int>& plain,
+                      std::vector<int>& layer) {
+    plain.clear();
+    layer.clear();
+    for (int tz = 0; tz * kPtZ < nzp; ++tz)
+        for (int tx = 0; tx * kPtX < nxp; ++tx) {
+            const int x0 = tx * kPtX, zt = tz * kPtZ;
+            // no layer cell, nor a cell past the grid, within 4 cells (above a reflecting top: model mirror rows)
+            const bool ok = x0 - 4 >= g.nb && x0 + kPtX + 4 <= g.nb + g.nx && zt + kPtZ + 4 <= ztop + g.nz &&
+                            (g.free_surface || zt - 4 >= ztop);
+            (ok ? plain : layer).push_back((tz << 16) | tx);
+        }
+}
 
 // The sweeps are captured as graphs on the plan's private stream and replayed on the caller's, as the tiled
 // sponge sweeps are.
