@@ -206,11 +206,13 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
             const int cz = a.fs && iz < 0 ? -iz : iz;
             li[k] = i < kPqZ * kPqX && pml_in_layer(a, cz, ix) ? pml_layer_index(a, cz, ix) : -1;
         }
+        // clamped to the field's first layer cell, so that no load sits in a divergent branch; a grid without
+        // layer cells (nb = 0) has no auxiliary fields to read
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {
             const int l = li[k] >= 0 ? li[k] : 0;
-            pxv[k] = Pin[pf + l];
-            pzv[k] = Pin[pf + a.nl + l];
+            pxv[k] = a.nl > 0 ? Pin[pf + l] : 0.f;
+            pzv[k] = a.nl > 0 ? Pin[pf + a.nl + l] : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {

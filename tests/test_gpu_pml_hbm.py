@@ -52,31 +52,32 @@ def dev():
     return d
 
 
-def _acq(nz, nx, fs, nt, ns, two_rows=False, v_max=4000.0, dx=12.0, f_peak=25.0):
+def _acq(nz, nx, fs, nt, ns, two_rows=False, v_max=4000.0, dx=12.0, f_peak=25.0, nb=6):
     rec_iz = np.full(nx, 0 if fs else 1, np.int32)
     rec_ix = np.arange(nx, dtype=np.int32)
     if two_rows:  # a surface spread and a buried one
         rec_iz = np.concatenate([rec_iz, np.full(nx, nz // 2 + 1, np.int32)])
         rec_ix = np.concatenate([rec_ix, rec_ix])
-    return fi.Acquisition(nz=nz, nx=nx, dz=10.0, dx=dx, dt=0.001, nt=nt, nb=6, free_surface=fs, v_max=v_max,
+    return fi.Acquisition(nz=nz, nx=nx, dz=10.0, dx=dx, dt=0.001, nt=nt, nb=nb, free_surface=fs, v_max=v_max,
                           src_iz=np.full(ns, 1, np.int32), src_ix=np.linspace(1, nx - 2, ns).astype(np.int32),
                           rec_iz=rec_iz, rec_ix=rec_ix, f_peak=f_peak, pml=True)
 
 
-@pytest.mark.parametrize("nz,nx,fs,nt,two_rows,B", [(9, 11, True, 160, False, 2), (9, 11, False, 160, False, 1),
-                                                    (40, 50, True, 300, True, 2), (37, 53, False, 300, True, 2),
-                                                    (62, 70, True, 400, False, 3)])
-def test_hbm_sweep_equals_lds_sweep(dev, nz, nx, fs, nt, two_rows, B):
+@pytest.mark.parametrize("nz,nx,fs,nt,two_rows,B,nb", [(9, 11, True, 160, False, 2, 6), (9, 11, False, 160, False, 1, 6),
+                                                       (40, 50, True, 300, True, 2, 6), (37, 53, False, 300, True, 2, 6),
+                                                       (62, 70, True, 400, False, 3, 6), (30, 36, False, 200, False, 2, 0)])
+def test_hbm_sweep_equals_lds_sweep(dev, nz, nx, fs, nt, two_rows, B, nb):
+    """nb = 0: a PML geometry without layer cells (reflecting edges), whose layer-class tiles hold none."""
     from paper_2603_16393_amd import FwiPlan
 
-    acq = _acq(nz, nx, fs, nt, 3, two_rows)
+    acq = _acq(nz, nx, fs, nt, 3, two_rows, nb=nb)
     rng = np.random.default_rng(11 * nz + nx + B)
     w = _t(fi.ricker(nt, acq.dt, acq.f_peak), dev)
     lds = FwiPlan(acq, max_batch=B, device=dev, split=-1)
     hbm = FwiPlan(acq, max_batch=B, device=dev, force_path=1)
     ck = FwiPlan(acq, max_batch=B, device=dev, ckpt_every=37)
     infos = [dict(p.info) for p in (lds, hbm, ck)]
-    _say(f"PML HBM sweep {nz}x{nx} fs={fs} B={B}: paths {[i['path'] for i in infos]}, "
+    _say(f"PML HBM sweep {nz}x{nx} fs={fs} B={B} nb={nb}: paths {[i['path'] for i in infos]}, "
          f"store modes {[i['store_mode'] for i in infos]}")
     assert [i["path"] for i in infos] == [2, 3, 3]
     assert infos[1]["store_mode"] == 0 and infos[2]["store_mode"] == 1 and infos[2]["ckpt_every"] == 37
