@@ -896,9 +896,9 @@ def bench_checkpointed(args, pml=False):
     updates = 3 * per_sweep  # forward, recomputation, adjoint
     if pml:
         # PML HBM sweep, per point-update: recomputation 24 B (u^n read, w read and written, K read, u^{n+1} and
-        # D written), adjoint 40 B (y^{n+1} read, nu and mu read and written, K and D read, the imaging sum read
-        # and written, y^n written); the layer's auxiliary fields are 1 % of the cells
-        alg = per_sweep * (24.0 + 40.0)
+        # D written), adjoint 32 B (mu and nu read and written, K and D read, the imaging sum read and written;
+        # the gathered y = r mu is formed from mu and K); the layer's auxiliary fields are 1 % of the cells
+        alg = per_sweep * (24.0 + 32.0)
         kernel = "k_pml_hbm_tile (recomputation + adjoint steps, one step per launch)"
         tr, ta = measured_traffic("pml_hbm", "recompute"), measured_traffic("pml_hbm", "adjoint")
         phase_traffic = (nt - 1) * (tr + ta) if tr and ta else None

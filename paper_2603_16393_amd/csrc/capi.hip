@@ -259,12 +259,12 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
     // fixed-size buffers
     size_t fixed = (nf * npts + max_batch * npts) * sizeof(float) + npts * sizeof(int) + (size_t)ns * nr * nt * 8 +
                    nf * nr * 8 + (size_t)ns * nr * 1000 * 8;
-    // PML HBM sweep: bordered planes (u, u, y, y), w, nu, mu, psi and phi (two each), traces, layer table
+    // PML HBM sweep: two bordered u planes, w, nu, mu (two), psi and phi (two each), traces, tile table
     const size_t plane = (size_t)(p.nzp + 8) * (p.nxp + 8);
     const size_t nl = (size_t)(p.nzp * p.nxp - p.g.nz * p.g.nx);
     const size_t ntiles = (size_t)((p.nzp + 15) / 16) * ((p.nxp + 63) / 64);
     const size_t fixed_hbm_pml =
-        (4 * nf * plane + 3 * nf * npts + 8 * nf * nl + 2 * nf * nr * (size_t)nt + npts + ntiles) * sizeof(float);
+        (2 * nf * plane + 4 * nf * npts + 8 * nf * nl + 2 * nf * nr * (size_t)nt + npts + ntiles) * sizeof(float);
     if (p.path == 1) fixed += (8 * nf * npts + 2 * nf * nr * (size_t)nt) * sizeof(float);
     if (p.path == 3) fixed += fixed_hbm_pml;
     const size_t full_store = nf * nsteps * npts * sizeof(float);
@@ -406,7 +406,7 @@ static int create(const fwi_geometry* geom, int max_batch, size_t budget, const 
         st = st ? st : alloc_n(p, &p.pml_tx, (size_t)p.nxp);
         st = st ? st : alloc_n(p, &p.pml_tz, (size_t)p.nzp);
         st = st ? st : alloc_n(p, &p.state, nf * (2 * plane + npts + 2 * nl2));
-        st = st ? st : alloc_n(p, &p.astate, nf * (2 * plane + 2 * npts + 2 * nl2));
+        st = st ? st : alloc_n(p, &p.astate, nf * (3 * npts + 2 * nl2));
         st = st ? st : alloc_n(p, &p.pml_tiles, tiles_plain.size());
         st = st ? st : alloc_n(p, &p.trace_buf, nf * nr * (size_t)nt);
         st = st ? st : alloc_n(p, &p.adj_buf, nf * nr * (size_t)nt);

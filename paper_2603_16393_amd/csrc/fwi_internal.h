@@ -295,7 +295,7 @@ struct Plan {
                                  // [max_batch*ns][nseg][(nzp + 8) (nxp + 8) + npts + 2 pml_nl] (u plane, w, psi)
     float* state = nullptr;      // tiled: [4][max_batch*ns][npts] u and w, each ping-pong; PML HBM sweep:
                                  // two bordered u planes, w, two psi buffers (offsets by max_batch)
-    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]; PML HBM sweep: two y planes, nu, mu,
+    float* astate = nullptr;     // tiled adjoint: [4][max_batch*ns][npts]; PML HBM sweep: two mu buffers, nu,
                                  // two phi buffers
     float* acc = nullptr;        // tiled adjoint: [max_batch*ns][npts]
     float* gpad = nullptr;       // [max_batch*ns][npts]

@@ -160,11 +160,44 @@ __device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __re
     }
 }
 
+// The adjoint's gathered field y = r mu of the tile and an HW-cell ring, from
+// mu and K (r = (v dt)^2 E, the product every sweep forms), into fw; rows
+// above a reflecting top are the even mirror images, cells past the grid (and
+// more than 4 rows above a reflecting top) zero.  Also the damping of the
+// staged columns and rows into txs, tzs.
+template <int HW, int WX>
+__device__ __forceinline__ void pml_stage_y(const PmlHbmArgs& a, const float* __restrict__ Mf,
+                                            const float* __restrict__ Kb, float* fw, float* txs, float* tzs, int zt,
+                                            int x0) {
+    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW;
+    for (int i = threadIdx.x; i < GZ * GX; i += 256) {
+        const int r = i / GX, c = i - (i / GX) * GX;
+        const int iz = zt - HW + r, ix = x0 - HW + c;
+        const int cz = a.fs && iz < 0 ? -iz : iz;
+        float v = 0.f;
+        if (iz >= -4 && cz >= 0 && cz < a.nzp && ix >= 0 && ix < a.nxp) {
+            const int p = cz * a.nxp + ix;
+            const float E = 1.f / (1.f + a.tx[ix] + a.tz[cz]);
+            v = (Kb[p] * E) * Mf[p];
+        }
+        fw[r * WX + c] = v;
+    }
+    for (int i = threadIdx.x; i < GX; i += 256) {
+        const int ix = x0 - HW + i;
+        txs[i] = ix >= 0 && ix < a.nxp ? a.tx[ix] : 0.f;
+    }
+    for (int i = threadIdx.x; i < GZ; i += 256) {
+        const int iz = zt - HW + i;
+        tzs[i] = iz >= 0 && iz < a.nzp ? a.tz[iz] : 0.f;
+    }
+}
+
 // One time step on a 64 x 16 tile of one field (block: 64 columns x 4 strips
 // of 4 rows; grid: the tiles of one class from a host list x fields, XCD-aware
 // order).
-// Forward: F = u^n, Fn = u^{n+1}, W = w, Dst = D^n slice (or null).
-// Adjoint: F = y^{n+1}, Fn = y^n, W = nu, MU = mu, Dst = D^n.
+// Forward: F = u^n and Fn = u^{n+1} (bordered planes), W = w, Dst = D^n slice
+// (or null).  Adjoint: F = mu^{n+1} and Fn = mu^n ([nf][npts]; the gathered
+// field y = r mu is formed while staging), W = nu, Dst = D^n.
 // Pin / Pout: auxiliary fields before / after the step, [nf][2][nl] each
 // (psi or phi, x then z); two buffers, because a tile also evaluates the Q
 // (G) values of the layer cells in its 4-cell ring, from their values before
@@ -179,8 +212,7 @@ template <bool ADJ, bool LAYER>
 __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const int* __restrict__ tiles, int n,
                                                       const float* __restrict__ F, float* __restrict__ Fn,
                                                       const float* __restrict__ Pin, float* __restrict__ Pout,
-                                                      float* __restrict__ W, float* __restrict__ MU,
-                                                      float* __restrict__ Dst, size_t dstride) {
+                                                      float* __restrict__ W, float* __restrict__ Dst, size_t dstride) {
     constexpr int HW = LAYER ? 8 : 4;  // staged ring
     constexpr int FX = kPtX + 2 * HW, FZ = kPtZ + 2 * HW;
     __shared__ float fw[FZ * FX];
@@ -190,8 +222,11 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
     const TileIdx ti = tile_of_block();
     const int code = tiles[ti.tx];
     const int f = ti.field, x0 = (code & 0xffff) * kPtX, zt = (code >> 16) * kPtZ;
-    const float* Ff = F + (size_t)f * a.plane;
-    pml_stage<HW, FX>(a, Ff, fw, txs, tzs, zt, x0, 0);
+    const int b = f / a.ns, s = f - (f / a.ns) * a.ns;
+    if (ADJ)
+        pml_stage_y<HW, FX>(a, F + (size_t)f * a.npts, a.K + (size_t)b * a.npts, fw, txs, tzs, zt, x0);
+    else
+        pml_stage<HW, FX>(a, F + (size_t)f * a.plane, fw, txs, tzs, zt, x0, 0);
     __syncthreads();
     if (LAYER) {
         constexpr int NQ = (kPqZ * kPqX + 255) / 256;
@@ -245,7 +280,6 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
     const int tx = threadIdx.x & 63, ts = threadIdx.x >> 6;
     const int ix = x0 + tx;
     if (ix >= a.nxp) return;
-    const int b = f / a.ns, s = f - (f / a.ns) * a.ns;
     const int sp = a.src_pt[s];
     float kv[4], wv[4], mv[4], gv[4], dv[4];
 #pragma unroll
@@ -256,7 +290,7 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
         kv[j] = a.K[(size_t)b * a.npts + p];
         wv[j] = W[fp];
         if (ADJ) {
-            mv[j] = MU[fp];
+            mv[j] = F[fp];
             gv[j] = a.gpad[fp];
             dv[j] = Dst[(size_t)f * dstride + p];
         }
@@ -279,7 +313,7 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
         const size_t fp = (size_t)f * a.npts + p;
         const int rec = pml_rec_of(a, iz, p);
         const size_t tr = ((size_t)f * a.nr + (rec >= 0 ? rec : 0)) * a.nt;
-        float out;
+        float out = 0.f;
         if (!ADJ) {
             float D = lap + div;
             if (p == sp) D += a.wavelet[n] * a.src_scale;
@@ -293,23 +327,22 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
             const float av = rec >= 0 ? a.adj[tr + n] * a.rec_invw[rec] : 0.f;
             const float Fv = (lap - div) + av;
             const float w = fmaf(pc.q, wv[j], fmaf(-pc.bq, mv[j], Fv));
-            const float mu = mv[j] + w;
             W[fp] = w;
-            MU[fp] = mu;
-            out = pc.r * mu;
+            Fn[fp] = mv[j] + w;
         }
-        const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
-        Fn[o] = out;
-        if (a.fs && iz >= 1 && iz <= 4) Fn[o - 2 * iz * a.S] = out;
+        if (!ADJ) {
+            const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
+            Fn[o] = out;
+            if (a.fs && iz >= 1 && iz <= 4) Fn[o - 2 * iz * a.S] = out;
+        }
     }
 }
 
 // Receivers at the start of a sweep (grid: receivers x fields).  Forward:
 // sample 0 of every trace is u^0 = 0.  Adjoint: mu^{N-1} = a^{N-1} / w at the
-// receivers, nu^{N-1} = mu^{N-1} and y = r mu (the other cells are zero).
+// receivers and nu^{N-1} = mu^{N-1} (the other cells are zero).
 template <bool ADJ>
-__global__ void k_pml_hbm_start(const PmlHbmArgs a, float* __restrict__ Y, float* __restrict__ W,
-                                float* __restrict__ MU) {
+__global__ void k_pml_hbm_start(const PmlHbmArgs a, float* __restrict__ W, float* __restrict__ MU) {
     const int rcv = blockIdx.x * 256 + threadIdx.x;
     if (rcv >= a.nr) return;
     const int f = blockIdx.y;
@@ -318,18 +351,10 @@ __global__ void k_pml_hbm_start(const PmlHbmArgs a, float* __restrict__ Y, float
         a.traces[tr] = 0.f;
         return;
     }
-    const int p = a.rec_pt[rcv];
-    const int iz = p / a.nxp, ix = p - (p / a.nxp) * a.nxp;
-    const int b = f / a.ns;
+    const size_t fp = (size_t)f * a.npts + a.rec_pt[rcv];
     const float mu = a.adj[tr + a.nt - 1] * a.rec_invw[rcv];
-    const size_t fp = (size_t)f * a.npts + p;
     W[fp] = mu;
     MU[fp] = mu;
-    const float E = 1.f / (1.f + a.tx[ix] + a.tz[iz]);
-    const float y = (a.K[(size_t)b * a.npts + p] * E) * mu;
-    const size_t o = (size_t)f * a.plane + (size_t)(iz + 4) * a.S + ix + 4;
-    Y[o] = y;
-    if (a.fs && iz >= 1 && iz <= 4) Y[o - 2 * iz * a.S] = y;
 }
 
 // Saves (SAVE) or restores the forward state of every field at checkpoint
@@ -395,7 +420,7 @@ PmlHbmArgs make_pml_hbm_args(const Plan& p) {
 // State buffers of the HBM sweep, offsets fixed by max_batch.
 struct PmlHbmState {
     float *F0, *F1, *W, *P0, *P1;      // forward: u planes (ping-pong), w, psi (ping-pong)
-    float *Y0, *Y1, *NU, *MU, *H0, *H1;  // adjoint: y planes, nu, mu, phi
+    float *M0, *M1, *NU, *H0, *H1;     // adjoint: mu (ping-pong), nu, phi (ping-pong)
 };
 
 PmlHbmState pml_hbm_state(const Plan& p) {
@@ -407,11 +432,10 @@ PmlHbmState pml_hbm_state(const Plan& p) {
     s.W = s.F1 + mf * plane;
     s.P0 = s.W + mf * npts;
     s.P1 = s.P0 + mf * nl2;
-    s.Y0 = p.astate;
-    s.Y1 = s.Y0 + mf * plane;
-    s.NU = s.Y1 + mf * plane;
-    s.MU = s.NU + mf * npts;
-    s.H0 = s.MU + mf * npts;
+    s.M0 = p.astate;
+    s.M1 = s.M0 + mf * npts;
+    s.NU = s.M1 + mf * npts;
+    s.H0 = s.NU + mf * npts;
     s.H1 = s.H0 + mf * nl2;
     return s;
 }
@@ -421,13 +445,13 @@ int hbm_grid(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
 // One step over all tiles: the plain tiles, then the layer tiles (independent launches within a step).
 template <bool ADJ>
 void pml_hbm_step(const Plan& p, const PmlHbmArgs& a, int nf, int n, const float* F, float* Fn, const float* Pin,
-                  float* Pout, float* W, float* MU, float* D, size_t dstride, hipStream_t st) {
+                  float* Pout, float* W, float* D, size_t dstride, hipStream_t st) {
     if (p.pml_ntp > 0)
         hipLaunchKernelGGL((k_pml_hbm_tile<ADJ, false>), dim3(p.pml_ntp, 1, nf), dim3(256), 0, st, a, p.pml_tiles, n,
-                           F, Fn, Pin, Pout, W, MU, D, dstride);
+                           F, Fn, Pin, Pout, W, D, dstride);
     if (p.pml_ntl > 0)
         hipLaunchKernelGGL((k_pml_hbm_tile<ADJ, true>), dim3(p.pml_ntl, 1, nf), dim3(256), 0, st, a,
-                           p.pml_tiles + p.pml_ntp, n, F, Fn, Pin, Pout, W, MU, D, dstride);
+                           p.pml_tiles + p.pml_ntp, n, F, Fn, Pin, Pout, W, D, dstride);
 }
 
 // Enqueues the whole forward sweep of B samples on st (reads p.wav, writes p.trace_buf; keeps the history of D
@@ -444,7 +468,7 @@ void pml_hbm_enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
     launch_fill(s.P0, nf * nl2, 0.f, st);
     launch_fill(s.P1, nf * nl2, 0.f, st);
     hipLaunchKernelGGL(k_pml_hbm_start<false>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, nullptr,
-                       nullptr, nullptr);
+                       nullptr);
     const int nsteps = p.g.nt - 1;
     const bool full = keep && p.store_mode == 0, ck = keep && p.store_mode == 1;
     const size_t dstride = (size_t)nsteps * npts;
@@ -453,8 +477,8 @@ void pml_hbm_enqueue_forward(Plan& p, int B, int keep, hipStream_t st) {
         if (ck && n % p.ckpt_every == 0)
             hipLaunchKernelGGL(k_pml_hbm_ckpt<true>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
                                p.ckpt, F0, s.W, P0, nf, p.nseg, n / p.ckpt_every, (int)plane, (int)npts, p.pml_nl);
-        pml_hbm_step<false>(p, a, nf, n, F0, F1, P0, P1, s.W, nullptr, full ? p.Dstore + (size_t)n * npts : nullptr,
-                            dstride, st);
+        pml_hbm_step<false>(p, a, nf, n, F0, F1, P0, P1, s.W, full ? p.Dstore + (size_t)n * npts : nullptr, dstride,
+                            st);
         std::swap(F0, F1);
         std::swap(P0, P1);
     }
@@ -468,18 +492,17 @@ void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
     PmlHbmState s = pml_hbm_state(p);
     const size_t plane = (size_t)a.plane, npts = (size_t)p.npts, nl2 = 2 * (size_t)p.pml_nl;
     const int nsteps = p.g.nt - 1;
-    launch_fill(s.Y0, nf * plane, 0.f, st);
-    launch_fill(s.Y1, nf * plane, 0.f, st);
+    launch_fill(s.M0, nf * npts, 0.f, st);
+    launch_fill(s.M1, nf * npts, 0.f, st);
     launch_fill(s.NU, nf * npts, 0.f, st);
-    launch_fill(s.MU, nf * npts, 0.f, st);
     launch_fill(s.H0, nf * nl2, 0.f, st);
     launch_fill(s.H1, nf * nl2, 0.f, st);
     launch_fill(p.gpad, nf * npts, 0.f, st);
-    hipLaunchKernelGGL(k_pml_hbm_start<true>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, s.Y0, s.NU, s.MU);
-    float *Y0 = s.Y0, *Y1 = s.Y1, *H0 = s.H0, *H1 = s.H1;
+    hipLaunchKernelGGL(k_pml_hbm_start<true>, dim3((p.g.nr + 255) / 256, nf), dim3(256), 0, st, a, s.NU, s.M0);
+    float *M0 = s.M0, *M1 = s.M1, *H0 = s.H0, *H1 = s.H1;
     auto adjoint_step = [&](int n, float* Dn, size_t dstride) {
-        pml_hbm_step<true>(p, a, nf, n, Y0, Y1, H0, H1, s.NU, s.MU, Dn, dstride, st);
-        std::swap(Y0, Y1);
+        pml_hbm_step<true>(p, a, nf, n, M0, M1, H0, H1, s.NU, Dn, dstride, st);
+        std::swap(M0, M1);
         std::swap(H0, H1);
     };
     if (p.store_mode == 0) {
@@ -497,8 +520,7 @@ void pml_hbm_enqueue_adjoint(Plan& p, int B, hipStream_t st) {
         hipLaunchKernelGGL(k_pml_hbm_ckpt<false>, dim3(hbm_grid(nf * (plane + npts + nl2))), dim3(256), 0, st,
                            p.ckpt, F0, s.W, P0, nf, p.nseg, c, (int)plane, (int)npts, p.pml_nl);
         for (int n = n0; n < n1; ++n) {
-            pml_hbm_step<false>(p, fa, nf, n, F0, F1, P0, P1, s.W, nullptr, p.Dstore + (size_t)(n - n0) * npts,
-                                dstride, st);
+            pml_hbm_step<false>(p, fa, nf, n, F0, F1, P0, P1, s.W, p.Dstore + (size_t)(n - n0) * npts, dstride, st);
             std::swap(F0, F1);
             std::swap(P0, P1);
         }
