@@ -142,13 +142,22 @@ constexpr int kPqX = kPtX + 8, kPqZ = kPtZ + 8;      // Q region: the tile and a
 template <int HW, int WX>
 __device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __restrict__ Ff, float* fw, float* txs,
                                           float* tzs, int zt, int x0, int off) {
-    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW;
-    for (int i = threadIdx.x; i < GZ * GX; i += 256) {
+    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW, N = (GZ * GX + 255) / 256;
+    float v[N];  // all loads of a thread first (clamped addresses), then the stores
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int i = threadIdx.x + k * 256;
         const int r = i / GX, c = i - (i / GX) * GX;
         const int iz = zt - HW + r, ix = x0 - HW + c;
-        float v = 0.f;
-        if (iz >= -4 && iz < a.nzp + 4 && ix >= -4 && ix < a.nxp + 4) v = Ff[(size_t)(iz + 4) * a.S + ix + 4];
-        fw[(r + off) * WX + c + off] = v;
+        const bool in = i < GZ * GX && iz >= -4 && iz < a.nzp + 4 && ix >= -4 && ix < a.nxp + 4;
+        const float t = Ff[in ? (size_t)(iz + 4) * a.S + ix + 4 : 0];
+        v[k] = in ? t : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int i = threadIdx.x + k * 256;
+        const int r = i / GX, c = i - (i / GX) * GX;
+        if (i < GZ * GX) fw[(r + off) * WX + c + off] = v[k];
     }
     for (int i = threadIdx.x; i < GX; i += 256) {
         const int ix = x0 - HW + i;
@@ -169,18 +178,29 @@ template <int HW, int WX>
 __device__ __forceinline__ void pml_stage_y(const PmlHbmArgs& a, const float* __restrict__ Mf,
                                             const float* __restrict__ Kb, float* fw, float* txs, float* tzs, int zt,
                                             int x0) {
-    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW;
-    for (int i = threadIdx.x; i < GZ * GX; i += 256) {
+    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW, N = (GZ * GX + 255) / 256;
+    float kv[N], mv[N], tv[N], zv[N];  // all loads of a thread first (clamped addresses), then the products
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int i = threadIdx.x + k * 256;
         const int r = i / GX, c = i - (i / GX) * GX;
         const int iz = zt - HW + r, ix = x0 - HW + c;
         const int cz = a.fs && iz < 0 ? -iz : iz;
-        float v = 0.f;
-        if (iz >= -4 && cz >= 0 && cz < a.nzp && ix >= 0 && ix < a.nxp) {
-            const int p = cz * a.nxp + ix;
-            const float E = 1.f / (1.f + a.tx[ix] + a.tz[cz]);
-            v = (Kb[p] * E) * Mf[p];
-        }
-        fw[r * WX + c] = v;
+        const bool in = i < GZ * GX && iz >= -4 && cz >= 0 && cz < a.nzp && ix >= 0 && ix < a.nxp;
+        const int zz = in ? cz : 0, xx = in ? ix : 0;
+        const int p = zz * a.nxp + xx;
+        kv[k] = Kb[p];
+        mv[k] = Mf[p];
+        tv[k] = a.tx[xx];
+        zv[k] = a.tz[zz];
+        if (!in) mv[k] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int i = threadIdx.x + k * 256;
+        if (i >= GZ * GX) break;
+        const float E = 1.f / (1.f + tv[k] + zv[k]);
+        fw[i] = (kv[k] * E) * mv[k];
     }
     for (int i = threadIdx.x; i < GX; i += 256) {
         const int ix = x0 - HW + i;
