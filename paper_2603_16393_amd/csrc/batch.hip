@@ -35,6 +35,23 @@
 
 namespace fwi {
 
+// A value every lane of the workgroup holds alike (a unit's descriptor
+// fields), moved into scalar registers word by word.  The unit bodies are
+// separate functions whose descriptor pointer arrives in vector registers;
+// without this their loop bounds, strides and base pointers would occupy
+// vector registers and vector instructions, where the plan's kernels keep
+// them in scalar ones.
+template <class T>
+__device__ __forceinline__ T uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized");
+    T r;
+    const unsigned* src = reinterpret_cast<const unsigned*>(&v);
+    unsigned* dst = reinterpret_cast<unsigned*>(&r);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return r;
+}
+
 // Variants compiled into the persistent kernel.
 //   LDS-resident register tiles (X, P, exact cover of the padded grid)
 #define FWI_BATCH_LDS(M) M(0, 3, 11, true) M(1, 3, 11, false) M(2, 3, 12, false) M(3, 2, 12, false) M(4, 4, 8, false) M(5, 1, 16, false)
@@ -455,16 +472,16 @@ __device__ __noinline__ void unit_glb_gradient(const BatchUnit* __restrict__ U, 
 // adjoint sweep (separate non-inlined entries: each gets its own registers).
 template <int X, int P, bool EX>
 __device__ __noinline__ void unit_lds_forward_store(const BatchUnit* __restrict__ U, float* lds) {
-    const LdsArgs a = U->la;
-    lds_field<X, P, false, EX, true>(a, 0, U->ax, U->az, lds);
+    const LdsArgs a = uniform(U->la);
+    lds_field<X, P, false, EX, true>(a, 0, uniform(U->ax), uniform(U->az), lds);
 }
 
 template <int X, int P, bool EX>
 __device__ __noinline__ void unit_lds_adjoint(const BatchUnit* __restrict__ U, float* lds) {
-    LdsArgs a = U->la;
-    a.adj = U->adj;
-    a.gpad = U->gpad;
-    lds_field<X, P, true, EX, false>(a, 0, U->ax, U->az, lds);
+    LdsArgs a = uniform(U->la);
+    a.adj = uniform(U->adj);
+    a.gpad = uniform(U->gpad);
+    lds_field<X, P, true, EX, false>(a, 0, uniform(U->ax), uniform(U->az), lds);
 }
 
 template <int X, int P, bool EX>
@@ -480,18 +497,18 @@ __device__ void unit_lds_gradient(const BatchUnit* __restrict__ U, float* lds) {
 // so a band that starts its adjoint early never meets forward words).
 template <int X, int PI, bool EX>
 __device__ __noinline__ void unit_split_forward_store(const BatchUnit* __restrict__ U, float* lds) {
-    const LdsArgs a = U->la;
-    split_field<X, PI, false, EX, true>(a, U->sp, 0, U->part, U->ax, U->az, lds);
+    const LdsArgs a = uniform(U->la);
+    split_field<X, PI, false, EX, true>(a, uniform(U->sp), 0, uniform(U->part), uniform(U->ax), uniform(U->az), lds);
 }
 
 template <int X, int PI, bool EX>
 __device__ __noinline__ void unit_split_adjoint(const BatchUnit* __restrict__ U, float* lds) {
-    LdsArgs a = U->la;
-    a.adj = U->adj;
-    a.gpad = U->gpad;
-    SplitArgs sp = U->sp;
-    sp.xchg = U->xchg_adj;
-    split_field<X, PI, true, EX, false>(a, sp, 0, U->part, U->ax, U->az, lds);
+    LdsArgs a = uniform(U->la);
+    a.adj = uniform(U->adj);
+    a.gpad = uniform(U->gpad);
+    SplitArgs sp = uniform(U->sp);
+    sp.xchg = uniform(U->xchg_adj);
+    split_field<X, PI, true, EX, false>(a, sp, 0, uniform(U->part), uniform(U->ax), uniform(U->az), lds);
 }
 
 template <int X, int PI, bool EX>
@@ -593,8 +610,8 @@ __global__ void k_batch_fold(const FoldReq* __restrict__ req, int nreq, long lon
 // the call happens once per unit.
 template <int X, int P, bool EX>
 __device__ __noinline__ void unit_lds_forward(const BatchUnit* __restrict__ U, float* lds) {
-    const LdsArgs a = U->la;
-    lds_field<X, P, false, EX, false>(a, 0, U->ax, U->az, lds);
+    const LdsArgs a = uniform(U->la);
+    lds_field<X, P, false, EX, false>(a, 0, uniform(U->ax), uniform(U->az), lds);
 }
 
 template <int RB, int SM>
@@ -604,8 +621,8 @@ __device__ __noinline__ void unit_glb_forward(const BatchUnit* __restrict__ U, f
 
 template <int X, int PI, bool EX>
 __device__ __noinline__ void unit_split_forward(const BatchUnit* __restrict__ U, float* lds) {
-    const LdsArgs a = U->la;
-    split_field<X, PI, false, EX, false>(a, U->sp, 0, U->part, U->ax, U->az, lds);
+    const LdsArgs a = uniform(U->la);
+    split_field<X, PI, false, EX, false>(a, uniform(U->sp), 0, uniform(U->part), uniform(U->ax), uniform(U->az), lds);
 }
 
 __device__ void run_unit_forward(const BatchUnit* U, float* lds) {
