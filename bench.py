@@ -205,7 +205,7 @@ MEASURED_TRAFFIC = {
                 "bytes": {"recompute": 1.674e8, "adjoint": 2.331e8}},
     # uneven persistent forward launch of the 64-request mix (profiles/k_batch_uneven64_hbm_traffic.md)
     "uneven": {"sources": (CSRC + "batch.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
-               "sha1": "89131c2aebfef7914550cba6f79dd6b123802a90", "bytes": {"forward": 1.2374e11, "gradient": 6.8432e11}},
+               "sha1": "dbdbfb0233fb10cbf8141e94e23e5b8f923df022", "bytes": {"forward": 1.2338e11, "gradient": 6.1162e11}},
 }
 
 
