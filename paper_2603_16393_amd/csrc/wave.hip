@@ -223,6 +223,10 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
             }
             return true;
         };
+        // the column of u^n a thread's tile points need vertically (rows 4 .. 15 of its strip), in registers
+        float ca[TROWS + 8];
+#pragma unroll
+        for (int i = 0; i < TROWS + 8; ++i) ca[i] = A[(ts * TROWS + 4 + i) * AX + tx + 8];
         constexpr int CH = 4;  // points whose loads are in flight together
 #pragma unroll
         for (int k0 = 0; k0 < NP; k0 += CH) {
@@ -261,9 +265,12 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
                 if (gz >= 0 && gz < nzp && gx >= 0 && gx < nxp) {
                     const int p = gz * nxp + gx;
                     const int li = (r + 4) * AX + c + 4;
-                    const float cc = A[li];
-                    const float lzs = FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX],
-                                               A[li + AX], A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
+                    const float cc = k < TROWS ? ca[k + 4] : A[li];
+                    const float lzs =
+                        k < TROWS ? FWI_LAPD(cc, ca[k], ca[k + 1], ca[k + 2], ca[k + 3], ca[k + 5], ca[k + 6],
+                                             ca[k + 7], ca[k + 8])
+                                  : FWI_LAPD(cc, A[li - 4 * AX], A[li - 3 * AX], A[li - 2 * AX], A[li - AX],
+                                             A[li + AX], A[li + 2 * AX], A[li + 3 * AX], A[li + 4 * AX]);
                     const float lxs = FWI_LAPD(cc, A[li - 4], A[li - 3], A[li - 2], A[li - 1], A[li + 1], A[li + 2],
                                                A[li + 3], A[li + 4]);
                     float D = fmaf(lzs, a.idz2, lxs * a.idx2);
@@ -323,6 +330,13 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
         }
     }
     const float src = ADJ ? 0.f : a.wavelet[m + 1];
+    // forward: the column of u^{n+1} the thread's points need vertically, in registers; the adjoint reads it
+    // from LDS (with its step-2 loads the column would leave 7 waves per SIMD instead of 8)
+    float cb[TROWS + 8] = {};
+    if (!ADJ) {
+#pragma unroll
+        for (int i = 0; i < TROWS + 8; ++i) cb[i] = Bt[(ts * TROWS + i) * EX + tx + 4];
+    }
 #pragma unroll
     for (int j = 0; j < TROWS; ++j) {
         const int lz = ts * TROWS + j;
@@ -330,9 +344,11 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
         if (gz >= nzp) break;
         const int p = gz * nxp + gx;
         const int li = (lz + 4) * EX + tx + 4;
-        const float cc = Bt[li];
-        const float lzs = FWI_LAPD(cc, Bt[li - 4 * EX], Bt[li - 3 * EX], Bt[li - 2 * EX], Bt[li - EX], Bt[li + EX],
-                                   Bt[li + 2 * EX], Bt[li + 3 * EX], Bt[li + 4 * EX]);
+        const float cc = ADJ ? Bt[li] : cb[j + 4];
+        const float lzs =
+            ADJ ? FWI_LAPD(cc, Bt[li - 4 * EX], Bt[li - 3 * EX], Bt[li - 2 * EX], Bt[li - EX], Bt[li + EX],
+                           Bt[li + 2 * EX], Bt[li + 3 * EX], Bt[li + 4 * EX])
+                : FWI_LAPD(cc, cb[j], cb[j + 1], cb[j + 2], cb[j + 3], cb[j + 5], cb[j + 6], cb[j + 7], cb[j + 8]);
         const float lxs = FWI_LAPD(cc, Bt[li - 4], Bt[li - 3], Bt[li - 2], Bt[li - 1], Bt[li + 1], Bt[li + 2],
                                    Bt[li + 3], Bt[li + 4]);
         float D = fmaf(lzs, a.idz2, lxs * a.idx2);
