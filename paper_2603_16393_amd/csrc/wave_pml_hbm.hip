@@ -135,11 +135,53 @@ __device__ __forceinline__ int pml_rec_of(const PmlHbmArgs& a, int iz, int p) {
 constexpr int kPtX = 64, kPtZ = 16;                  // tile
 constexpr int kPqX = kPtX + 8, kPqZ = kPtZ + 8;      // Q region: the tile and a 4-cell ring
 
+// Position of the n-th (from 0) set bit of m, for n < popcount(m).
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int n) {
+    int pos = 0;
+    unsigned int w = (unsigned int)m;
+    int c = __popc(w);
+    if (n >= c) {
+        n -= c;
+        pos = 32;
+        w = (unsigned int)(m >> 32);
+    }
+#pragma unroll
+    for (int h = 16; h >= 1; h >>= 1) {
+        c = __popc(w & ((1u << h) - 1u));
+        if (n >= c) {
+            n -= c;
+            pos += h;
+            w >>= h;
+        }
+    }
+    return pos;
+}
+
+// Damping of the staged columns and rows (thread t holds column t and row t;
+// a staged window is at most 80 columns and 32 rows), loaded with the
+// staging loads from clamped addresses and stored to txs, tzs after them:
+// zero past the grid.
+template <int HW>
+__device__ __forceinline__ void pml_stage_damping_load(const PmlHbmArgs& a, int zt, int x0, float& dxv, float& dzv) {
+    const int t = threadIdx.x;
+    dxv = a.tx[min(max(x0 - HW + t, 0), a.nxp - 1)];
+    dzv = a.tz[min(max(zt - HW + t, 0), a.nzp - 1)];
+}
+template <int HW>
+__device__ __forceinline__ void pml_stage_damping_store(const PmlHbmArgs& a, int zt, int x0, float dxv, float dzv,
+                                                        float* txs, float* tzs) {
+    constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW;
+    static_assert(GX <= 256 && GZ <= 256, "one damping value per thread");
+    const int t = threadIdx.x, ix = x0 - HW + t, iz = zt - HW + t;
+    if (t < GX) txs[t] = ix >= 0 && ix < a.nxp ? dxv : 0.f;
+    if (t < GZ) tzs[t] = iz >= 0 && iz < a.nzp ? dzv : 0.f;
+}
+
 // Stages the gathered field of the tile and an HW-cell ring into fw (row
 // stride WX, offset off rows and columns), from the bordered plane (zero past
 // its border), and the damping of those columns and rows into txs, tzs (zero
 // past the grid).
-template <int HW, int WX>
+template <int HW, int WX, bool DAMP>
 __device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __restrict__ Ff, float* fw, float* txs,
                                           float* tzs, int zt, int x0, int off) {
     constexpr int GX = kPtX + 2 * HW, GZ = kPtZ + 2 * HW, N = (GZ * GX + 255) / 256;
@@ -153,28 +195,27 @@ __device__ __forceinline__ void pml_stage(const PmlHbmArgs& a, const float* __re
         const float t = Ff[in ? (size_t)(iz + 4) * a.S + ix + 4 : 0];
         v[k] = in ? t : 0.f;
     }
+    float dxv = 0.f, dzv = 0.f;
+    if (DAMP) pml_stage_damping_load<HW>(a, zt, x0, dxv, dzv);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int i = threadIdx.x + k * 256;
         const int r = i / GX, c = i - (i / GX) * GX;
         if (i < GZ * GX) fw[(r + off) * WX + c + off] = v[k];
     }
-    for (int i = threadIdx.x; i < GX; i += 256) {
-        const int ix = x0 - HW + i;
-        txs[i] = ix >= 0 && ix < a.nxp ? a.tx[ix] : 0.f;
-    }
-    for (int i = threadIdx.x; i < GZ; i += 256) {
-        const int iz = zt - HW + i;
-        tzs[i] = iz >= 0 && iz < a.nzp ? a.tz[iz] : 0.f;
-    }
+    if (DAMP) pml_stage_damping_store<HW>(a, zt, x0, dxv, dzv, txs, tzs);
 }
+
+// Without DAMP (plain tiles: the staged cells are model cells, or outside the
+// grid), the damping is not staged; in the adjoint's gathered field E = 1 /
+// (1 + 0 + 0) = 1 there, so y = K mu has the bits of (K E) mu.
 
 // The adjoint's gathered field y = r mu of the tile and an HW-cell ring, from
 // mu and K (r = (v dt)^2 E, the product every sweep forms), into fw; rows
 // above a reflecting top are the even mirror images, cells past the grid (and
 // more than 4 rows above a reflecting top) zero.  Also the damping of the
 // staged columns and rows into txs, tzs.
-template <int HW, int WX>
+template <int HW, int WX, bool DAMP>
 __device__ __forceinline__ void pml_stage_y(const PmlHbmArgs& a, const float* __restrict__ Mf,
                                             const float* __restrict__ Kb, float* fw, float* txs, float* tzs, int zt,
                                             int x0) {
@@ -191,25 +232,29 @@ __device__ __forceinline__ void pml_stage_y(const PmlHbmArgs& a, const float* __
         const int p = zz * a.nxp + xx;
         kv[k] = Kb[p];
         mv[k] = Mf[p];
-        tv[k] = a.tx[xx];
-        zv[k] = a.tz[zz];
+        if (DAMP) {
+            tv[k] = a.tx[xx];
+            zv[k] = a.tz[zz];
+        }
         if (!in) mv[k] = 0.f;
     }
+    float dxv = 0.f, dzv = 0.f;
+    if (DAMP) pml_stage_damping_load<HW>(a, zt, x0, dxv, dzv);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int i = threadIdx.x + k * 256;
-        if (i >= GZ * GX) break;
-        const float E = 1.f / (1.f + tv[k] + zv[k]);
-        fw[i] = (kv[k] * E) * mv[k];
+        // formed for every k (clamped loads), stored where the window has the cell: a conditional product
+        // lets the compiler move its loads into the condition, where they would be waited for one by one
+        float y;
+        if (DAMP) {
+            const float E = 1.f / (1.f + tv[k] + zv[k]);
+            y = (kv[k] * E) * mv[k];
+        } else {
+            y = kv[k] * mv[k];  // (K E) mu with E = 1
+        }
+        if (i < GZ * GX) fw[i] = y;
     }
-    for (int i = threadIdx.x; i < GX; i += 256) {
-        const int ix = x0 - HW + i;
-        txs[i] = ix >= 0 && ix < a.nxp ? a.tx[ix] : 0.f;
-    }
-    for (int i = threadIdx.x; i < GZ; i += 256) {
-        const int iz = zt - HW + i;
-        tzs[i] = iz >= 0 && iz < a.nzp ? a.tz[iz] : 0.f;
-    }
+    if (DAMP) pml_stage_damping_store<HW>(a, zt, x0, dxv, dzv, txs, tzs);
 }
 
 // One time step on a 64 x 16 tile of one field (block: 64 columns x 4 strips
@@ -243,77 +288,126 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
     const int code = tiles[ti.tx];
     const int f = ti.field, x0 = (code & 0xffff) * kPtX, zt = (code >> 16) * kPtZ;
     const int b = f / a.ns, s = f - (f / a.ns) * a.ns;
-    if (ADJ)
-        pml_stage_y<HW, FX>(a, F + (size_t)f * a.npts, a.K + (size_t)b * a.npts, fw, txs, tzs, zt, x0);
-    else
-        pml_stage<HW, FX>(a, F + (size_t)f * a.plane, fw, txs, tzs, zt, x0, 0);
-    __syncthreads();
+    // the thread's 4 cells of the update (column tx, rows 4 ts .. 4 ts + 3 of the tile): their loads go out
+    // before the staging, since no block writes what another block reads of them (column clamped, so that
+    // the threads past the grid's last column load too); the adjoint's layer tiles issue them after the Q
+    // phase instead, since their staging holds 40 values per thread and both would cost occupancy
+    constexpr bool EARLY = !(ADJ && LAYER);
+    const int tx = threadIdx.x & 63, ts = threadIdx.x >> 6;
+    const int ix = x0 + tx;
+    float kv[4], wv[4], mv[4], gv[4], dv[4];
+    int rv[4];  // receiver of each cell, or -1
+    auto load_update = [&]() {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int iz = min(zt + ts * 4 + j, a.nzp - 1);
+            const int p = iz * a.nxp + min(ix, a.nxp - 1);
+            const size_t fp = (size_t)f * a.npts + p;
+            kv[j] = a.K[(size_t)b * a.npts + p];
+            wv[j] = W[fp];
+            rv[j] = pml_rec_of(a, iz, p);
+            if (ADJ) {
+                mv[j] = F[fp];
+                gv[j] = a.gpad[fp];
+                dv[j] = Dst[(size_t)f * dstride + p];
+            }
+        }
+    };
+    if (EARLY) load_update();
+    // Layer tiles: the layer cells of the Q region are a small part of it (a frame 6 cells wide), so each wave
+    // lists those among its candidates (chunk k: region cells wave base + k * 256 + lane) by ballots and
+    // evaluates Q (G) of the listed cells only, two per lane at a time; the other cells of gxs, gzs hold zero.
+    constexpr int NQ = (kPqZ * kPqX + 255) / 256;
+    const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+    unsigned long long qm[NQ];  // layer cells among the wave's candidates of chunk k
+    int qc[NQ + 1];             // listed cells in the chunks before k
     if (LAYER) {
-        constexpr int NQ = (kPqZ * kPqX + 255) / 256;
-        const size_t pf = (size_t)f * 2 * a.nl;
-        int li[NQ];
-        float pxv[NQ], pzv[NQ];
+        qc[0] = 0;
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {
             const int i = threadIdx.x + k * 256;
             const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
             const int iz = zt - 4 + r, ix = x0 - 4 + c;
             const int cz = a.fs && iz < 0 ? -iz : iz;
-            li[k] = i < kPqZ * kPqX && pml_in_layer(a, cz, ix) ? pml_layer_index(a, cz, ix) : -1;
+            qm[k] = __ballot(i < kPqZ * kPqX && pml_in_layer(a, cz, ix));
+            qc[k + 1] = qc[k] + __popcll(qm[k]);
         }
-        // clamped to the field's first layer cell, so that no load sits in a divergent branch; a grid without
-        // layer cells (nb = 0) has no auxiliary fields to read
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const int l = li[k] >= 0 ? li[k] : 0;
-            pxv[k] = a.nl > 0 ? Pin[pf + l] : 0.f;
-            pzv[k] = a.nl > 0 ? Pin[pf + a.nl + l] : 0.f;
+        for (int i = threadIdx.x; i < kPqZ * kPqX; i += 256) {
+            gxs[i] = 0.f;
+            gzs[i] = 0.f;
         }
+    }
+    if (ADJ)
+        pml_stage_y<HW, FX, LAYER>(a, F + (size_t)f * a.npts, a.K + (size_t)b * a.npts, fw, txs, tzs, zt, x0);
+    else
+        pml_stage<HW, FX, LAYER>(a, F + (size_t)f * a.plane, fw, txs, tzs, zt, x0, 0);
+    __syncthreads();
+    if (LAYER) {
+        const size_t pf = (size_t)f * 2 * a.nl;
+        const int total = qc[NQ];
+        for (int t0 = 0; t0 < total; t0 += 128) {
+            int iv[2];
+            float pxv[2], pzv[2];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const int i = threadIdx.x + k * 256;
-            if (i >= kPqZ * kPqX) break;
-            const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
-            const int iz = zt - 4 + r, ix = x0 - 4 + c;
-            // rows above a reflecting top hold the odd mirror of Q_z (G_z) of the layer cells below
-            const bool mirror = a.fs && iz < 0;
-            const int cz = mirror ? -iz : iz;
-            float ox = 0.f, oz = 0.f;
-            if (li[k] >= 0) {
-                float px1, pz1;
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + u * 64 + lane;  // entry t of the wave's list
+                int k = 0;
+#pragma unroll
+                for (int kk = 1; kk < NQ; ++kk) k += t >= qc[kk];
+                unsigned long long m = qm[0];
+                int base = 0;
+#pragma unroll
+                for (int kk = 1; kk < NQ; ++kk)
+                    if (k == kk) {
+                        m = qm[kk];
+                        base = qc[kk];
+                    }
+                const int i = wbase + k * 256 + nth_set_bit(m, t - base);
+                iv[u] = t < total ? i : -1;
+                const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
+                const int iz = zt - 4 + r, ix = x0 - 4 + c;
+                const int cz = a.fs && iz < 0 ? -iz : iz;
+                // a listed cell exists, so the field has layer cells; past the list, the field's first one
+                const int l = t < total ? pml_layer_index(a, cz, ix) : 0;
+                pxv[u] = Pin[pf + l];
+                pzv[u] = Pin[pf + a.nl + l];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int i = iv[u];
+                if (i < 0) continue;
+                const int r = i / kPqX, c = i - (i / kPqX) * kPqX;
+                const int iz = zt - 4 + r, ix = x0 - 4 + c;
+                // rows above a reflecting top hold the odd mirror of Q_z (G_z) of the layer cells below
+                const bool mirror = a.fs && iz < 0;
+                const int cz = mirror ? -iz : iz;
+                float ox, oz, px1, pz1;
                 pml_aux<ADJ>(a, fw + (cz - zt + HW) * FX + (ix - x0 + HW), FX, txs[ix - x0 + HW], tzs[cz - zt + HW],
-                             pxv[k], pzv[k], ox, oz, px1, pz1);
+                             pxv[u], pzv[u], ox, oz, px1, pz1);
                 if (!mirror && r >= 4 && r < 4 + kPtZ && c >= 4 && c < 4 + kPtX) {
-                    Pout[pf + li[k]] = px1;
-                    Pout[pf + a.nl + li[k]] = pz1;
+                    const int l = pml_layer_index(a, cz, ix);
+                    Pout[pf + l] = px1;
+                    Pout[pf + a.nl + l] = pz1;
                 }
                 if (mirror) {
                     ox = 0.f;
                     oz = -oz;
                 }
+                gxs[i] = ox;
+                gzs[i] = oz;
             }
-            gxs[i] = ox;
-            gzs[i] = oz;
         }
         __syncthreads();
     }
-    const int tx = threadIdx.x & 63, ts = threadIdx.x >> 6;
-    const int ix = x0 + tx;
+    if (!EARLY) load_update();
     if (ix >= a.nxp) return;
     const int sp = a.src_pt[s];
-    float kv[4], wv[4], mv[4], gv[4], dv[4];
+    const float srcv = ADJ ? 0.f : a.wavelet[n] * a.src_scale;
+    float av[4];  // adjoint: sources of the receiver cells, loaded before the update's first store
+    if (ADJ) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int iz = min(zt + ts * 4 + j, a.nzp - 1);
-        const int p = iz * a.nxp + ix;
-        const size_t fp = (size_t)f * a.npts + p;
-        kv[j] = a.K[(size_t)b * a.npts + p];
-        wv[j] = W[fp];
-        if (ADJ) {
-            mv[j] = F[fp];
-            gv[j] = a.gpad[fp];
-            dv[j] = Dst[(size_t)f * dstride + p];
-        }
+        for (int j = 0; j < 4; ++j)
+            av[j] = rv[j] >= 0 ? a.adj[((size_t)f * a.nr + rv[j]) * a.nt + n] * a.rec_invw[rv[j]] : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -324,19 +418,27 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
         const float* c = fw + (lz + HW) * FX + tx + HW;
         const float c0 = c[0];
         const float lap = pml_lap(a, c, FX);
-        const PmlCoef pc = pml_coef(a, kv[j], txs[tx + HW], tzs[lz + HW], iz, ix);
+        PmlCoef pc;
+        if (LAYER) {
+            pc = pml_coef(a, kv[j], txs[tx + HW], tzs[lz + HW], iz, ix);
+        } else {  // a model cell with both damping values 0: E = 1, so r = K, q = 1, bq = 0
+            pc.r = kv[j];
+            pc.q = 1.f;
+            pc.bq = 0.f;
+            pc.deep = true;
+        }
         float div = 0.f;  // Q (G) is zero within 4 cells of a deep cell, and in a tile whose ring has no layer
         if (LAYER && !pc.deep) {
             const int q = (lz + 4) * kPqX + tx + 4;
             div = pml_div(a, gxs + q, gzs + q, kPqX);
         }
         const size_t fp = (size_t)f * a.npts + p;
-        const int rec = pml_rec_of(a, iz, p);
+        const int rec = rv[j];
         const size_t tr = ((size_t)f * a.nr + (rec >= 0 ? rec : 0)) * a.nt;
         float out = 0.f;
         if (!ADJ) {
             float D = lap + div;
-            if (p == sp) D += a.wavelet[n] * a.src_scale;
+            if (p == sp) D += srcv;
             const float w = fmaf(pc.r, D, fmaf(pc.q, wv[j], -pc.bq * c0));
             W[fp] = w;
             out = c0 + w;
@@ -344,8 +446,7 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
             if (rec >= 0 && a.traces) a.traces[tr + n + 1] = out;
         } else {
             a.gpad[fp] = fmaf(c0, dv[j], gv[j]);  // imaging: y^{n+1} D^n
-            const float av = rec >= 0 ? a.adj[tr + n] * a.rec_invw[rec] : 0.f;
-            const float Fv = (lap - div) + av;
+            const float Fv = (lap - div) + av[j];
             const float w = fmaf(pc.q, wv[j], fmaf(-pc.bq, mv[j], Fv));
             W[fp] = w;
             Fn[fp] = mv[j] + w;
