@@ -196,6 +196,10 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
     const bool rec1 = (zt + TZ + 4 > a.rec_z0) && (zt - 4 <= a.rec_z1);
     const int tx = tid % TX, ts = tid / TX;
     float w1[TROWS];
+    // step 2 updates the same four tile points: K, the damping product, the receiver and its weight of each,
+    // loaded in step 1, stay in registers
+    float kt[TROWS], dt[TROWS], it[TROWS];
+    int rt[TROWS];
     {
         constexpr int NRING = EZ * EX - TZ * TX;  // 704
         constexpr int NP = TROWS + (NRING + 255) / 256;
@@ -284,7 +288,13 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
                         if (rr >= 0 && a.traces) a.traces[(trf + rr) * a.nt + m + 1] = un;
                     }
                 }
-                if (k < TROWS) w1[k] = wn;
+                if (k < TROWS) {
+                    w1[k] = wn;
+                    kt[k] = kv[kk];
+                    dt[k] = dv[kk];
+                    rt[k] = rv[kk];
+                    it[k] = iv[kk];
+                }
                 Bt[r * EX + c] = un;
             }
         }
@@ -301,28 +311,18 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
     // step 2 on the tile (the mapping of k_wave_tile)
     const int gx = x0 + tx;
     if (gx >= nxp) return;
-    const float axv = ax_g[gx];
-    const bool rec2 = (zt + TZ > a.rec_z0) && (zt <= a.rec_z1);
+    const bool rec2 = (zt + TZ > a.rec_z0) && (zt <= a.rec_z1);  // implies rec1
     float* un_g = a.unxt + (size_t)field * a.npts;
     float* wo = wout + (size_t)field * a.npts;
-    float kv[TROWS], zv[TROWS], av[TROWS], iv[TROWS], d1[TROWS], d2[TROWS], sv[TROWS];
+    float av[TROWS], d1[TROWS], d2[TROWS], sv[TROWS];
     int rv[TROWS];
 #pragma unroll
     for (int j = 0; j < TROWS; ++j) {
         const int gz = min(zt + ts * TROWS + j, nzp - 1);
         const int p = gz * nxp + gx;
-        kv[j] = Kb[p];
-        zv[j] = az_g[gz];
-        rv[j] = -1;
-        av[j] = iv[j] = d1[j] = d2[j] = sv[j] = 0.f;
-        if (rec2) {
-            rv[j] = a.rec_map[p];
-            if (ADJ) {
-                const int q = max(rv[j], 0);
-                av[j] = a.adj[(trf + q) * a.nt + (a.nt - 2 - m)];
-                iv[j] = a.rec_invw[q];
-            }
-        }
+        rv[j] = rec2 ? rt[j] : -1;
+        av[j] = d1[j] = d2[j] = sv[j] = 0.f;
+        if (ADJ && rec2) av[j] = a.adj[(trf + max(rv[j], 0)) * a.nt + (a.nt - 2 - m)];
         if (ADJ && a.Din) {
             d1[j] = a.Din[(size_t)field * a.dstride + p];
             d2[j] = Din2[(size_t)field * a.dstride + p];
@@ -354,8 +354,8 @@ __global__ __launch_bounds__(256) void k_wave_tile2(TileArgs a, int m, const flo
         float D = fmaf(lzs, a.idz2, lxs * a.idx2);
         const int rr = rv[j];
         if (!ADJ && p == sp) D = fmaf(src, a.src_scale, D);
-        if (ADJ && rr >= 0) D = fmaf(iv[j], av[j], D);
-        const float wn = fmaf(kv[j], D, (axv * zv[j]) * w1[j]);
+        if (ADJ && rr >= 0) D = fmaf(it[j], av[j], D);
+        const float wn = fmaf(kt[j], D, dt[j] * w1[j]);
         const float un = cc + wn;
         wo[p] = wn;
         un_g[p] = un;
