@@ -65,9 +65,12 @@ def _acq(nz, nx, fs, nt, ns, two_rows=False, v_max=4000.0, dx=12.0, f_peak=25.0,
 
 @pytest.mark.parametrize("nz,nx,fs,nt,two_rows,B,nb", [(9, 11, True, 160, False, 2, 6), (9, 11, False, 160, False, 1, 6),
                                                        (40, 50, True, 300, True, 2, 6), (37, 53, False, 300, True, 2, 6),
-                                                       (62, 70, True, 400, False, 3, 6), (30, 36, False, 200, False, 2, 0)])
+                                                       (62, 70, True, 400, False, 3, 6), (30, 36, False, 200, False, 2, 0),
+                                                       (20, 24, False, 200, True, 2, 20), (16, 40, True, 200, False, 2, 20)])
 def test_hbm_sweep_equals_lds_sweep(dev, nz, nx, fs, nt, two_rows, B, nb):
-    """nb = 0: a PML geometry without layer cells (reflecting edges), whose layer-class tiles hold none."""
+    """nb = 0: a PML geometry without layer cells (reflecting edges), whose layer-class tiles hold none.
+    nb = 20: tiles lying mostly or wholly in the layer, whose waves list more layer cells than one pass of
+    two per lane takes."""
     from paper_2603_16393_amd import FwiPlan
 
     acq = _acq(nz, nx, fs, nt, 3, two_rows, nb=nb)
