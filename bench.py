@@ -201,7 +201,7 @@ MEASURED_TRAFFIC = {
               "bytes": {"forward": 9.922e7 + 6.48e7, "recompute": 9.922e7 + 2 * 6.48e7, "adjoint": 2.976e8}},
     # HBM-swept PML, per launch of the 400 x 800 checkpointed workload
     # (profiles/k_pml_hbm_tile_ckpt_400x800_hbm_traffic.md): recomputation (D written) and adjoint
-    "pml_hbm": {"sources": (CSRC + "wave_pml_hbm.hip", CSRC + "pml_stencil.h"), "sha1": "aada8428d3846f6deb9da20556239aa8d3dece94",
+    "pml_hbm": {"sources": (CSRC + "wave_pml_hbm.hip", CSRC + "pml_stencil.h"), "sha1": "67081226c82d5c5b73b66944a505dd0547996631",
                 "bytes": {"recompute": 1.680e8, "adjoint": 2.274e8}},
     # uneven persistent forward launch of the 64-request mix (profiles/k_batch_uneven64_hbm_traffic.md)
     "uneven": {"sources": (CSRC + "batch.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),

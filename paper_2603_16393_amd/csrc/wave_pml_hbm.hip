@@ -268,7 +268,8 @@ __device__ __forceinline__ void pml_stage_y(const PmlHbmArgs& a, const float* __
 // (G) values of the layer cells in its 4-cell ring, from their values before
 // the step, while the owning tile replaces them.  Plain tiles (LAYER false:
 // no layer cell within 4 cells, rows past a reflecting top being mirror
-// images of model rows) stage u with a 4-cell ring and run the leapfrog; layer
+// images of model rows) stage u with a 4-cell ring and run the leapfrog (their
+// cells and rings are model cells: no damping is staged, E = 1); layer
 // tiles stage an 8-cell ring and keep Q (G) of the tile and its ring in LDS,
 // zero outside the layer and the grid, odd across a reflecting top.  The two
 // classes are separate launches so that the plain tiles, most of the grid,
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(256) k_pml_hbm_tile(const PmlHbmArgs a, const 
         }
     };
     if (EARLY) load_update();
-    // Layer tiles: the layer cells of the Q region are a small part of it (a frame 6 cells wide), so each wave
+    // Layer tiles: the layer cells of the Q region are a small part of it (a frame nb cells wide), so each wave
     // lists those among its candidates (chunk k: region cells wave base + k * 256 + lane) by ballots and
     // evaluates Q (G) of the listed cells only, two per lane at a time; the other cells of gxs, gzs hold zero.
     constexpr int NQ = (kPqZ * kPqX + 255) / 256;
