@@ -97,16 +97,24 @@ __device__ int lower_bound_d(const double* A, int n, double x) {
     return lo;
 }
 
-__device__ int lower_bound_i(const int* A, int n, int x) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (A[mid] < x)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Q searches of one non-decreasing array in lockstep (the same steps for all, so
+// their reads overlap instead of waiting one by one): out[q] = first index k in
+// [0, n) with A[k] >= x[q], n if none.  Each step halves the candidate range
+// [base, base + len] of every query.
+template <int Q, class T>
+__device__ void lower_bound_n(const T* A, int n, const T (&x)[Q], int (&out)[Q]) {
+    int base[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) base[q] = 0;
+    int len = n;
+    while (len > 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) base[q] = (A[base[q] + half] < x[q]) ? base[q] + half : base[q];
+        len -= half;
     }
-    return lo;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) out[q] = (n > 0 && A[base[q]] < x[q]) ? base[q] + 1 : base[q];
 }
 
 __device__ inline double xi_weight(int j, int nxi) {
@@ -271,19 +279,51 @@ __global__ __launch_bounds__(W2T) void k_w2_misfit(int ntr, int nt, int nxi, dou
     const float* y = dsyn + (size_t)u * nt;
     const double cp = cprime[t];
     const double norm = reduction ? (double)ntr : *sobs;
-    for (int k = threadIdx.x; k < nt; k += W2T) H[k] = om[k] * (double)y[k] + cp;
+    // loops over a thread's elements e = threadIdx.x + i W2T take G of them at a time, so that their global
+    // loads and LDS searches overlap
+    constexpr int G = 4;
+    for (int k0 = threadIdx.x; k0 < nt; k0 += G * W2T) {
+        double ov[G];
+        float yv[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = min(k0 + g * W2T, nt - 1);
+            ov[g] = om[k];
+            yv[g] = y[k];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (k0 + g * W2T < nt) H[k0 + g * W2T] = ov[g] * (double)yv[g] + cp;
+    }
     __syncthreads();
     const double Z = build_cdf(H, F, Fh, nt, dt, epsp, sh);
     const double inv = 1.0 / (Z + epsp);
     const double Fmax = Fh[nt - 1];
     double m2 = 0.0;
-    for (int j = threadIdx.x; j < nxi; j += W2T) {
-        int k;
-        const double Q = quantile(F, Fh, nt, dt, (double)j / (double)(nxi - 1), Fmax, &k);
-        const double d = Q - qo[j];
-        dl[j] = d;
-        kst[j] = k;
-        m2 += xi_weight(j, nxi) * d * d;
+    // quantiles (as quantile() forms them), G xi nodes per thread at a time
+    for (int j0 = threadIdx.x; j0 < nxi; j0 += G * W2T) {
+        double x[G], qv[G];
+        int kk[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int j = min(j0 + g * W2T, nxi - 1);
+            const double xi = (double)j / (double)(nxi - 1);
+            x[g] = xi > Fmax ? Fmax : xi;
+            qv[g] = qo[j];
+        }
+        lower_bound_n<G>(Fh, nt, x, kk);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int j = j0 + g * W2T;
+            if (j >= nxi) break;
+            // x <= Fh[nt-1] keeps k <= nt-1; the min only matters for non-finite traces
+            const int k = min(kk[g], nt - 1);
+            const double Q = k == 0 ? 0.0 : dt * ((double)(k - 1) + (x[g] - F[k - 1]) / (F[k] - F[k - 1]));
+            const double d = Q - qv[g];
+            dl[j] = d;
+            kst[j] = k;
+            m2 += xi_weight(j, nxi) * d * d;
+        }
     }
     m2 = block_reduce<OpSum>(m2, sh);
     const double W2 = sqrt(m2);
@@ -291,30 +331,41 @@ __global__ __launch_bounds__(W2T) void k_w2_misfit(int ntr, int nt, int nxi, dou
     if (!adj) return;
     const double dm = squared ? 1.0 / norm : (W2 > 0.0 ? 1.0 / (2.0 * W2 * norm) : 0.0);
     // Fbar_k into Fh (the running max is no longer needed after the barrier in block_reduce)
-    for (int k = threadIdx.x; k < nt; k += W2T) {
-        const int j0 = lower_bound_i(kst, nxi, k);
-        const int j1 = lower_bound_i(kst, nxi, k + 1);
-        const int j2 = lower_bound_i(kst, nxi, k + 2);
-        double fb = 0.0;
-        // xi nodes bracketed by [k-1, k]: term dQ/dF_k
-        for (int j = j0; j < j1; ++j) {
-            const double xi = (double)j / (double)(nxi - 1);
-            if (k == 0 || xi > Fmax) continue;
-            const double den = F[k] - F[k - 1];
-            const double al = (xi - F[k - 1]) / den;
-            const double qb = dm * 2.0 * xi_weight(j, nxi) * dl[j];
-            fb += qb * (-dt * al / den);
+    for (int k0 = threadIdx.x; k0 < nt; k0 += G * W2T) {
+        int kx[3 * G], jr[3 * G];  // first xi nodes bracketed at k, k + 1, k + 2 of the G elements
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            kx[3 * g] = k0 + g * W2T;
+            kx[3 * g + 1] = k0 + g * W2T + 1;
+            kx[3 * g + 2] = k0 + g * W2T + 2;
         }
-        // xi nodes bracketed by [k, k+1]: term dQ/dF_k as the left end
-        for (int j = j1; j < j2; ++j) {
-            const double xi = (double)j / (double)(nxi - 1);
-            if (xi > Fmax) continue;
-            const double den = F[k + 1] - F[k];
-            const double al = (xi - F[k]) / den;
-            const double qb = dm * 2.0 * xi_weight(j, nxi) * dl[j];
-            fb += qb * (dt * (al - 1.0) / den);
+        lower_bound_n<3 * G>(kst, nxi, kx, jr);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = k0 + g * W2T;
+            if (k >= nt) break;
+            const int j0 = jr[3 * g], j1 = jr[3 * g + 1], j2 = jr[3 * g + 2];
+            double fb = 0.0;
+            // xi nodes bracketed by [k-1, k]: term dQ/dF_k
+            for (int j = j0; j < j1; ++j) {
+                const double xi = (double)j / (double)(nxi - 1);
+                if (k == 0 || xi > Fmax) continue;
+                const double den = F[k] - F[k - 1];
+                const double al = (xi - F[k - 1]) / den;
+                const double qb = dm * 2.0 * xi_weight(j, nxi) * dl[j];
+                fb += qb * (-dt * al / den);
+            }
+            // xi nodes bracketed by [k, k+1]: term dQ/dF_k as the left end
+            for (int j = j1; j < j2; ++j) {
+                const double xi = (double)j / (double)(nxi - 1);
+                if (xi > Fmax) continue;
+                const double den = F[k + 1] - F[k];
+                const double al = (xi - F[k]) / den;
+                const double qb = dm * 2.0 * xi_weight(j, nxi) * dl[j];
+                fb += qb * (dt * (al - 1.0) / den);
+            }
+            Fh[k] = fb;
         }
-        Fh[k] = fb;
     }
     block_scan<OpSum, true>(Fh, nt, sh);  // Fh[m] = S_m = sum_{k >= m} Fbar_k
     double part = 0.0;
@@ -328,10 +379,18 @@ __global__ __launch_bounds__(W2T) void k_w2_misfit(int ntr, int nt, int nxi, dou
     const double T = block_reduce<OpSum>(part, sh);
     const double Zb = -T * inv * inv;
     float* a = adj + (size_t)u * nt;
-    for (int m = threadIdx.x; m < nt; m += W2T) {
-        const double tau = (m == 0 || m == nt - 1) ? 0.5 : 1.0;
-        const double hb = F[m] * inv + Zb * dt * tau;
-        a[m] = (float)(om[m] * hb);
+    for (int m0 = threadIdx.x; m0 < nt; m0 += G * W2T) {
+        double ov[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) ov[g] = om[min(m0 + g * W2T, nt - 1)];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int m = m0 + g * W2T;
+            if (m >= nt) break;
+            const double tau = (m == 0 || m == nt - 1) ? 0.5 : 1.0;
+            const double hb = F[m] * inv + Zb * dt * tau;
+            a[m] = (float)(ov[g] * hb);
+        }
     }
 }
 
