@@ -21,6 +21,7 @@
 // round the tiles up have K = 0 and start at zero, so they remain zero even
 // though they are written every step.
 #include <algorithm>
+#include <cmath>
 
 #include "fwi_internal.h"
 #include "wave_lds_body.h"
@@ -35,10 +36,14 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_lds(LdsArgs a, const float
     lds_field<X, P, ADJ, EXACT, STORE>(a, blockIdx.x, ax_g, az_g, lds);
 }
 
+// Threads of a split-sweep workgroup: 2-row interior tiles take 768 (three
+// waves per SIMD for the same band), the others 512.
+constexpr int split_threads(int PI) { return PI == 2 ? 768 : kLdsThreads; }
+
 // Split sweep: workgroup b holds band g = b % G of field b / G (wave_split_body.h).
 // Launched cooperatively, so all F * G workgroups are resident together.
 template <int X, int PI, bool ADJ, bool XEXACT, bool STORE>
-__global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs sp, const float* __restrict__ ax_g,
+__global__ __launch_bounds__(split_threads(PI)) void k_wave_split(LdsArgs a, SplitArgs sp, const float* __restrict__ ax_g,
                                                             const float* __restrict__ az_g) {
     extern __shared__ float lds[];
     const int lf = blockIdx.x / sp.G;
@@ -54,7 +59,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_wave_split(LdsArgs a, SplitArgs
     M(4, 8)
 
 // Interior tiles of the split sweep (X columns, PI rows): a band has 8
-// boundary rows and nstrip interior strips of PI rows, nstrip <= 512 / ncg.
+// boundary rows and nstrip interior strips of PI rows, nstrip <= split_threads(PI) / ncg.
 #define FWI_SPLIT_TILES(M) M(3, 2) M(3, 3) M(3, 4)
 
 size_t split_lds_bytes(int X, int PI, int ncg, int nstrip) {
@@ -101,10 +106,16 @@ bool lds_choose_layout(int nzp, int nxp, int req_X, int req_P, int* Xo, int* Po,
 // instructions per point, 4 cycles each, over 4 SIMDs), LDS traffic
 // ((P+8)/P + 8/X reads and one write per point, 128 bytes per cycle) and,
 // split, the latency of the halo exchange (about 0.6 us measured for one
-// tagged message between two workgroups).
-static double lds_step_cycles(int X, int P, int ncg, int H, bool split) {
+// tagged message between two workgroups) plus the latency the band's waves
+// leave exposed, about 2400 cycles divided by the waves per SIMD (`threads`
+// busy threads).  The last term is fitted to the 110 x 150 band of 38 rows:
+// 3-row tiles on 500 threads (2 waves per SIMD) took 2.61 us per forward
+// step, 2-row tiles on 750 threads (3 waves) 2.47 us and 4-row tiles on 400
+// threads about 25 % more than 3-row ones.
+static double lds_step_cycles(int X, int P, int ncg, int H, bool split, int threads = kLdsThreads) {
     const double pts = (double)ncg * X * H;
-    return pts * (33.0 / 64.0 + ((P + 8.0) / P + 8.0 / X + 1.0) / 32.0) + (split ? 1500.0 : 0.0);
+    const double waves = std::ceil(threads / 64.0) / 4.0;
+    return pts * (33.0 / 64.0 + ((P + 8.0) / P + 8.0 / X + 1.0) / 32.0) + (split ? 1500.0 + 2400.0 / waves : 0.0);
 }
 
 bool lds_choose_split(int nzp, int nxp, int nfields, int ncu, int X1, int P1, int force, int* Xo, int* Po, int* ncgo,
@@ -117,14 +128,14 @@ bool lds_choose_split(int nzp, int nxp, int nfields, int ncu, int X1, int P1, in
 #define FWI_TRY(XX, PP)                                                                                   \
     {                                                                                                     \
         const int ncg = (nxp + XX - 1) / XX;                                                              \
-        const int smax = kLdsThreads / ncg;                                                               \
+        const int smax = split_threads(PP) / ncg;                                                         \
         if (smax >= 8) {                                                                                  \
             const int G = (nzp + 8 + smax * PP - 1) / (8 + smax * PP);                                    \
             const int nstrip = std::max(1, ((nzp + G - 1) / G - 8 + PP - 1) / PP);                        \
             const int H = 8 + nstrip * PP;                                                                \
             if (G >= 2 && (long long)nfields * G <= ncu && nstrip <= smax &&                              \
                 split_lds_bytes(XX, PP, ncg, nstrip) <= (size_t)kLdsBytes) {                              \
-                const double c = lds_step_cycles(XX, PP, ncg, H, true);                                   \
+                const double c = lds_step_cycles(XX, PP, ncg, H, true, ncg * std::max(8, nstrip));        \
                 if (c < best) {                                                                           \
                     best = c;                                                                             \
                     *Xo = XX;                                                                             \
@@ -154,7 +165,7 @@ static int split_dispatch(const LdsArgs& a, SplitArgs sp, int nfields, hipStream
         if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != \
             hipSuccess)                                                                                       \
             return hip_ok(hipGetLastError());                                                                 \
-        return hip_ok(hipLaunchCooperativeKernel((const void*)kern, dim3(nfields * sp.G), dim3(kLdsThreads),   \
+        return hip_ok(hipLaunchCooperativeKernel((const void*)kern, dim3(nfields * sp.G), dim3(split_threads(PP)), \
                                                  args, (unsigned)bytes, st));                                 \
     }
     FWI_SPLIT_TILES(FWI_CASE)

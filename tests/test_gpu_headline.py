@@ -103,7 +103,7 @@ def test_headline_plan_is_the_benchmarked_configuration(run):
     info = run["gpu"]["info"]
     assert info["path"] == 0
     assert info["lds_split"] == 3
-    assert (info["lds_tile_x"], info["lds_tile_z"]) == (3, 3)
+    assert (info["lds_tile_x"], info["lds_tile_z"]) == (3, 2)  # 2-row interior tiles, 768-thread workgroups
 
 
 def test_headline_traces(run):
