@@ -190,7 +190,7 @@ CSRC = "paper_2603_16393_amd/csrc/"
 MEASURED_TRAFFIC = {
     # split LDS-resident sweep of the default workload (profiles/k_wave_split_b16_70x70_hbm_traffic.md)
     "split": {"sources": (CSRC + "wave_lds.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
-              "sha1": "b15c9031c2c614128e071569d042ba7c6e4e3eec", "bytes": {"forward": 9.0976e9, "adjoint": 8.5382e9}},
+              "sha1": "e0d5113fc72f665f11f56be04632f7df5c4f9750", "bytes": {"forward": 9.0976e9, "adjoint": 8.5382e9}},
     # PML row bands (profiles/k_wave_pml_b16_70x70_hbm_traffic.md)
     "pml": {"sources": (CSRC + "wave_pml.hip", CSRC + "pml_stencil.h", CSRC + "wave_split_body.h"),
             "sha1": "b81ad6386bd6265bd3c4f2f4f6a6209533ab3a71",
@@ -205,7 +205,7 @@ MEASURED_TRAFFIC = {
                 "bytes": {"recompute": 1.680e8, "adjoint": 2.274e8}},
     # uneven persistent forward launch of the 64-request mix (profiles/k_batch_uneven64_hbm_traffic.md)
     "uneven": {"sources": (CSRC + "batch.hip", CSRC + "wave_lds_body.h", CSRC + "wave_split_body.h"),
-               "sha1": "dbdbfb0233fb10cbf8141e94e23e5b8f923df022", "bytes": {"forward": 1.2338e11, "gradient": 6.1162e11}},
+               "sha1": "4c3b6de45e11beecd404a54bb1784f4e26cd9fa3", "bytes": {"forward": 1.2338e11, "gradient": 6.1162e11}},
 }
 
 

@@ -250,7 +250,8 @@ __device__ __forceinline__ void split_tile_gpad(const SplitTile<R, X>& t, const 
         }
 }
 
-// The whole workgroup (kLdsThreads threads) calls this for band g of `field`;
+// The whole workgroup calls this for band g of `field` (k_wave_split: 768
+// threads with 2-row interior tiles, 512 otherwise; the batch kernel: 512);
 // a.nstrip is the number of interior strips of PI rows, so the band has
 // H = 8 + a.nstrip * PI rows and uses (2 (H + 8) S + H) floats of LDS.
 // XEXACT: the column groups tile the padded width exactly (no column guards;
