@@ -197,7 +197,7 @@ MEASURED_TRAFFIC = {
             "bytes": {"forward": 4.2920e9, "adjoint": 4.3224e9}},
     # two-step tiled sweep of the 400 x 800 workload, per launch (profiles/k_wave_tile2_ckpt_400x800_hbm_traffic.md):
     # forward launch u, w, K read and u, w written; a recomputation launch also writes its two D slices
-    "tile2": {"sources": (CSRC + "wave.hip",), "sha1": "2bd6c63bda07e59de0b47c7f6632be302420bc5c",
+    "tile2": {"sources": (CSRC + "wave.hip",), "sha1": "0b5141fee21e1db97a56bc6319161c3e02d43582",
               "bytes": {"forward": 9.922e7 + 6.48e7, "recompute": 9.922e7 + 2 * 6.48e7, "adjoint": 2.976e8}},
     # HBM-swept PML, per launch of the 400 x 800 checkpointed workload
     # (profiles/k_pml_hbm_tile_ckpt_400x800_hbm_traffic.md): recomputation (D written) and adjoint

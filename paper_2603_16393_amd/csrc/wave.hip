@@ -676,11 +676,27 @@ __global__ void k_fold_columns(int B, int ns, int nx, int nzp, int nxp, int nb, 
     const int npts = nzp * nxp;
     const float* Kr = K + (size_t)b * npts + z * nxp;
     const float wz = 2.f * wgt_row[z] * dt;
+    // columns in chunks of CH whose loads go out together (the edge columns sum the whole sponge width); each
+    // column's shots are added in ascending order, then the columns in ascending order.  Every lane runs the
+    // same chunk loop (a separate path for the single-column lanes measured slower: a wave holding an edge
+    // lane then runs both)
+    constexpr int CH = 8;
     float sum = 0.f;
-    for (int x = xlo; x <= xhi; ++x) {
-        float gs = 0.f;
-        for (int s = 0; s < ns; ++s) gs += gpad[((size_t)b * ns + s) * npts + z * nxp + x];
-        sum += gs * (wz / sqrtf(Kr[x]));
+    for (int x0 = xlo; x0 <= xhi; x0 += CH) {
+        float gs[CH], kv[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            gs[c] = 0.f;
+            kv[c] = Kr[min(x0 + c, xhi)];
+        }
+        for (int s = 0; s < ns; ++s) {
+            const float* g = gpad + ((size_t)b * ns + s) * npts + z * nxp;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) gs[c] += g[min(x0 + c, xhi)];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            if (x0 + c <= xhi) sum += gs[c] * (wz / sqrtf(kv[c]));
     }
     tmp[i] = sum;
 }
@@ -694,8 +710,17 @@ __global__ void k_fold_rows(int B, int nz, int nx, int nzp, int ztop, const floa
     const int iz = q / nx, ix = q - (q / nx) * nx;
     const int zlo = (iz == 0) ? 0 : iz + ztop;
     const int zhi = (iz == nz - 1) ? nzp - 1 : iz + ztop;
+    // rows in chunks of CH whose loads go out together, added in ascending order
+    constexpr int CH = 8;
     float sum = 0.f;
-    for (int z = zlo; z <= zhi; ++z) sum += tmp[((size_t)b * nzp + z) * nx + ix];
+    for (int z0 = zlo; z0 <= zhi; z0 += CH) {
+        float v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) v[c] = tmp[((size_t)b * nzp + min(z0 + c, zhi)) * nx + ix];
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            if (z0 + c <= zhi) sum += v[c];
+    }
     grad[i] = sum * (scale ? scale[b] : 1.f);
 }
 
