@@ -1,9 +1,10 @@
 // Preconditioned guidance update on gfx950 (Sec. 5.2: Eqs. tv, rho, kappa,
 // precond_step; the gradient, preconditioner and update lines of Algorithm 2).
 //
-// One 256-thread workgroup per sample: a fixed-order FP64 reduction gives the
-// total variation of the clean estimate and an exact max gives ||s g||_inf;
-// then every cell is updated in one pass.
+// kGP 256-thread workgroups per sample: each forms the sample's fixed-order
+// FP64 reduction (the total variation of the clean estimate) and exact max
+// (||s g||_inf) in the same order, so all hold the same values, and then
+// updates its share of the cells (the FP64 power per cell dominates).
 #include <cmath>
 
 #include "fwi_internal.h"
@@ -11,6 +12,7 @@
 namespace fwi {
 
 constexpr int GT = 256;
+constexpr int kGP = 8;  // workgroups per sample
 
 __global__ __launch_bounds__(GT) void k_guidance(int nz, int nx, const float* __restrict__ vprop,
                                                  const float* __restrict__ h, const float* __restrict__ g,
@@ -56,9 +58,9 @@ __global__ __launch_bounds__(GT) void k_guidance(int nz, int nx, const float* __
     tv /= (double)n;
     const double ex = tv - tau > 0.0 ? tv - tau : 0.0;
     const double rho = rho0 * exp(-ex / c);
-    if (threadIdx.x == 0 && rho_out) rho_out[b] = (float)rho;
+    if (blockIdx.y == 0 && threadIdx.x == 0 && rho_out) rho_out[b] = (float)rho;
     const double num = gm + eps;
-    for (size_t i = threadIdx.x; i < n; i += GT) {
+    for (size_t i = blockIdx.y * GT + threadIdx.x; i < n; i += (size_t)GT * gridDim.y) {
         const double gi = fabs(s * (double)gb[i]);
         double kap = pow(num / (gi + eps), gamma);
         if (kappa_max > 0.0 && kap > kappa_max) kap = kappa_max;
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(GT) void k_guidance(int nz, int nx, const float* __
 int launch_guidance(int B, int nz, int nx, const float* v_prop, const float* h, const float* g, const float* v0hat,
                     const fwi_guidance_params& gp, float* v_next, float* rho_out, hipStream_t st) {
     if (B == 0) return FWI_OK;
-    hipLaunchKernelGGL(k_guidance, dim3(B), dim3(GT), 0, st, nz, nx, v_prop, h, g, v0hat, gp.rho0, gp.c, gp.tau,
+    hipLaunchKernelGGL(k_guidance, dim3(B, kGP), dim3(GT), 0, st, nz, nx, v_prop, h, g, v0hat, gp.rho0, gp.c, gp.tau,
                        gp.gamma, gp.eps, gp.kappa_max, gp.unit_scale, v_next, rho_out);
     return hip_ok(hipGetLastError());
 }
